@@ -1,0 +1,238 @@
+"""Pins of the oracle's field operations: streaming with bounce-back, the
+interaction force stencil (Eq. 13), the open-boundary mirror (Sec. 2.1),
+IVSD (Eqs. 16-17), the Set-3 treatment (Sec. 2.3) and exact mass
+bookkeeping."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2111_08666_amd import inputs as I
+
+CS2 = 1.0 / 3.0
+
+
+def _open_channel(nx=12, ny=10, G=3.5, xi=0.0, rho0=None, mask=None, **kw):
+    if mask is None:
+        mask = np.zeros((ny, nx), np.uint8)
+        mask[0] = mask[-1] = 1
+    if rho0 is None:
+        rho0 = np.zeros((2, ny, nx))
+        rho0[0], rho0[1] = 0.03, 1.0
+        rho0[:, mask.astype(bool)] = 0
+    P = O.make_params(q=9, nx=nx, ny=ny, periodic=0, open_x=1, G=G, xi=xi,
+                      tau=(1.0, 1.0), rho_in1=1.0, rho_out2=1.0, **kw)
+    return O.OracleSim(params=P, mask=mask, rho0=rho0)
+
+
+def test_streaming_is_a_permutation_with_bounce_back():
+    """A unit pulse in one post-collision population moves one node along
+    its velocity, or comes back reversed from a solid node."""
+    nx, ny = 8, 6
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[0] = mask[-1] = 1
+    mask[3, 5] = 1
+    rho0 = np.zeros((2, ny, nx))
+    rho0[:, ~mask.astype(bool)] = 1.0
+    P = O.make_params(q=9, nx=nx, ny=ny, periodic=1, open_x=0, G=0.0)
+    s = O.OracleSim(params=P, mask=mask, rho0=rho0)
+    e, w, opp = O.lattice(9)
+    fs = np.zeros((2, 9, ny, nx))
+    fs[0, 5, 2, 3] = 1.0   # moving (+1, +1) from (3, 2) -> (4, 3), fluid
+    fs[0, 1, 3, 4] = 1.0   # moving +x from (4, 3) into solid (5, 3): comes back as i = 3
+    fs[0, 3, 2, 0] = 1.0   # moving -x across the periodic x edge -> (7, 2)
+    s.set_fstar(fs)
+    r = s.density()[0]
+    assert r[3, 4] == 2.0 and r[2, 7] == 1.0 and r.sum() == 3.0
+
+
+def test_force_of_linear_pseudopotential_is_exact_gradient():
+    """With psi linear in x, sum_i w_i psi(x+e_i) e_i = c_s^2 grad psi, so
+    Eq. 13 gives F^s = -G rho^s c_s^2 grad psi^sbar at interior nodes."""
+    nx, ny = 16, 8
+    x = np.arange(nx)[None, :] * np.ones((ny, 1))
+    rho0 = np.stack([0.5 + 0.01 * x, 0.8 - 0.02 * x])
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[0] = mask[-1] = 1
+    rho0[:, mask.astype(bool)] = 0
+    G = 2.0
+    s = _open_channel(nx, ny, G=G, rho0=rho0, mask=mask)
+    F = s.force()
+    rho = s.density()
+    sl = (slice(2, ny - 2), slice(2, nx - 2))
+    # rest equilibria of a linear field stream into the same linear field
+    assert np.abs(rho[:, sl[0], sl[1]] - rho0[:, sl[0], sl[1]]).max() < 1e-15
+    assert np.abs(F[0, 0][sl] - (-G * rho[0][sl] * CS2 * (-0.02))).max() < 1e-15
+    assert np.abs(F[1, 0][sl] - (-G * rho[1][sl] * CS2 * 0.01)).max() < 1e-15
+    assert np.abs(F[:, 1][(slice(0, None),) + sl]).max() < 1e-16
+
+
+def test_open_face_force_mirror():
+    """At the inlet and outlet columns the missing neighbours are mirrored,
+    so F_x vanishes and F_y uses only the neighbours along the face."""
+    nx, ny = 10, 12
+    rng = np.random.default_rng(0)
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[0] = mask[-1] = 1
+    rho0 = np.stack([rng.uniform(0.02, 1.0, (ny, nx)), rng.uniform(0.02, 1.0, (ny, nx))])
+    rho0[:, mask.astype(bool)] = 0
+    G = 3.5
+    s = _open_channel(nx, ny, G=G, rho0=rho0, mask=mask)
+    F = s.force()
+    rho = s.density()
+    psi = s.psi()
+    for x in (0, nx - 1):
+        assert np.abs(F[:, 0, 1:-1, x]).max() == 0.0
+        for y in range(2, ny - 2):
+            for c in range(2):
+                exp = -G * rho[c, y, x] * (1 / 9) * (psi[1 - c, y + 1, x] - psi[1 - c, y - 1, x])
+                assert abs(F[c, 1, y, x] - exp) < 1e-15
+    assert np.abs(F[:, 0, 2:-2, 2:-2]).max() > 0  # interior is not mirrored
+
+
+@pytest.mark.parametrize("xi", [-0.4, 0.0, 0.3])
+def test_ivsd_flat_wall_is_chi_times_density(xi):
+    """Next to a uniform fluid, the virtual solid density is chi^s rho^s
+    with chi1 = 1 + xi and chi2 = 1 - xi (Sec. 2.2)."""
+    nx, ny = 6, 8
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[0] = mask[-1] = 1
+    rho0 = np.zeros((2, ny, nx))
+    rho0[0], rho0[1] = 0.3, 0.9
+    rho0[:, mask.astype(bool)] = 0
+    P = O.make_params(q=9, nx=nx, ny=ny, periodic=1, G=3.5, xi=xi)
+    s = O.OracleSim(params=P, mask=mask, rho0=rho0)
+    psi = s.psi()
+    assert np.abs(psi[0, 0] - (1 + xi) * 0.3).max() < 1e-15
+    assert np.abs(psi[1, -1] - (1 - xi) * 0.9).max() < 1e-15
+
+
+def test_ivsd_weighted_mean_on_a_corner():
+    """A solid node with fluid only at one axis and one diagonal neighbour:
+    the weighted mean (w_axis rho_a + w_diag rho_d) / (w_axis + w_diag)."""
+    nx, ny = 5, 5
+    mask = np.ones((ny, nx), np.uint8)
+    mask[2, 3] = 0        # axis neighbour (+x) of (2, 2)
+    mask[3, 3] = 0        # diagonal neighbour (+1, +1) of (2, 2)
+    rho0 = np.zeros((2, ny, nx))
+    rho0[:, 2, 3] = (0.2, 0.6)
+    rho0[:, 3, 3] = (0.8, 0.1)
+    xi = 0.25
+    P = O.make_params(q=9, nx=nx, ny=ny, periodic=3, G=3.5, xi=xi)
+    s = O.OracleSim(params=P, mask=mask, rho0=rho0)
+    rho = s.density()
+    psi = s.psi()
+    for c, chi in enumerate((1 + xi, 1 - xi)):
+        exp = chi * (rho[c, 2, 3] / 9 + rho[c, 3, 3] / 36) / (1 / 9 + 1 / 36)
+        assert abs(psi[c, 2, 2] - exp) < 1e-15
+
+
+def test_closed_box_mass_is_conserved():
+    p = I.drainage_2d(nx=48, ny=24, r=(2.0, 4.0), porosity=0.75, seed=3, G=3.5, theta=60)
+    P = O.make_params(p, periodic=3, open_x=0)
+    mask = p.mask.copy()
+    s = O.OracleSim(params=P, mask=mask, rho0=p.rho0)
+    m0 = s.observables()["mass"]
+    s.step(500)
+    m1 = s.observables()["mass"]
+    for c in range(2):
+        assert abs(m1[c] - m0[c]) / m0[c] < 1e-12
+
+
+def test_open_box_mass_identity():
+    """With open faces the change of each component's mass over one step is
+    exactly what the boundary treatment set minus what streamed out."""
+    p = I.drainage_2d(nx=48, ny=24, r=(2.0, 4.0), porosity=0.75, seed=3, G=3.5, theta=45,
+                      rho_in1=1.02)
+    s = O.OracleSim(p)
+    prev = s.observables()
+    for _ in range(40):
+        s.step(1)
+        o = s.observables()
+        for c in range(2):
+            d = o["mass"][c] - prev["mass"][c]
+            assert abs(d - (o["flux_in"][c] - o["flux_out"][c])) < 1e-12 * o["mass"][c]
+        prev = o
+
+
+def test_set3_inlet_and_outlet_rules():
+    """Set-3 (Sec. 2.3): component 1 has the prescribed density at the
+    inlet, component 2 at the outlet; component 2's inlet links keep the
+    node's own post-collision values (Eq. 28); component 1's outlet links
+    keep their initial values (Eq. 26, frozen reading)."""
+    p = I.drainage_2d(nx=40, ny=20, r=(2.0, 3.0), porosity=0.8, seed=4, G=3.5, theta=45,
+                      rho_in1=1.03, rho_out2=0.99)
+    s = O.OracleSim(p)
+    s.step(7)
+    rho = s.density()
+    fluid = ~p.mask.astype(bool)
+    yi = np.where(fluid[:, 0])[0]
+    yo = np.where(fluid[:, -1])[0]
+    assert np.abs(rho[0, yi, 0] - 1.03).max() < 1e-14
+    assert np.abs(rho[1, yo, -1] - 0.99).max() < 1e-14
+    e, w, _ = O.lattice(9)
+    fs = s.fstar()
+    # Eq. 28: with component 2's f* zero except the inlet's own (1, 5, 8)
+    # links, the inlet density of component 2 is exactly their sum.
+    z = np.zeros_like(fs)
+    z[0] = fs[0]
+    for i in (1, 5, 8):
+        z[1, i, yi, 0] = 0.1 * i
+    s.set_fstar(z)
+    # (rows next to a wall also receive bounced-back links, so skip them)
+    assert np.abs(s.density()[1, yi[1:-1], 0] - 1.4).max() < 1e-14
+    # Eq. 26: with component 1's f* all zero, its outlet density is the sum
+    # of the frozen initial (3, 6, 7) links, w * rho0.
+    z = np.zeros_like(fs)
+    z[1] = fs[1]
+    s.set_fstar(z)
+    r = s.density()
+    exp = (w[3] + w[6] + w[7]) * p.rho0[0, yo, -1]
+    assert np.abs(r[0, yo, -1] - exp).max() < 1e-15
+    assert np.abs(r[0, yi, 0] - 1.03).max() < 1e-14    # Zou-He is unaffected
+    assert np.abs(r[0][:, 1:-1]).max() == 0.0
+
+
+def test_periodic_translation_is_bitwise():
+    rng = np.random.default_rng(1)
+    nx, ny = 24, 20
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[5:8, 4:9] = 1
+    rho0 = np.stack([rng.uniform(0.05, 1.0, (ny, nx)), rng.uniform(0.05, 1.0, (ny, nx))])
+    rho0[:, mask.astype(bool)] = 0
+    P = O.make_params(q=9, nx=nx, ny=ny, periodic=3, G=3.5, xi=-0.3, tau=(0.8, 1.3))
+    a = O.OracleSim(params=P, mask=mask, rho0=rho0)
+    b = O.OracleSim(params=P, mask=np.roll(mask, (3, 7), (0, 1)), rho0=np.roll(rho0, (3, 7), (1, 2)))
+    a.step(30)
+    b.step(30)
+    assert np.array_equal(np.roll(a.density(), (3, 7), (1, 2)), b.density())
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_component_swap_symmetry(q):
+    """Swapping the components together with xi -> -xi (equal tau) swaps
+    the density fields (Sec. 2.2: chi1 = 1 + xi, chi2 = 1 - xi)."""
+    rng = np.random.default_rng(2)
+    shape = (12, 14) if q == 9 else (8, 9, 10)
+    mask = (rng.uniform(size=shape) < 0.15).astype(np.uint8)
+    rho0 = np.stack([rng.uniform(0.05, 1.0, shape), rng.uniform(0.05, 1.0, shape)])
+    rho0[:, mask.astype(bool)] = 0
+    per = 3 if q == 9 else 7
+    kw = dict(q=q, nx=shape[-1], ny=shape[-2], nz=1 if q == 9 else shape[0], periodic=per,
+              G=3.5, tau=(0.9, 0.9))
+    a = O.OracleSim(params=O.make_params(xi=0.3, **kw), mask=mask, rho0=rho0)
+    b = O.OracleSim(params=O.make_params(xi=-0.3, **kw), mask=mask, rho0=rho0[::-1].copy())
+    a.step(20)
+    b.step(20)
+    ra, rb = a.density(), b.density()
+    assert np.abs(ra - rb[::-1]).max() < 1e-13
+
+
+def test_invalid_inputs_are_rejected():
+    mask = np.zeros((6, 6), np.uint8)
+    rho0 = np.ones((2, 6, 6))
+    with pytest.raises(ValueError, match="tau"):
+        O.OracleSim(params=O.make_params(nx=6, ny=6, periodic=3, tau=(0.5, 1.0)), mask=mask, rho0=rho0)
+    with pytest.raises(ValueError, match="closed domain edge"):
+        O.OracleSim(params=O.make_params(nx=6, ny=6, periodic=1), mask=mask, rho0=rho0)
+    with pytest.raises(ValueError, match="xi"):
+        O.OracleSim(params=O.make_params(nx=6, ny=6, periodic=3, xi=1.0), mask=mask, rho0=rho0)
