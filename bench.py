@@ -1,0 +1,175 @@
+"""Benchmark of the fused two-component LBM step on one MI355X.
+
+Workload (default): D2Q9, 1024 x 512 heterogeneous disc medium (radii 4-20,
+porosity 0.55, seed 2), viscosity ratio 10 through the MRT collision, G =
+3.5, xi = -0.4, Set-3 pressure inlet/outlet.  A step is one fused launch over
+the whole grid; the timed region replays HIP graphs of the step with the
+state resident in HBM.
+
+Prints one JSON line: MLUPS over all lattice nodes (both components per
+node), the roofline of the step kernel (algorithmic bytes per launch / mean
+kernel time from HIP events on the solver's stream) and the FP64 oracle
+timed on the host cores as a CPU baseline.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per fluid node and step: every population read once and
+# written once (two components)
+BYTES_PER_NODE = {(9, 0): 2 * 9 * 2 * 4, (9, 1): 2 * (8 * 2 + 4) * 2,
+                  (19, 0): 2 * 19 * 2 * 4, (19, 1): 2 * (18 * 2 + 4) * 2}
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.hip", "lattice.h", "lbm_device.h"):
+        with open(os.path.join(ROOT, "paper_2111_08666_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def workload(name):
+    from paper_2111_08666_amd import inputs as I
+    if name == "d2q9_1024x512":
+        return I.large_drainage(collision=1)
+    if name == "d2q9_128x64":
+        return I.small_drainage()
+    if name.startswith("d3q19_"):
+        n = int(name.split("_")[1])
+        return I.drainage_3d(n=n)
+    raise SystemExit(f"unknown workload {name}")
+
+
+def traffic_for(kernel, wl):
+    """Measured HBM bytes per launch from committed counter summaries, if
+    they were taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        data = json.load(f)
+    rec = data.get(f"{kernel}|{wl}")
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(problem, seconds=12.0):
+    import oracle as O
+    s = O.OracleSim(problem)
+    s.step(2)  # warm
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        s.step(5)
+        steps += 5
+    dt = time.perf_counter() - t0
+    return {"value": problem.n_nodes * steps / dt / 1e6, "unit": "MLUPS", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"{steps} steps of the same {problem.nx}x{problem.ny}x{problem.nz} workload "
+                      f"(FP64 oracle, OpenMP over nodes)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=2000)
+    ap.add_argument("--workload", default="d2q9_1024x512")
+    ap.add_argument("--chunk", type=int, default=100, help="steps per captured graph")
+    ap.add_argument("--storage", type=int, default=0, help="0 FP32, 1 BF16 deviations")
+    ap.add_argument("--eager", action="store_true", help="plain launches instead of graphs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-samples", type=int, default=300)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2111_08666_amd import lbm
+
+    dev = torch.device("cuda:0")
+    problem = workload(args.workload)
+    print(f"[bench] workload {args.workload}: {problem.nx}x{problem.ny}x{problem.nz}, "
+          f"fluid {problem.n_fluid}, collision {problem.collision}", file=sys.stderr, flush=True)
+    solver = lbm.Solver(problem, storage=args.storage, device=dev)
+    stream = solver.stream
+    chunk = max(2, args.chunk - args.chunk % 2)
+    steps = max(chunk, args.steps - args.steps % chunk)
+
+    def run(n):
+        if args.eager:
+            solver.step(n)
+        else:
+            solver.step_graph(chunk, n // chunk)
+
+    run(max(chunk, args.warmup - args.warmup % chunk))
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    run(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ms_per_step = wall * 1e3 / steps
+
+    # per-launch kernel durations: events bracketing single launches
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.kernel_samples)]
+    for a, b in evs:
+        a.record(stream)
+        solver.step(1)
+        b.record(stream)
+    torch.cuda.synchronize()
+    k_ms = sorted(a.elapsed_time(b) for a, b in evs)
+    k_mean = sum(k_ms) / len(k_ms)
+    obs = solver.observables()
+
+    kname, grid, block = solver.kernel_info()
+    bpn = BYTES_PER_NODE[(problem.q, args.storage)]
+    alg_bytes = bpn * problem.n_fluid
+    achieved = alg_bytes / (k_mean * 1e-3) / 1e9
+    traffic = traffic_for(kname, args.workload)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "kernel": kname,
+                "kernel_ms_mean": round(k_mean, 5), "kernel_ms_median": round(k_ms[len(k_ms) // 2], 5),
+                "alg_bytes_per_launch": alg_bytes, "bytes_per_fluid_node": bpn,
+                "graph_ms_per_step": round(e0.elapsed_time(e1) / steps, 5)}
+    mlups = problem.n_nodes * steps / wall / 1e6
+    out = {
+        "metric": "MLUPS (2-component step) + % HBM roofline",
+        "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if args.storage == 0 else "bf16-dev/f32",
+        "data": "synthetic (seeded disc medium; the paper's geometry is not available)",
+        "config": {"workload": problem.name, "q": problem.q, "nx": problem.nx, "ny": problem.ny,
+                   "nz": problem.nz, "n_fluid": problem.n_fluid,
+                   "collision": ["SRT", "MRT", "TRT"][problem.collision],
+                   "storage": "f32" if args.storage == 0 else "bf16-dev",
+                   "launch": "eager" if args.eager else f"hipGraph x{chunk}",
+                   "mflups_fluid": round(problem.n_fluid * steps / wall / 1e6, 1),
+                   "mass_after": obs["mass"], "grid_blocks": grid, "block_threads": block},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(problem)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,176 @@
+/* lbm.h - C ABI of the MI355X two-component pseudopotential LBM library.
+ *
+ * The library advances the improved multicomponent pseudopotential lattice
+ * Boltzmann model of Sedahmed, Coelho & Warda (arXiv:2111.08666): two
+ * immiscible components with Shan-Chen cohesion (Sec. 2.1, Eq. 13, psi =
+ * rho), IVSD fluid-solid adhesion (Sec. 2.2, Eqs. 15-17), a forced collision
+ * with a density-weighted mixture relaxation time (Eqs. 1-11; SRT, or MRT /
+ * TRT variants with the same viscosity law), pull streaming with half-way
+ * bounce-back, and the pressure inlet/outlet treatment Set-3 (Sec. 2.3,
+ * Eqs. 18-28).  Every step runs in HIP kernels on one GPU.
+ *
+ * Conventions shared by every entry point:
+ *  - Host pointers are read during the call only; nothing is retained.
+ *  - Device memory is owned by the caller: the workspace handed to
+ *    lbm_create / lbm_batch_create is borrowed until the matching destroy.
+ *    The library itself allocates no device memory.
+ *  - All GPU work is enqueued on the caller's HIP stream (hipStream_t passed
+ *    as void*; NULL = the default stream), in stream order.  Only
+ *    lbm_observables, lbm_get_density with a host destination, lbm_save,
+ *    lbm_load and the create calls synchronise that stream.
+ *  - Every call returns an lbm_status; on failure lbm_last_error() returns a
+ *    message.  Invalid arguments are rejected before any device work.
+ *  - A context is not thread-safe; distinct contexts are independent.
+ *  - Fields are indexed with x fastest: node (x, y, z) is at
+ *    x + nx * (y + ny * z).  Component 1 (index 0) is the invading,
+ *    non-wetting fluid driven in at x = 0; component 2 (index 1) is the
+ *    resident, wetting fluid held at x = nx - 1.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,    /* bad argument; nothing was done */
+  LBM_ENOMEM = -2,    /* workspace too small or misaligned */
+  LBM_EDEVICE = -3,   /* a HIP call failed */
+  LBM_EUNSTABLE = -4, /* a density became non-finite or negative */
+  LBM_ESTATE = -5     /* call not valid in the current state */
+} lbm_status;
+
+enum { LBM_SRT = 0, LBM_MRT = 1, LBM_TRT = 2 };            /* lbm_params.collision */
+enum { LBM_STORE_F32 = 0, LBM_STORE_BF16DEV = 1 };          /* lbm_params.storage */
+
+/* Problem geometry (Sec. 2.3 and Sec. 4.2: a solid map phi, periodic or
+ * open axes, the inlet at x = 0 and the outlet at x = nx - 1). */
+typedef struct {
+  int32_t q;              /* 9 (D2Q9) or 19 (D3Q19) */
+  int32_t nx, ny, nz;     /* nz = 1 for D2Q9 */
+  const uint8_t *solid;   /* host, nx*ny*nz bytes, 1 = solid (phi of Eq. 16) */
+  uint32_t periodic;      /* bit0 x, bit1 y, bit2 z */
+  int32_t open_x;         /* 1: pressure inlet x = 0 and outlet x = nx-1 */
+  int32_t porous_x0;      /* saturation window [porous_x0, porous_x1) */
+  int32_t porous_x1;      /* 0 = nx */
+} lbm_geometry;
+
+/* Model parameters (Sec. 2 and Sec. 3). */
+typedef struct {
+  double tau[2];          /* tau^(1), tau^(2) > 1/2; nu = (tau - 1/2)/3 */
+  double G;               /* G_coh = G_ads (Eq. 13, Sec. 2.2) */
+  double xi;              /* wettability: chi1 = 1 + xi, chi2 = 1 - xi, |xi| < 1 */
+  double rho_in1;         /* component-1 density at the inlet (Eqs. 22-25) */
+  double rho_out2;        /* component-2 density at the outlet (Eqs. 18-21) */
+  double rho_in2;         /* Set-1 only: component-2 inlet density */
+  double rho_out1;        /* Set-1 only: component-1 outlet density */
+  double g[3];            /* body acceleration, F^b = rho^s g (Eq. 12) */
+  int32_t collision;      /* LBM_SRT (Eq. 1), LBM_MRT (D2Q9), LBM_TRT */
+  int32_t bc_set;         /* 3 = Set-3 (the paper's); 1, 2 = Set-1, Set-2 */
+  int32_t half_force_shift; /* 1: u = (j + F/2)/rho (default); 0: u = j/rho */
+  int32_t mrt_sj_mode;    /* MRT momentum rate: 0 = s_nu, 1 = s_q */
+  double lambda;          /* magic (1/s_nu - 1/2)(1/s_q - 1/2); <= 0: s_q = s_nu */
+  double s_e, s_eps;      /* MRT energy-mode rates; <= 0: equal to s_nu */
+  int32_t storage;        /* LBM_STORE_F32 or LBM_STORE_BF16DEV */
+  int32_t reserved;
+} lbm_params;
+
+/* Observables at the current time (Eq. 14 pressure, Sec. 4.2 saturation).
+ * Sums are accumulated in FP64 on the GPU in a fixed order. */
+typedef struct {
+  int64_t step;
+  double mass[2];         /* sum of rho^s over fluid nodes */
+  double n_fluid;
+  double n_window;        /* fluid nodes with porous_x0 <= x < porous_x1 */
+  double sw_count;        /* window nodes with rho2 > rho1 */
+  double sum_rho_w;       /* window sum of rho2 */
+  double sum_rho;         /* window sum of rho1 + rho2 */
+  double s_w;             /* sw_count / n_window */
+  double s_w_weighted;    /* sum_rho_w / sum_rho */
+  double p_in, p_out;     /* mean P = (rho1+rho2)/3 + G rho1 rho2 / 3 over face
+                             nodes at least 3 nodes from any solid */
+  double pc;              /* p_in - p_out */
+  double n_in, n_out;
+  int32_t flags;          /* bit0 non-finite density, bit1 negative density */
+  int32_t reserved;
+} lbm_obs;
+
+typedef struct lbm_ctx lbm_ctx;
+typedef struct lbm_batch lbm_batch;
+
+/* Size in bytes of the device workspace lbm_create needs (0 if invalid). */
+size_t lbm_workspace_bytes(const lbm_geometry *geom, const lbm_params *params);
+
+/* Create a solver.  rho_init: host, 2*nx*ny*nz doubles (component 1 then 2;
+ * values at solid nodes ignored) placed as rest equilibria w_i rho (the
+ * first step starts by streaming them).  workspace: device, >= the size
+ * above, 256-byte aligned.  Validates all inputs first (tau > 1/2, |xi| < 1,
+ * finite non-negative densities, fluid nodes never touching a closed domain
+ * edge, open-face fluid nodes with a fluid neighbour); then uploads the
+ * geometry tables and initial state and synchronises the stream. */
+lbm_status lbm_create(const lbm_geometry *geom, const lbm_params *params,
+                      const double *rho_init, void *workspace, size_t ws_bytes,
+                      void *hip_stream, lbm_ctx **out);
+
+/* Change the Zou-He densities (a pressure increment, Sec. 4.2); stream-ordered. */
+lbm_status lbm_set_bc(lbm_ctx *ctx, double rho_in1, double rho_out2);
+
+/* Enqueue n time steps (one fused kernel launch each).  Asynchronous. */
+lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
+
+/* Capture n steps into a HIP graph once and replay it `reps` times; for
+ * launch-bound small domains.  n must be even.  Asynchronous. */
+lbm_status lbm_step_graph(lbm_ctx *ctx, int64_t n, int64_t reps);
+
+/* Observables at the current time; synchronises the stream.  Returns
+ * LBM_EUNSTABLE (with *out filled) once a density is non-finite or negative;
+ * later lbm_step calls then return LBM_EUNSTABLE too. */
+lbm_status lbm_observables(lbm_ctx *ctx, lbm_obs *out);
+
+/* Densities rho^s at the current time as float, 2*nx*ny*nz values
+ * (component 1 then 2; 0 at solid nodes).  dst_is_device = 1: dst is a
+ * device pointer (stream-ordered); 0: host pointer (synchronises). */
+lbm_status lbm_get_density(lbm_ctx *ctx, float *dst, int32_t dst_is_device);
+
+/* Checkpoint: all state needed to continue bit-identically.  With
+ * host_blob = NULL, *bytes receives the size.  Both synchronise. */
+lbm_status lbm_save(lbm_ctx *ctx, void *host_blob, size_t *bytes);
+lbm_status lbm_load(lbm_ctx *ctx, const void *host_blob, size_t bytes);
+
+int64_t lbm_get_step(const lbm_ctx *ctx);
+lbm_status lbm_destroy(lbm_ctx *ctx);
+
+/* Last error message of ctx (or of the calling thread's last failed create
+ * when ctx is NULL).  Never NULL. */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+/* Name, grid size (blocks) and block size of the fused step kernel the
+ * context launches; for profiling. */
+lbm_status lbm_kernel_info(const lbm_ctx *ctx, char *name, size_t name_len,
+                           int64_t *grid_blocks, int32_t *block_threads);
+
+/* ---- batches: many instances of uneven size advanced together ----------
+ * One launch per step covers every instance through a flat table of
+ * (instance, tile) blocks; steps can be captured in one HIP graph.  All
+ * instances must share q and storage.  rho_inits[k] as for lbm_create. */
+size_t lbm_batch_workspace_bytes(int32_t k, const lbm_geometry *geoms, const lbm_params *params);
+lbm_status lbm_batch_create(int32_t k, const lbm_geometry *geoms, const lbm_params *params,
+                            const double *const *rho_inits, void *workspace,
+                            size_t ws_bytes, void *hip_stream, lbm_batch **out);
+lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
+/* n steps captured once into a HIP graph, replayed reps times (n even). */
+lbm_status lbm_batch_step_graph(lbm_batch *b, int64_t n, int64_t reps);
+lbm_status lbm_batch_observables(lbm_batch *b, lbm_obs *out /* k entries */);
+lbm_status lbm_batch_get_density(lbm_batch *b, int32_t k, float *dst, int32_t dst_is_device);
+lbm_status lbm_batch_destroy(lbm_batch *b);
+const char *lbm_batch_last_error(const lbm_batch *b);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

@@ -1,0 +1,614 @@
+// Host runtime behind the C ABI of include/lbm.h: argument validation, node
+// tables, workspace carving, kernel launches, HIP graphs and checkpoints.
+// A single-instance context is a batch of one.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_device.h"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_err = "";
+
+// host copies of the lattice tables (velocity sets of the kernels)
+const int E9[9][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {-1, 0, 0}, {0, -1, 0},
+                      {1, 1, 0}, {-1, 1, 0}, {-1, -1, 0}, {1, -1, 0}};
+const int E19[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0},
+                        {0, 0, 1},  {0, 0, -1}, {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                        {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                        {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+double weight(int q, int i) {
+  if (q == 9) return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+  return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+const int *evec(int q, int i) { return q == 9 ? E9[i] : E19[i]; }
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v, size_t a = kAlign) { return (v + a - 1) / a * a; }
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+struct Layout {
+  int32_t pitch;
+  int64_t plane, n_nodes;
+  size_t buf_bytes, info_bytes, frozen_bytes;
+  int32_t tiles_x, tiles_y, tiles_z;
+  int64_t blocks;
+};
+
+Layout make_layout(const lbm_geometry &g, const lbm_params &p) {
+  Layout L{};
+  L.pitch = (int32_t)round_up(g.nx, 64);
+  L.n_nodes = (int64_t)g.nx * g.ny * g.nz;
+  L.plane = round_up((int64_t)L.pitch * g.ny * g.nz, 64);
+  if (p.storage == LBM_STORE_F32)
+    L.buf_bytes = align_up((size_t)2 * g.q * L.plane * sizeof(float));
+  else
+    L.buf_bytes = align_up((size_t)2 * L.plane * sizeof(float) + (size_t)2 * (g.q - 1) * L.plane * 2);
+  L.info_bytes = align_up((size_t)L.plane * sizeof(uint32_t));
+  L.frozen_bytes = align_up((size_t)2 * g.q * g.ny * g.nz * sizeof(float));
+  L.tiles_x = (int32_t)((g.nx + kTileX - 1) / kTileX);
+  if (g.q == 9) {
+    L.tiles_y = (int32_t)((g.ny + kTileY - 1) / kTileY);
+    L.tiles_z = 1;
+  } else {
+    L.tiles_y = (int32_t)((g.ny + kTileY3 - 1) / kTileY3);
+    const int64_t xy = (int64_t)L.tiles_x * L.tiles_y;
+    int64_t tz = (4096 + xy - 1) / xy;           // aim at >= 4096 blocks
+    tz = std::min<int64_t>(tz, std::max(1, g.nz / 24));  // keep z chunks >= ~24 planes
+    L.tiles_z = (int32_t)std::max<int64_t>(1, tz);
+  }
+  L.blocks = (int64_t)L.tiles_x * L.tiles_y * L.tiles_z;
+  return L;
+}
+
+bool bad(std::string &err, const std::string &msg) {
+  err = msg;
+  return false;
+}
+
+// Validation of one instance; no device work.
+bool validate(const lbm_geometry *g, const lbm_params *p, const double *rho0, std::string &err) {
+  if (!g || !p) return bad(err, "null geometry or params");
+  if (g->q != 9 && g->q != 19) return bad(err, "q must be 9 or 19");
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return bad(err, "grid sizes must be >= 1");
+  if (g->q == 9 && g->nz != 1) return bad(err, "D2Q9 needs nz = 1");
+  if ((int64_t)g->nx * g->ny * g->nz > (int64_t)1 << 31) return bad(err, "grid too large");
+  if (!g->solid) return bad(err, "solid map is NULL");
+  if (g->open_x && ((g->periodic & 1) || g->nx < 3)) return bad(err, "open x needs nx >= 3 and x not periodic");
+  for (int c = 0; c < 2; ++c)
+    if (!(p->tau[c] > 0.5) || !std::isfinite(p->tau[c])) return bad(err, "tau must exceed 1/2");
+  if (!(std::fabs(p->xi) < 1.0)) return bad(err, "|xi| must be < 1");
+  if (!std::isfinite(p->G)) return bad(err, "G must be finite");
+  if (p->collision < 0 || p->collision > 2) return bad(err, "collision must be SRT, MRT or TRT");
+  if (p->collision == LBM_MRT && g->q != 9) return bad(err, "MRT is defined for D2Q9 only");
+  if (p->bc_set < 1 || p->bc_set > 3) return bad(err, "bc_set must be 1, 2 or 3");
+  if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_BF16DEV) return bad(err, "unknown storage");
+  const double vals[] = {p->rho_in1, p->rho_out2, p->rho_in2, p->rho_out1, p->g[0], p->g[1], p->g[2]};
+  for (double v : vals)
+    if (!std::isfinite(v)) return bad(err, "boundary densities and g must be finite");
+  const int64_t N = (int64_t)g->nx * g->ny * g->nz;
+  const bool perx = g->periodic & 1, pery = g->periodic & 2, perz = g->periodic & 4;
+  for (int64_t n = 0; n < N; ++n) {
+    if (g->solid[n]) continue;
+    const int x = (int)(n % g->nx), y = (int)((n / g->nx) % g->ny), z = (int)(n / ((int64_t)g->nx * g->ny));
+    int nfluid = 0;
+    for (int i = 1; i < g->q; ++i) {
+      const int *e = evec(g->q, i);
+      int a = x + e[0], b = y + e[1], c = z + e[2];
+      const bool ox = a < 0 || a >= g->nx, oy = b < 0 || b >= g->ny, oz = c < 0 || c >= g->nz;
+      if ((oy && !pery) || (oz && !perz) || (ox && !perx && !g->open_x))
+        return bad(err, "fluid node touches a closed domain edge (make it solid or periodic)");
+      if (ox && !perx) continue;  // across the open face
+      a = (a + g->nx) % g->nx; b = (b + g->ny) % g->ny; c = (c + g->nz) % g->nz;
+      if (!g->solid[a + (int64_t)g->nx * (b + (int64_t)g->ny * c)]) ++nfluid;
+    }
+    if (g->open_x && (x == 0 || x == g->nx - 1) && nfluid == 0)
+      return bad(err, "fluid node on an open face without a fluid neighbour");
+    if (rho0) {
+      const double r1 = rho0[n], r2 = rho0[N + n];
+      if (!std::isfinite(r1) || !std::isfinite(r2) || r1 < 0 || r2 < 0)
+        return bad(err, "initial densities must be finite and >= 0");
+      if (!(r1 + r2 > 0)) return bad(err, "total initial density must be > 0");
+    }
+  }
+  return true;
+}
+
+// Node info words in the pitched layout.
+void build_info(const lbm_geometry &g, const Layout &L, std::vector<uint32_t> &info) {
+  info.assign((size_t)L.plane, kSolid);
+  const int q = g.q;
+  const bool perx = g.periodic & 1, pery = g.periodic & 2, perz = g.periodic & 4;
+  const int x0 = g.porous_x0, x1 = g.porous_x1 > 0 ? g.porous_x1 : g.nx;
+  auto solid_at = [&](int a, int b, int c, bool &inside) -> bool {
+    inside = true;
+    if (a < 0 || a >= g.nx) { if (!perx) { inside = false; return false; } a = (a + g.nx) % g.nx; }
+    if (b < 0 || b >= g.ny) { if (!pery) { inside = false; return false; } b = (b + g.ny) % g.ny; }
+    if (c < 0 || c >= g.nz) { if (!perz) { inside = false; return false; } c = (c + g.nz) % g.nz; }
+    return g.solid[a + (int64_t)g.nx * (b + (int64_t)g.ny * c)] != 0;
+  };
+  for (int z = 0; z < g.nz; ++z)
+    for (int y = 0; y < g.ny; ++y)
+      for (int x = 0; x < g.nx; ++x) {
+        const int64_t n = x + (int64_t)g.nx * (y + (int64_t)g.ny * z);
+        uint32_t w = 0;
+        if (g.solid[n]) {
+          w = kSolid;
+          for (int i = 1; i < q; ++i) {
+            const int *e = evec(q, i);
+            bool in;
+            const bool s = solid_at(x + e[0], y + e[1], z + e[2], in);
+            if (in && !s) w |= 1u << i;
+          }
+        } else {
+          for (int i = 1; i < q; ++i) {
+            const int *e = evec(q, i);
+            bool in;
+            const bool s = solid_at(x - e[0], y - e[1], z - e[2], in);
+            if (in && s) w |= 1u << i;
+          }
+          if (g.open_x && x == 0) w |= kInlet;
+          if (g.open_x && x == g.nx - 1) w |= kOutlet;
+          if (x >= x0 && x < x1) w |= kWindow;
+          if (x == 0 || x == g.nx - 1) {
+            // boundary pressure uses face nodes at least 3 nodes from any solid
+            bool far = true;
+            const int rz = g.nz > 1 ? 2 : 0;
+            for (int dz = -rz; dz <= rz && far; ++dz)
+              for (int dy = -2; dy <= 2 && far; ++dy)
+                for (int dx = -2; dx <= 2 && far; ++dx) {
+                  bool in;
+                  if (solid_at(x + dx, y + dy, z + dz, in) && in) far = false;
+                }
+            if (far) w |= kPFace;
+          }
+        }
+        info[(size_t)x + (size_t)L.pitch * (y + (size_t)g.ny * z)] = w;
+      }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+struct lbm_batch {
+  int32_t k = 0, q = 9, storage = 0, collision = 0;
+  std::vector<InstDev> h;
+  std::vector<Layout> lay;
+  InstDev *d_insts = nullptr;
+  int32_t *d_block_inst = nullptr;
+  int64_t n_blocks = 0;
+  double *partials = nullptr;
+  double *result = nullptr;
+  int obs_blocks = 1;
+  hipStream_t stream = nullptr;
+  int parity = 0;
+  int64_t step = 0;
+  bool unstable = false;
+  std::string err;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  int64_t graph_n = 0;
+  int graph_parity = 0;
+};
+
+struct lbm_ctx {
+  lbm_batch *b;
+};
+
+namespace {
+
+lbm_status fail(lbm_batch *b, lbm_status s, const std::string &msg) {
+  if (b) b->err = msg;
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(b, expr)                                                                  \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return fail(b, LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_));   \
+  } while (0)
+
+size_t batch_bytes(int32_t k, const lbm_geometry *g, const lbm_params *p, int64_t *n_blocks_out,
+                   int *obs_blocks_out) {
+  size_t bytes = align_up(sizeof(InstDev) * (size_t)k);
+  int64_t nb = 0;
+  int ob = 1;
+  for (int i = 0; i < k; ++i) {
+    const Layout L = make_layout(g[i], p[i]);
+    nb += L.blocks;
+    bytes += L.info_bytes + L.frozen_bytes + 2 * L.buf_bytes;
+    InstDev tmp{};
+    tmp.nx = g[i].nx; tmp.ny = g[i].ny; tmp.nz = g[i].nz;
+    ob = std::max(ob, obs_blocks(tmp));
+  }
+  bytes += align_up(sizeof(int32_t) * (size_t)nb);
+  bytes += align_up(sizeof(double) * kObsFields * (size_t)ob);
+  bytes += align_up(sizeof(double) * kObsFields * (size_t)k);
+  if (n_blocks_out) *n_blocks_out = nb;
+  if (obs_blocks_out) *obs_blocks_out = ob;
+  return bytes;
+}
+
+lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
+                        const double *const *rho0, void *ws, size_t ws_bytes, void *stream,
+                        lbm_batch **out) {
+  if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (k < 1 || !g || !p || !rho0) return fail(nullptr, LBM_EINVAL, "need k >= 1 and non-NULL arrays");
+  std::string err;
+  for (int i = 0; i < k; ++i) {
+    if (!rho0[i]) return fail(nullptr, LBM_EINVAL, "rho_init is NULL");
+    if (!validate(&g[i], &p[i], rho0[i], err))
+      return fail(nullptr, LBM_EINVAL, (k > 1 ? "instance " + std::to_string(i) + ": " : "") + err);
+    if (g[i].q != g[0].q || p[i].storage != p[0].storage || p[i].collision != p[0].collision)
+      return fail(nullptr, LBM_EINVAL, "all instances must share q, storage and collision");
+  }
+  int64_t nb;
+  int ob;
+  const size_t need = batch_bytes(k, g, p, &nb, &ob);
+  if (!ws) return fail(nullptr, LBM_EINVAL, "workspace is NULL");
+  if (ws_bytes < need)
+    return fail(nullptr, LBM_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  if (reinterpret_cast<uintptr_t>(ws) % kAlign) return fail(nullptr, LBM_ENOMEM, "workspace must be 256-byte aligned");
+  if (nb > 0x7fffffff) return fail(nullptr, LBM_EINVAL, "too many blocks");
+
+  lbm_batch *b = new lbm_batch();
+  b->k = k;
+  b->q = g[0].q;
+  b->storage = p[0].storage;
+  b->collision = p[0].collision;
+  b->stream = reinterpret_cast<hipStream_t>(stream);
+  b->n_blocks = nb;
+  b->obs_blocks = ob;
+  char *cur = reinterpret_cast<char *>(ws);
+  auto take = [&](size_t n) { char *r = cur; cur += align_up(n); return r; };
+  b->d_insts = reinterpret_cast<InstDev *>(take(sizeof(InstDev) * (size_t)k));
+  b->d_block_inst = reinterpret_cast<int32_t *>(take(sizeof(int32_t) * (size_t)nb));
+  b->partials = reinterpret_cast<double *>(take(sizeof(double) * kObsFields * (size_t)ob));
+  b->result = reinterpret_cast<double *>(take(sizeof(double) * kObsFields * (size_t)k));
+
+  std::vector<int32_t> table((size_t)nb);
+  int64_t base = 0;
+  std::vector<uint32_t> info;
+  for (int i = 0; i < k; ++i) {
+    const Layout L = make_layout(g[i], p[i]);
+    InstDev h{};
+    h.info = reinterpret_cast<const uint32_t *>(take(L.info_bytes));
+    h.frozen = reinterpret_cast<const float *>(take(L.frozen_bytes));
+    h.f[0] = reinterpret_cast<float *>(take(L.buf_bytes));
+    h.f[1] = reinterpret_cast<float *>(take(L.buf_bytes));
+    h.plane = L.plane;
+    h.nx = g[i].nx; h.ny = g[i].ny; h.nz = g[i].nz; h.pitch = L.pitch;
+    h.periodic = (int32_t)g[i].periodic; h.open_x = g[i].open_x;
+    h.bc_set = p[i].bc_set; h.collision = p[i].collision;
+    h.half_shift = p[i].half_force_shift; h.sj_mode = p[i].mrt_sj_mode;
+    h.storage = p[i].storage; h.q = g[i].q;
+    h.tiles_x = L.tiles_x; h.tiles_y = L.tiles_y; h.tiles_z = L.tiles_z;
+    h.block_base = (int32_t)base;
+    h.tau1 = (float)p[i].tau[0]; h.tau2 = (float)p[i].tau[1];
+    h.G = (float)p[i].G;
+    h.chi1 = (float)(1.0 + p[i].xi); h.chi2 = (float)(1.0 - p[i].xi);
+    h.gx = (float)p[i].g[0]; h.gy = (float)p[i].g[1]; h.gz = (float)p[i].g[2];
+    h.rho_in1 = (float)p[i].rho_in1; h.rho_out2 = (float)p[i].rho_out2;
+    h.rho_in2 = (float)p[i].rho_in2; h.rho_out1 = (float)p[i].rho_out1;
+    h.lambda = (float)p[i].lambda; h.s_e = (float)p[i].s_e; h.s_eps = (float)p[i].s_eps;
+    for (int64_t t = 0; t < L.blocks; ++t) table[(size_t)(base + t)] = i;
+    base += L.blocks;
+    b->h.push_back(h);
+    b->lay.push_back(L);
+
+    // node table
+    build_info(g[i], L, info);
+    HIPCHK(b, hipMemcpyAsync((void *)h.info, info.data(), sizeof(uint32_t) * info.size(),
+                             hipMemcpyHostToDevice, b->stream));
+    // held (frozen) links: rest equilibria of the initial densities
+    const int64_t N = L.n_nodes;
+    const int64_t nt = (int64_t)g[i].ny * g[i].nz;
+    std::vector<float> frz((size_t)(2 * g[i].q * nt), 0.f);
+    for (int64_t t = 0; t < nt; ++t) {
+      const int64_t no = (g[i].nx - 1) + (int64_t)g[i].nx * t, ni = (int64_t)g[i].nx * t;
+      for (int qi = 0; qi < g[i].q; ++qi) {
+        frz[(size_t)(qi * nt + t)] = (float)(weight(g[i].q, qi) * rho0[i][no]);
+        frz[(size_t)((g[i].q + qi) * nt + t)] = (float)(weight(g[i].q, qi) * rho0[i][N + ni]);
+      }
+    }
+    HIPCHK(b, hipMemcpyAsync((void *)h.frozen, frz.data(), sizeof(float) * frz.size(),
+                             hipMemcpyHostToDevice, b->stream));
+    // initial densities staged as float in buffer 1, then rest equilibria into buffer 0
+    std::vector<float> r0((size_t)(2 * N));
+    for (int64_t n = 0; n < 2 * N; ++n) r0[(size_t)n] = (float)rho0[i][n];
+    HIPCHK(b, hipMemcpyAsync(h.f[1], r0.data(), sizeof(float) * r0.size(), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(b, hipMemcpyAsync(b->d_insts + i, &b->h.back(), sizeof(InstDev), hipMemcpyHostToDevice, b->stream));
+    HIPCHK(b, launch_init(b->d_insts + i, h, h.f[1], 0, b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));  // host staging vectors die here
+  }
+  HIPCHK(b, hipMemcpyAsync(b->d_block_inst, table.data(), sizeof(int32_t) * table.size(),
+                           hipMemcpyHostToDevice, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  *out = b;
+  return LBM_OK;
+}
+
+lbm_status batch_step(lbm_batch *b, int64_t n) {
+  if (!b) return fail(nullptr, LBM_EINVAL, "NULL handle");
+  if (n < 0) return fail(b, LBM_EINVAL, "n must be >= 0");
+  if (b->unstable) return fail(b, LBM_EUNSTABLE, "state is unstable (non-finite or negative density)");
+  const int32_t *table = b->k > 1 ? b->d_block_inst : nullptr;
+  for (int64_t s = 0; s < n; ++s) {
+    HIPCHK(b, launch_step(b->d_insts, table, b->n_blocks, b->q, b->collision, b->storage, b->parity, b->stream));
+    b->parity ^= 1;
+    b->step++;
+  }
+  return LBM_OK;
+}
+
+lbm_status batch_step_graph(lbm_batch *b, int64_t n, int64_t reps) {
+  if (!b) return fail(nullptr, LBM_EINVAL, "NULL handle");
+  if (n <= 0 || (n & 1) || reps < 0) return fail(b, LBM_EINVAL, "n must be even and > 0, reps >= 0");
+  if (!b->stream) return fail(b, LBM_ESTATE, "graph capture needs a non-default stream");
+  if (b->unstable) return fail(b, LBM_EUNSTABLE, "state is unstable (non-finite or negative density)");
+  if (!b->gexec || b->graph_n != n || b->graph_parity != b->parity) {
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+    HIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    const int32_t *table = b->k > 1 ? b->d_block_inst : nullptr;
+    int par = b->parity;
+    for (int64_t s = 0; s < n; ++s) {
+      hipError_t e = launch_step(b->d_insts, table, b->n_blocks, b->q, b->collision, b->storage, par, b->stream);
+      if (e != hipSuccess) {
+        hipGraph_t tmp;
+        (void)hipStreamEndCapture(b->stream, &tmp);
+        if (tmp) (void)hipGraphDestroy(tmp);
+        return fail(b, LBM_EDEVICE, std::string("capture: ") + hipGetErrorString(e));
+      }
+      par ^= 1;
+    }
+    HIPCHK(b, hipStreamEndCapture(b->stream, &b->graph));
+    HIPCHK(b, hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+    b->graph_n = n;
+    b->graph_parity = b->parity;
+  }
+  for (int64_t r = 0; r < reps; ++r) {
+    HIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
+    b->step += n;
+  }
+  return LBM_OK;
+}
+
+void fill_obs(const lbm_batch *b, int i, const double *r, lbm_obs *o) {
+  std::memset(o, 0, sizeof(*o));
+  o->step = b->step;
+  o->mass[0] = r[0];
+  o->mass[1] = r[1];
+  o->n_fluid = r[2];
+  o->n_window = r[3];
+  o->sw_count = r[4];
+  o->sum_rho_w = r[5];
+  o->sum_rho = r[6];
+  o->s_w = r[3] > 0 ? r[4] / r[3] : 0.0;
+  o->s_w_weighted = r[6] > 0 ? r[5] / r[6] : 0.0;
+  o->n_in = r[8];
+  o->n_out = r[10];
+  o->p_in = r[8] > 0 ? r[7] / r[8] : 0.0;
+  o->p_out = r[10] > 0 ? r[9] / r[10] : 0.0;
+  o->pc = o->p_in - o->p_out;
+  o->flags = (int32_t)r[11];
+  (void)i;
+}
+
+lbm_status batch_observables(lbm_batch *b, lbm_obs *out) {
+  if (!b || !out) return fail(b, LBM_EINVAL, "NULL argument");
+  for (int i = 0; i < b->k; ++i)
+    HIPCHK(b, launch_observables(b->d_insts + i, b->h[i], b->parity, b->partials, obs_blocks(b->h[i]),
+                                 b->result + (size_t)kObsFields * i, b->stream));
+  std::vector<double> r((size_t)kObsFields * b->k);
+  HIPCHK(b, hipMemcpyAsync(r.data(), b->result, sizeof(double) * r.size(), hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  bool bad_state = false;
+  for (int i = 0; i < b->k; ++i) {
+    fill_obs(b, i, r.data() + (size_t)kObsFields * i, out + i);
+    if (out[i].flags) bad_state = true;
+  }
+  if (bad_state) {
+    b->unstable = true;
+    return fail(b, LBM_EUNSTABLE, "non-finite or negative density");
+  }
+  return LBM_OK;
+}
+
+lbm_status batch_density(lbm_batch *b, int32_t i, float *dst, int32_t dst_is_device) {
+  if (!b || !dst) return fail(b, LBM_EINVAL, "NULL argument");
+  if (i < 0 || i >= b->k) return fail(b, LBM_EINVAL, "instance index out of range");
+  const InstDev &h = b->h[(size_t)i];
+  const int64_t N = (int64_t)h.nx * h.ny * h.nz;
+  if (dst_is_device) {
+    HIPCHK(b, launch_density(b->d_insts + i, h, b->parity, dst, b->stream));
+    return LBM_OK;
+  }
+  // stage in the idle ping-pong buffer (rewritten by the next step anyway)
+  float *stage = h.f[b->parity ^ 1];
+  HIPCHK(b, launch_density(b->d_insts + i, h, b->parity, stage, b->stream));
+  HIPCHK(b, hipMemcpyAsync(dst, stage, sizeof(float) * 2 * (size_t)N, hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+struct CkptHeader {
+  char magic[8];
+  int32_t version, k, q, storage;
+  int32_t parity, pad;
+  int64_t step;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_geometry *geom, const lbm_params *params) {
+  std::string err;
+  if (!geom || !params) return 0;
+  if (!validate(geom, params, nullptr, err)) return 0;
+  return batch_bytes(1, geom, params, nullptr, nullptr);
+}
+
+lbm_status lbm_create(const lbm_geometry *geom, const lbm_params *params, const double *rho_init,
+                      void *workspace, size_t ws_bytes, void *hip_stream, lbm_ctx **out) {
+  if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  const double *r[1] = {rho_init};
+  lbm_batch *b = nullptr;
+  lbm_status s = create_batch(1, geom, params, r, workspace, ws_bytes, hip_stream, &b);
+  if (s != LBM_OK) return s;
+  *out = new lbm_ctx{b};
+  return LBM_OK;
+}
+
+lbm_status lbm_set_bc(lbm_ctx *ctx, double rho_in1, double rho_out2) {
+  if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL handle");
+  lbm_batch *b = ctx->b;
+  if (!std::isfinite(rho_in1) || !std::isfinite(rho_out2) || rho_in1 <= 0 || rho_out2 <= 0)
+    return fail(b, LBM_EINVAL, "boundary densities must be finite and > 0");
+  b->h[0].rho_in1 = (float)rho_in1;
+  b->h[0].rho_out2 = (float)rho_out2;
+  HIPCHK(b, hipMemcpyAsync(b->d_insts, &b->h[0], sizeof(InstDev), hipMemcpyHostToDevice, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *ctx, int64_t n) {
+  if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL handle");
+  return batch_step(ctx->b, n);
+}
+
+lbm_status lbm_step_graph(lbm_ctx *ctx, int64_t n, int64_t reps) {
+  if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL handle");
+  return batch_step_graph(ctx->b, n, reps);
+}
+
+lbm_status lbm_observables(lbm_ctx *ctx, lbm_obs *out) {
+  if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL handle");
+  return batch_observables(ctx->b, out);
+}
+
+lbm_status lbm_get_density(lbm_ctx *ctx, float *dst, int32_t dst_is_device) {
+  if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL handle");
+  return batch_density(ctx->b, 0, dst, dst_is_device);
+}
+
+lbm_status lbm_save(lbm_ctx *ctx, void *host_blob, size_t *bytes) {
+  if (!ctx || !bytes) return fail(nullptr, LBM_EINVAL, "NULL argument");
+  lbm_batch *b = ctx->b;
+  const Layout &L = b->lay[0];
+  const size_t need = sizeof(CkptHeader) + L.buf_bytes + sizeof(InstDev);
+  if (!host_blob) { *bytes = need; return LBM_OK; }
+  if (*bytes < need) return fail(b, LBM_EINVAL, "checkpoint buffer too small");
+  CkptHeader hd{};
+  std::memcpy(hd.magic, "LBMCKPT", 8);
+  hd.version = 1; hd.k = 1; hd.q = b->q; hd.storage = b->storage;
+  hd.parity = b->parity; hd.step = b->step;
+  char *p = reinterpret_cast<char *>(host_blob);
+  std::memcpy(p, &hd, sizeof(hd));
+  std::memcpy(p + sizeof(hd), &b->h[0], sizeof(InstDev));
+  HIPCHK(b, hipMemcpyAsync(p + sizeof(hd) + sizeof(InstDev), b->h[0].f[b->parity], L.buf_bytes,
+                           hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  *bytes = need;
+  return LBM_OK;
+}
+
+lbm_status lbm_load(lbm_ctx *ctx, const void *host_blob, size_t bytes) {
+  if (!ctx || !host_blob) return fail(nullptr, LBM_EINVAL, "NULL argument");
+  lbm_batch *b = ctx->b;
+  const Layout &L = b->lay[0];
+  const size_t need = sizeof(CkptHeader) + L.buf_bytes + sizeof(InstDev);
+  if (bytes < need) return fail(b, LBM_EINVAL, "checkpoint too small");
+  CkptHeader hd;
+  std::memcpy(&hd, host_blob, sizeof(hd));
+  InstDev saved;
+  std::memcpy(&saved, reinterpret_cast<const char *>(host_blob) + sizeof(hd), sizeof(InstDev));
+  const InstDev &cur = b->h[0];
+  if (std::memcmp(hd.magic, "LBMCKPT", 8) || hd.version != 1 || hd.q != b->q || hd.storage != b->storage ||
+      saved.nx != cur.nx || saved.ny != cur.ny || saved.nz != cur.nz)
+    return fail(b, LBM_EINVAL, "checkpoint does not match this context");
+  b->parity = hd.parity;
+  b->step = hd.step;
+  b->h[0].rho_in1 = saved.rho_in1;
+  b->h[0].rho_out2 = saved.rho_out2;
+  HIPCHK(b, hipMemcpyAsync(b->h[0].f[b->parity], reinterpret_cast<const char *>(host_blob) + sizeof(hd) + sizeof(InstDev),
+                           L.buf_bytes, hipMemcpyHostToDevice, b->stream));
+  HIPCHK(b, hipMemcpyAsync(b->d_insts, &b->h[0], sizeof(InstDev), hipMemcpyHostToDevice, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  b->unstable = false;
+  return LBM_OK;
+}
+
+int64_t lbm_get_step(const lbm_ctx *ctx) { return ctx ? ctx->b->step : -1; }
+
+lbm_status lbm_destroy(lbm_ctx *ctx) {
+  if (!ctx) return LBM_OK;
+  lbm_batch_destroy(ctx->b);
+  delete ctx;
+  return LBM_OK;
+}
+
+const char *lbm_last_error(const lbm_ctx *ctx) {
+  if (ctx && ctx->b) return ctx->b->err.c_str();
+  return g_err.c_str();
+}
+
+lbm_status lbm_kernel_info(const lbm_ctx *ctx, char *name, size_t name_len, int64_t *grid_blocks,
+                           int32_t *block_threads) {
+  if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL handle");
+  const lbm_batch *b = ctx->b;
+  if (name && name_len) std::snprintf(name, name_len, "%s", step_kernel_name(b->q, b->collision, b->storage));
+  if (grid_blocks) *grid_blocks = b->n_blocks;
+  if (block_threads) *block_threads = 256;
+  return LBM_OK;
+}
+
+size_t lbm_batch_workspace_bytes(int32_t k, const lbm_geometry *geoms, const lbm_params *params) {
+  if (k < 1 || !geoms || !params) return 0;
+  std::string err;
+  for (int i = 0; i < k; ++i)
+    if (!validate(&geoms[i], &params[i], nullptr, err)) return 0;
+  return batch_bytes(k, geoms, params, nullptr, nullptr);
+}
+
+lbm_status lbm_batch_create(int32_t k, const lbm_geometry *geoms, const lbm_params *params,
+                            const double *const *rho_inits, void *workspace, size_t ws_bytes,
+                            void *hip_stream, lbm_batch **out) {
+  return create_batch(k, geoms, params, rho_inits, workspace, ws_bytes, hip_stream, out);
+}
+
+lbm_status lbm_batch_step(lbm_batch *b, int64_t n) { return batch_step(b, n); }
+lbm_status lbm_batch_step_graph(lbm_batch *b, int64_t n, int64_t reps) { return batch_step_graph(b, n, reps); }
+lbm_status lbm_batch_observables(lbm_batch *b, lbm_obs *out) { return batch_observables(b, out); }
+lbm_status lbm_batch_get_density(lbm_batch *b, int32_t k, float *dst, int32_t dst_is_device) {
+  return batch_density(b, k, dst, dst_is_device);
+}
+
+lbm_status lbm_batch_destroy(lbm_batch *b) {
+  if (!b) return LBM_OK;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  delete b;
+  return LBM_OK;
+}
+
+const char *lbm_batch_last_error(const lbm_batch *b) { return b ? b->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,55 @@
+// Internal definitions shared by the host runtime and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+// Per-node info word.  For a fluid node, bit i (i < Q) says that the pull
+// source x - e_i is solid (half-way bounce-back on link i).  For a solid node,
+// bit i says that x + e_i is an in-domain fluid node (enters Eq. 17).
+constexpr uint32_t kSolid = 1u << 24;
+constexpr uint32_t kInlet = 1u << 25;   // fluid node at x = 0 of an open x axis
+constexpr uint32_t kOutlet = 1u << 26;  // fluid node at x = nx-1 of an open x axis
+constexpr uint32_t kPFace = 1u << 27;   // face node used in the boundary pressure
+constexpr uint32_t kWindow = 1u << 28;  // inside the saturation window
+constexpr uint32_t kLinkMask = (1u << 19) - 1u;
+
+// 2D step tile: 64 lanes cover 60 interior columns plus 2 halo columns on
+// each side; TY interior rows plus 2 halo rows above and below.
+constexpr int kTileX = 60;
+constexpr int kTileY = 12;
+// 3D step tile: the same 64-lane rows, TY3 interior rows in y, marching in z.
+constexpr int kTileY3 = 4;
+
+// Device-side description of one instance (array in device memory).
+struct InstDev {
+  float *f[2];            // ping-pong post-collision state (layout by storage)
+  const uint32_t *info;   // node info words, pitched like one population plane
+  const float *frozen;    // [2][Q][ny*nz]: component-1 outlet / component-2 inlet links
+  int64_t plane;          // elements between consecutive population planes
+  int32_t nx, ny, nz, pitch;  // pitch = row stride in elements
+  int32_t periodic, open_x, bc_set, collision;
+  int32_t half_shift, sj_mode, storage, q;
+  int32_t tiles_x, tiles_y, tiles_z, block_base;
+  float tau1, tau2, G, chi1, chi2, gx, gy, gz;
+  float rho_in1, rho_out2, rho_in2, rho_out1;
+  float lambda, s_e, s_eps, pad0;
+};
+
+// Reduction record written per block by the observables kernel.
+constexpr int kObsFields = 12;  // mass0 mass1 nfluid nwin swcount sumrw sumr pin nin pout nout flags
+
+// Launchers (defined in the .hip sources).
+hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, const float *rho0_dev,
+                       int parity, hipStream_t s);
+hipError_t launch_step(const InstDev *d_insts, const int32_t *block_inst, int64_t n_blocks,
+                       int q, int collision, int storage, int parity, hipStream_t s);
+hipError_t launch_observables(const InstDev *d_inst, const InstDev &h_inst, int parity,
+                              double *partials, int n_blocks, double *result, hipStream_t s);
+hipError_t launch_density(const InstDev *d_inst, const InstDev &h_inst, int parity,
+                          float *dst, hipStream_t s);
+const char *step_kernel_name(int q, int collision, int storage);
+int obs_blocks(const InstDev &h_inst);
+
+}  // namespace lbm

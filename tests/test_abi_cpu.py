@@ -1,0 +1,79 @@
+"""The C-ABI library on a machine without a GPU: it loads, exports every
+symbol include/lbm.h declares, and rejects invalid input before any device
+call."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2111_08666_amd import inputs as I
+from paper_2111_08666_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    L = lbm.lib()
+    names = _declared()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(lbm.EXPORTS) == names
+
+
+def test_workspace_query_and_validation_without_device():
+    p = I.drainage_2d(nx=64, ny=32, r=(2.0, 4.0), porosity=0.8, seed=1)
+    assert lbm.workspace_bytes(p) > 2 * 2 * 9 * 64 * 32 * 4
+    assert lbm.workspace_bytes(p, lbm.STORE_BF16DEV) < lbm.workspace_bytes(p)
+    bad = I.drainage_2d(nx=64, ny=32, r=(2.0, 4.0), porosity=0.8, seed=1)
+    bad.tau = (0.5, 1.0)
+    assert lbm.workspace_bytes(bad) == 0
+
+
+def _create(problem, ws=None, nbytes=0):
+    L = lbm.lib()
+    keep = []
+    g = lbm.make_geometry(problem, keep)
+    par = lbm.make_params(problem)
+    rho0 = np.ascontiguousarray(problem.rho0, dtype=np.float64)
+    h = C.c_void_p()
+    st = L.lbm_create(C.byref(g), C.byref(par), rho0.ctypes.data, ws, nbytes, None, C.byref(h))
+    return st, L.lbm_last_error(None).decode()
+
+
+@pytest.mark.parametrize("mutate,msg", [
+    (lambda p: setattr(p, "tau", (0.45, 1.0)), "tau"),
+    (lambda p: setattr(p, "xi", 1.2), "xi"),
+    (lambda p: setattr(p, "collision", 7), "collision"),
+    (lambda p: setattr(p, "bc_set", 0), "bc_set"),
+    (lambda p: p.rho0.__setitem__((0, 5, 5), np.nan), "initial densities"),
+    (lambda p: p.mask.__setitem__((0, slice(None)), 0), "closed domain edge"),
+])
+def test_invalid_inputs_rejected_before_device_work(mutate, msg):
+    p = I.drainage_2d(nx=64, ny=32, r=(2.0, 4.0), porosity=0.8, seed=1)
+    mutate(p)
+    st, err = _create(p)
+    assert st == lbm.LBM_EINVAL and msg in err
+
+
+def test_small_or_misaligned_workspace_rejected():
+    p = I.drainage_2d(nx=64, ny=32, r=(2.0, 4.0), porosity=0.8, seed=1)
+    st, err = _create(p, ws=C.c_void_p(4096), nbytes=16)
+    assert st == lbm.LBM_ENOMEM and "too small" in err
+    st, err = _create(p, ws=C.c_void_p(4096 + 8), nbytes=1 << 30)
+    assert st == lbm.LBM_ENOMEM and "aligned" in err
+
+
+def test_mrt_needs_d2q9():
+    m = I.sphere_medium(24, 12, 12, 2.0, 3.0, 0.8, seed=1)
+    p = I.Problem(q=19, mask=m, rho0=I.reservoir_front(m, 8), collision=1)
+    st, err = _create(p)
+    assert st == lbm.LBM_EINVAL and "MRT" in err
