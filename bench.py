@@ -85,6 +85,7 @@ def main():
     ap.add_argument("--workload", default="d2q9_1024x512")
     ap.add_argument("--chunk", type=int, default=100, help="steps per captured graph")
     ap.add_argument("--storage", type=int, default=0, help="0 FP32, 1 BF16 deviations")
+    ap.add_argument("--math", type=int, default=0, help="node arithmetic: 0 FP64, 1 FP32")
     ap.add_argument("--eager", action="store_true", help="plain launches instead of graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-samples", type=int, default=300)
@@ -101,7 +102,7 @@ def main():
     problem = workload(args.workload)
     print(f"[bench] workload {args.workload}: {problem.nx}x{problem.ny}x{problem.nz}, "
           f"fluid {problem.n_fluid}, collision {problem.collision}", file=sys.stderr, flush=True)
-    solver = lbm.Solver(problem, storage=args.storage, device=dev)
+    solver = lbm.Solver(problem, storage=args.storage, device=dev, math=args.math)
     stream = solver.stream
     chunk = max(2, args.chunk - args.chunk % 2)
     steps = max(chunk, args.steps - args.steps % chunk)
@@ -155,7 +156,8 @@ def main():
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if args.storage == 0 else "bf16-dev/f32",
+        "dtype": ("f64 math, " if args.math == 0 else "f32 math, ")
+                 + ("f32 storage" if args.storage == 0 else "bf16-deviation storage"),
         "data": "synthetic (seeded disc medium; the paper's geometry is not available)",
         "config": {"workload": problem.name, "q": problem.q, "nx": problem.nx, "ny": problem.ny,
                    "nz": problem.nz, "n_fluid": problem.n_fluid,

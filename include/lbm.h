@@ -47,6 +47,7 @@ typedef enum {
 
 enum { LBM_SRT = 0, LBM_MRT = 1, LBM_TRT = 2 };            /* lbm_params.collision */
 enum { LBM_STORE_F32 = 0, LBM_STORE_BF16DEV = 1 };          /* lbm_params.storage */
+enum { LBM_MATH_F64 = 0, LBM_MATH_F32 = 1 };                /* lbm_params.math */
 
 /* Problem geometry (Sec. 2.3 and Sec. 4.2: a solid map phi, periodic or
  * open axes, the inlet at x = 0 and the outlet at x = nx - 1). */
@@ -76,8 +77,8 @@ typedef struct {
   int32_t mrt_sj_mode;    /* MRT momentum rate: 0 = s_nu, 1 = s_q */
   double lambda;          /* magic (1/s_nu - 1/2)(1/s_q - 1/2); <= 0: s_q = s_nu */
   double s_e, s_eps;      /* MRT energy-mode rates; <= 0: equal to s_nu */
-  int32_t storage;        /* LBM_STORE_F32 or LBM_STORE_BF16DEV */
-  int32_t reserved;
+  int32_t storage;        /* LBM_STORE_F32 or LBM_STORE_BF16DEV: how f* is held */
+  int32_t math;           /* node arithmetic: LBM_MATH_F64 (default) or LBM_MATH_F32 */
 } lbm_params;
 
 /* Observables at the current time (Eq. 14 pressure, Sec. 4.2 saturation).

@@ -1,6 +1,6 @@
 // Lattice constants and node-local arithmetic of the two-component
 // pseudopotential LBM (Sedahmed, Coelho & Warda, arXiv:2111.08666, Sec. 2),
-// written for the GPU in FP32.  Everything here is inlined into the kernels.
+// written for the GPU.  Everything here is inlined into the kernels.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -17,8 +17,8 @@ template <> struct Lat<9> {
   static constexpr int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
   static constexpr int ez[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
   static constexpr int opp[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
-  static constexpr float w[9] = {4.f / 9.f,  1.f / 9.f,  1.f / 9.f,  1.f / 9.f, 1.f / 9.f,
-                                 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
+  static constexpr double w[9] = {4.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0,  1.0 / 9.0, 1.0 / 9.0,
+                                  1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 };
 
 // D3Q19: rest, 6 axis links (w = 1/18), 12 face diagonals (w = 1/36); each
@@ -28,51 +28,48 @@ template <> struct Lat<19> {
   static constexpr int ey[19] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
   static constexpr int ez[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
   static constexpr int opp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
-  static constexpr float w[19] = {1.f / 3.f,  1.f / 18.f, 1.f / 18.f, 1.f / 18.f, 1.f / 18.f,
-                                  1.f / 18.f, 1.f / 18.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f,
-                                  1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f,
-                                  1.f / 36.f, 1.f / 36.f, 1.f / 36.f, 1.f / 36.f};
+  static constexpr double w[19] = {1.0 / 3.0,  1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+                                   1.0 / 18.0, 1.0 / 18.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                                   1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+                                   1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0};
 };
 
 // ---------------------------------------------------------------------------
+// Node arithmetic runs in the type R (double by default, float optional);
+// populations are held and stored as float.
+// ---------------------------------------------------------------------------
+
 // Zou-He pressure completion at an x face (Eqs. 18-25): given the density
 // rho_b and zero tangential velocity, the links pointing into the domain
 // (e_x == dir) are rebuilt from their opposites, the normal mass flux
 // m = rho_b - (sum of tangential links) - 2 (sum of outgoing links), and the
 // tangential momentum of the face-parallel links.  D2Q9: Eqs. 19-21 / 23-25;
 // D3Q19: the on-site rule of Hecht & Harting (2010).
-// ---------------------------------------------------------------------------
-template <int Q>
-__device__ __forceinline__ void zou_he(float (&f)[Q], float rho_b, int dir) {
+template <int Q, typename R>
+__device__ __forceinline__ void zou_he(float (&f)[Q], R rho_b, int dir) {
   using L = Lat<Q>;
-  float par = 0.f, out = 0.f, ny_ = 0.f, nz_ = 0.f;
+  R par = 0, out = 0, ny_ = 0, nz_ = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (L::ex[i] == 0) {
-      par += f[i];
-      if (L::ey[i]) ny_ += L::ey[i] * f[i];
-      if (L::ez[i]) nz_ += L::ez[i] * f[i];
+      par += (R)f[i];
+      if (L::ey[i]) ny_ += L::ey[i] * (R)f[i];
+      if (L::ez[i]) nz_ += L::ez[i] * (R)f[i];
     }
   }
-  if (dir > 0) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i)
-      if (L::ex[i] < 0) out += f[i];
-  } else {
-#pragma unroll
-    for (int i = 0; i < Q; ++i)
-      if (L::ex[i] > 0) out += f[i];
-  }
-  const float m = rho_b - par - 2.f * out;
-  ny_ *= 0.5f;
-  nz_ *= 0.5f;
+  for (int i = 0; i < Q; ++i)
+    if (L::ex[i] == -dir) out += (R)f[i];
+  const R m = rho_b - par - R(2) * out;
+  ny_ *= R(0.5);
+  nz_ *= R(0.5);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     if (L::ex[i] == dir) {
-      float v = f[L::opp[i]] + 6.f * L::w[i] * m;
+      R v = (R)f[L::opp[i]] + R(6) * (R)L::w[i] * m;
       if (L::ey[i]) v -= L::ey[i] * ny_;
       if (L::ez[i]) v -= L::ez[i] * nz_;
-      f[i] = v;
+      f[i] = (float)v;
     }
   }
 }
@@ -80,14 +77,14 @@ __device__ __forceinline__ void zou_he(float (&f)[Q], float rho_b, int dir) {
 // Inlet / outlet completion of one node for both components (Sec. 2.3).
 // own(c, i) returns this node's post-collision value (Eq. 28),
 // frozen(c, i) the held initial value (Eq. 26, Eq. 27).
-template <int Q, class OwnF, class FrozenF>
+template <int Q, typename R, class OwnF, class FrozenF>
 __device__ __forceinline__ void complete_boundary(const InstDev &d, uint32_t info, float (&f0)[Q],
                                                   float (&f1)[Q], OwnF own, FrozenF frozen) {
   using L = Lat<Q>;
   if (info & kInlet) {
-    zou_he<Q>(f0, d.rho_in1, +1);  // component 1: Eqs. 22-25
+    zou_he<Q, R>(f0, (R)d.rho_in1, +1);  // component 1: Eqs. 22-25
     if (d.bc_set == 1) {
-      zou_he<Q>(f1, d.rho_in2, +1);
+      zou_he<Q, R>(f1, (R)d.rho_in2, +1);
     } else if (d.bc_set == 2) {
 #pragma unroll
       for (int i = 0; i < Q; ++i)
@@ -99,9 +96,9 @@ __device__ __forceinline__ void complete_boundary(const InstDev &d, uint32_t inf
     }
   }
   if (info & kOutlet) {
-    zou_he<Q>(f1, d.rho_out2, -1);  // component 2: Eqs. 18-21
+    zou_he<Q, R>(f1, (R)d.rho_out2, -1);  // component 2: Eqs. 18-21
     if (d.bc_set == 1) {
-      zou_he<Q>(f0, d.rho_out1, -1);
+      zou_he<Q, R>(f0, (R)d.rho_out1, -1);
     } else {
 #pragma unroll
       for (int i = 0; i < Q; ++i)
@@ -110,22 +107,33 @@ __device__ __forceinline__ void complete_boundary(const InstDev &d, uint32_t inf
   }
 }
 
+// Sum of the populations, pairing opposite links first.
+template <int Q, typename R>
+__device__ __forceinline__ R sum_q(const float (&f)[Q]) {
+  R s = (R)f[0];
+#pragma unroll
+  for (int i = 1; i < Q; ++i)
+    if (Lat<Q>::opp[i] > i) s += (R)f[i] + (R)f[Lat<Q>::opp[i]];
+  return s;
+}
+
 // ---------------------------------------------------------------------------
 // Relaxation rates at a node.  tau_s is the density-weighted mean of the
 // component relaxation times (Eq. 6 with nu = (tau - 1/2)/3); the shear rate
 // is 1/tau_s, the odd (energy-flux) rate follows the magic parameter lambda.
 // ---------------------------------------------------------------------------
-struct Rates {
-  float s_nu, s_q, s_e, s_eps, s_j;
+template <typename R> struct Rates {
+  R s_nu, s_q, s_e, s_eps, s_j;
 };
 
-__device__ __forceinline__ Rates node_rates(const InstDev &d, float rho1, float rho2, float inv_rho) {
-  Rates r;
-  const float tau_s = (rho1 * d.tau1 + rho2 * d.tau2) * inv_rho;
-  r.s_nu = 1.f / tau_s;
-  r.s_q = d.lambda > 0.f ? 1.f / (0.5f + d.lambda / (tau_s - 0.5f)) : r.s_nu;
-  r.s_e = d.s_e > 0.f ? d.s_e : r.s_nu;
-  r.s_eps = d.s_eps > 0.f ? d.s_eps : r.s_nu;
+template <typename R>
+__device__ __forceinline__ Rates<R> node_rates(const InstDev &d, R rho1, R rho2, R inv_rho) {
+  Rates<R> r;
+  const R tau_s = (rho1 * (R)d.tau1 + rho2 * (R)d.tau2) * inv_rho;
+  r.s_nu = R(1) / tau_s;
+  r.s_q = d.lambda > 0 ? R(1) / (R(0.5) + (R)d.lambda / (tau_s - R(0.5))) : r.s_nu;
+  r.s_e = d.s_e > 0 ? (R)d.s_e : r.s_nu;
+  r.s_eps = d.s_eps > 0 ? (R)d.s_eps : r.s_nu;
   r.s_j = d.sj_mode ? r.s_q : r.s_nu;
   return r;
 }
@@ -133,120 +141,121 @@ __device__ __forceinline__ Rates node_rates(const InstDev &d, float rho1, float 
 // ---------------------------------------------------------------------------
 // Forced collision of one component at one node, in place (Eqs. 1, 2, 11).
 // u: common velocity (with the half-force shift), F: this component's force.
-// COLL: 0 SRT, 1 MRT (D2Q9 Lallemand-Luo moments), 2 TRT.
+// COLL: 0 SRT, 1 MRT (D2Q9 Lallemand-Luo moments), 2 TRT.  The update is
+// formed as an increment f* - f so the populations' own rounding is not
+// repeated.
 // ---------------------------------------------------------------------------
-template <int Q, int COLL>
-__device__ __forceinline__ void collide_component(float (&f)[Q], float rho, float ux, float uy,
-                                                  float uz, float Fx, float Fy, float Fz,
-                                                  const Rates &r) {
+template <int Q, int COLL, typename R>
+__device__ __forceinline__ void collide_component(float (&fo)[Q], R rho, R ux, R uy, R uz, R Fx,
+                                                  R Fy, R Fz, const Rates<R> &r) {
   using L = Lat<Q>;
-  const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
-  const float uF = ux * Fx + uy * Fy + uz * Fz;
+  R f[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) f[i] = (R)fo[i];
+  const R usq15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
+  const R uF = ux * Fx + uy * Fy + uz * Fz;
   if constexpr (COLL == 0) {
-    const float om = r.s_nu, fo = 1.f - 0.5f * om;
+    const R om = r.s_nu, fac = R(1) - R(0.5) * om;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const float eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
-      const float eF = L::ex[i] * Fx + L::ey[i] * Fy + L::ez[i] * Fz;
-      const float feq = L::w[i] * rho * (1.f + 3.f * eu + 4.5f * eu * eu - usq15);
-      const float S = L::w[i] * (3.f * (eF - uF) + 9.f * eu * eF);
-      f[i] = f[i] + om * (feq - f[i]) + fo * S;
+      const R eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
+      const R eF = L::ex[i] * Fx + L::ey[i] * Fy + L::ez[i] * Fz;
+      const R w = (R)L::w[i];
+      const R feq = w * rho * (R(1) + R(3) * eu + R(4.5) * eu * eu - usq15);
+      const R S = w * (R(3) * (eF - uF) + R(9) * eu * eF);
+      fo[i] = (float)(f[i] + (om * (feq - f[i]) + fac * S));
     }
   } else if constexpr (COLL == 2) {
-    const float sp = r.s_nu, sm = r.s_q;
-    const float fp = 1.f - 0.5f * sp, fm = 1.f - 0.5f * sm;
-    float o[Q];
+    const R sp = r.s_nu, sm = r.s_q;
+    const R fp = R(1) - R(0.5) * sp, fm = R(1) - R(0.5) * sm;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int b = L::opp[i];
-      const float eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
-      const float eF = L::ex[i] * Fx + L::ey[i] * Fy + L::ez[i] * Fz;
+      const R eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
+      const R eF = L::ex[i] * Fx + L::ey[i] * Fy + L::ez[i] * Fz;
+      const R w = (R)L::w[i];
       // symmetric / antisymmetric parts of feq and S
-      const float eq_p = L::w[i] * rho * (1.f + 4.5f * eu * eu - usq15);
-      const float eq_m = L::w[i] * rho * 3.f * eu;
-      const float S_p = L::w[i] * (9.f * eu * eF - 3.f * uF);
-      const float S_m = L::w[i] * 3.f * eF;
-      const float f_p = 0.5f * (f[i] + f[b]), f_m = 0.5f * (f[i] - f[b]);
-      o[i] = f[i] + sp * (eq_p - f_p) + sm * (eq_m - f_m) + fp * S_p + fm * S_m;
+      const R eq_p = w * rho * (R(1) + R(4.5) * eu * eu - usq15);
+      const R eq_m = w * rho * R(3) * eu;
+      const R S_p = w * (R(9) * eu * eF - R(3) * uF);
+      const R S_m = w * R(3) * eF;
+      const R f_p = R(0.5) * (f[i] + f[b]), f_m = R(0.5) * (f[i] - f[b]);
+      fo[i] = (float)(f[i] + (sp * (eq_p - f_p) + sm * (eq_m - f_m) + fp * S_p + fm * S_m));
     }
-#pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = o[i];
   } else {
     static_assert(Q == 9, "MRT is D2Q9 only");
-    // moments of the deviation from the rest state: only non-conserved rows
-    const float a = f[1] + f[2] + f[3] + f[4];
-    const float dg = f[5] + f[6] + f[7] + f[8];
-    const float m_e = -4.f * f[0] - a + 2.f * dg;
-    const float m_eps = 4.f * f[0] - 2.f * a + dg;
-    const float d13 = f[1] - f[3], d24 = f[2] - f[4];
-    const float p5 = f[5] - f[7], p6 = f[6] - f[8];
-    const float m_jx = d13 + p5 - p6;
-    const float m_qx = -2.f * d13 + p5 - p6;
-    const float m_jy = d24 + p5 + p6;
-    const float m_qy = -2.f * d24 + p5 + p6;
-    const float m_pxx = (f[1] + f[3]) - (f[2] + f[4]);
-    const float m_pxy = (f[5] + f[7]) - (f[6] + f[8]);
-    const float u2 = ux * ux + uy * uy;
+    // non-conserved moments (Lallemand-Luo rows e, eps, jx, qx, jy, qy, pxx, pxy)
+    const R a = f[1] + f[2] + f[3] + f[4];
+    const R dg = f[5] + f[6] + f[7] + f[8];
+    const R m_e = R(-4) * f[0] - a + R(2) * dg;
+    const R m_eps = R(4) * f[0] - R(2) * a + dg;
+    const R d13 = f[1] - f[3], d24 = f[2] - f[4];
+    const R p5 = f[5] - f[7], p6 = f[6] - f[8];
+    const R m_jx = d13 + p5 - p6;
+    const R m_qx = R(-2) * d13 + p5 - p6;
+    const R m_jy = d24 + p5 + p6;
+    const R m_qy = R(-2) * d24 + p5 + p6;
+    const R m_pxx = (f[1] + f[3]) - (f[2] + f[4]);
+    const R m_pxy = (f[5] + f[7]) - (f[6] + f[8]);
+    const R u2 = ux * ux + uy * uy;
     // equilibrium moments of Eq. 2 and moments of the source of Eq. 11
-    const float e_eq = rho * (-2.f + 3.f * u2), eps_eq = rho * (1.f - 3.f * u2);
-    const float jx_eq = rho * ux, jy_eq = rho * uy;
-    const float pxx_eq = rho * (ux * ux - uy * uy), pxy_eq = rho * ux * uy;
-    const float S_e = 6.f * uF, S_eps = -6.f * uF;
-    const float S_pxx = 2.f * (ux * Fx - uy * Fy), S_pxy = ux * Fy + uy * Fx;
-    const float dm_e = r.s_e * (e_eq - m_e) + (1.f - 0.5f * r.s_e) * S_e;
-    const float dm_eps = r.s_eps * (eps_eq - m_eps) + (1.f - 0.5f * r.s_eps) * S_eps;
-    const float dm_jx = r.s_j * (jx_eq - m_jx) + (1.f - 0.5f * r.s_j) * Fx;
-    const float dm_jy = r.s_j * (jy_eq - m_jy) + (1.f - 0.5f * r.s_j) * Fy;
-    const float dm_qx = r.s_q * (-jx_eq - m_qx) - (1.f - 0.5f * r.s_q) * Fx;
-    const float dm_qy = r.s_q * (-jy_eq - m_qy) - (1.f - 0.5f * r.s_q) * Fy;
-    const float dm_pxx = r.s_nu * (pxx_eq - m_pxx) + (1.f - 0.5f * r.s_nu) * S_pxx;
-    const float dm_pxy = r.s_nu * (pxy_eq - m_pxy) + (1.f - 0.5f * r.s_nu) * S_pxy;
+    const R e_eq = rho * (R(-2) + R(3) * u2), eps_eq = rho * (R(1) - R(3) * u2);
+    const R jx_eq = rho * ux, jy_eq = rho * uy;
+    const R pxx_eq = rho * (ux * ux - uy * uy), pxy_eq = rho * ux * uy;
+    const R S_e = R(6) * uF, S_eps = R(-6) * uF;
+    const R S_pxx = R(2) * (ux * Fx - uy * Fy), S_pxy = ux * Fy + uy * Fx;
+    const R dm_e = r.s_e * (e_eq - m_e) + (R(1) - R(0.5) * r.s_e) * S_e;
+    const R dm_eps = r.s_eps * (eps_eq - m_eps) + (R(1) - R(0.5) * r.s_eps) * S_eps;
+    const R dm_jx = r.s_j * (jx_eq - m_jx) + (R(1) - R(0.5) * r.s_j) * Fx;
+    const R dm_jy = r.s_j * (jy_eq - m_jy) + (R(1) - R(0.5) * r.s_j) * Fy;
+    const R dm_qx = r.s_q * (-jx_eq - m_qx) - (R(1) - R(0.5) * r.s_q) * Fx;
+    const R dm_qy = r.s_q * (-jy_eq - m_qy) - (R(1) - R(0.5) * r.s_q) * Fy;
+    const R dm_pxx = r.s_nu * (pxx_eq - m_pxx) + (R(1) - R(0.5) * r.s_nu) * S_pxx;
+    const R dm_pxy = r.s_nu * (pxy_eq - m_pxy) + (R(1) - R(0.5) * r.s_nu) * S_pxy;
     // f += M^-1 dm, M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
-    const float ce = dm_e * (1.f / 36.f), cp = dm_eps * (1.f / 36.f);
-    const float jx = dm_jx * (1.f / 6.f), qx = dm_qx * (1.f / 12.f);
-    const float jy = dm_jy * (1.f / 6.f), qy = dm_qy * (1.f / 12.f);
-    const float pxx = dm_pxx * 0.25f, pxy = dm_pxy * 0.25f;
-    f[0] += -4.f * ce + 4.f * cp;
-    const float ax = -ce - 2.f * cp;
-    f[1] += ax + jx - 2.f * qx + pxx;
-    f[2] += ax + jy - 2.f * qy - pxx;
-    f[3] += ax - jx + 2.f * qx + pxx;
-    f[4] += ax - jy + 2.f * qy - pxx;
-    const float dd = 2.f * ce + cp;
-    f[5] += dd + jx + qx + jy + qy + pxy;
-    f[6] += dd - jx - qx + jy + qy - pxy;
-    f[7] += dd - jx - qx - jy - qy + pxy;
-    f[8] += dd + jx + qx - jy - qy - pxy;
+    const R ce = dm_e * R(1.0 / 36.0), cp = dm_eps * R(1.0 / 36.0);
+    const R jx = dm_jx * R(1.0 / 6.0), qx = dm_qx * R(1.0 / 12.0);
+    const R jy = dm_jy * R(1.0 / 6.0), qy = dm_qy * R(1.0 / 12.0);
+    const R pxx = dm_pxx * R(0.25), pxy = dm_pxy * R(0.25);
+    const R ax = -ce - R(2) * cp;
+    const R dd = R(2) * ce + cp;
+    fo[0] = (float)(f[0] + (R(-4) * ce + R(4) * cp));
+    fo[1] = (float)(f[1] + (ax + jx - R(2) * qx + pxx));
+    fo[2] = (float)(f[2] + (ax + jy - R(2) * qy - pxx));
+    fo[3] = (float)(f[3] + (ax - jx + R(2) * qx + pxx));
+    fo[4] = (float)(f[4] + (ax - jy + R(2) * qy - pxx));
+    fo[5] = (float)(f[5] + (dd + jx + qx + jy + qy + pxy));
+    fo[6] = (float)(f[6] + (dd - jx - qx + jy + qy - pxy));
+    fo[7] = (float)(f[7] + (dd - jx - qx - jy - qy + pxy));
+    fo[8] = (float)(f[8] + (dd + jx + qx - jy - qy - pxy));
   }
 }
 
 // Mixture velocity, rates and the collision of both components at a node.
-// rho1/rho2 are the node densities (sums of f0/f1), F the per-component
-// forces (interaction + body).
-template <int Q, int COLL>
-__device__ __forceinline__ void collide_node(const InstDev &d, float (&f0)[Q], float (&f1)[Q],
-                                             float rho1, float rho2, float F1x, float F1y,
-                                             float F1z, float F2x, float F2y, float F2z) {
+// rho1/rho2 are the node densities, F the per-component forces
+// (interaction + body).
+template <int Q, int COLL, typename R>
+__device__ __forceinline__ void collide_node(const InstDev &d, float (&f0)[Q], float (&f1)[Q], R rho1,
+                                             R rho2, R F1x, R F1y, R F1z, R F2x, R F2y, R F2z) {
   using L = Lat<Q>;
-  // momentum summed over opposite pairs: differences of nearby values
-  float jx = 0.f, jy = 0.f, jz = 0.f;
+  // momentum summed over opposite pairs
+  R jx = 0, jy = 0, jz = 0;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     if (L::opp[i] < i) continue;
-    const float d0 = f0[i] - f0[L::opp[i]], d1 = f1[i] - f1[L::opp[i]];
-    const float dsum = d0 + d1;
+    const R dsum = ((R)f0[i] - (R)f0[L::opp[i]]) + ((R)f1[i] - (R)f1[L::opp[i]]);
     if (L::ex[i]) jx += L::ex[i] * dsum;
     if (L::ey[i]) jy += L::ey[i] * dsum;
     if (L::ez[i]) jz += L::ez[i] * dsum;
   }
-  const float rho = rho1 + rho2, inv_rho = 1.f / rho;
-  const float h = d.half_shift ? 0.5f : 0.f;
-  const float ux = (jx + h * (F1x + F2x)) * inv_rho;
-  const float uy = (jy + h * (F1y + F2y)) * inv_rho;
-  const float uz = (jz + h * (F1z + F2z)) * inv_rho;
-  const Rates r = node_rates(d, rho1, rho2, inv_rho);
-  collide_component<Q, COLL>(f0, rho1, ux, uy, uz, F1x, F1y, F1z, r);
-  collide_component<Q, COLL>(f1, rho2, ux, uy, uz, F2x, F2y, F2z, r);
+  const R rho = rho1 + rho2, inv_rho = R(1) / rho;
+  const R h = d.half_shift ? R(0.5) : R(0);
+  const R ux = (jx + h * (F1x + F2x)) * inv_rho;
+  const R uy = (jy + h * (F1y + F2y)) * inv_rho;
+  const R uz = (jz + h * (F1z + F2z)) * inv_rho;
+  const Rates<R> r = node_rates<R>(d, rho1, rho2, inv_rho);
+  collide_component<Q, COLL, R>(f0, rho1, ux, uy, uz, F1x, F1y, F1z, r);
+  collide_component<Q, COLL, R>(f1, rho2, ux, uy, uz, F2x, F2y, F2z, r);
 }
 
 // ---------------------------------------------------------------------------

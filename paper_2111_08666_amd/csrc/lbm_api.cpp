@@ -92,6 +92,7 @@ bool validate(const lbm_geometry *g, const lbm_params *p, const double *rho0, st
   if (p->collision == LBM_MRT && g->q != 9) return bad(err, "MRT is defined for D2Q9 only");
   if (p->bc_set < 1 || p->bc_set > 3) return bad(err, "bc_set must be 1, 2 or 3");
   if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_BF16DEV) return bad(err, "unknown storage");
+  if (p->math != LBM_MATH_F64 && p->math != LBM_MATH_F32) return bad(err, "unknown math precision");
   const double vals[] = {p->rho_in1, p->rho_out2, p->rho_in2, p->rho_out1, p->g[0], p->g[1], p->g[2]};
   for (double v : vals)
     if (!std::isfinite(v)) return bad(err, "boundary densities and g must be finite");
@@ -180,7 +181,7 @@ void build_info(const lbm_geometry &g, const Layout &L, std::vector<uint32_t> &i
 
 // ---------------------------------------------------------------------------
 struct lbm_batch {
-  int32_t k = 0, q = 9, storage = 0, collision = 0;
+  int32_t k = 0, q = 9, storage = 0, collision = 0, math = 0;
   std::vector<InstDev> h;
   std::vector<Layout> lay;
   InstDev *d_insts = nullptr;
@@ -251,8 +252,9 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
     if (!rho0[i]) return fail(nullptr, LBM_EINVAL, "rho_init is NULL");
     if (!validate(&g[i], &p[i], rho0[i], err))
       return fail(nullptr, LBM_EINVAL, (k > 1 ? "instance " + std::to_string(i) + ": " : "") + err);
-    if (g[i].q != g[0].q || p[i].storage != p[0].storage || p[i].collision != p[0].collision)
-      return fail(nullptr, LBM_EINVAL, "all instances must share q, storage and collision");
+    if (g[i].q != g[0].q || p[i].storage != p[0].storage || p[i].collision != p[0].collision ||
+        p[i].math != p[0].math)
+      return fail(nullptr, LBM_EINVAL, "all instances must share q, storage, collision and math");
   }
   int64_t nb;
   int ob;
@@ -268,6 +270,7 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
   b->q = g[0].q;
   b->storage = p[0].storage;
   b->collision = p[0].collision;
+  b->math = p[0].math;
   b->stream = reinterpret_cast<hipStream_t>(stream);
   b->n_blocks = nb;
   b->obs_blocks = ob;
@@ -296,13 +299,13 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
     h.storage = p[i].storage; h.q = g[i].q;
     h.tiles_x = L.tiles_x; h.tiles_y = L.tiles_y; h.tiles_z = L.tiles_z;
     h.block_base = (int32_t)base;
-    h.tau1 = (float)p[i].tau[0]; h.tau2 = (float)p[i].tau[1];
-    h.G = (float)p[i].G;
-    h.chi1 = (float)(1.0 + p[i].xi); h.chi2 = (float)(1.0 - p[i].xi);
-    h.gx = (float)p[i].g[0]; h.gy = (float)p[i].g[1]; h.gz = (float)p[i].g[2];
-    h.rho_in1 = (float)p[i].rho_in1; h.rho_out2 = (float)p[i].rho_out2;
-    h.rho_in2 = (float)p[i].rho_in2; h.rho_out1 = (float)p[i].rho_out1;
-    h.lambda = (float)p[i].lambda; h.s_e = (float)p[i].s_e; h.s_eps = (float)p[i].s_eps;
+    h.tau1 = p[i].tau[0]; h.tau2 = p[i].tau[1];
+    h.G = p[i].G;
+    h.chi1 = 1.0 + p[i].xi; h.chi2 = 1.0 - p[i].xi;
+    h.gx = p[i].g[0]; h.gy = p[i].g[1]; h.gz = p[i].g[2];
+    h.rho_in1 = p[i].rho_in1; h.rho_out2 = p[i].rho_out2;
+    h.rho_in2 = p[i].rho_in2; h.rho_out1 = p[i].rho_out1;
+    h.lambda = p[i].lambda; h.s_e = p[i].s_e; h.s_eps = p[i].s_eps;
     for (int64_t t = 0; t < L.blocks; ++t) table[(size_t)(base + t)] = i;
     base += L.blocks;
     b->h.push_back(h);
@@ -346,7 +349,7 @@ lbm_status batch_step(lbm_batch *b, int64_t n) {
   if (b->unstable) return fail(b, LBM_EUNSTABLE, "state is unstable (non-finite or negative density)");
   const int32_t *table = b->k > 1 ? b->d_block_inst : nullptr;
   for (int64_t s = 0; s < n; ++s) {
-    HIPCHK(b, launch_step(b->d_insts, table, b->n_blocks, b->q, b->collision, b->storage, b->parity, b->stream));
+    HIPCHK(b, launch_step(b->d_insts, table, b->n_blocks, b->q, b->collision, b->storage, b->math, b->parity, b->stream));
     b->parity ^= 1;
     b->step++;
   }
@@ -365,7 +368,7 @@ lbm_status batch_step_graph(lbm_batch *b, int64_t n, int64_t reps) {
     const int32_t *table = b->k > 1 ? b->d_block_inst : nullptr;
     int par = b->parity;
     for (int64_t s = 0; s < n; ++s) {
-      hipError_t e = launch_step(b->d_insts, table, b->n_blocks, b->q, b->collision, b->storage, par, b->stream);
+      hipError_t e = launch_step(b->d_insts, table, b->n_blocks, b->q, b->collision, b->storage, b->math, par, b->stream);
       if (e != hipSuccess) {
         hipGraph_t tmp;
         (void)hipStreamEndCapture(b->stream, &tmp);
@@ -482,8 +485,8 @@ lbm_status lbm_set_bc(lbm_ctx *ctx, double rho_in1, double rho_out2) {
   lbm_batch *b = ctx->b;
   if (!std::isfinite(rho_in1) || !std::isfinite(rho_out2) || rho_in1 <= 0 || rho_out2 <= 0)
     return fail(b, LBM_EINVAL, "boundary densities must be finite and > 0");
-  b->h[0].rho_in1 = (float)rho_in1;
-  b->h[0].rho_out2 = (float)rho_out2;
+  b->h[0].rho_in1 = rho_in1;
+  b->h[0].rho_out2 = rho_out2;
   HIPCHK(b, hipMemcpyAsync(b->d_insts, &b->h[0], sizeof(InstDev), hipMemcpyHostToDevice, b->stream));
   HIPCHK(b, hipStreamSynchronize(b->stream));
   return LBM_OK;
@@ -574,7 +577,7 @@ lbm_status lbm_kernel_info(const lbm_ctx *ctx, char *name, size_t name_len, int6
                            int32_t *block_threads) {
   if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL handle");
   const lbm_batch *b = ctx->b;
-  if (name && name_len) std::snprintf(name, name_len, "%s", step_kernel_name(b->q, b->collision, b->storage));
+  if (name && name_len) std::snprintf(name, name_len, "%s", step_kernel_name(b->q, b->collision, b->storage, b->math));
   if (grid_blocks) *grid_blocks = b->n_blocks;
   if (block_threads) *block_threads = 256;
   return LBM_OK;

@@ -32,9 +32,9 @@ struct InstDev {
   int32_t periodic, open_x, bc_set, collision;
   int32_t half_shift, sj_mode, storage, q;
   int32_t tiles_x, tiles_y, tiles_z, block_base;
-  float tau1, tau2, G, chi1, chi2, gx, gy, gz;
-  float rho_in1, rho_out2, rho_in2, rho_out1;
-  float lambda, s_e, s_eps, pad0;
+  double tau1, tau2, G, chi1, chi2, gx, gy, gz;
+  double rho_in1, rho_out2, rho_in2, rho_out1;
+  double lambda, s_e, s_eps;
 };
 
 // Reduction record written per block by the observables kernel.
@@ -44,12 +44,12 @@ constexpr int kObsFields = 12;  // mass0 mass1 nfluid nwin swcount sumrw sumr pi
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, const float *rho0_dev,
                        int parity, hipStream_t s);
 hipError_t launch_step(const InstDev *d_insts, const int32_t *block_inst, int64_t n_blocks,
-                       int q, int collision, int storage, int parity, hipStream_t s);
+                       int q, int collision, int storage, int math, int parity, hipStream_t s);
 hipError_t launch_observables(const InstDev *d_inst, const InstDev &h_inst, int parity,
                               double *partials, int n_blocks, double *result, hipStream_t s);
 hipError_t launch_density(const InstDev *d_inst, const InstDev &h_inst, int parity,
                           float *dst, hipStream_t s);
-const char *step_kernel_name(int q, int collision, int storage);
+const char *step_kernel_name(int q, int collision, int storage, int math);
 int obs_blocks(const InstDev &h_inst);
 
 }  // namespace lbm

@@ -10,6 +10,9 @@
 // The force at x needs psi within one node, psi at a solid node needs rho
 // within one more (Eq. 17), and rho needs the pull: each block therefore
 // recomputes densities on a two-node halo around its tile in LDS.
+//
+// Populations are loaded and stored as float (or BF16 deviations); the node
+// arithmetic runs in R = double (default) or float.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
@@ -18,6 +21,8 @@
 #include "lbm_device.h"
 
 namespace lbm {
+
+template <typename R> struct Vec2 { R x, y; };
 
 // ---------------------------------------------------------------------------
 // population access by storage kind
@@ -32,7 +37,6 @@ template <int Q> struct Pop<Q, 0> {  // FP32 planes [s][i][plane]
 };
 
 template <int Q> struct Pop<Q, 1> {  // BF16 deviations
-  __device__ static __forceinline__ const float *rho(const float *b) { return b; }
   __device__ static __forceinline__ const uint16_t *dev(const float *b, int64_t plane) {
     return reinterpret_cast<const uint16_t *>(b + 2 * plane);
   }
@@ -41,7 +45,7 @@ template <int Q> struct Pop<Q, 1> {  // BF16 deviations
                                               int64_t off) {
     const float r = b[(int64_t)s * plane + off];
     const uint16_t v = dev(b, plane)[(int64_t)(s * (Q - 1) + i - 1) * plane + off];
-    return Lat<Q>::w[i] * r + bf16_to_f32(v);
+    return (float)Lat<Q>::w[i] * r + bf16_to_f32(v);
   }
   // f*_0 at off (implicit: w_0 rho - sum of deviations)
   __device__ static __forceinline__ float get0(const float *__restrict__ b, int64_t plane, int s,
@@ -51,7 +55,7 @@ template <int Q> struct Pop<Q, 1> {  // BF16 deviations
     float sum = 0.f;
 #pragma unroll
     for (int i = 1; i < Q; ++i) sum += bf16_to_f32(dv[(int64_t)(s * (Q - 1) + i - 1) * plane + off]);
-    return Lat<Q>::w[0] * r - sum;
+    return (float)Lat<Q>::w[0] * r - sum;
   }
 };
 
@@ -81,8 +85,9 @@ __device__ __forceinline__ void pop_store(float *__restrict__ b, int64_t plane, 
     uint16_t *dv = reinterpret_cast<uint16_t *>(b + 2 * plane);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      dv[(int64_t)(i - 1) * plane + off] = f32_to_bf16(f0[i] - Lat<Q>::w[i] * rho1);
-      dv[(int64_t)(Q - 1 + i - 1) * plane + off] = f32_to_bf16(f1[i] - Lat<Q>::w[i] * rho2);
+      const float w = (float)Lat<Q>::w[i];
+      dv[(int64_t)(i - 1) * plane + off] = f32_to_bf16(f0[i] - w * rho1);
+      dv[(int64_t)(Q - 1 + i - 1) * plane + off] = f32_to_bf16(f1[i] - w * rho2);
     }
   }
 }
@@ -91,7 +96,7 @@ __device__ __forceinline__ void pop_store(float *__restrict__ b, int64_t plane, 
 // Pull one fluid node's populations for both components and complete the
 // inlet/outlet links.  (x, y, z) are in-domain coordinates.
 // ---------------------------------------------------------------------------
-template <int Q, int ST>
+template <int Q, int ST, typename R>
 __device__ __forceinline__ void gather(const InstDev &d, const float *__restrict__ fin, uint32_t info,
                                        int x, int y, int z, float (&f0)[Q], float (&f1)[Q]) {
   using L = Lat<Q>;
@@ -123,20 +128,10 @@ __device__ __forceinline__ void gather(const InstDev &d, const float *__restrict
   if (bnd) {
     const int t = y + d.ny * z;
     const int64_t nt = (int64_t)d.ny * d.nz;
-    complete_boundary<Q>(
+    complete_boundary<Q, R>(
         d, info, f0, f1, [&](int s, int i) { return pop_get<Q, ST>(fin, plane, s, i, off); },
         [&](int s, int i) { return d.frozen[(int64_t)(s * Q + i) * nt + t]; });
   }
-}
-
-template <int Q>
-__device__ __forceinline__ float sum_q(const float (&f)[Q]) {
-  // pairwise over opposite links first (keeps FP32 sums well conditioned)
-  float s = f[0];
-#pragma unroll
-  for (int i = 1; i < Q; ++i)
-    if (Lat<Q>::opp[i] > i) s += f[i] + f[Lat<Q>::opp[i]];
-  return s;
 }
 
 // ---------------------------------------------------------------------------
@@ -150,11 +145,12 @@ __device__ __forceinline__ float sum_q(const float (&f)[Q]) {
 // ---------------------------------------------------------------------------
 constexpr int kRH = kTileY + 4;
 
-template <int COLL, int ST>
+template <int COLL, int ST, typename R>
 __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ insts,
                                                   const int32_t *__restrict__ block_inst, int parity) {
   using L = Lat<9>;
-  __shared__ float2 psi[kRH][64];
+  using V = Vec2<R>;
+  __shared__ V psi[kRH][64];
 
   const int inst = block_inst ? block_inst[blockIdx.x] : 0;
   const InstDev &d = insts[inst];
@@ -188,15 +184,15 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
       if (py) gy += gy < 0 ? ny : -ny;
       else in = false;
     }
-    float rho1 = 0.f, rho2 = 0.f;
+    R rho1 = 0, rho2 = 0;
     uint32_t inf = kSolid;
     if (in) {
       inf = d.info[gx + (int64_t)d.pitch * gy];
       if (!(inf & kSolid)) {
         float a[9], b[9];
-        gather<9, ST>(d, fin, inf, gx, gy, 0, a, b);
-        rho1 = sum_q<9>(a);
-        rho2 = sum_q<9>(b);
+        gather<9, ST, R>(d, fin, inf, gx, gy, 0, a, b);
+        rho1 = sum_q<9, R>(a);
+        rho2 = sum_q<9, R>(b);
         if (k < 3) {
 #pragma unroll
           for (int i = 0; i < 9; ++i) {
@@ -208,7 +204,7 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
     }
     info[k] = inf;
     valid[k] = in;
-    psi[r][lane] = make_float2(rho1, rho2);
+    psi[r][lane] = V{rho1, rho2};
   }
   __syncthreads();
 
@@ -219,58 +215,60 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
     if (!valid[k] || !(info[k] & kSolid) || r < 1 || r > kRH - 2 || lane < 1 || lane > 62) continue;
     const uint32_t nb = info[k];
     if (!(nb & kLinkMask)) continue;
-    float s1 = 0.f, s2 = 0.f, den = 0.f;
+    R s1 = 0, s2 = 0, den = 0;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
       if (nb & (1u << i)) {
-        const float2 p = psi[r + L::ey[i]][lane + L::ex[i]];
-        s1 += L::w[i] * p.x;
-        s2 += L::w[i] * p.y;
-        den += L::w[i];
+        const V p = psi[r + L::ey[i]][lane + L::ex[i]];
+        const R w = (R)L::w[i];
+        s1 += w * p.x;
+        s2 += w * p.y;
+        den += w;
       }
     }
-    const float inv = 1.f / den;
-    psi[r][lane] = make_float2(d.chi1 * s1 * inv, d.chi2 * s2 * inv);
+    const R inv = R(1) / den;
+    psi[r][lane] = V{(R)d.chi1 * s1 * inv, (R)d.chi2 * s2 * inv};
   }
   __syncthreads();
 
   // Phase 3: force + collision for interior rows
+  const R w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     const int r = 2 + wave + 4 * k;
     const int gy_raw = ty * kTileY - 2 + r;
     if (!valid[k] || !col_store || gy_raw >= ny || (info[k] & kSolid)) continue;
     const uint32_t inf = info[k];
-    const float2 c = psi[r][lane];
-    const float rho1 = c.x, rho2 = c.y;
+    const V c = psi[r][lane];
+    const R rho1 = c.x, rho2 = c.y;
     // sum_i w_i psi(x + e_i) e_i by opposite pairs
-    float sx1, sy1, sx2, sy2;  // sums of the other component's psi
+    R sx1, sy1, sx2, sy2;  // sums of component 1's / 2's psi
     {
-      const float2 p1 = psi[r][lane + 1], p3 = psi[r][lane - 1];
-      const float2 p2 = psi[r + 1][lane], p4 = psi[r - 1][lane];
-      const float2 p5 = psi[r + 1][lane + 1], p7 = psi[r - 1][lane - 1];
-      const float2 p6 = psi[r + 1][lane - 1], p8 = psi[r - 1][lane + 1];
+      const V p2 = psi[r + 1][lane], p4 = psi[r - 1][lane];
       if (inf & (kInlet | kOutlet)) {
         // mirrored neighbours cancel every pair with an x component
-        sx1 = 0.f;
-        sx2 = 0.f;
-        sy1 = (1.f / 9.f) * (p2.x - p4.x);
-        sy2 = (1.f / 9.f) * (p2.y - p4.y);
+        sx1 = 0;
+        sx2 = 0;
+        sy1 = w1 * (p2.x - p4.x);
+        sy2 = w1 * (p2.y - p4.y);
       } else {
-        const float a57 = p5.x - p7.x, a68 = p6.x - p8.x;
-        const float b57 = p5.y - p7.y, b68 = p6.y - p8.y;
-        sx1 = (1.f / 9.f) * (p1.x - p3.x) + (1.f / 36.f) * (a57 - a68);
-        sy1 = (1.f / 9.f) * (p2.x - p4.x) + (1.f / 36.f) * (a57 + a68);
-        sx2 = (1.f / 9.f) * (p1.y - p3.y) + (1.f / 36.f) * (b57 - b68);
-        sy2 = (1.f / 9.f) * (p2.y - p4.y) + (1.f / 36.f) * (b57 + b68);
+        const V p1 = psi[r][lane + 1], p3 = psi[r][lane - 1];
+        const V p5 = psi[r + 1][lane + 1], p7 = psi[r - 1][lane - 1];
+        const V p6 = psi[r + 1][lane - 1], p8 = psi[r - 1][lane + 1];
+        const R a57 = p5.x - p7.x, a68 = p6.x - p8.x;
+        const R b57 = p5.y - p7.y, b68 = p6.y - p8.y;
+        sx1 = w1 * (p1.x - p3.x) + w5 * (a57 - a68);
+        sy1 = w1 * (p2.x - p4.x) + w5 * (a57 + a68);
+        sx2 = w1 * (p1.y - p3.y) + w5 * (b57 - b68);
+        sy2 = w1 * (p2.y - p4.y) + w5 * (b57 + b68);
       }
     }
-    const float G = d.G;
-    const float F1x = -G * rho1 * sx2 + rho1 * d.gx, F1y = -G * rho1 * sy2 + rho1 * d.gy;
-    const float F2x = -G * rho2 * sx1 + rho2 * d.gx, F2y = -G * rho2 * sy1 + rho2 * d.gy;
-    collide_node<9, COLL>(d, f0[k], f1[k], rho1, rho2, F1x, F1y, 0.f, F2x, F2y, 0.f);
+    const R G = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy;
+    const R F1x = -G * rho1 * sx2 + rho1 * gxb, F1y = -G * rho1 * sy2 + rho1 * gyb;
+    const R F2x = -G * rho2 * sx1 + rho2 * gxb, F2y = -G * rho2 * sy1 + rho2 * gyb;
+    collide_node<9, COLL, R>(d, f0[k], f1[k], rho1, rho2, F1x, F1y, R(0), F2x, F2y, R(0));
     const int64_t off = gx + (int64_t)d.pitch * gy_raw;
-    pop_store<9, ST>(fout, d.plane, off, f0[k], f1[k], rho1, rho2);
+    pop_store<9, ST>(fout, d.plane, off, f0[k], f1[k], (float)rho1, (float)rho2);
   }
 }
 
@@ -286,11 +284,12 @@ constexpr int kRing = 5;
 
 __device__ __forceinline__ int ring(int z) { return ((z % kRing) + kRing) % kRing; }
 
-template <int COLL, int ST>
+template <int COLL, int ST, typename R>
 __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ insts,
                                                    const int32_t *__restrict__ block_inst, int parity) {
   using L = Lat<19>;
-  __shared__ float2 psi[kRing][kRH3][64];
+  using V = Vec2<R>;
+  __shared__ V psi[kRing][kRH3][64];
 
   const int inst = block_inst ? block_inst[blockIdx.x] : 0;
   const InstDev &d = insts[inst];
@@ -338,31 +337,31 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
     int zz;
     const bool zin = wrap_z(zp, zz);
     {
-      float rho1 = 0.f, rho2 = 0.f;
+      R rho1 = 0, rho2 = 0;
       uint32_t inf = kSolid;
       if (in_i && zin) {
         inf = d.info[gx + (int64_t)d.pitch * gyi + slab * zz];
         if (!(inf & kSolid)) {
-          gather<19, ST>(d, fin, inf, gx, gyi, zz, a, b);
-          rho1 = sum_q<19>(a);
-          rho2 = sum_q<19>(b);
+          gather<19, ST, R>(d, fin, inf, gx, gyi, zz, a, b);
+          rho1 = sum_q<19, R>(a);
+          rho2 = sum_q<19, R>(b);
         }
       }
       inf_out = inf;
-      psi[slot][ri][lane] = make_float2(rho1, rho2);
+      psi[slot][ri][lane] = V{rho1, rho2};
     }
     {
-      float rho1 = 0.f, rho2 = 0.f;
+      R rho1 = 0, rho2 = 0;
       if (in_h && zin) {
         const uint32_t inf = d.info[gx + (int64_t)d.pitch * gyh + slab * zz];
         if (!(inf & kSolid)) {
           float ha[19], hb[19];
-          gather<19, ST>(d, fin, inf, gx, gyh, zz, ha, hb);
-          rho1 = sum_q<19>(ha);
-          rho2 = sum_q<19>(hb);
+          gather<19, ST, R>(d, fin, inf, gx, gyh, zz, ha, hb);
+          rho1 = sum_q<19, R>(ha);
+          rho2 = sum_q<19, R>(hb);
         }
       }
-      psi[slot][rh][lane] = make_float2(rho1, rho2);
+      psi[slot][rh][lane] = V{rho1, rho2};
     }
   };
 
@@ -379,47 +378,49 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
       if (!in || r < 1 || r > kRH3 - 2 || lane < 1 || lane > 62) continue;
       const uint32_t nb = d.info[gx + (int64_t)d.pitch * (h ? gyh : gyi) + slab * zz];
       if (!(nb & kSolid) || !(nb & kLinkMask)) continue;
-      float s1 = 0.f, s2 = 0.f, den = 0.f;
+      R s1 = 0, s2 = 0, den = 0;
 #pragma unroll
       for (int i = 1; i < 19; ++i) {
         if (nb & (1u << i)) {
-          const float2 p = psi[ring(zp + L::ez[i])][r + L::ey[i]][lane + L::ex[i]];
-          s1 += L::w[i] * p.x;
-          s2 += L::w[i] * p.y;
-          den += L::w[i];
+          const V p = psi[ring(zp + L::ez[i])][r + L::ey[i]][lane + L::ex[i]];
+          const R w = (R)L::w[i];
+          s1 += w * p.x;
+          s2 += w * p.y;
+          den += w;
         }
       }
-      const float inv = 1.f / den;
-      psi[slot][r][lane] = make_float2(d.chi1 * s1 * inv, d.chi2 * s2 * inv);
+      const R inv = R(1) / den;
+      psi[slot][r][lane] = V{(R)d.chi1 * s1 * inv, (R)d.chi2 * s2 * inv};
     }
   };
 
   // force (Eq. 13 with the open-face mirror) + collision + store, plane z
   auto collide_plane = [&](int z, float (&a)[19], float (&b)[19], uint32_t inf) {
     if (!store_ok || (inf & kSolid)) return;
-    const float2 c = psi[ring(z)][ri][lane];
-    const float rho1 = c.x, rho2 = c.y;
-    float sx1 = 0.f, sy1 = 0.f, sz1 = 0.f, sx2 = 0.f, sy2 = 0.f, sz2 = 0.f;
+    const V c = psi[ring(z)][ri][lane];
+    const R rho1 = c.x, rho2 = c.y;
+    R sx1 = 0, sy1 = 0, sz1 = 0, sx2 = 0, sy2 = 0, sz2 = 0;
     const bool open_face = (inf & (kInlet | kOutlet)) != 0;
 #pragma unroll
     for (int i = 1; i < 19; ++i) {
       if (L::opp[i] < i) continue;
       const int o = L::opp[i];
       if (open_face && L::ex[i] != 0) continue;  // mirrored pair cancels
-      const float2 pa = psi[ring(z + L::ez[i])][ri + L::ey[i]][lane + L::ex[i]];
-      const float2 pb = psi[ring(z + L::ez[o])][ri + L::ey[o]][lane + L::ex[o]];
-      const float d1 = L::w[i] * (pa.x - pb.x), d2 = L::w[i] * (pa.y - pb.y);
+      const V pa = psi[ring(z + L::ez[i])][ri + L::ey[i]][lane + L::ex[i]];
+      const V pb = psi[ring(z + L::ez[o])][ri + L::ey[o]][lane + L::ex[o]];
+      const R w = (R)L::w[i];
+      const R d1 = w * (pa.x - pb.x), d2 = w * (pa.y - pb.y);
       if (L::ex[i]) { sx1 += L::ex[i] * d1; sx2 += L::ex[i] * d2; }
       if (L::ey[i]) { sy1 += L::ey[i] * d1; sy2 += L::ey[i] * d2; }
       if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
     }
-    const float G = d.G;
-    collide_node<19, COLL>(d, a, b, rho1, rho2, -G * rho1 * sx2 + rho1 * d.gx,
-                           -G * rho1 * sy2 + rho1 * d.gy, -G * rho1 * sz2 + rho1 * d.gz,
-                           -G * rho2 * sx1 + rho2 * d.gx, -G * rho2 * sy1 + rho2 * d.gy,
-                           -G * rho2 * sz1 + rho2 * d.gz);
+    const R G = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
+    collide_node<19, COLL, R>(d, a, b, rho1, rho2, -G * rho1 * sx2 + rho1 * gxb,
+                              -G * rho1 * sy2 + rho1 * gyb, -G * rho1 * sz2 + rho1 * gzb,
+                              -G * rho2 * sx1 + rho2 * gxb, -G * rho2 * sy1 + rho2 * gyb,
+                              -G * rho2 * sz1 + rho2 * gzb);
     const int64_t off = gx + (int64_t)d.pitch * gyi_raw + slab * z;
-    pop_store<19, ST>(fout, d.plane, off, a, b, rho1, rho2);
+    pop_store<19, ST>(fout, d.plane, off, a, b, (float)rho1, (float)rho2);
   };
 
   // register ring: slot k holds the interior populations of plane z with (z - z0) % 3 == k
@@ -471,8 +472,8 @@ __global__ void init_kernel(const InstDev *__restrict__ insts, const float *__re
     float a[Q], c[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      a[i] = Lat<Q>::w[i] * r1;
-      c[i] = Lat<Q>::w[i] * r2;
+      a[i] = (float)(Lat<Q>::w[i] * (double)r1);
+      c[i] = (float)(Lat<Q>::w[i] * (double)r2);
     }
     if constexpr (ST == 0) {
 #pragma unroll
@@ -503,7 +504,7 @@ __global__ __launch_bounds__(256) void obs_kernel(const InstDev *__restrict__ in
   const int64_t n_nodes = (int64_t)d.nx * d.ny * d.nz;
   double acc[kObsFields - 1] = {0};
   int flags = 0;
-  const float third = 1.f / 3.f;
+  const double third = 1.0 / 3.0;
   for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < n_nodes;
        n += (int64_t)gridDim.x * blockDim.x) {
     const int x = n % d.nx;
@@ -512,10 +513,10 @@ __global__ __launch_bounds__(256) void obs_kernel(const InstDev *__restrict__ in
     const uint32_t inf = d.info[x + (int64_t)d.pitch * yz];
     if (inf & kSolid) continue;
     float a[Q], b[Q];
-    gather<Q, ST>(d, fin, inf, x, y, z, a, b);
-    const float r1 = sum_q<Q>(a), r2 = sum_q<Q>(b);
+    gather<Q, ST, double>(d, fin, inf, x, y, z, a, b);
+    const double r1 = sum_q<Q, double>(a), r2 = sum_q<Q, double>(b);
     if (!isfinite(r1) || !isfinite(r2)) flags |= 1;
-    if (r1 < 0.f || r2 < 0.f) flags |= 2;
+    if (r1 < 0.0 || r2 < 0.0) flags |= 2;
     acc[0] += r1;
     acc[1] += r2;
     acc[2] += 1.0;
@@ -523,10 +524,10 @@ __global__ __launch_bounds__(256) void obs_kernel(const InstDev *__restrict__ in
       acc[3] += 1.0;
       acc[4] += (r2 > r1) ? 1.0 : 0.0;
       acc[5] += r2;
-      acc[6] += (double)r1 + (double)r2;
+      acc[6] += r1 + r2;
     }
     if (inf & kPFace) {
-      const double P = (double)third * ((double)r1 + r2) + (double)d.G * third * (double)r1 * r2;
+      const double P = third * (r1 + r2) + d.G * third * r1 * r2;
       if (x == 0) { acc[7] += P; acc[8] += 1.0; }
       else { acc[9] += P; acc[10] += 1.0; }
     }
@@ -585,9 +586,9 @@ __global__ void density_kernel(const InstDev *__restrict__ insts, int parity, fl
     float r1 = 0.f, r2 = 0.f;
     if (!(inf & kSolid)) {
       float a[Q], b[Q];
-      gather<Q, ST>(d, fin, inf, x, y, z, a, b);
-      r1 = sum_q<Q>(a);
-      r2 = sum_q<Q>(b);
+      gather<Q, ST, double>(d, fin, inf, x, y, z, a, b);
+      r1 = (float)sum_q<Q, double>(a);
+      r2 = (float)sum_q<Q, double>(b);
     }
     dst[n] = r1;
     dst[n_nodes + n] = r2;
@@ -623,34 +624,42 @@ hipError_t launch_init(const InstDev *d_inst, const InstDev &h, const float *rho
   return hipGetLastError();
 }
 
-template <int COLL, int ST>
+template <int COLL, int ST, typename R>
 static void launch_step_q(int q, const InstDev *d, const int32_t *bi, int64_t nb, int parity,
                           hipStream_t s) {
-  if (q == 9) step_d2q9<COLL, ST><<<dim3((unsigned)nb), dim3(256), 0, s>>>(d, bi, parity);
-  else if constexpr (COLL != 1) step_d3q19<COLL, ST><<<dim3((unsigned)nb), dim3(256), 0, s>>>(d, bi, parity);
+  if (q == 9) step_d2q9<COLL, ST, R><<<dim3((unsigned)nb), dim3(256), 0, s>>>(d, bi, parity);
+  else if constexpr (COLL != 1) step_d3q19<COLL, ST, R><<<dim3((unsigned)nb), dim3(256), 0, s>>>(d, bi, parity);
+}
+
+template <typename R>
+static void launch_step_r(int q, int collision, int storage, const InstDev *d, const int32_t *bi,
+                          int64_t nb, int parity, hipStream_t s) {
+  if (storage == 0) {
+    if (collision == 0) launch_step_q<0, 0, R>(q, d, bi, nb, parity, s);
+    else if (collision == 1) launch_step_q<1, 0, R>(q, d, bi, nb, parity, s);
+    else launch_step_q<2, 0, R>(q, d, bi, nb, parity, s);
+  } else {
+    if (collision == 0) launch_step_q<0, 1, R>(q, d, bi, nb, parity, s);
+    else if (collision == 1) launch_step_q<1, 1, R>(q, d, bi, nb, parity, s);
+    else launch_step_q<2, 1, R>(q, d, bi, nb, parity, s);
+  }
 }
 
 hipError_t launch_step(const InstDev *d_insts, const int32_t *block_inst, int64_t n_blocks, int q,
-                       int collision, int storage, int parity, hipStream_t s) {
-  if (storage == 0) {
-    if (collision == 0) launch_step_q<0, 0>(q, d_insts, block_inst, n_blocks, parity, s);
-    else if (collision == 1) launch_step_q<1, 0>(q, d_insts, block_inst, n_blocks, parity, s);
-    else launch_step_q<2, 0>(q, d_insts, block_inst, n_blocks, parity, s);
-  } else {
-    if (collision == 0) launch_step_q<0, 1>(q, d_insts, block_inst, n_blocks, parity, s);
-    else if (collision == 1) launch_step_q<1, 1>(q, d_insts, block_inst, n_blocks, parity, s);
-    else launch_step_q<2, 1>(q, d_insts, block_inst, n_blocks, parity, s);
-  }
+                       int collision, int storage, int math, int parity, hipStream_t s) {
+  if (math == 0) launch_step_r<double>(q, collision, storage, d_insts, block_inst, n_blocks, parity, s);
+  else launch_step_r<float>(q, collision, storage, d_insts, block_inst, n_blocks, parity, s);
   return hipGetLastError();
 }
 
-const char *step_kernel_name(int q, int collision, int storage) {
-  static const char *names[2][3][2] = {
-      {{"step_d2q9<0,0>", "step_d2q9<0,1>"}, {"step_d2q9<1,0>", "step_d2q9<1,1>"},
-       {"step_d2q9<2,0>", "step_d2q9<2,1>"}},
-      {{"step_d3q19<0,0>", "step_d3q19<0,1>"}, {"step_d3q19<1,0>", "step_d3q19<1,1>"},
-       {"step_d3q19<2,0>", "step_d3q19<2,1>"}}};
-  return names[q == 19][collision][storage];
+const char *step_kernel_name(int q, int collision, int storage, int math) {
+  static const char *lat[2] = {"step_d2q9", "step_d3q19"};
+  static const char *coll[3] = {"SRT", "MRT", "TRT"};
+  static const char *st[2] = {"f32", "bf16dev"};
+  static const char *mt[2] = {"double", "float"};
+  static thread_local char buf[96];
+  snprintf(buf, sizeof buf, "%s<%s,%s,%s>", lat[q == 19], coll[collision], st[storage], mt[math]);
+  return buf;
 }
 
 hipError_t launch_observables(const InstDev *d_inst, const InstDev &h, int parity, double *partials,

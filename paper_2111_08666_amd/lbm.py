@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 SRT, MRT, TRT = 0, 1, 2
 STORE_F32, STORE_BF16DEV = 0, 1
+MATH_F64, MATH_F32 = 0, 1
 
 EXPORTS = [
     "lbm_workspace_bytes", "lbm_create", "lbm_set_bc", "lbm_step", "lbm_step_graph",
@@ -40,7 +41,7 @@ class Params(C.Structure):
                 ("g", C.c_double * 3), ("collision", C.c_int32), ("bc_set", C.c_int32),
                 ("half_force_shift", C.c_int32), ("mrt_sj_mode", C.c_int32),
                 ("lam", C.c_double), ("s_e", C.c_double), ("s_eps", C.c_double),
-                ("storage", C.c_int32), ("reserved", C.c_int32)]
+                ("storage", C.c_int32), ("math", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -125,7 +126,7 @@ def make_geometry(problem, keep: list) -> Geometry:
     return g
 
 
-def make_params(problem, storage=STORE_F32) -> Params:
+def make_params(problem, storage=STORE_F32, math=MATH_F64) -> Params:
     p = Params()
     p.tau[0], p.tau[1] = problem.tau
     p.G, p.xi = problem.G, problem.xi
@@ -137,6 +138,7 @@ def make_params(problem, storage=STORE_F32) -> Params:
     p.half_force_shift, p.mrt_sj_mode = problem.half_force_shift, problem.mrt_sj_mode
     p.lam, p.s_e, p.s_eps = problem.lam, problem.s_e, problem.s_eps
     p.storage = storage
+    p.math = math
     return p
 
 
@@ -164,7 +166,7 @@ class Solver:
     """One instance on one GPU.  torch allocates the workspace; every kernel
     runs on `stream` (default: a new non-default torch stream)."""
 
-    def __init__(self, problem, storage=STORE_F32, device="cuda:0", stream=None):
+    def __init__(self, problem, storage=STORE_F32, device="cuda:0", stream=None, math=MATH_F64):
         import torch
         self.problem = problem
         self.shape = problem.mask.shape
@@ -172,7 +174,7 @@ class Solver:
         L = lib()
         keep = []
         self._g = make_geometry(problem, keep)
-        self._p = make_params(problem, storage)
+        self._p = make_params(problem, storage, math)
         self._keep = keep
         nbytes = L.lbm_workspace_bytes(C.byref(self._g), C.byref(self._p))
         if nbytes == 0:
@@ -262,14 +264,14 @@ class Solver:
 class BatchSolver:
     """Many instances advanced by one launch per step (flat block table)."""
 
-    def __init__(self, problems, storage=STORE_F32, device="cuda:0", stream=None):
+    def __init__(self, problems, storage=STORE_F32, device="cuda:0", stream=None, math=MATH_F64):
         import torch
         self.problems = list(problems)
         k = len(self.problems)
         L = lib()
         keep = []
         self._g = (Geometry * k)(*[make_geometry(p, keep) for p in self.problems])
-        self._p = (Params * k)(*[make_params(p, storage) for p in self.problems])
+        self._p = (Params * k)(*[make_params(p, storage, math) for p in self.problems])
         self._keep = keep
         nbytes = L.lbm_batch_workspace_bytes(k, self._g, self._p)
         if nbytes == 0:
