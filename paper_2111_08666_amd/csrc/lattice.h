@@ -107,6 +107,22 @@ __device__ __forceinline__ void complete_boundary(const InstDev &d, uint32_t inf
   }
 }
 
+// Reciprocal: hardware estimate refined by two Newton steps in double (to
+// full precision), one in float.
+template <typename R> __device__ __forceinline__ R rcp(R x);
+template <> __device__ __forceinline__ double rcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+template <> __device__ __forceinline__ float rcp<float>(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  const float e = __builtin_fmaf(-x, r, 1.f);
+  return __builtin_fmaf(r, e, r);
+}
+
 // Sum of the populations, pairing opposite links first.
 template <int Q, typename R>
 __device__ __forceinline__ R sum_q(const float (&f)[Q]) {
@@ -130,8 +146,10 @@ template <typename R>
 __device__ __forceinline__ Rates<R> node_rates(const InstDev &d, R rho1, R rho2, R inv_rho) {
   Rates<R> r;
   const R tau_s = (rho1 * (R)d.tau1 + rho2 * (R)d.tau2) * inv_rho;
-  r.s_nu = R(1) / tau_s;
-  r.s_q = d.lambda > 0 ? R(1) / (R(0.5) + (R)d.lambda / (tau_s - R(0.5))) : r.s_nu;
+  r.s_nu = rcp<R>(tau_s);
+  // 1/s_q = 1/2 + lambda/(tau_s - 1/2)  =>  s_q = (tau_s - 1/2) / ((tau_s - 1/2)/2 + lambda)
+  const R a = tau_s - R(0.5);
+  r.s_q = d.lambda > 0 ? a * rcp<R>(R(0.5) * a + (R)d.lambda) : r.s_nu;
   r.s_e = d.s_e > 0 ? (R)d.s_e : r.s_nu;
   r.s_eps = d.s_eps > 0 ? (R)d.s_eps : r.s_nu;
   r.s_j = d.sj_mode ? r.s_q : r.s_nu;
@@ -248,7 +266,7 @@ __device__ __forceinline__ void collide_node(const InstDev &d, float (&f0)[Q], f
     if (L::ey[i]) jy += L::ey[i] * dsum;
     if (L::ez[i]) jz += L::ez[i] * dsum;
   }
-  const R rho = rho1 + rho2, inv_rho = R(1) / rho;
+  const R rho = rho1 + rho2, inv_rho = rcp<R>(rho);
   const R h = d.half_shift ? R(0.5) : R(0);
   const R ux = (jx + h * (F1x + F2x)) * inv_rho;
   const R uy = (jy + h * (F1y + F2y)) * inv_rho;

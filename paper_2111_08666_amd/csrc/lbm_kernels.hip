@@ -24,52 +24,42 @@ namespace lbm {
 
 template <typename R> struct Vec2 { R x, y; };
 
+// global-memory views of the state (lets the compiler emit global, not flat, accesses)
+typedef __attribute__((address_space(1))) float gf;
+typedef __attribute__((address_space(1))) const float gcf;
+typedef __attribute__((address_space(1))) const uint32_t gcu32;
+typedef __attribute__((address_space(1))) uint16_t gu16;
+typedef __attribute__((address_space(1))) const uint16_t gcu16;
+
+__device__ __forceinline__ gcf *G(const float *p) { return (gcf *)p; }
+__device__ __forceinline__ gf *G(float *p) { return (gf *)p; }
+
 // ---------------------------------------------------------------------------
 // population access by storage kind
+// FP32:  buffer = [s][i][plane] floats
+// BF16:  buffer = [s][plane] float densities, then [s][i-1][plane] bf16
+//        deviations d_i = f*_i - w_i rho (i >= 1); f*_0 = w_0 rho - sum d_i.
 // ---------------------------------------------------------------------------
-template <int Q, int ST> struct Pop;
-
-template <int Q> struct Pop<Q, 0> {  // FP32 planes [s][i][plane]
-  __device__ static __forceinline__ float get(const float *__restrict__ b, int64_t plane, int s, int i,
-                                              int64_t off) {
-    return b[(int64_t)(s * Q + i) * plane + off];
-  }
-};
-
-template <int Q> struct Pop<Q, 1> {  // BF16 deviations
-  __device__ static __forceinline__ const uint16_t *dev(const float *b, int64_t plane) {
-    return reinterpret_cast<const uint16_t *>(b + 2 * plane);
-  }
-  // f*_i at off, i >= 1
-  __device__ static __forceinline__ float get(const float *__restrict__ b, int64_t plane, int s, int i,
-                                              int64_t off) {
-    const float r = b[(int64_t)s * plane + off];
-    const uint16_t v = dev(b, plane)[(int64_t)(s * (Q - 1) + i - 1) * plane + off];
-    return (float)Lat<Q>::w[i] * r + bf16_to_f32(v);
-  }
-  // f*_0 at off (implicit: w_0 rho - sum of deviations)
-  __device__ static __forceinline__ float get0(const float *__restrict__ b, int64_t plane, int s,
-                                               int64_t off) {
-    const float r = b[(int64_t)s * plane + off];
-    const uint16_t *dv = dev(b, plane);
-    float sum = 0.f;
-#pragma unroll
-    for (int i = 1; i < Q; ++i) sum += bf16_to_f32(dv[(int64_t)(s * (Q - 1) + i - 1) * plane + off]);
-    return (float)Lat<Q>::w[0] * r - sum;
-  }
-};
-
 template <int Q, int ST>
-__device__ __forceinline__ float pop_get(const float *__restrict__ b, int64_t plane, int s, int i, int64_t off) {
-  if constexpr (ST == 1) {
-    if (i == 0) return Pop<Q, 1>::get0(b, plane, s, off);
+__device__ __forceinline__ float pop_get(gcf *__restrict__ b, int64_t plane, int s, int i, int64_t off) {
+  if constexpr (ST == 0) {
+    return b[(int64_t)(s * Q + i) * plane + off];
+  } else {
+    const float r = b[(int64_t)s * plane + off];
+    gcu16 *dv = (gcu16 *)(b + 2 * plane);
+    if (i == 0) {
+      float sum = 0.f;
+#pragma unroll
+      for (int j = 1; j < Q; ++j) sum += bf16_to_f32(dv[(int64_t)(s * (Q - 1) + j - 1) * plane + off]);
+      return (float)Lat<Q>::w[0] * r - sum;
+    }
+    return (float)Lat<Q>::w[i] * r + bf16_to_f32(dv[(int64_t)(s * (Q - 1) + i - 1) * plane + off]);
   }
-  return Pop<Q, ST>::get(b, plane, s, i, off);
 }
 
 // Store both components' post-collision populations of one node.
 template <int Q, int ST>
-__device__ __forceinline__ void pop_store(float *__restrict__ b, int64_t plane, int64_t off,
+__device__ __forceinline__ void pop_store(gf *__restrict__ b, int64_t plane, int64_t off,
                                           const float (&f0)[Q], const float (&f1)[Q], float rho1,
                                           float rho2) {
   if constexpr (ST == 0) {
@@ -82,7 +72,7 @@ __device__ __forceinline__ void pop_store(float *__restrict__ b, int64_t plane, 
     // collision conserves each component's node mass, so rho is stored as is
     b[off] = rho1;
     b[plane + off] = rho2;
-    uint16_t *dv = reinterpret_cast<uint16_t *>(b + 2 * plane);
+    gu16 *dv = (gu16 *)(b + 2 * plane);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const float w = (float)Lat<Q>::w[i];
@@ -92,46 +82,69 @@ __device__ __forceinline__ void pop_store(float *__restrict__ b, int64_t plane, 
   }
 }
 
-// ---------------------------------------------------------------------------
-// Pull one fluid node's populations for both components and complete the
-// inlet/outlet links.  (x, y, z) are in-domain coordinates.
-// ---------------------------------------------------------------------------
+// Inlet/outlet completion of one pulled node (links already pulled).
 template <int Q, int ST, typename R>
-__device__ __forceinline__ void gather(const InstDev &d, const float *__restrict__ fin, uint32_t info,
-                                       int x, int y, int z, float (&f0)[Q], float (&f1)[Q]) {
+__device__ __forceinline__ void complete(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int y,
+                                         int z, int64_t off, float (&f0)[Q], float (&f1)[Q]) {
+  const int t = y + d.ny * z;
+  const int64_t nt = (int64_t)d.ny * d.nz;
+  gcf *frz = G(d.frozen);
+  complete_boundary<Q, R>(
+      d, info, f0, f1, [&](int s, int i) { return pop_get<Q, ST>(fin, d.plane, s, i, off); },
+      [&](int s, int i) { return frz[(int64_t)(s * Q + i) * nt + t]; });
+}
+
+// ---------------------------------------------------------------------------
+// Pull one fluid node's populations for both components: f_i(x) = f*_i(x-e_i),
+// or this node's f*_opp(i) where x - e_i is solid.  Every address is valid:
+// sources wrap periodically, and a wrapped source across an open face is a
+// missing link whose value complete() overwrites.
+// ---------------------------------------------------------------------------
+template <int Q, int ST>
+__device__ __forceinline__ void pull(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int x, int y,
+                                     int z, float (&f0)[Q], float (&f1)[Q]) {
   using L = Lat<Q>;
   const int64_t plane = d.plane;
   const int64_t rowp = d.pitch;
   const int64_t slab = (int64_t)d.pitch * d.ny;
   const int64_t off = x + rowp * y + slab * z;
-  const bool bnd = (info & (kInlet | kOutlet)) != 0;
+  const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
+  const int64_t xs[3] = {xp, x, xm};  // source x for e_x = -1, 0, +1
+  const int64_t ys[3] = {yp * rowp, y * rowp, ym * rowp};
+  const int64_t zs[3] = {zp * slab, z * slab, zm * slab};
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    if (info & (1u << i)) {  // bounce-back: this node's opposite post-collision value
-      f0[i] = pop_get<Q, ST>(fin, plane, 0, L::opp[i], off);
-      f1[i] = pop_get<Q, ST>(fin, plane, 1, L::opp[i], off);
-      continue;
+    const bool bb = (info >> i) & 1u;
+    const int64_t src = xs[L::ex[i] + 1] + ys[L::ey[i] + 1] + zs[L::ez[i] + 1];
+    const int64_t o = bb ? off : src;
+    const int pi = bb ? L::opp[i] : i;
+    if constexpr (ST == 0) {
+      f0[i] = fin[(int64_t)pi * plane + o];
+      f1[i] = fin[(int64_t)(Q + pi) * plane + o];
+    } else {
+      f0[i] = pop_get<Q, 1>(fin, plane, 0, pi, o);
+      f1[i] = pop_get<Q, 1>(fin, plane, 1, pi, o);
     }
-    if (bnd && L::ex[i] != 0 && ((info & kInlet) ? L::ex[i] > 0 : L::ex[i] < 0)) {
-      f0[i] = 0.f;  // missing link, completed below
-      f1[i] = 0.f;
-      continue;
-    }
-    int sx = x - L::ex[i], sy = y - L::ey[i], sz = z - L::ez[i];
-    if (L::ex[i]) sx += sx < 0 ? d.nx : (sx >= d.nx ? -d.nx : 0);
-    if (L::ey[i]) sy += sy < 0 ? d.ny : (sy >= d.ny ? -d.ny : 0);
-    if (L::ez[i]) sz += sz < 0 ? d.nz : (sz >= d.nz ? -d.nz : 0);
-    const int64_t so = sx + rowp * sy + slab * sz;
-    f0[i] = pop_get<Q, ST>(fin, plane, 0, i, so);
-    f1[i] = pop_get<Q, ST>(fin, plane, 1, i, so);
   }
-  if (bnd) {
-    const int t = y + d.ny * z;
-    const int64_t nt = (int64_t)d.ny * d.nz;
-    complete_boundary<Q, R>(
-        d, info, f0, f1, [&](int s, int i) { return pop_get<Q, ST>(fin, plane, s, i, off); },
-        [&](int s, int i) { return d.frozen[(int64_t)(s * Q + i) * nt + t]; });
-  }
+}
+
+// pull + inlet/outlet completion.  (x, y, z) are in-domain coordinates.
+template <int Q, int ST, typename R>
+__device__ __forceinline__ void gather(const InstDev &d, gcf *__restrict__ fin, uint32_t info,
+                                       int x, int y, int z, float (&f0)[Q], float (&f1)[Q]) {
+  pull<Q, ST>(d, fin, info, x, y, z, f0, f1);
+  if (info & (kInlet | kOutlet))
+    complete<Q, ST, R>(d, fin, info, y, z, x + (int64_t)d.pitch * (y + (int64_t)d.ny * z), f0, f1);
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; renumber them so each XCD
+// works on a contiguous range of tiles and neighbouring tiles share its L2.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
+  return xcd * q8 + min(xcd, r8) + (b >> 3);
 }
 
 // ---------------------------------------------------------------------------
@@ -152,13 +165,15 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
   using V = Vec2<R>;
   __shared__ V psi[kRH][64];
 
-  const int inst = block_inst ? block_inst[blockIdx.x] : 0;
+  const int bid = xcd_block();
+  const int inst = block_inst ? block_inst[bid] : 0;
   const InstDev &d = insts[inst];
-  const int lb = blockIdx.x - d.block_base;
+  const int lb = bid - d.block_base;
   const int tx = lb % d.tiles_x, ty = lb / d.tiles_x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const float *__restrict__ fin = d.f[parity];
-  float *__restrict__ fout = d.f[parity ^ 1];
+  gcf *__restrict__ fin = G(d.f[parity]);
+  gf *__restrict__ fout = G(d.f[parity ^ 1]);
+  gcu32 *__restrict__ infop = (gcu32 *)d.info;
   const int nx = d.nx, ny = d.ny;
   const bool px = d.periodic & 1, py = d.periodic & 2;
 
@@ -171,47 +186,52 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
     else col_in = false;
   }
 
-  float f0[3][9], f1[3][9];
-  uint32_t info[4];
+  // rows owned: k = 0..2 interior (2 + wave + 4k), k = 3 halo
+  int rows[4], gy[4];
   bool valid[4];
-  // rows owned: k = 0..2 interior, k = 3 halo
+  uint32_t info[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int r = k < 3 ? 2 + wave + 4 * k : (wave < 2 ? wave : 12 + wave);
-    int gy = ty * kTileY - 2 + r;
+    rows[k] = k < 3 ? 2 + wave + 4 * k : (wave < 2 ? wave : 12 + wave);
+    int y = ty * kTileY - 2 + rows[k];
     bool in = col_in;
-    if (gy < 0 || gy >= ny) {
-      if (py) gy += gy < 0 ? ny : -ny;
+    if (y < 0 || y >= ny) {
+      if (py) y += y < 0 ? ny : -ny;
       else in = false;
     }
-    R rho1 = 0, rho2 = 0;
-    uint32_t inf = kSolid;
-    if (in) {
-      inf = d.info[gx + (int64_t)d.pitch * gy];
-      if (!(inf & kSolid)) {
-        float a[9], b[9];
-        gather<9, ST, R>(d, fin, inf, gx, gy, 0, a, b);
-        rho1 = sum_q<9, R>(a);
-        rho2 = sum_q<9, R>(b);
-        if (k < 3) {
-#pragma unroll
-          for (int i = 0; i < 9; ++i) {
-            f0[k][i] = a[i];
-            f1[k][i] = b[i];
-          }
-        }
-      }
-    }
-    info[k] = inf;
+    gy[k] = in ? y : 0;
     valid[k] = in;
-    psi[r][lane] = V{rho1, rho2};
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) info[k] = valid[k] ? infop[gx + (int64_t)d.pitch * gy[k]] : kSolid;
+
+  // Phase 1: issue every pull of this thread unconditionally (solid and
+  // out-of-domain lanes read valid addresses inside the same cache lines and
+  // discard the values), then complete and sum
+  const int gxa = col_in ? gx : (gx < 0 ? 0 : nx - 1);
+  float f0[3][9], f1[3][9], h0[9], h1[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) pull<9, ST>(d, fin, info[k], gxa, gy[k], 0, f0[k], f1[k]);
+  pull<9, ST>(d, fin, info[3], gxa, gy[3], 0, h0, h1);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    R rho1 = 0, rho2 = 0;
+    if (!(info[k] & kSolid)) {
+      float(&a)[9] = k < 3 ? f0[k < 3 ? k : 0] : h0;
+      float(&b)[9] = k < 3 ? f1[k < 3 ? k : 0] : h1;
+      if (info[k] & (kInlet | kOutlet))
+        complete<9, ST, R>(d, fin, info[k], gy[k], 0, gx + (int64_t)d.pitch * gy[k], a, b);
+      rho1 = sum_q<9, R>(a);
+      rho2 = sum_q<9, R>(b);
+    }
+    psi[rows[k]][lane] = V{rho1, rho2};
   }
   __syncthreads();
 
   // Phase 2: psi at solid nodes = chi^s * weighted mean of fluid-neighbour rho^s
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int r = k < 3 ? 2 + wave + 4 * k : (wave < 2 ? wave : 12 + wave);
+    const int r = rows[k];
     if (!valid[k] || !(info[k] & kSolid) || r < 1 || r > kRH - 2 || lane < 1 || lane > 62) continue;
     const uint32_t nb = info[k];
     if (!(nb & kLinkMask)) continue;
@@ -226,7 +246,7 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
         den += w;
       }
     }
-    const R inv = R(1) / den;
+    const R inv = rcp<R>(den);
     psi[r][lane] = V{(R)d.chi1 * s1 * inv, (R)d.chi2 * s2 * inv};
   }
   __syncthreads();
@@ -235,7 +255,7 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
   const R w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    const int r = 2 + wave + 4 * k;
+    const int r = rows[k];
     const int gy_raw = ty * kTileY - 2 + r;
     if (!valid[k] || !col_store || gy_raw >= ny || (info[k] & kSolid)) continue;
     const uint32_t inf = info[k];
@@ -263,9 +283,9 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
         sy2 = w1 * (p2.y - p4.y) + w5 * (b57 + b68);
       }
     }
-    const R G = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy;
-    const R F1x = -G * rho1 * sx2 + rho1 * gxb, F1y = -G * rho1 * sy2 + rho1 * gyb;
-    const R F2x = -G * rho2 * sx1 + rho2 * gxb, F2y = -G * rho2 * sy1 + rho2 * gyb;
+    const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy;
+    const R F1x = -G_ * rho1 * sx2 + rho1 * gxb, F1y = -G_ * rho1 * sy2 + rho1 * gyb;
+    const R F2x = -G_ * rho2 * sx1 + rho2 * gxb, F2y = -G_ * rho2 * sy1 + rho2 * gyb;
     collide_node<9, COLL, R>(d, f0[k], f1[k], rho1, rho2, F1x, F1y, R(0), F2x, F2y, R(0));
     const int64_t off = gx + (int64_t)d.pitch * gy_raw;
     pop_store<9, ST>(fout, d.plane, off, f0[k], f1[k], (float)rho1, (float)rho2);
@@ -291,14 +311,15 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
   using V = Vec2<R>;
   __shared__ V psi[kRing][kRH3][64];
 
-  const int inst = block_inst ? block_inst[blockIdx.x] : 0;
+  const int bid = xcd_block();
+  const int inst = block_inst ? block_inst[bid] : 0;
   const InstDev &d = insts[inst];
-  const int lb = blockIdx.x - d.block_base;
+  const int lb = bid - d.block_base;
   const int tx = lb % d.tiles_x, ty = (lb / d.tiles_x) % d.tiles_y;
   const int zc = lb / (d.tiles_x * d.tiles_y);  // z chunk
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const float *__restrict__ fin = d.f[parity];
-  float *__restrict__ fout = d.f[parity ^ 1];
+  gcf *__restrict__ fin = G(d.f[parity]);
+  gf *__restrict__ fout = G(d.f[parity ^ 1]);
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const bool px = d.periodic & 1, py = d.periodic & 2, pz = d.periodic & 4;
   const int zlen = (nz + d.tiles_z - 1) / d.tiles_z;
@@ -461,7 +482,7 @@ template <int Q, int ST>
 __global__ void init_kernel(const InstDev *__restrict__ insts, const float *__restrict__ rho0, int parity) {
   const InstDev &d = insts[0];
   const int64_t n_nodes = (int64_t)d.nx * d.ny * d.nz;
-  float *b = d.f[parity];
+  gf *b = G(d.f[parity]);
   for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < n_nodes;
        n += (int64_t)gridDim.x * blockDim.x) {
     const int x = n % d.nx;
@@ -500,7 +521,7 @@ template <int Q, int ST>
 __global__ __launch_bounds__(256) void obs_kernel(const InstDev *__restrict__ insts, int parity,
                                                   double *__restrict__ partials) {
   const InstDev &d = insts[0];
-  const float *fin = d.f[parity];
+  gcf *fin = G(d.f[parity]);
   const int64_t n_nodes = (int64_t)d.nx * d.ny * d.nz;
   double acc[kObsFields - 1] = {0};
   int flags = 0;
@@ -575,7 +596,7 @@ __global__ void obs_final(const double *__restrict__ partials, int n_blocks, dou
 template <int Q, int ST>
 __global__ void density_kernel(const InstDev *__restrict__ insts, int parity, float *__restrict__ dst) {
   const InstDev &d = insts[0];
-  const float *fin = d.f[parity];
+  gcf *fin = G(d.f[parity]);
   const int64_t n_nodes = (int64_t)d.nx * d.ny * d.nz;
   for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < n_nodes;
        n += (int64_t)gridDim.x * blockDim.x) {
