@@ -86,6 +86,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=100, help="steps per captured graph")
     ap.add_argument("--storage", type=int, default=0, help="0 FP32, 1 BF16 deviations")
     ap.add_argument("--math", type=int, default=0, help="node arithmetic: 0 FP64, 1 FP32")
+    ap.add_argument("--strategy", type=int, default=0, help="0 auto, 1 fused, 2 split")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--eager", action="store_true", help="plain launches instead of graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-samples", type=int, default=300)
@@ -102,8 +104,13 @@ def main():
     problem = workload(args.workload)
     print(f"[bench] workload {args.workload}: {problem.nx}x{problem.ny}x{problem.nz}, "
           f"fluid {problem.n_fluid}, collision {problem.collision}", file=sys.stderr, flush=True)
-    solver = lbm.Solver(problem, storage=args.storage, device=dev, math=args.math)
+    solver = lbm.Solver(problem, storage=args.storage, device=dev, math=args.math,
+                        strategy=args.strategy)
     stream = solver.stream
+    tune = None
+    if not args.no_autotune and args.strategy == 0:
+        tune = solver.autotune(10)
+        print("[bench] autotune:\n" + tune, file=sys.stderr, flush=True)
     chunk = max(2, args.chunk - args.chunk % 2)
     steps = max(chunk, args.steps - args.steps % chunk)
 
@@ -165,7 +172,8 @@ def main():
                    "storage": "f32" if args.storage == 0 else "bf16-dev",
                    "launch": "eager" if args.eager else f"hipGraph x{chunk}",
                    "mflups_fluid": round(problem.n_fluid * steps / wall / 1e6, 1),
-                   "mass_after": obs["mass"], "grid_blocks": grid, "block_threads": block},
+                   "mass_after": obs["mass"], "grid_blocks": grid, "block_threads": block,
+                   "autotune": tune.strip().splitlines() if tune else None},
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:

@@ -48,6 +48,7 @@ typedef enum {
 enum { LBM_SRT = 0, LBM_MRT = 1, LBM_TRT = 2 };            /* lbm_params.collision */
 enum { LBM_STORE_F32 = 0, LBM_STORE_BF16DEV = 1 };          /* lbm_params.storage */
 enum { LBM_MATH_F64 = 0, LBM_MATH_F32 = 1 };                /* lbm_params.math */
+enum { LBM_AUTO = 0, LBM_FUSED = 1, LBM_SPLIT = 2 };        /* lbm_params.strategy */
 
 /* Problem geometry (Sec. 2.3 and Sec. 4.2: a solid map phi, periodic or
  * open axes, the inlet at x = 0 and the outlet at x = nx - 1). */
@@ -79,6 +80,10 @@ typedef struct {
   double s_e, s_eps;      /* MRT energy-mode rates; <= 0: equal to s_nu */
   int32_t storage;        /* LBM_STORE_F32 or LBM_STORE_BF16DEV: how f* is held */
   int32_t math;           /* node arithmetic: LBM_MATH_F64 (default) or LBM_MATH_F32 */
+  int32_t strategy;       /* LBM_AUTO, LBM_FUSED (one launch per step, halo
+                             densities recomputed per block) or LBM_SPLIT
+                             (density, solid-density and collide launches) */
+  int32_t tile_rows;      /* fused D2Q9 tile height: 8, 12 or 16 (0 = 12) */
 } lbm_params;
 
 /* Observables at the current time (Eq. 14 pressure, Sec. 4.2 saturation).
@@ -150,10 +155,17 @@ lbm_status lbm_destroy(lbm_ctx *ctx);
  * when ctx is NULL).  Never NULL. */
 const char *lbm_last_error(const lbm_ctx *ctx);
 
-/* Name, grid size (blocks) and block size of the fused step kernel the
- * context launches; for profiling. */
+/* Name, grid size (blocks) and block size of the step kernel the context
+ * launches (the collide kernel for the split strategy); for profiling. */
 lbm_status lbm_kernel_info(const lbm_ctx *ctx, char *name, size_t name_len,
                            int64_t *grid_blocks, int32_t *block_threads);
+
+/* Time every step variant that can run this context (fused with each tile
+ * height, split) for `steps` steps each (even, >= 2) with HIP events and keep
+ * the fastest.  The timed steps are ordinary steps: the state advances by
+ * (number of variants) x steps.  report (optional) receives one line per
+ * variant with its milliseconds per step.  Synchronises the stream. */
+lbm_status lbm_autotune(lbm_ctx *ctx, int64_t steps, char *report, size_t report_len);
 
 /* ---- batches: many instances of uneven size advanced together ----------
  * One launch per step covers every instance through a flat table of

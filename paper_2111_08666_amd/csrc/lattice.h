@@ -167,41 +167,52 @@ template <int Q, int COLL, typename R>
 __device__ __forceinline__ void collide_component(float (&fo)[Q], R rho, R ux, R uy, R uz, R Fx,
                                                   R Fy, R Fz, const Rates<R> &r) {
   using L = Lat<Q>;
-  R f[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) f[i] = (R)fo[i];
   const R usq15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
   const R uF = ux * Fx + uy * Fy + uz * Fz;
   if constexpr (COLL == 0) {
     const R om = r.s_nu, fac = R(1) - R(0.5) * om;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
+      const R fi = (R)fo[i];
       const R eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
       const R eF = L::ex[i] * Fx + L::ey[i] * Fy + L::ez[i] * Fz;
       const R w = (R)L::w[i];
       const R feq = w * rho * (R(1) + R(3) * eu + R(4.5) * eu * eu - usq15);
       const R S = w * (R(3) * (eF - uF) + R(9) * eu * eF);
-      fo[i] = (float)(f[i] + (om * (feq - f[i]) + fac * S));
+      fo[i] = (float)(fi + (om * (feq - fi) + fac * S));
     }
   } else if constexpr (COLL == 2) {
     const R sp = r.s_nu, sm = r.s_q;
     const R fp = R(1) - R(0.5) * sp, fm = R(1) - R(0.5) * sm;
+    {  // rest population: symmetric part only
+      const R f0 = (R)fo[0];
+      const R w = (R)L::w[0];
+      fo[0] = (float)(f0 + (sp * (w * rho * (R(1) - usq15) - f0) - fp * w * R(3) * uF));
+    }
+    // opposite pairs (i, b): the pair's symmetric and antisymmetric parts
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 1; i < Q; ++i) {
       const int b = L::opp[i];
+      if (b < i) continue;
+      const R fi = (R)fo[i], fb = (R)fo[b];
       const R eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
       const R eF = L::ex[i] * Fx + L::ey[i] * Fy + L::ez[i] * Fz;
       const R w = (R)L::w[i];
-      // symmetric / antisymmetric parts of feq and S
       const R eq_p = w * rho * (R(1) + R(4.5) * eu * eu - usq15);
       const R eq_m = w * rho * R(3) * eu;
       const R S_p = w * (R(9) * eu * eF - R(3) * uF);
       const R S_m = w * R(3) * eF;
-      const R f_p = R(0.5) * (f[i] + f[b]), f_m = R(0.5) * (f[i] - f[b]);
-      fo[i] = (float)(f[i] + (sp * (eq_p - f_p) + sm * (eq_m - f_m) + fp * S_p + fm * S_m));
+      const R f_p = R(0.5) * (fi + fb), f_m = R(0.5) * (fi - fb);
+      const R dp = sp * (eq_p - f_p) + fp * S_p;  // change of the symmetric part
+      const R dm = sm * (eq_m - f_m) + fm * S_m;  // change of the antisymmetric part
+      fo[i] = (float)(fi + (dp + dm));
+      fo[b] = (float)(fb + (dp - dm));
     }
   } else {
     static_assert(Q == 9, "MRT is D2Q9 only");
+    R f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = (R)fo[i];
     // non-conserved moments (Lallemand-Luo rows e, eps, jx, qx, jy, qy, pxx, pxy)
     const R a = f[1] + f[2] + f[3] + f[4];
     const R dg = f[5] + f[6] + f[7] + f[8];
@@ -279,9 +290,8 @@ __device__ __forceinline__ void collide_node(const InstDev &d, float (&f0)[Q], f
 // ---------------------------------------------------------------------------
 // BF16 deviation storage: per component and node the density rho (FP32) and
 // d_i = f*_i - w_i rho for i >= 1 (BF16, round to nearest even).  The rest
-// population is implicit, f*_0 = w_0 rho - sum_i d_i, so the stored state
+// population is implicit, f*_0 = rho - sum_i f*_i, so the stored state
 // holds each node's mass exactly.
-// Buffer layout: [rho planes: 2 x plane floats][d planes: 2 x (Q-1) x plane bf16]
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ uint16_t f32_to_bf16(float v) {
   uint32_t u = __float_as_uint(v);

@@ -38,35 +38,45 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 struct Layout {
   int32_t pitch;
-  int64_t plane, n_nodes;
-  size_t buf_bytes, info_bytes, frozen_bytes;
+  int64_t ystride, zstride, n_nodes;
+  size_t buf_bytes, info_bytes, frozen_bytes, psi_bytes;
+};
+
+// Fused-kernel tiling of one instance for a tile height (D2Q9) / fixed 3D tile.
+struct Tiling {
   int32_t tiles_x, tiles_y, tiles_z;
   int64_t blocks;
 };
+
+Tiling make_tiling(int q, int nx, int ny, int nz, int ty) {
+  Tiling t{};
+  t.tiles_x = (nx + kTileX - 1) / kTileX;
+  if (q == 9) {
+    t.tiles_y = (ny + ty - 1) / ty;
+    t.tiles_z = 1;
+  } else {
+    t.tiles_y = (ny + kTileY3 - 1) / kTileY3;
+    const int64_t xy = (int64_t)t.tiles_x * t.tiles_y;
+    int64_t tz = (4096 + xy - 1) / xy;                  // aim at >= 4096 blocks
+    tz = std::min<int64_t>(tz, std::max(1, nz / 24));  // keep z chunks >= ~24 planes
+    t.tiles_z = (int32_t)std::max<int64_t>(1, tz);
+  }
+  t.blocks = (int64_t)t.tiles_x * t.tiles_y * t.tiles_z;
+  return t;
+}
 
 Layout make_layout(const lbm_geometry &g, const lbm_params &p) {
   Layout L{};
   L.pitch = (int32_t)round_up(g.nx, 64);
   L.n_nodes = (int64_t)g.nx * g.ny * g.nz;
-  L.plane = round_up((int64_t)L.pitch * g.ny * g.nz, 64);
-  if (p.storage == LBM_STORE_F32)
-    L.buf_bytes = align_up((size_t)2 * g.q * L.plane * sizeof(float));
-  else
-    L.buf_bytes = align_up((size_t)2 * L.plane * sizeof(float) + (size_t)2 * (g.q - 1) * L.plane * 2);
-  L.info_bytes = align_up((size_t)L.plane * sizeof(uint32_t));
+  // row block per (y, z): FP32 2Q populations; BF16 2 densities + 2(Q-1) bf16 deviations
+  L.ystride = (int64_t)(p.storage == LBM_STORE_F32 ? 2 * g.q : g.q + 1) * L.pitch;
+  L.zstride = L.ystride * g.ny;
+  L.buf_bytes = align_up((size_t)L.zstride * g.nz * sizeof(float));
+  L.info_bytes = align_up((size_t)L.pitch * g.ny * g.nz * sizeof(uint32_t));
   L.frozen_bytes = align_up((size_t)2 * g.q * g.ny * g.nz * sizeof(float));
-  L.tiles_x = (int32_t)((g.nx + kTileX - 1) / kTileX);
-  if (g.q == 9) {
-    L.tiles_y = (int32_t)((g.ny + kTileY - 1) / kTileY);
-    L.tiles_z = 1;
-  } else {
-    L.tiles_y = (int32_t)((g.ny + kTileY3 - 1) / kTileY3);
-    const int64_t xy = (int64_t)L.tiles_x * L.tiles_y;
-    int64_t tz = (4096 + xy - 1) / xy;           // aim at >= 4096 blocks
-    tz = std::min<int64_t>(tz, std::max(1, g.nz / 24));  // keep z chunks >= ~24 planes
-    L.tiles_z = (int32_t)std::max<int64_t>(1, tz);
-  }
-  L.blocks = (int64_t)L.tiles_x * L.tiles_y * L.tiles_z;
+  L.psi_bytes = align_up((size_t)L.pitch * g.ny * g.nz * 2 * sizeof(double));
+  (void)p;
   return L;
 }
 
@@ -93,6 +103,9 @@ bool validate(const lbm_geometry *g, const lbm_params *p, const double *rho0, st
   if (p->bc_set < 1 || p->bc_set > 3) return bad(err, "bc_set must be 1, 2 or 3");
   if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_BF16DEV) return bad(err, "unknown storage");
   if (p->math != LBM_MATH_F64 && p->math != LBM_MATH_F32) return bad(err, "unknown math precision");
+  if (p->strategy < LBM_AUTO || p->strategy > LBM_SPLIT) return bad(err, "unknown strategy");
+  if (p->tile_rows != 0 && p->tile_rows != 8 && p->tile_rows != 12 && p->tile_rows != 16)
+    return bad(err, "tile_rows must be 0, 8, 12 or 16");
   const double vals[] = {p->rho_in1, p->rho_out2, p->rho_in2, p->rho_out1, p->g[0], p->g[1], p->g[2]};
   for (double v : vals)
     if (!std::isfinite(v)) return bad(err, "boundary densities and g must be finite");
@@ -126,7 +139,7 @@ bool validate(const lbm_geometry *g, const lbm_params *p, const double *rho0, st
 
 // Node info words in the pitched layout.
 void build_info(const lbm_geometry &g, const Layout &L, std::vector<uint32_t> &info) {
-  info.assign((size_t)L.plane, kSolid);
+  info.assign((size_t)L.pitch * g.ny * g.nz, kSolid);
   const int q = g.q;
   const bool perx = g.periodic & 1, pery = g.periodic & 2, perz = g.periodic & 4;
   const int x0 = g.porous_x0, x1 = g.porous_x1 > 0 ? g.porous_x1 : g.nx;
@@ -182,10 +195,12 @@ void build_info(const lbm_geometry &g, const Layout &L, std::vector<uint32_t> &i
 // ---------------------------------------------------------------------------
 struct lbm_batch {
   int32_t k = 0, q = 9, storage = 0, collision = 0, math = 0;
+  int32_t strategy = LBM_FUSED, ty = 12;
   std::vector<InstDev> h;
   std::vector<Layout> lay;
   InstDev *d_insts = nullptr;
   int32_t *d_block_inst = nullptr;
+  int64_t table_cap = 0;
   int64_t n_blocks = 0;
   double *partials = nullptr;
   double *result = nullptr;
@@ -227,8 +242,8 @@ size_t batch_bytes(int32_t k, const lbm_geometry *g, const lbm_params *p, int64_
   int ob = 1;
   for (int i = 0; i < k; ++i) {
     const Layout L = make_layout(g[i], p[i]);
-    nb += L.blocks;
-    bytes += L.info_bytes + L.frozen_bytes + 2 * L.buf_bytes;
+    nb += make_tiling(g[i].q, g[i].nx, g[i].ny, g[i].nz, 8).blocks;
+    bytes += L.info_bytes + L.frozen_bytes + L.psi_bytes + 2 * L.buf_bytes;
     InstDev tmp{};
     tmp.nx = g[i].nx; tmp.ny = g[i].ny; tmp.nz = g[i].nz;
     ob = std::max(ob, obs_blocks(tmp));
@@ -239,6 +254,43 @@ size_t batch_bytes(int32_t k, const lbm_geometry *g, const lbm_params *p, int64_
   if (n_blocks_out) *n_blocks_out = nb;
   if (obs_blocks_out) *obs_blocks_out = ob;
   return bytes;
+}
+
+// Tilings, block table and descriptors for a step variant; synchronises.
+lbm_status apply_plan(lbm_batch *b, int strategy, int ty) {
+  std::vector<int32_t> table;
+  int64_t base = 0;
+  for (int i = 0; i < b->k; ++i) {
+    InstDev &h = b->h[(size_t)i];
+    const Tiling t = make_tiling(b->q, h.nx, h.ny, h.nz, ty);
+    h.tiles_x = t.tiles_x; h.tiles_y = t.tiles_y; h.tiles_z = t.tiles_z;
+    h.block_base = (int32_t)base;
+    for (int64_t j = 0; j < t.blocks; ++j) table.push_back(i);
+    base += t.blocks;
+  }
+  if (base > b->table_cap) return fail(b, LBM_EINVAL, "block table capacity exceeded");
+  b->strategy = strategy;
+  b->ty = ty;
+  b->n_blocks = base;
+  HIPCHK(b, hipMemcpyAsync(b->d_block_inst, table.data(), sizeof(int32_t) * table.size(),
+                           hipMemcpyHostToDevice, b->stream));
+  HIPCHK(b, hipMemcpyAsync(b->d_insts, b->h.data(), sizeof(InstDev) * b->h.size(), hipMemcpyHostToDevice,
+                           b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  return LBM_OK;
+}
+
+StepLaunch step_launch(const lbm_batch *b, int parity) {
+  StepLaunch L;
+  L.d_insts = b->d_insts;
+  L.h = b->h.data();
+  L.block_inst = b->k > 1 ? b->d_block_inst : nullptr;
+  L.n_blocks = b->n_blocks;
+  L.k = b->k; L.q = b->q; L.collision = b->collision; L.storage = b->storage; L.math = b->math;
+  L.strategy = b->strategy; L.ty = b->ty; L.parity = parity;
+  return L;
 }
 
 lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
@@ -281,24 +333,23 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
   b->partials = reinterpret_cast<double *>(take(sizeof(double) * kObsFields * (size_t)ob));
   b->result = reinterpret_cast<double *>(take(sizeof(double) * kObsFields * (size_t)k));
 
-  std::vector<int32_t> table((size_t)nb);
-  int64_t base = 0;
+  b->table_cap = nb;
   std::vector<uint32_t> info;
   for (int i = 0; i < k; ++i) {
     const Layout L = make_layout(g[i], p[i]);
     InstDev h{};
     h.info = reinterpret_cast<const uint32_t *>(take(L.info_bytes));
     h.frozen = reinterpret_cast<const float *>(take(L.frozen_bytes));
+    h.psi = reinterpret_cast<double *>(take(L.psi_bytes));
     h.f[0] = reinterpret_cast<float *>(take(L.buf_bytes));
     h.f[1] = reinterpret_cast<float *>(take(L.buf_bytes));
-    h.plane = L.plane;
+    h.ystride = L.ystride;
+    h.zstride = L.zstride;
     h.nx = g[i].nx; h.ny = g[i].ny; h.nz = g[i].nz; h.pitch = L.pitch;
     h.periodic = (int32_t)g[i].periodic; h.open_x = g[i].open_x;
     h.bc_set = p[i].bc_set; h.collision = p[i].collision;
     h.half_shift = p[i].half_force_shift; h.sj_mode = p[i].mrt_sj_mode;
     h.storage = p[i].storage; h.q = g[i].q;
-    h.tiles_x = L.tiles_x; h.tiles_y = L.tiles_y; h.tiles_z = L.tiles_z;
-    h.block_base = (int32_t)base;
     h.tau1 = p[i].tau[0]; h.tau2 = p[i].tau[1];
     h.G = p[i].G;
     h.chi1 = 1.0 + p[i].xi; h.chi2 = 1.0 - p[i].xi;
@@ -306,8 +357,6 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
     h.rho_in1 = p[i].rho_in1; h.rho_out2 = p[i].rho_out2;
     h.rho_in2 = p[i].rho_in2; h.rho_out1 = p[i].rho_out1;
     h.lambda = p[i].lambda; h.s_e = p[i].s_e; h.s_eps = p[i].s_eps;
-    for (int64_t t = 0; t < L.blocks; ++t) table[(size_t)(base + t)] = i;
-    base += L.blocks;
     b->h.push_back(h);
     b->lay.push_back(L);
 
@@ -336,9 +385,13 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
     HIPCHK(b, launch_init(b->d_insts + i, h, h.f[1], 0, b->stream));
     HIPCHK(b, hipStreamSynchronize(b->stream));  // host staging vectors die here
   }
-  HIPCHK(b, hipMemcpyAsync(b->d_block_inst, table.data(), sizeof(int32_t) * table.size(),
-                           hipMemcpyHostToDevice, b->stream));
-  HIPCHK(b, hipStreamSynchronize(b->stream));
+  // default plan: the split step for D3Q19 (its per-block working set does
+  // not fit the L2), the fused step otherwise
+  int strategy = p[0].strategy;
+  if (strategy == LBM_AUTO) strategy = b->q == 19 ? LBM_SPLIT : LBM_FUSED;
+  if (strategy == LBM_SPLIT && (b->collision == LBM_MRT && b->q != 9)) strategy = LBM_FUSED;
+  const lbm_status ps = apply_plan(b, strategy, p[0].tile_rows ? p[0].tile_rows : 12);
+  if (ps != LBM_OK) { delete b; return ps; }
   *out = b;
   return LBM_OK;
 }
@@ -347,9 +400,8 @@ lbm_status batch_step(lbm_batch *b, int64_t n) {
   if (!b) return fail(nullptr, LBM_EINVAL, "NULL handle");
   if (n < 0) return fail(b, LBM_EINVAL, "n must be >= 0");
   if (b->unstable) return fail(b, LBM_EUNSTABLE, "state is unstable (non-finite or negative density)");
-  const int32_t *table = b->k > 1 ? b->d_block_inst : nullptr;
   for (int64_t s = 0; s < n; ++s) {
-    HIPCHK(b, launch_step(b->d_insts, table, b->n_blocks, b->q, b->collision, b->storage, b->math, b->parity, b->stream));
+    HIPCHK(b, launch_step(step_launch(b, b->parity), b->stream));
     b->parity ^= 1;
     b->step++;
   }
@@ -365,10 +417,9 @@ lbm_status batch_step_graph(lbm_batch *b, int64_t n, int64_t reps) {
     if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
     HIPCHK(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    const int32_t *table = b->k > 1 ? b->d_block_inst : nullptr;
     int par = b->parity;
     for (int64_t s = 0; s < n; ++s) {
-      hipError_t e = launch_step(b->d_insts, table, b->n_blocks, b->q, b->collision, b->storage, b->math, par, b->stream);
+      hipError_t e = launch_step(step_launch(b, par), b->stream);
       if (e != hipSuccess) {
         hipGraph_t tmp;
         (void)hipStreamEndCapture(b->stream, &tmp);
@@ -577,9 +628,62 @@ lbm_status lbm_kernel_info(const lbm_ctx *ctx, char *name, size_t name_len, int6
                            int32_t *block_threads) {
   if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL handle");
   const lbm_batch *b = ctx->b;
-  if (name && name_len) std::snprintf(name, name_len, "%s", step_kernel_name(b->q, b->collision, b->storage, b->math));
-  if (grid_blocks) *grid_blocks = b->n_blocks;
+  if (name && name_len)
+    std::snprintf(name, name_len, "%s", step_kernel_name(b->q, b->collision, b->storage, b->math, b->strategy, b->ty));
+  if (grid_blocks) {
+    if (b->strategy == LBM_SPLIT) {
+      const InstDev &h = b->h[0];
+      *grid_blocks = ((int64_t)((h.nx + 63) / 64) * h.ny * h.nz + 3) / 4;
+    } else {
+      *grid_blocks = b->n_blocks;
+    }
+  }
   if (block_threads) *block_threads = 256;
+  return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_ctx *ctx, int64_t steps, char *report, size_t report_len) {
+  if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL handle");
+  lbm_batch *b = ctx->b;
+  if (steps < 2 || (steps & 1)) return fail(b, LBM_EINVAL, "steps must be even and >= 2");
+  struct Cand { int strategy, ty; };
+  std::vector<Cand> cands;
+  if (b->q == 9) {
+    for (int ty : {8, 12, 16}) cands.push_back({LBM_FUSED, ty});
+  } else {
+    cands.push_back({LBM_FUSED, 12});
+  }
+  if (!(b->collision == LBM_MRT && b->q != 9)) cands.push_back({LBM_SPLIT, 12});
+  hipEvent_t e0, e1;
+  HIPCHK(b, hipEventCreate(&e0));
+  HIPCHK(b, hipEventCreate(&e1));
+  std::string rep;
+  float best = 1e30f;
+  Cand bestc = cands[0];
+  for (const Cand &c : cands) {
+    lbm_status st = apply_plan(b, c.strategy, c.ty);
+    if (st != LBM_OK) return st;
+    st = batch_step(b, 2);  // warm-up
+    if (st != LBM_OK) return st;
+    HIPCHK(b, hipEventRecord(e0, b->stream));
+    st = batch_step(b, steps);
+    if (st != LBM_OK) return st;
+    HIPCHK(b, hipEventRecord(e1, b->stream));
+    HIPCHK(b, hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(b, hipEventElapsedTime(&ms, e0, e1));
+    ms /= (float)steps;
+    char line[128];
+    std::snprintf(line, sizeof line, "%s %.5f ms/step\n",
+                  step_kernel_name(b->q, b->collision, b->storage, b->math, c.strategy, c.ty), ms);
+    rep += line;
+    if (ms < best) { best = ms; bestc = c; }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  lbm_status st = apply_plan(b, bestc.strategy, bestc.ty);
+  if (st != LBM_OK) return st;
+  if (report && report_len) std::snprintf(report, report_len, "%s", rep.c_str());
   return LBM_OK;
 }
 

@@ -16,19 +16,19 @@ constexpr uint32_t kWindow = 1u << 28;  // inside the saturation window
 constexpr uint32_t kLinkMask = (1u << 19) - 1u;
 
 // 2D step tile: 64 lanes cover 60 interior columns plus 2 halo columns on
-// each side; TY interior rows plus 2 halo rows above and below.
+// each side; TY interior rows (8, 12 or 16) plus 2 halo rows above and below.
 constexpr int kTileX = 60;
-constexpr int kTileY = 12;
 // 3D step tile: the same 64-lane rows, TY3 interior rows in y, marching in z.
-constexpr int kTileY3 = 4;
+constexpr int kTileY3 = 8;
 
 // Device-side description of one instance (array in device memory).
 struct InstDev {
   float *f[2];            // ping-pong post-collision state (layout by storage)
-  const uint32_t *info;   // node info words, pitched like one population plane
+  const uint32_t *info;   // node info words, index x + pitch * (y + ny * z)
   const float *frozen;    // [2][Q][ny*nz]: component-1 outlet / component-2 inlet links
-  int64_t plane;          // elements between consecutive population planes
-  int32_t nx, ny, nz, pitch;  // pitch = row stride in elements
+  double *psi;            // split step: [nz][ny][pitch] x (rho1, rho2) / virtual solid density
+  int64_t ystride, zstride;  // f buffers: row blocks of (y, z) at y * ystride + z * zstride
+  int32_t nx, ny, nz, pitch;  // pitch = padded row length (a multiple of 64)
   int32_t periodic, open_x, bc_set, collision;
   int32_t half_shift, sj_mode, storage, q;
   int32_t tiles_x, tiles_y, tiles_z, block_base;
@@ -43,13 +43,21 @@ constexpr int kObsFields = 12;  // mass0 mass1 nfluid nwin swcount sumrw sumr pi
 // Launchers (defined in the .hip sources).
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, const float *rho0_dev,
                        int parity, hipStream_t s);
-hipError_t launch_step(const InstDev *d_insts, const int32_t *block_inst, int64_t n_blocks,
-                       int q, int collision, int storage, int math, int parity, hipStream_t s);
+// One step of every instance of a batch.  strategy 1: fused kernel (one
+// launch over a flat block table); 2: split step (three launches per instance).
+struct StepLaunch {
+  const InstDev *d_insts;
+  const InstDev *h;            // host copies (grid sizes of the split kernels)
+  const int32_t *block_inst;   // fused: block -> instance table (NULL for one instance)
+  int64_t n_blocks;
+  int k, q, collision, storage, math, strategy, ty, parity;
+};
+hipError_t launch_step(const StepLaunch &L, hipStream_t s);
 hipError_t launch_observables(const InstDev *d_inst, const InstDev &h_inst, int parity,
                               double *partials, int n_blocks, double *result, hipStream_t s);
 hipError_t launch_density(const InstDev *d_inst, const InstDev &h_inst, int parity,
                           float *dst, hipStream_t s);
-const char *step_kernel_name(int q, int collision, int storage, int math);
+const char *step_kernel_name(int q, int collision, int storage, int math, int strategy, int ty);
 int obs_blocks(const InstDev &h_inst);
 
 }  // namespace lbm

@@ -1,9 +1,11 @@
 // HIP kernels for gfx950: the fused two-component step (D2Q9 and D3Q19),
 // initialisation, observables and density extraction.
 //
-// State between steps: the post-collision populations f*^s_i(x) in a
-// structure-of-arrays layout, plane (s, i) holding one value per node with x
-// fastest (row pitch a multiple of 64 elements), two buffers in ping-pong.
+// State between steps: the post-collision populations f*^s_i(x), two buffers
+// in ping-pong, in a row-interleaved structure of arrays: for each (z, y) row a
+// block holding, population after population, one value per x (row pitch a
+// multiple of 64).  Accesses stay coalesced along x and the pulls of a wave
+// touch a few contiguous row blocks instead of 2Q planes far apart.
 // One step pulls f(x) = f*(x - e_i) (bounce-back from solid sources), completes
 // the inlet/outlet links, forms the densities, the solid pseudopotential,
 // the interaction force and the collision, and writes f* to the other buffer.
@@ -35,108 +37,165 @@ __device__ __forceinline__ gcf *G(const float *p) { return (gcf *)p; }
 __device__ __forceinline__ gf *G(float *p) { return (gf *)p; }
 
 // ---------------------------------------------------------------------------
-// population access by storage kind
-// FP32:  buffer = [s][i][plane] floats
-// BF16:  buffer = [s][plane] float densities, then [s][i-1][plane] bf16
-//        deviations d_i = f*_i - w_i rho (i >= 1); f*_0 = w_0 rho - sum d_i.
+// population access by storage kind; a node is addressed by its row block
+// offset `row` (y * ystride + z * zstride, in floats) and its x
+// FP32:  row block = [s][i][pitch] floats
+// BF16:  row block = [s][pitch] float densities, then [s][i-1][pitch] bf16
+//        deviations d_i = f*_i - w_i rho (i >= 1); f*_0 = rho - sum_i f*_i.
 // ---------------------------------------------------------------------------
+template <int Q>
+__device__ __forceinline__ float bf16_pop(gcf *__restrict__ b, int pitch, int s, int i, int64_t row, int x,
+                                          float r) {
+  gcu16 *dv = (gcu16 *)b;
+  const int64_t k = 2 * row + (int64_t)(4 + s * (Q - 1) + i - 1) * pitch + x;
+  return __builtin_fmaf((float)Lat<Q>::w[i], r, bf16_to_f32(dv[k]));
+}
+
 template <int Q, int ST>
-__device__ __forceinline__ float pop_get(gcf *__restrict__ b, int64_t plane, int s, int i, int64_t off) {
+__device__ __forceinline__ float pop_get(gcf *__restrict__ b, int pitch, int s, int i, int64_t row, int x) {
   if constexpr (ST == 0) {
-    return b[(int64_t)(s * Q + i) * plane + off];
+    return b[row + (int64_t)(s * Q + i) * pitch + x];
   } else {
-    const float r = b[(int64_t)s * plane + off];
-    gcu16 *dv = (gcu16 *)(b + 2 * plane);
+    const float r = b[row + (int64_t)s * pitch + x];
     if (i == 0) {
+      // the rest population closes the node's mass: rho - sum of the others,
+      // reconstructed exactly as a pull elsewhere reconstructs them
       float sum = 0.f;
 #pragma unroll
-      for (int j = 1; j < Q; ++j) sum += bf16_to_f32(dv[(int64_t)(s * (Q - 1) + j - 1) * plane + off]);
-      return (float)Lat<Q>::w[0] * r - sum;
+      for (int j = 1; j < Q; ++j) sum += bf16_pop<Q>(b, pitch, s, j, row, x, r);
+      return r - sum;
     }
-    return (float)Lat<Q>::w[i] * r + bf16_to_f32(dv[(int64_t)(s * (Q - 1) + i - 1) * plane + off]);
+    return bf16_pop<Q>(b, pitch, s, i, row, x, r);
   }
 }
 
 // Store both components' post-collision populations of one node.
 template <int Q, int ST>
-__device__ __forceinline__ void pop_store(gf *__restrict__ b, int64_t plane, int64_t off,
+__device__ __forceinline__ void pop_store(gf *__restrict__ b, int pitch, int64_t row, int x,
                                           const float (&f0)[Q], const float (&f1)[Q], float rho1,
                                           float rho2) {
   if constexpr (ST == 0) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      b[(int64_t)i * plane + off] = f0[i];
-      b[(int64_t)(Q + i) * plane + off] = f1[i];
+      b[row + (int64_t)i * pitch + x] = f0[i];
+      b[row + (int64_t)(Q + i) * pitch + x] = f1[i];
     }
   } else {
     // collision conserves each component's node mass, so rho is stored as is
-    b[off] = rho1;
-    b[plane + off] = rho2;
-    gu16 *dv = (gu16 *)(b + 2 * plane);
+    b[row + x] = rho1;
+    b[row + pitch + x] = rho2;
+    gu16 *dv = (gu16 *)b;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const float w = (float)Lat<Q>::w[i];
-      dv[(int64_t)(i - 1) * plane + off] = f32_to_bf16(f0[i] - w * rho1);
-      dv[(int64_t)(Q - 1 + i - 1) * plane + off] = f32_to_bf16(f1[i] - w * rho2);
+      dv[2 * row + (int64_t)(4 + i - 1) * pitch + x] = f32_to_bf16(f0[i] - w * rho1);
+      dv[2 * row + (int64_t)(4 + Q - 1 + i - 1) * pitch + x] = f32_to_bf16(f1[i] - w * rho2);
     }
   }
 }
 
 // Inlet/outlet completion of one pulled node (links already pulled).
 template <int Q, int ST, typename R>
-__device__ __forceinline__ void complete(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int y,
-                                         int z, int64_t off, float (&f0)[Q], float (&f1)[Q]) {
+__device__ __forceinline__ void complete(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int x,
+                                         int y, int z, float (&f0)[Q], float (&f1)[Q]) {
   const int t = y + d.ny * z;
   const int64_t nt = (int64_t)d.ny * d.nz;
+  const int64_t row = y * d.ystride + z * d.zstride;
   gcf *frz = G(d.frozen);
   complete_boundary<Q, R>(
-      d, info, f0, f1, [&](int s, int i) { return pop_get<Q, ST>(fin, d.plane, s, i, off); },
+      d, info, f0, f1, [&](int s, int i) { return pop_get<Q, ST>(fin, d.pitch, s, i, row, x); },
       [&](int s, int i) { return frz[(int64_t)(s * Q + i) * nt + t]; });
 }
 
 // ---------------------------------------------------------------------------
-// Pull one fluid node's populations for both components: f_i(x) = f*_i(x-e_i),
-// or this node's f*_opp(i) where x - e_i is solid.  Every address is valid:
-// sources wrap periodically, and a wrapped source across an open face is a
-// missing link whose value complete() overwrites.
+// Streaming.  f_i(x) = f*_i(x - e_i), or f*_opp(i)(x) where x - e_i is solid.
+// FP32 storage keeps the bounce-back values in ghost slots: when fluid node x
+// stores its post-collision state, it also writes f*_opp(i)(x) into link i's
+// slot of each solid source node x - e_i.  A slot (i, s) of a solid node s has
+// exactly one writer (x = s + e_i), so every pull is the uniform
+// f_i(x) = buf[i][x - e_i].  BF16 storage reads the node's own opposite slot.
+// Sources wrap periodically; a wrapped source across an open face is a
+// missing link whose value the inlet/outlet completion overwrites.
 // ---------------------------------------------------------------------------
-template <int Q, int ST>
-__device__ __forceinline__ void pull(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int x, int y,
-                                     int z, float (&f0)[Q], float (&f1)[Q]) {
-  using L = Lat<Q>;
-  const int64_t plane = d.plane;
-  const int64_t rowp = d.pitch;
-  const int64_t slab = (int64_t)d.pitch * d.ny;
-  const int64_t off = x + rowp * y + slab * z;
-  const int xm = x == 0 ? d.nx - 1 : x - 1, xp = x == d.nx - 1 ? 0 : x + 1;
+
+// Source row offsets (in floats) for a node row (y, z): src[ey+1][ez+1] is
+// the row of (y - ey, z - ez) with periodic wrap.  Uniform across a wave when
+// y and z are.
+template <int Q>
+__device__ __forceinline__ void source_rows(const InstDev &d, int y, int z, int64_t (&src)[3][3]) {
   const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
   const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
-  const int64_t xs[3] = {xp, x, xm};  // source x for e_x = -1, 0, +1
-  const int64_t ys[3] = {yp * rowp, y * rowp, ym * rowp};
-  const int64_t zs[3] = {zp * slab, z * slab, zm * slab};
+  const int ys[3] = {yp, y, ym}, zs[3] = {zp, z, zm};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) src[a][b] = ys[a] * d.ystride + zs[b] * d.zstride;
+}
+
+// Source x for e_x = -1, 0, +1 (periodic wrap).
+__device__ __forceinline__ void source_x(const InstDev &d, int x, int (&xs)[3]) {
+  xs[0] = x == d.nx - 1 ? 0 : x + 1;
+  xs[1] = x;
+  xs[2] = x == 0 ? d.nx - 1 : x - 1;
+}
+
+// Pull both components at (x, row src[1][1]) given its source rows.
+template <int Q, int ST>
+__device__ __forceinline__ void pull_row(const InstDev &d, gcf *__restrict__ fin, uint32_t info,
+                                         const int64_t (&src)[3][3], const int (&xs)[3], float (&f0)[Q],
+                                         float (&f1)[Q]) {
+  using L = Lat<Q>;
+  const int pitch = d.pitch;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const bool bb = (info >> i) & 1u;
-    const int64_t src = xs[L::ex[i] + 1] + ys[L::ey[i] + 1] + zs[L::ez[i] + 1];
-    const int64_t o = bb ? off : src;
-    const int pi = bb ? L::opp[i] : i;
+    const int64_t row = src[L::ey[i] + 1][L::ez[i] + 1];
+    const int sx = xs[L::ex[i] + 1];
     if constexpr (ST == 0) {
-      f0[i] = fin[(int64_t)pi * plane + o];
-      f1[i] = fin[(int64_t)(Q + pi) * plane + o];
+      gcf *b = fin + row + (int64_t)i * pitch;
+      f0[i] = b[(uint32_t)sx];
+      f1[i] = b[(int64_t)Q * pitch + (uint32_t)sx];
     } else {
-      f0[i] = pop_get<Q, 1>(fin, plane, 0, pi, o);
-      f1[i] = pop_get<Q, 1>(fin, plane, 1, pi, o);
+      const bool bb = (info >> i) & 1u;
+      const int64_t r = bb ? src[1][1] : row;
+      const int x = bb ? xs[1] : sx;
+      const int pi = bb ? L::opp[i] : i;
+      f0[i] = pop_get<Q, 1>(fin, pitch, 0, pi, r, x);
+      f1[i] = pop_get<Q, 1>(fin, pitch, 1, pi, r, x);
     }
   }
 }
 
-// pull + inlet/outlet completion.  (x, y, z) are in-domain coordinates.
+// Ghost slots (FP32 storage): link i of each solid source x - e_i receives f*_opp(i)(x).
+template <int Q, int ST>
+__device__ __forceinline__ void store_ghosts(const InstDev &d, gf *__restrict__ fout, uint32_t info,
+                                             const int64_t (&src)[3][3], const int (&xs)[3],
+                                             const float (&f0)[Q], const float (&f1)[Q]) {
+  if constexpr (ST == 0) {
+    using L = Lat<Q>;
+    if (!(info & kLinkMask)) return;
+    const int pitch = d.pitch;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if (info & (1u << i)) {
+        gf *b = fout + src[L::ey[i] + 1][L::ez[i] + 1] + (int64_t)i * pitch;
+        const uint32_t sx = (uint32_t)xs[L::ex[i] + 1];
+        b[sx] = f0[L::opp[i]];
+        b[(int64_t)Q * pitch + sx] = f1[L::opp[i]];
+      }
+    }
+  }
+}
+
+// Pull + completion for one fluid node at in-domain (x, y, z) (per-lane rows).
 template <int Q, int ST, typename R>
 __device__ __forceinline__ void gather(const InstDev &d, gcf *__restrict__ fin, uint32_t info,
                                        int x, int y, int z, float (&f0)[Q], float (&f1)[Q]) {
-  pull<Q, ST>(d, fin, info, x, y, z, f0, f1);
-  if (info & (kInlet | kOutlet))
-    complete<Q, ST, R>(d, fin, info, y, z, x + (int64_t)d.pitch * (y + (int64_t)d.ny * z), f0, f1);
+  int64_t src[3][3];
+  int xs[3];
+  source_rows<Q>(d, y, z, src);
+  source_x(d, x, xs);
+  pull_row<Q, ST>(d, fin, info, src, xs, f0, f1);
+  if (info & (kInlet | kOutlet)) complete<Q, ST, R>(d, fin, info, x, y, z, f0, f1);
 }
 
 // Blocks are dealt round-robin to the 8 XCDs; renumber them so each XCD
@@ -148,21 +207,22 @@ __device__ __forceinline__ int xcd_block() {
 }
 
 // ---------------------------------------------------------------------------
-// D2Q9 fused step.  Block = 4 waves over a region of 64 columns x 16 rows:
-// 60 x 12 interior nodes plus a 2-node halo.  Wave w owns interior rows
-// 2 + w + 4k (k = 0..2) and one halo row.
-// Phase 1: pull + complete + densities for all 64 x 16 region nodes -> LDS.
+// D2Q9 fused step.  Block = 4 waves over a region of 64 columns x (TY + 4)
+// rows: 60 x TY interior nodes plus a 2-node halo.  Wave w owns interior rows
+// 2 + w + 4k (k < TY/4) and one halo row; a row is wave-uniform, so every pull
+// is one load from a scalar row base plus the lane's x.
+// Phase 1: pull + complete + densities for all region nodes -> LDS.
 // Phase 2: virtual solid density (Eq. 17) in place at solid region nodes.
 // Phase 3: force (Eq. 13 with the open-face mirror) and collision for the
 //          interior nodes, whose pulled populations stayed in registers.
 // ---------------------------------------------------------------------------
-constexpr int kRH = kTileY + 4;
-
-template <int COLL, int ST, typename R>
+template <int COLL, int ST, typename R, int TY>
 __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ insts,
                                                   const int32_t *__restrict__ block_inst, int parity) {
   using L = Lat<9>;
   using V = Vec2<R>;
+  constexpr int KR = TY / 4;        // interior rows per wave
+  constexpr int kRH = TY + 4;       // region rows
   __shared__ V psi[kRH][64];
 
   const int bid = xcd_block();
@@ -170,7 +230,8 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
   const InstDev &d = insts[inst];
   const int lb = bid - d.block_base;
   const int tx = lb % d.tiles_x, ty = lb / d.tiles_x;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   gcf *__restrict__ fin = G(d.f[parity]);
   gf *__restrict__ fout = G(d.f[parity ^ 1]);
   gcu32 *__restrict__ infop = (gcu32 *)d.info;
@@ -185,42 +246,49 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
     if (px) gx += gx < 0 ? nx : -nx;
     else col_in = false;
   }
+  const int gxa = col_in ? gx : (gx < 0 ? 0 : nx - 1);
+  int xs[3];
+  source_x(d, gxa, xs);
 
-  // rows owned: k = 0..2 interior (2 + wave + 4k), k = 3 halo
-  int rows[4], gy[4];
-  bool valid[4];
-  uint32_t info[4];
+  // rows owned (wave-uniform): k < KR interior (2 + wave + 4k), k = KR halo
+  int rows[KR + 1], gy[KR + 1];
+  bool row_in[KR + 1];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    rows[k] = k < 3 ? 2 + wave + 4 * k : (wave < 2 ? wave : 12 + wave);
-    int y = ty * kTileY - 2 + rows[k];
-    bool in = col_in;
+  for (int k = 0; k <= KR; ++k) {
+    rows[k] = k < KR ? 2 + wave + 4 * k : (wave < 2 ? wave : TY + wave);
+    int y = ty * TY - 2 + rows[k];
+    bool in = true;
     if (y < 0 || y >= ny) {
       if (py) y += y < 0 ? ny : -ny;
       else in = false;
     }
     gy[k] = in ? y : 0;
-    valid[k] = in;
+    row_in[k] = in;
   }
+  uint32_t info[KR + 1];
 #pragma unroll
-  for (int k = 0; k < 4; ++k) info[k] = valid[k] ? infop[gx + (int64_t)d.pitch * gy[k]] : kSolid;
+  for (int k = 0; k <= KR; ++k)
+    info[k] = (row_in[k] && col_in) ? infop[gx + (int64_t)d.pitch * gy[k]] : kSolid;
 
-  // Phase 1: issue every pull of this thread unconditionally (solid and
-  // out-of-domain lanes read valid addresses inside the same cache lines and
-  // discard the values), then complete and sum
-  const int gxa = col_in ? gx : (gx < 0 ? 0 : nx - 1);
-  float f0[3][9], f1[3][9], h0[9], h1[9];
+  // Phase 1: issue every pull of this thread, then complete and sum.  Solid
+  // and out-of-domain lanes read valid addresses in the same rows and discard
+  // them (the BF16 layout pulls only for fluid lanes, to bound the loads in
+  // flight).
+  float f0[KR][9], f1[KR][9], h0[9], h1[9];
+  int64_t srow[KR + 1][3][3];
 #pragma unroll
-  for (int k = 0; k < 3; ++k) pull<9, ST>(d, fin, info[k], gxa, gy[k], 0, f0[k], f1[k]);
-  pull<9, ST>(d, fin, info[3], gxa, gy[3], 0, h0, h1);
+  for (int k = 0; k <= KR; ++k) source_rows<9>(d, gy[k], 0, srow[k]);
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < KR; ++k)
+    if (ST == 0 || !(info[k] & kSolid)) pull_row<9, ST>(d, fin, info[k], srow[k], xs, f0[k], f1[k]);
+  if (ST == 0 || !(info[KR] & kSolid)) pull_row<9, ST>(d, fin, info[KR], srow[KR], xs, h0, h1);
+#pragma unroll
+  for (int k = 0; k <= KR; ++k) {
     R rho1 = 0, rho2 = 0;
     if (!(info[k] & kSolid)) {
-      float(&a)[9] = k < 3 ? f0[k < 3 ? k : 0] : h0;
-      float(&b)[9] = k < 3 ? f1[k < 3 ? k : 0] : h1;
-      if (info[k] & (kInlet | kOutlet))
-        complete<9, ST, R>(d, fin, info[k], gy[k], 0, gx + (int64_t)d.pitch * gy[k], a, b);
+      float(&a)[9] = k < KR ? f0[k < KR ? k : 0] : h0;
+      float(&b)[9] = k < KR ? f1[k < KR ? k : 0] : h1;
+      if (info[k] & (kInlet | kOutlet)) complete<9, ST, R>(d, fin, info[k], gx, gy[k], 0, a, b);
       rho1 = sum_q<9, R>(a);
       rho2 = sum_q<9, R>(b);
     }
@@ -230,9 +298,10 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
 
   // Phase 2: psi at solid nodes = chi^s * weighted mean of fluid-neighbour rho^s
 #pragma unroll
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k <= KR; ++k) {
     const int r = rows[k];
-    if (!valid[k] || !(info[k] & kSolid) || r < 1 || r > kRH - 2 || lane < 1 || lane > 62) continue;
+    if (!row_in[k] || !col_in || !(info[k] & kSolid) || r < 1 || r > kRH - 2 || lane < 1 || lane > 62)
+      continue;
     const uint32_t nb = info[k];
     if (!(nb & kLinkMask)) continue;
     R s1 = 0, s2 = 0, den = 0;
@@ -254,10 +323,10 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
   // Phase 3: force + collision for interior rows
   const R w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
 #pragma unroll
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < KR; ++k) {
     const int r = rows[k];
-    const int gy_raw = ty * kTileY - 2 + r;
-    if (!valid[k] || !col_store || gy_raw >= ny || (info[k] & kSolid)) continue;
+    const int gy_raw = ty * TY - 2 + r;
+    if (!row_in[k] || !col_store || gy_raw >= ny || (info[k] & kSolid)) continue;
     const uint32_t inf = info[k];
     const V c = psi[r][lane];
     const R rho1 = c.x, rho2 = c.y;
@@ -287,19 +356,22 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
     const R F1x = -G_ * rho1 * sx2 + rho1 * gxb, F1y = -G_ * rho1 * sy2 + rho1 * gyb;
     const R F2x = -G_ * rho2 * sx1 + rho2 * gxb, F2y = -G_ * rho2 * sy1 + rho2 * gyb;
     collide_node<9, COLL, R>(d, f0[k], f1[k], rho1, rho2, F1x, F1y, R(0), F2x, F2y, R(0));
-    const int64_t off = gx + (int64_t)d.pitch * gy_raw;
-    pop_store<9, ST>(fout, d.plane, off, f0[k], f1[k], (float)rho1, (float)rho2);
+    pop_store<9, ST>(fout, d.pitch, gy_raw * d.ystride, gx, f0[k], f1[k], (float)rho1, (float)rho2);
+    store_ghosts<9, ST>(d, fout, inf, srow[k], xs, f0[k], f1[k]);
   }
 }
 
 // ---------------------------------------------------------------------------
 // D3Q19 fused step.  A block owns a 60 x kTileY3 column of (x, y) and marches
-// through z.  Per z plane it keeps densities of a 64 x (kTileY3 + 4) region in
-// an LDS ring of five planes (z-2 .. z+2), completes psi at solid nodes of
-// plane z+1 in place, and collides plane z with populations pulled two
-// iterations earlier and held in registers.
+// through a chunk of z.  Per plane it keeps densities of the 64 x (kTileY3+4)
+// region in an LDS ring of five planes (z-2 .. z+2): at plane z it forms rho of
+// plane z+2, psi at the solid nodes of plane z+1, and collides plane z.  The
+// interior populations of plane z are pulled again for the collision (they
+// were fetched two planes earlier and come from cache), which keeps the
+// register footprint small.  Wave w owns interior rows 2+w and 6+w and one
+// halo row; rows and planes are wave-uniform.
 // ---------------------------------------------------------------------------
-constexpr int kRH3 = kTileY3 + 4;   // 8 region rows: wave w owns interior row 2+w and one halo row
+constexpr int kRH3 = kTileY3 + 4;
 constexpr int kRing = 5;
 
 __device__ __forceinline__ int ring(int z) { return ((z % kRing) + kRing) % kRing; }
@@ -317,14 +389,16 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
   const int lb = bid - d.block_base;
   const int tx = lb % d.tiles_x, ty = (lb / d.tiles_x) % d.tiles_y;
   const int zc = lb / (d.tiles_x * d.tiles_y);  // z chunk
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   gcf *__restrict__ fin = G(d.f[parity]);
   gf *__restrict__ fout = G(d.f[parity ^ 1]);
+  gcu32 *__restrict__ infop = (gcu32 *)d.info;
   const int nx = d.nx, ny = d.ny, nz = d.nz;
   const bool px = d.periodic & 1, py = d.periodic & 2, pz = d.periodic & 4;
   const int zlen = (nz + d.tiles_z - 1) / d.tiles_z;
   const int z0 = zc * zlen, z1 = min(nz, z0 + zlen);
-  const int64_t slab = (int64_t)d.pitch * ny;
+  const int64_t islab = (int64_t)d.pitch * ny;
 
   int gx = tx * kTileX - 2 + lane;
   const bool col_store = lane >= 2 && lane < 62 && gx < nx;
@@ -333,71 +407,73 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
     if (px) gx += gx < 0 ? nx : -nx;
     else col_in = false;
   }
-  // rows of this wave: interior row ri = 2 + wave, halo row rh
-  const int ri = 2 + wave, rh = wave < 2 ? wave : 4 + wave;
-  int gyi = ty * kTileY3 - 2 + ri, gyh = ty * kTileY3 - 2 + rh;
-  const int gyi_raw = gyi;
-  bool in_i = col_in, in_h = col_in;
-  if (gyi < 0 || gyi >= ny) { if (py) gyi += gyi < 0 ? ny : -ny; else in_i = false; }
-  if (gyh < 0 || gyh >= ny) { if (py) gyh += gyh < 0 ? ny : -ny; else in_h = false; }
-  const bool store_ok = col_store && gyi_raw < ny;
+  const int gxa = col_in ? gx : (gx < 0 ? 0 : nx - 1);
+  int xs[3];
+  source_x(d, gxa, xs);
+  // rows of this wave (uniform): interior rows 2+w, 6+w (k = 0, 1) and a halo row (k = 2)
+  int rows[3], gy[3], gy_raw[3];
+  bool row_in[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    rows[k] = k < 2 ? 2 + wave + 4 * k : (wave < 2 ? wave : kTileY3 + wave);
+    int y = ty * kTileY3 - 2 + rows[k];
+    gy_raw[k] = y;
+    bool in = true;
+    if (y < 0 || y >= ny) {
+      if (py) y += y < 0 ? ny : -ny;
+      else in = false;
+    }
+    gy[k] = in ? y : 0;
+    row_in[k] = in;
+  }
 
   // plane index with periodic wrap; false if outside a closed z edge
-  auto wrap_z = [&](int zp, int &zz) -> bool {
+  auto wrap_z = [&](int zp, int &zz) __attribute__((always_inline)) -> bool {
     zz = zp;
     if (zz < 0 || zz >= nz) {
       if (pz) { zz += zz < 0 ? nz : -nz; return true; }
+      zz = 0;
       return false;
     }
     return true;
   };
 
-  // densities of plane zp -> LDS ring; the interior node's pulled populations -> (a, b)
-  auto load_plane = [&](int zp, float (&a)[19], float (&b)[19], uint32_t &inf_out) {
+  // densities of the region rows of plane zp -> LDS ring
+  auto load_plane = [&](int zp) __attribute__((always_inline)) {
     const int slot = ring(zp);
     int zz;
     const bool zin = wrap_z(zp, zz);
-    {
+    uint32_t inf[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      inf[k] = (row_in[k] && col_in && zin) ? infop[gx + (int64_t)d.pitch * gy[k] + islab * zz] : kSolid;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
       R rho1 = 0, rho2 = 0;
-      uint32_t inf = kSolid;
-      if (in_i && zin) {
-        inf = d.info[gx + (int64_t)d.pitch * gyi + slab * zz];
-        if (!(inf & kSolid)) {
-          gather<19, ST, R>(d, fin, inf, gx, gyi, zz, a, b);
-          rho1 = sum_q<19, R>(a);
-          rho2 = sum_q<19, R>(b);
-        }
+      if (!(inf[k] & kSolid)) {
+        int64_t src[3][3];
+        source_rows<19>(d, gy[k], zz, src);
+        float a[19], b[19];
+        pull_row<19, ST>(d, fin, inf[k], src, xs, a, b);
+        if (inf[k] & (kInlet | kOutlet)) complete<19, ST, R>(d, fin, inf[k], gx, gy[k], zz, a, b);
+        rho1 = sum_q<19, R>(a);
+        rho2 = sum_q<19, R>(b);
       }
-      inf_out = inf;
-      psi[slot][ri][lane] = V{rho1, rho2};
-    }
-    {
-      R rho1 = 0, rho2 = 0;
-      if (in_h && zin) {
-        const uint32_t inf = d.info[gx + (int64_t)d.pitch * gyh + slab * zz];
-        if (!(inf & kSolid)) {
-          float ha[19], hb[19];
-          gather<19, ST, R>(d, fin, inf, gx, gyh, zz, ha, hb);
-          rho1 = sum_q<19, R>(ha);
-          rho2 = sum_q<19, R>(hb);
-        }
-      }
-      psi[slot][rh][lane] = V{rho1, rho2};
+      psi[slot][rows[k]][lane] = V{rho1, rho2};
     }
   };
 
   // virtual solid density (Eq. 17) at the solid nodes of plane zp, in place;
   // reads rho at planes zp-1 .. zp+1
-  auto solid_psi = [&](int zp) {
+  auto solid_psi = [&](int zp) __attribute__((always_inline)) {
     const int slot = ring(zp);
     int zz;
     if (!wrap_z(zp, zz)) return;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int r = h ? rh : ri;
-      const bool in = h ? in_h : in_i;
-      if (!in || r < 1 || r > kRH3 - 2 || lane < 1 || lane > 62) continue;
-      const uint32_t nb = d.info[gx + (int64_t)d.pitch * (h ? gyh : gyi) + slab * zz];
+    for (int k = 0; k < 3; ++k) {
+      const int r = rows[k];
+      if (!row_in[k] || !col_in || r < 1 || r > kRH3 - 2 || lane < 1 || lane > 62) continue;
+      const uint32_t nb = infop[gx + (int64_t)d.pitch * gy[k] + islab * zz];
       if (!(nb & kSolid) || !(nb & kLinkMask)) continue;
       R s1 = 0, s2 = 0, den = 0;
 #pragma unroll
@@ -410,73 +486,205 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
           den += w;
         }
       }
-      const R inv = R(1) / den;
+      const R inv = rcp<R>(den);
       psi[slot][r][lane] = V{(R)d.chi1 * s1 * inv, (R)d.chi2 * s2 * inv};
     }
   };
 
   // force (Eq. 13 with the open-face mirror) + collision + store, plane z
-  auto collide_plane = [&](int z, float (&a)[19], float (&b)[19], uint32_t inf) {
-    if (!store_ok || (inf & kSolid)) return;
-    const V c = psi[ring(z)][ri][lane];
-    const R rho1 = c.x, rho2 = c.y;
-    R sx1 = 0, sy1 = 0, sz1 = 0, sx2 = 0, sy2 = 0, sz2 = 0;
-    const bool open_face = (inf & (kInlet | kOutlet)) != 0;
+  auto collide_plane = [&](int z) __attribute__((always_inline)) {
+#pragma unroll 1
+    for (int k = 0; k < 2; ++k) {
+      if (!col_store || !row_in[k] || gy_raw[k] >= ny) continue;
+      const int ri = rows[k];
+      const uint32_t inf = infop[gx + (int64_t)d.pitch * gy[k] + islab * z];
+      if (inf & kSolid) continue;
+      int64_t src[3][3];
+      source_rows<19>(d, gy[k], z, src);
+      float a[19], b[19];
+      pull_row<19, ST>(d, fin, inf, src, xs, a, b);
+      if (inf & (kInlet | kOutlet)) complete<19, ST, R>(d, fin, inf, gx, gy[k], z, a, b);
+      const V c = psi[ring(z)][ri][lane];
+      const R rho1 = c.x, rho2 = c.y;
+      R sx1 = 0, sy1 = 0, sz1 = 0, sx2 = 0, sy2 = 0, sz2 = 0;
+      const bool open_face = (inf & (kInlet | kOutlet)) != 0;
 #pragma unroll
-    for (int i = 1; i < 19; ++i) {
-      if (L::opp[i] < i) continue;
-      const int o = L::opp[i];
-      if (open_face && L::ex[i] != 0) continue;  // mirrored pair cancels
-      const V pa = psi[ring(z + L::ez[i])][ri + L::ey[i]][lane + L::ex[i]];
-      const V pb = psi[ring(z + L::ez[o])][ri + L::ey[o]][lane + L::ex[o]];
-      const R w = (R)L::w[i];
-      const R d1 = w * (pa.x - pb.x), d2 = w * (pa.y - pb.y);
-      if (L::ex[i]) { sx1 += L::ex[i] * d1; sx2 += L::ex[i] * d2; }
-      if (L::ey[i]) { sy1 += L::ey[i] * d1; sy2 += L::ey[i] * d2; }
-      if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
+      for (int i = 1; i < 19; ++i) {
+        if (L::opp[i] < i) continue;
+        const int o = L::opp[i];
+        if (open_face && L::ex[i] != 0) continue;  // mirrored pair cancels
+        const V pa = psi[ring(z + L::ez[i])][ri + L::ey[i]][lane + L::ex[i]];
+        const V pb = psi[ring(z + L::ez[o])][ri + L::ey[o]][lane + L::ex[o]];
+        const R w = (R)L::w[i];
+        const R d1 = w * (pa.x - pb.x), d2 = w * (pa.y - pb.y);
+        if (L::ex[i]) { sx1 += L::ex[i] * d1; sx2 += L::ex[i] * d2; }
+        if (L::ey[i]) { sy1 += L::ey[i] * d1; sy2 += L::ey[i] * d2; }
+        if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
+      }
+      const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
+      collide_node<19, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb,
+                                -G_ * rho1 * sy2 + rho1 * gyb, -G_ * rho1 * sz2 + rho1 * gzb,
+                                -G_ * rho2 * sx1 + rho2 * gxb, -G_ * rho2 * sy1 + rho2 * gyb,
+                                -G_ * rho2 * sz1 + rho2 * gzb);
+      pop_store<19, ST>(fout, d.pitch, gy_raw[k] * d.ystride + z * d.zstride, gx, a, b, (float)rho1,
+                        (float)rho2);
+      store_ghosts<19, ST>(d, fout, inf, src, xs, a, b);
     }
-    const R G = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
-    collide_node<19, COLL, R>(d, a, b, rho1, rho2, -G * rho1 * sx2 + rho1 * gxb,
-                              -G * rho1 * sy2 + rho1 * gyb, -G * rho1 * sz2 + rho1 * gzb,
-                              -G * rho2 * sx1 + rho2 * gxb, -G * rho2 * sy1 + rho2 * gyb,
-                              -G * rho2 * sz1 + rho2 * gzb);
-    const int64_t off = gx + (int64_t)d.pitch * gyi_raw + slab * z;
-    pop_store<19, ST>(fout, d.plane, off, a, b, (float)rho1, (float)rho2);
   };
 
-  // register ring: slot k holds the interior populations of plane z with (z - z0) % 3 == k
-  float ra0[3][19], ra1[3][19];
-  uint32_t rinf[3];
-  // prologue: densities of planes z0-2 .. z0+1 (z0-2 and z0-1 only for the halo)
-  load_plane(z0 - 2, ra0[1], ra1[1], rinf[1]);
-  load_plane(z0 - 1, ra0[2], ra1[2], rinf[2]);
-  load_plane(z0, ra0[0], ra1[0], rinf[0]);
-  load_plane(z0 + 1, ra0[1], ra1[1], rinf[1]);
+  // prologue: densities of planes z0-2 .. z0+1, psi of planes z0-1 and z0
+  for (int zp = z0 - 2; zp <= z0 + 1; ++zp) load_plane(zp);
   __syncthreads();
   solid_psi(z0 - 1);
   solid_psi(z0);
   __syncthreads();
-
-  auto body = [&](auto kc, int z) {
-    constexpr int K = decltype(kc)::value;
-    constexpr int K2 = (K + 2) % 3;
-    load_plane(z + 2, ra0[K2], ra1[K2], rinf[K2]);
+  for (int z = z0; z < z1; ++z) {
+    load_plane(z + 2);
     __syncthreads();
     solid_psi(z + 1);  // needs rho at z .. z+2
     __syncthreads();
-    collide_plane(z, ra0[K], ra1[K], rinf[K]);
+    collide_plane(z);
     // ring slot of z-2 is rewritten at z+3: every read of it is behind this barrier
     __syncthreads();
-  };
-  for (int z = z0; z < z1; z += 3) {
-    body(std::integral_constant<int, 0>{}, z);
-    if (z + 1 < z1) body(std::integral_constant<int, 1>{}, z + 1);
-    if (z + 2 < z1) body(std::integral_constant<int, 2>{}, z + 2);
   }
 }
 
 // ---------------------------------------------------------------------------
-// initial state: f*_i = w_i rho0 at fluid nodes (rest equilibrium)
+// Split step (three launches) for grids whose per-block working set does not
+// fit the L2: the halo recompute of the fused kernels would then refetch
+// populations from memory.  Each wave owns 64 consecutive x of one (y, z)
+// row (wave-uniform rows), one thread per node.
+//   rho_kernel:     pull + complete -> rho^s(x) into the psi array (double2)
+//   psi_kernel:     virtual solid density (Eq. 17) at solid nodes, in place
+//   collide_kernel: force from psi (Eq. 13 with the open-face mirror), pull
+//                   again, collide, store
+// psi array layout: index x + pitch * (y + ny * z), like the node info.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool wave_row(const InstDev &d, int &x, int &y, int &z) {
+  const int segs = (d.nx + 63) >> 6;
+  const int64_t W = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t row = W / segs;
+  const int seg = (int)(W - row * segs);
+  y = (int)(row % d.ny);
+  z = (int)(row / d.ny);
+  x = seg * 64 + (int)(threadIdx.x & 63);
+  return z < d.nz && x < d.nx;
+}
+
+typedef __attribute__((address_space(1))) double gd;
+typedef __attribute__((address_space(1))) const double gcd;
+
+// psi entries are (rho1, rho2) pairs of doubles
+__device__ __forceinline__ Vec2<double> psi_ld(gcd *p, int64_t j) {
+  return Vec2<double>{p[2 * j], p[2 * j + 1]};
+}
+__device__ __forceinline__ void psi_st(gd *p, int64_t j, double a, double b) {
+  p[2 * j] = a;
+  p[2 * j + 1] = b;
+}
+
+template <int Q, int ST>
+__global__ __launch_bounds__(256) void rho_kernel(const InstDev *__restrict__ insts, int parity) {
+  const InstDev &d = insts[0];
+  int x, y, z;
+  if (!wave_row(d, x, y, z)) return;
+  const int64_t pi = x + (int64_t)d.pitch * (y + (int64_t)d.ny * z);
+  const uint32_t info = ((gcu32 *)d.info)[pi];
+  if (info & kSolid) return;
+  gcf *__restrict__ fin = G(d.f[parity]);
+  int64_t src[3][3];
+  int xs[3];
+  source_rows<Q>(d, y, z, src);
+  source_x(d, x, xs);
+  float a[Q], b[Q];
+  pull_row<Q, ST>(d, fin, info, src, xs, a, b);
+  if (info & (kInlet | kOutlet)) complete<Q, ST, double>(d, fin, info, x, y, z, a, b);
+  psi_st((gd *)d.psi, pi, sum_q<Q, double>(a), sum_q<Q, double>(b));
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void psi_kernel(const InstDev *__restrict__ insts) {
+  using L = Lat<Q>;
+  const InstDev &d = insts[0];
+  int x, y, z;
+  if (!wave_row(d, x, y, z)) return;
+  const int64_t pi = x + (int64_t)d.pitch * (y + (int64_t)d.ny * z);
+  const uint32_t nb = ((gcu32 *)d.info)[pi];
+  if (!(nb & kSolid) || !(nb & kLinkMask)) return;
+  gd *__restrict__ psi = (gd *)d.psi;
+  int xs[3];
+  source_x(d, x, xs);  // xs[1 - e_x]: x + e_x with wrap
+  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
+  const int yy[3] = {ym, y, yp}, zz[3] = {zm, z, zp};  // index by e + 1
+  double s1 = 0, s2 = 0, den = 0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (nb & (1u << i)) {
+      const int64_t j = xs[1 - L::ex[i]] + (int64_t)d.pitch * (yy[L::ey[i] + 1] + (int64_t)d.ny * zz[L::ez[i] + 1]);
+      const Vec2<double> p = psi_ld(psi, j);
+      s1 += L::w[i] * p.x;
+      s2 += L::w[i] * p.y;
+      den += L::w[i];
+    }
+  }
+  const double inv = rcp<double>(den);
+  psi_st(psi, pi, d.chi1 * s1 * inv, d.chi2 * s2 * inv);
+}
+
+template <int Q, int COLL, int ST, typename R>
+__global__ __launch_bounds__(256) void collide_kernel(const InstDev *__restrict__ insts, int parity) {
+  using L = Lat<Q>;
+  const InstDev &d = insts[0];
+  int x, y, z;
+  if (!wave_row(d, x, y, z)) return;
+  const int64_t pi = x + (int64_t)d.pitch * (y + (int64_t)d.ny * z);
+  const uint32_t info = ((gcu32 *)d.info)[pi];
+  if (info & kSolid) return;
+  gcd *__restrict__ psi = (gcd *)d.psi;
+  gcf *__restrict__ fin = G(d.f[parity]);
+  gf *__restrict__ fout = G(d.f[parity ^ 1]);
+  int xs[3];
+  source_x(d, x, xs);
+  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
+  const int yy[3] = {ym, y, yp}, zz[3] = {zm, z, zp};
+  // force: sum_i w_i psi(x + e_i) e_i by opposite pairs; at an open face the
+  // mirrored pairs with an x component cancel
+  const Vec2<double> c = psi_ld(psi, pi);
+  const R rho1 = (R)c.x, rho2 = (R)c.y;
+  const bool open_face = (info & (kInlet | kOutlet)) != 0;
+  R sx1 = 0, sy1 = 0, sz1 = 0, sx2 = 0, sy2 = 0, sz2 = 0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (L::opp[i] < i) continue;
+    const int o = L::opp[i];
+    if (L::ex[i] != 0 && open_face) continue;
+    const int64_t ja = xs[1 - L::ex[i]] + (int64_t)d.pitch * (yy[L::ey[i] + 1] + (int64_t)d.ny * zz[L::ez[i] + 1]);
+    const int64_t jb = xs[1 - L::ex[o]] + (int64_t)d.pitch * (yy[L::ey[o] + 1] + (int64_t)d.ny * zz[L::ez[o] + 1]);
+    const Vec2<double> pa = psi_ld(psi, ja), pb = psi_ld(psi, jb);
+    const R w = (R)L::w[i];
+    const R d1 = w * ((R)pa.x - (R)pb.x), d2 = w * ((R)pa.y - (R)pb.y);
+    if (L::ex[i]) { sx1 += L::ex[i] * d1; sx2 += L::ex[i] * d2; }
+    if (L::ey[i]) { sy1 += L::ey[i] * d1; sy2 += L::ey[i] * d2; }
+    if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
+  }
+  int64_t src[3][3];
+  source_rows<Q>(d, y, z, src);
+  float a[Q], b[Q];
+  pull_row<Q, ST>(d, fin, info, src, xs, a, b);
+  if (info & (kInlet | kOutlet)) complete<Q, ST, R>(d, fin, info, x, y, z, a, b);
+  const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
+  collide_node<Q, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb, -G_ * rho1 * sy2 + rho1 * gyb,
+                           -G_ * rho1 * sz2 + rho1 * gzb, -G_ * rho2 * sx1 + rho2 * gxb,
+                           -G_ * rho2 * sy1 + rho2 * gyb, -G_ * rho2 * sz1 + rho2 * gzb);
+  pop_store<Q, ST>(fout, d.pitch, y * d.ystride + z * d.zstride, x, a, b, (float)rho1, (float)rho2);
+  store_ghosts<Q, ST>(d, fout, info, src, xs, a, b);
+}
+
+// ---------------------------------------------------------------------------
+// initial state: f*_i = w_i rho0 at fluid nodes (rest equilibrium), and the
+// ghost slots of solid sources (FP32 storage)
 // ---------------------------------------------------------------------------
 template <int Q, int ST>
 __global__ void init_kernel(const InstDev *__restrict__ insts, const float *__restrict__ rho0, int parity) {
@@ -487,24 +695,22 @@ __global__ void init_kernel(const InstDev *__restrict__ insts, const float *__re
        n += (int64_t)gridDim.x * blockDim.x) {
     const int x = n % d.nx;
     const int64_t yz = n / d.nx;
-    const int64_t off = x + (int64_t)d.pitch * yz;
-    const bool solid = d.info[off] & kSolid;
-    const float r1 = solid ? 0.f : rho0[n], r2 = solid ? 0.f : rho0[n_nodes + n];
+    const int y = yz % d.ny, z = yz / d.ny;
+    const uint32_t info = d.info[x + (int64_t)d.pitch * yz];
+    if (info & kSolid) continue;
+    const float r1 = rho0[n], r2 = rho0[n_nodes + n];
     float a[Q], c[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       a[i] = (float)(Lat<Q>::w[i] * (double)r1);
       c[i] = (float)(Lat<Q>::w[i] * (double)r2);
     }
-    if constexpr (ST == 0) {
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        b[(int64_t)i * d.plane + off] = a[i];
-        b[(int64_t)(Q + i) * d.plane + off] = c[i];
-      }
-    } else {
-      pop_store<Q, 1>(b, d.plane, off, a, c, r1, r2);
-    }
+    pop_store<Q, ST>(b, d.pitch, y * d.ystride + z * d.zstride, x, a, c, r1, r2);
+    int64_t src[3][3];
+    int xs[3];
+    source_rows<Q>(d, y, z, src);
+    source_x(d, x, xs);
+    store_ghosts<Q, ST>(d, b, info, src, xs, a, c);
   }
 }
 
@@ -646,40 +852,74 @@ hipError_t launch_init(const InstDev *d_inst, const InstDev &h, const float *rho
 }
 
 template <int COLL, int ST, typename R>
-static void launch_step_q(int q, const InstDev *d, const int32_t *bi, int64_t nb, int parity,
-                          hipStream_t s) {
-  if (q == 9) step_d2q9<COLL, ST, R><<<dim3((unsigned)nb), dim3(256), 0, s>>>(d, bi, parity);
-  else if constexpr (COLL != 1) step_d3q19<COLL, ST, R><<<dim3((unsigned)nb), dim3(256), 0, s>>>(d, bi, parity);
-}
-
-template <typename R>
-static void launch_step_r(int q, int collision, int storage, const InstDev *d, const int32_t *bi,
-                          int64_t nb, int parity, hipStream_t s) {
-  if (storage == 0) {
-    if (collision == 0) launch_step_q<0, 0, R>(q, d, bi, nb, parity, s);
-    else if (collision == 1) launch_step_q<1, 0, R>(q, d, bi, nb, parity, s);
-    else launch_step_q<2, 0, R>(q, d, bi, nb, parity, s);
-  } else {
-    if (collision == 0) launch_step_q<0, 1, R>(q, d, bi, nb, parity, s);
-    else if (collision == 1) launch_step_q<1, 1, R>(q, d, bi, nb, parity, s);
-    else launch_step_q<2, 1, R>(q, d, bi, nb, parity, s);
+static void launch_fused_q(int q, int ty, const InstDev *d, const int32_t *bi, int64_t nb, int parity,
+                           hipStream_t s) {
+  const dim3 g((unsigned)nb), b(256);
+  if (q == 9) {
+    if (ty == 8) step_d2q9<COLL, ST, R, 8><<<g, b, 0, s>>>(d, bi, parity);
+    else if (ty == 16) step_d2q9<COLL, ST, R, 16><<<g, b, 0, s>>>(d, bi, parity);
+    else step_d2q9<COLL, ST, R, 12><<<g, b, 0, s>>>(d, bi, parity);
+  } else if constexpr (COLL != 1) {
+    step_d3q19<COLL, ST, R><<<g, b, 0, s>>>(d, bi, parity);
   }
 }
 
-hipError_t launch_step(const InstDev *d_insts, const int32_t *block_inst, int64_t n_blocks, int q,
-                       int collision, int storage, int math, int parity, hipStream_t s) {
-  if (math == 0) launch_step_r<double>(q, collision, storage, d_insts, block_inst, n_blocks, parity, s);
-  else launch_step_r<float>(q, collision, storage, d_insts, block_inst, n_blocks, parity, s);
+template <int COLL, int ST, typename R>
+static void launch_split_q(int q, const InstDev *d, const InstDev &h, int parity, hipStream_t s) {
+  const int64_t waves = (int64_t)((h.nx + 63) / 64) * h.ny * h.nz;
+  const dim3 g((unsigned)((waves + 3) / 4)), b(256);
+  if (q == 9) {
+    rho_kernel<9, ST><<<g, b, 0, s>>>(d, parity);
+    psi_kernel<9><<<g, b, 0, s>>>(d);
+    collide_kernel<9, COLL, ST, R><<<g, b, 0, s>>>(d, parity);
+  } else if constexpr (COLL != 1) {
+    rho_kernel<19, ST><<<g, b, 0, s>>>(d, parity);
+    psi_kernel<19><<<g, b, 0, s>>>(d);
+    collide_kernel<19, COLL, ST, R><<<g, b, 0, s>>>(d, parity);
+  }
+}
+
+template <typename R>
+static void launch_r(const StepLaunch &L, hipStream_t s) {
+#define LBM_DISPATCH(COLL, ST)                                                                    \
+  do {                                                                                            \
+    if (L.strategy == 2) {                                                                        \
+      for (int i = 0; i < L.k; ++i) launch_split_q<COLL, ST, R>(L.q, L.d_insts + i, L.h[i], L.parity, s); \
+    } else {                                                                                      \
+      launch_fused_q<COLL, ST, R>(L.q, L.ty, L.d_insts, L.block_inst, L.n_blocks, L.parity, s);   \
+    }                                                                                             \
+  } while (0)
+  if (L.storage == 0) {
+    if (L.collision == 0) LBM_DISPATCH(0, 0);
+    else if (L.collision == 1) LBM_DISPATCH(1, 0);
+    else LBM_DISPATCH(2, 0);
+  } else {
+    if (L.collision == 0) LBM_DISPATCH(0, 1);
+    else if (L.collision == 1) LBM_DISPATCH(1, 1);
+    else LBM_DISPATCH(2, 1);
+  }
+#undef LBM_DISPATCH
+}
+
+hipError_t launch_step(const StepLaunch &L, hipStream_t s) {
+  if (L.math == 0) launch_r<double>(L, s);
+  else launch_r<float>(L, s);
   return hipGetLastError();
 }
 
-const char *step_kernel_name(int q, int collision, int storage, int math) {
-  static const char *lat[2] = {"step_d2q9", "step_d3q19"};
+const char *step_kernel_name(int q, int collision, int storage, int math, int strategy, int ty) {
+  static const char *lat[2] = {"d2q9", "d3q19"};
   static const char *coll[3] = {"SRT", "MRT", "TRT"};
   static const char *st[2] = {"f32", "bf16dev"};
   static const char *mt[2] = {"double", "float"};
-  static thread_local char buf[96];
-  snprintf(buf, sizeof buf, "%s<%s,%s,%s>", lat[q == 19], coll[collision], st[storage], mt[math]);
+  static thread_local char buf[128];
+  if (strategy == 2)
+    snprintf(buf, sizeof buf, "collide_kernel<%d,%s,%s,%s> (+rho_kernel, psi_kernel)", q, coll[collision],
+             st[storage], mt[math]);
+  else if (q == 9)
+    snprintf(buf, sizeof buf, "step_d2q9<%s,%s,%s,%d>", coll[collision], st[storage], mt[math], ty);
+  else
+    snprintf(buf, sizeof buf, "step_d3q19<%s,%s,%s>", coll[collision], st[storage], mt[math]);
   return buf;
 }
 

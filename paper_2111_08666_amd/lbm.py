@@ -18,11 +18,12 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, 
 SRT, MRT, TRT = 0, 1, 2
 STORE_F32, STORE_BF16DEV = 0, 1
 MATH_F64, MATH_F32 = 0, 1
+AUTO, FUSED, SPLIT = 0, 1, 2
 
 EXPORTS = [
     "lbm_workspace_bytes", "lbm_create", "lbm_set_bc", "lbm_step", "lbm_step_graph",
     "lbm_observables", "lbm_get_density", "lbm_save", "lbm_load", "lbm_get_step",
-    "lbm_destroy", "lbm_last_error", "lbm_kernel_info", "lbm_batch_workspace_bytes",
+    "lbm_destroy", "lbm_last_error", "lbm_kernel_info", "lbm_autotune", "lbm_batch_workspace_bytes",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_step_graph", "lbm_batch_observables",
     "lbm_batch_get_density", "lbm_batch_destroy", "lbm_batch_last_error",
 ]
@@ -41,7 +42,8 @@ class Params(C.Structure):
                 ("g", C.c_double * 3), ("collision", C.c_int32), ("bc_set", C.c_int32),
                 ("half_force_shift", C.c_int32), ("mrt_sj_mode", C.c_int32),
                 ("lam", C.c_double), ("s_e", C.c_double), ("s_eps", C.c_double),
-                ("storage", C.c_int32), ("math", C.c_int32)]
+                ("storage", C.c_int32), ("math", C.c_int32),
+                ("strategy", C.c_int32), ("tile_rows", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -96,6 +98,7 @@ def lib():
         L.lbm_last_error.restype = C.c_char_p
         L.lbm_last_error.argtypes = [vp]
         L.lbm_kernel_info.argtypes = [vp, C.c_char_p, sz, C.POINTER(i64), C.POINTER(i32)]
+        L.lbm_autotune.argtypes = [vp, i64, C.c_char_p, sz]
         L.lbm_batch_workspace_bytes.restype = sz
         L.lbm_batch_workspace_bytes.argtypes = [i32, G, P]
         L.lbm_batch_create.argtypes = [i32, G, P, C.POINTER(vp), vp, sz, vp, C.POINTER(vp)]
@@ -108,6 +111,7 @@ def lib():
         L.lbm_batch_last_error.argtypes = [vp]
         for name in ("lbm_create", "lbm_set_bc", "lbm_step", "lbm_step_graph", "lbm_observables",
                      "lbm_get_density", "lbm_save", "lbm_load", "lbm_destroy", "lbm_kernel_info",
+                     "lbm_autotune",
                      "lbm_batch_create", "lbm_batch_step", "lbm_batch_step_graph",
                      "lbm_batch_observables", "lbm_batch_get_density", "lbm_batch_destroy"):
             getattr(L, name).restype = C.c_int
@@ -126,7 +130,7 @@ def make_geometry(problem, keep: list) -> Geometry:
     return g
 
 
-def make_params(problem, storage=STORE_F32, math=MATH_F64) -> Params:
+def make_params(problem, storage=STORE_F32, math=MATH_F64, strategy=AUTO, tile_rows=0) -> Params:
     p = Params()
     p.tau[0], p.tau[1] = problem.tau
     p.G, p.xi = problem.G, problem.xi
@@ -139,6 +143,8 @@ def make_params(problem, storage=STORE_F32, math=MATH_F64) -> Params:
     p.lam, p.s_e, p.s_eps = problem.lam, problem.s_e, problem.s_eps
     p.storage = storage
     p.math = math
+    p.strategy = strategy
+    p.tile_rows = tile_rows
     return p
 
 
@@ -166,7 +172,8 @@ class Solver:
     """One instance on one GPU.  torch allocates the workspace; every kernel
     runs on `stream` (default: a new non-default torch stream)."""
 
-    def __init__(self, problem, storage=STORE_F32, device="cuda:0", stream=None, math=MATH_F64):
+    def __init__(self, problem, storage=STORE_F32, device="cuda:0", stream=None, math=MATH_F64,
+                 strategy=AUTO, tile_rows=0):
         import torch
         self.problem = problem
         self.shape = problem.mask.shape
@@ -174,7 +181,7 @@ class Solver:
         L = lib()
         keep = []
         self._g = make_geometry(problem, keep)
-        self._p = make_params(problem, storage, math)
+        self._p = make_params(problem, storage, math, strategy, tile_rows)
         self._keep = keep
         nbytes = L.lbm_workspace_bytes(C.byref(self._g), C.byref(self._p))
         if nbytes == 0:
@@ -253,6 +260,11 @@ class Solver:
         buf = C.create_string_buffer(blob, len(blob))
         self._chk(lib().lbm_load(self._h, buf, len(blob)))
 
+    def autotune(self, steps=20) -> str:
+        rep = C.create_string_buffer(1024)
+        self._chk(lib().lbm_autotune(self._h, int(steps), rep, 1024))
+        return rep.value.decode()
+
     def kernel_info(self):
         name = C.create_string_buffer(128)
         g = C.c_int64()
@@ -264,14 +276,15 @@ class Solver:
 class BatchSolver:
     """Many instances advanced by one launch per step (flat block table)."""
 
-    def __init__(self, problems, storage=STORE_F32, device="cuda:0", stream=None, math=MATH_F64):
+    def __init__(self, problems, storage=STORE_F32, device="cuda:0", stream=None, math=MATH_F64,
+                 strategy=AUTO, tile_rows=0):
         import torch
         self.problems = list(problems)
         k = len(self.problems)
         L = lib()
         keep = []
         self._g = (Geometry * k)(*[make_geometry(p, keep) for p in self.problems])
-        self._p = (Params * k)(*[make_params(p, storage, math) for p in self.problems])
+        self._p = (Params * k)(*[make_params(p, storage, math, strategy, tile_rows) for p in self.problems])
         self._keep = keep
         nbytes = L.lbm_batch_workspace_bytes(k, self._g, self._p)
         if nbytes == 0:

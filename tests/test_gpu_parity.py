@@ -91,12 +91,13 @@ def _rel_err(g, o, mask):
     return float((np.abs(g.astype(np.float64) - o) / np.abs(o))[:, fluid].max())
 
 
+@pytest.mark.parametrize("strategy", ["fused", "split"])
 @pytest.mark.parametrize("name", sorted(PROBLEMS))
-def test_density_parity_200_steps(lbm, name):
+def test_density_parity_200_steps(lbm, name, strategy):
     p = PROBLEMS[name]
-    print(f"[parity] {name} {p.mask.shape} q={p.q} coll={p.collision}", flush=True)
+    print(f"[parity] {name} {p.mask.shape} q={p.q} coll={p.collision} {strategy}", flush=True)
     ref = _oracle_series(p, CHECKPOINTS)
-    s = lbm.Solver(p)
+    s = lbm.Solver(p, strategy=lbm.FUSED if strategy == "fused" else lbm.SPLIT)
     t = 0
     worst = 0.0
     for c in CHECKPOINTS:
@@ -105,7 +106,31 @@ def test_density_parity_200_steps(lbm, name):
         err = _rel_err(s.density(), ref[c], p.mask)
         worst = max(worst, err)
         assert err <= REL_TOL, (name, c, err)
-    print(f"[parity] {name}: worst relative density error {worst:.2e}", flush=True)
+    print(f"[parity] {name} {strategy}: worst relative density error {worst:.2e}", flush=True)
+
+
+@pytest.mark.parametrize("tile_rows", [8, 16])
+def test_fused_tile_heights_match_oracle(lbm, tile_rows):
+    p = PROBLEMS["drain_mrt"]
+    ref = _oracle_series(p, (77,))
+    s = lbm.Solver(p, strategy=lbm.FUSED, tile_rows=tile_rows)
+    s.step(77)
+    assert _rel_err(s.density(), ref[77], p.mask) <= REL_TOL
+
+
+def test_autotune_keeps_the_physics(lbm):
+    """Autotuning runs ordinary steps with each variant and keeps the fastest;
+    the state afterwards still follows the oracle."""
+    p = PROBLEMS["drain_trt"]
+    s = lbm.Solver(p)
+    rep = s.autotune(4)
+    n_var = len(rep.strip().splitlines())
+    assert n_var == 4  # three tile heights and the split step
+    total = s.t
+    assert total == n_var * (4 + 2)
+    s.step(200 - total)
+    ref = _oracle_series(p, (200,))
+    assert _rel_err(s.density(), ref[200], p.mask) <= REL_TOL
 
 
 @pytest.mark.parametrize("name", ["drain_srt", "drain_mrt", "droplet_wall_mrt", "set2"])

@@ -1,0 +1,151 @@
+"""D3Q19 against the FP64 oracle (1e-5 relative over 200 steps), and the two
+reduced-precision variants: FP32 node arithmetic and BF16-deviation storage,
+whose error against the oracle is measured and bounded here."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2111_08666_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+REL_TOL = 1e-5
+CHECKPOINTS = (1, 10, 50, 100, 200)
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_08666_amd import lbm as L
+    L.lib()
+    return L
+
+
+def problems3d():
+    out = {}
+    # open drainage through Boolean spheres; 40 x 20 x 18 is one ragged x tile,
+    # 3 ragged y tiles and one z chunk
+    m = I.sphere_medium(40, 20, 18, 2.0, 4.0, 0.6, seed=5)
+    r0 = I.reservoir_front(m, 8, 1.0, 0.027)
+    out["d3_drain_trt"] = I.Problem(q=19, mask=m, rho0=r0, periodic=0, open_x=1, porous_x0=8,
+                                    porous_x1=32, tau=I.TAU_M10, G=3.5, xi=I.xi_of_theta(60),
+                                    rho_in1=1.015, collision=2)
+    out["d3_drain_srt"] = I.Problem(q=19, mask=m, rho0=r0, periodic=0, open_x=1, porous_x0=8,
+                                    porous_x1=32, tau=(1.0, 0.8), G=3.5, xi=I.xi_of_theta(45),
+                                    rho_in1=1.02, collision=0)
+    # fully periodic droplet with z chunks (nz = 72 -> several chunks)
+    n = (24, 20, 72)
+    mask = np.zeros(n[::-1], np.uint8)
+    r0 = I.tanh_droplet(n[::-1], (12, 10, 36), 7, (1.0, 0.027), (0.027, 1.0))
+    out["d3_droplet_periodic_chunks"] = I.Problem(q=19, mask=mask, rho0=r0, periodic=7, open_x=0,
+                                                  tau=(1.0, 1.0), G=3.5, collision=0)
+    # closed y/z walls, periodic x, sessile droplet on the z = 0 wall, TRT
+    mask = np.zeros((26, 18, 66), np.uint8)
+    mask[0] = mask[-1] = 1
+    mask[:, 0] = mask[:, -1] = 1
+    r0 = I.tanh_droplet(mask.shape, (33, 9, 0.5), 8, (1.0, 0.027), (0.027, 1.0), mask=mask)
+    out["d3_sessile_trt"] = I.Problem(q=19, mask=mask, rho0=r0, periodic=1, open_x=0,
+                                      tau=(1.7, 0.62), G=3.5, xi=-0.3, collision=2)
+    return out
+
+
+P3 = problems3d()
+
+
+def _series(p, solver, checkpoints):
+    o = O.OracleSim(p)
+    t = 0
+    errs = []
+    fluid = ~p.mask.astype(bool)
+    for c in checkpoints:
+        o.step(c - t)
+        solver.step(c - t)
+        t = c
+        ref = o.density()
+        g = solver.density().astype(np.float64)
+        errs.append(float((np.abs(g - ref) / np.abs(ref))[:, fluid].max()))
+    return errs
+
+
+@pytest.mark.parametrize("strategy", ["fused", "split"])
+@pytest.mark.parametrize("name", sorted(P3))
+def test_d3q19_density_parity_200_steps(lbm, name, strategy):
+    p = P3[name]
+    print(f"[parity3d] {name} {p.mask.shape} {strategy}", flush=True)
+    s = lbm.Solver(p, strategy=lbm.FUSED if strategy == "fused" else lbm.SPLIT)
+    errs = _series(p, s, CHECKPOINTS)
+    print(f"[parity3d] {name} {strategy} errors {['%.1e' % e for e in errs]}", flush=True)
+    assert max(errs) <= REL_TOL, errs
+
+
+def test_d3q19_observables(lbm):
+    p = P3["d3_drain_trt"]
+    o, s = O.OracleSim(p), lbm.Solver(p)
+    o.step(100)
+    s.step(100)
+    a, b = o.observables(), s.observables()
+    assert a["n_in"] == b["n_in"] and a["n_window"] == b["n_window"]
+    for c in range(2):
+        assert abs(a["mass"][c] - b["mass"][c]) <= 1e-6 * a["mass"][c]
+    assert abs(a["pc"] - b["pc"]) <= 1e-6
+
+
+def _drain2d():
+    return I.drainage_2d(nx=127, ny=37, r=(2.0, 5.0), porosity=0.7, seed=12, G=3.5, theta=60,
+                         tau=I.TAU_M10, rho_in1=1.01, minor=0.027, collision=1)
+
+
+# Stated bounds for the reduced-precision variants (200 steps, fluid nodes,
+# relative to the FP64 oracle).  Measured values are printed by the tests.
+F32_MATH_BOUND = 2e-4
+BF16_BOUND = 2e-2
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_fp32_math_error_is_bounded(lbm, q):
+    p = _drain2d() if q == 9 else P3["d3_drain_trt"]
+    errs = _series(p, lbm.Solver(p, math=lbm.MATH_F32), CHECKPOINTS)
+    print(f"[fp32-math] q={q} errors {['%.1e' % e for e in errs]}", flush=True)
+    assert max(errs) <= F32_MATH_BOUND, errs
+
+
+@pytest.mark.parametrize("strategy", ["fused", "split"])
+@pytest.mark.parametrize("q", [9, 19])
+def test_bf16_deviation_storage_error_is_bounded(lbm, q, strategy):
+    p = _drain2d() if q == 9 else P3["d3_drain_trt"]
+    s = lbm.Solver(p, storage=lbm.STORE_BF16DEV, strategy=lbm.FUSED if strategy == "fused" else lbm.SPLIT)
+    errs = _series(p, s, CHECKPOINTS)
+    print(f"[bf16-dev] q={q} {strategy} errors {['%.1e' % e for e in errs]}", flush=True)
+    assert max(errs) <= BF16_BOUND, errs
+
+
+def test_bf16_storage_conserves_mass_in_a_closed_box(lbm):
+    """Densities are stored exactly (FP32) and f0 is implied by them, so a
+    closed box keeps each component's mass to FP32 rounding of the sums."""
+    p = I.drainage_2d(nx=96, ny=40, r=(2.0, 5.0), porosity=0.7, seed=9, G=3.5, theta=60,
+                      tau=I.TAU_M10, minor=0.027, collision=1)
+    p.open_x, p.periodic = 0, 1
+    drift = {}
+    for st in (lbm.STORE_BF16DEV, lbm.STORE_F32):
+        s = lbm.Solver(p, storage=st)
+        m0 = s.observables()["mass"]
+        s.step(1000)
+        m1 = s.observables()["mass"]
+        drift[st] = [abs(m1[c] - m0[c]) / m0[c] for c in range(2)]
+    print(f"[mass] relative drift over 1000 steps: bf16-dev {drift[lbm.STORE_BF16DEV]}, "
+          f"f32 {drift[lbm.STORE_F32]}", flush=True)
+    assert max(drift[lbm.STORE_BF16DEV]) <= 1e-5
+
+
+def test_bf16_batch_matches_single(lbm):
+    ps = [_drain2d(), I.drainage_2d(nx=64, ny=30, r=(2.0, 4.0), porosity=0.7, seed=31, G=3.5,
+                                    theta=100, tau=I.TAU_M10, rho_in1=1.015, minor=0.027,
+                                    collision=1)]
+    b = lbm.BatchSolver(ps, storage=lbm.STORE_BF16DEV)
+    b.step(30)
+    for i, p in enumerate(ps):
+        s = lbm.Solver(p, storage=lbm.STORE_BF16DEV)
+        s.step(30)
+        assert np.array_equal(b.density(i), s.density())
