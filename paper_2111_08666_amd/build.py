@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = [os.path.join(HERE, "csrc", s) for s in ("lbm_kernels.hip", "lbm_api.cpp")]
+SOURCES = [os.path.join(HERE, "csrc", s) for s in ("lbm_kernels.hip", "lbm_api.cpp", "unet_kernels.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

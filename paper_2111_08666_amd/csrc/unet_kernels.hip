@@ -1,0 +1,623 @@
+// U-Net surrogate kernels for gfx950: implicit-GEMM convolutions on the BF16
+// matrix cores (v_mfma_f32_32x32x16_bf16, FP32 accumulation), pooling,
+// transposed convolution, the sigmoid head with a masked cross-entropy loss,
+// and Adam.  C ABI in include/unet.h.
+//
+// MFMA operand layout (one wave, 32x32 output tile, K = 16 per instruction):
+//   A fragment, lane l: A[row = l % 32][k = 8 * (l / 32) + j], j = 0..7
+//   B fragment, lane l: B[k = 8 * (l / 32) + j][col = l % 32]
+//   C, lane l, register r: C[row = 8 * (r / 4) + 4 * (l / 32) + r % 4][col = l % 32]
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/unet.h"
+
+namespace unet {
+
+typedef __bf16 bf16x8 __attribute__((__vector_size__(8 * sizeof(__bf16))));
+typedef float floatx16 __attribute__((__vector_size__(16 * sizeof(float))));
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ uint16_t f2bf(float v) {
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 load8(const uint16_t *p) {
+  const uint4 v = *reinterpret_cast<const uint4 *>(p);
+  return __builtin_bit_cast(bf16x8, v);
+}
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0)); }
+__device__ __forceinline__ bf16x8 pack8(const uint16_t (&v)[8]) {
+  uint4 u;
+  u.x = v[0] | ((uint32_t)v[1] << 16);
+  u.y = v[2] | ((uint32_t)v[3] << 16);
+  u.z = v[4] | ((uint32_t)v[5] << 16);
+  u.w = v[6] | ((uint32_t)v[7] << 16);
+  return __builtin_bit_cast(bf16x8, u);
+}
+
+__device__ __forceinline__ floatx16 mfma(bf16x8 a, bf16x8 b, floatx16 c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ int c_row(int r, int lane) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }
+
+// ---------------------------------------------------------------------------
+// one MFMA, for checking the operand layout: C(32x32) = A(32x16) B(16x32),
+// row-major, A/B BF16, C FP32
+// ---------------------------------------------------------------------------
+__global__ void mfma_probe_kernel(const uint16_t *A, const uint16_t *B, float *C) {
+  const int l = threadIdx.x;
+  uint16_t a[8], b[8];
+  for (int j = 0; j < 8; ++j) {
+    a[j] = A[(l % 32) * 16 + 8 * (l / 32) + j];
+    b[j] = B[(8 * (l / 32) + j) * 32 + (l % 32)];
+  }
+  floatx16 acc = {};
+  acc = mfma(pack8(a), pack8(b), acc);
+  for (int r = 0; r < 16; ++r) C[c_row(r, l) * 32 + (l % 32)] = acc[r];
+}
+
+// ---------------------------------------------------------------------------
+// Implicit-GEMM forward: C[p][co] = sum_k A(p, k) B(k, co).  Block = 4 waves,
+// 64 x 64 output tile (2 x 2 waves of 32 x 32).
+//   MODE 0, 3x3 convolution:  k = (tap, ci), A = x[p + off(tap)][ci] (zero
+//          outside), B = w[co][tap][ci]; output at p.
+//   MODE 1, transposed 2x2 convolution, tap = blockIdx.z: k = ci,
+//          A = x[p][ci], B = w[co][tap][ci]; output at 2p + tap (grid 2h x 2w).
+//   MODE 2, data gradient of the transposed convolution: k = (tap, co'),
+//          A = dy[2p + tap][co'], B = wt[ci][tap][co'] (here the output
+//          channel is ci, the reduction channel co').
+// K chunks of 8 never straddle a tap because channel counts are multiples of 8.
+// ---------------------------------------------------------------------------
+struct GemmArgs {
+  const uint16_t *x;  // A source
+  int n, h, w;        // A-source grid for MODE 0/1 (= output grid for MODE 0); input grid for MODE 2
+  int kc;             // reduction channels (cin for MODE 0/1, cout' for MODE 2)
+  int x_cs, x_co;
+  const uint16_t *wgt;
+  const float *bias;
+  int nout;           // output channels
+  uint16_t *y;
+  int y_cs, y_co;
+  int relu;
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) void igemm_fwd(GemmArgs a) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int64_t P = (int64_t)a.n * a.h * a.w;  // rows of A (pixels of the A grid)
+  const int64_t pix = (int64_t)blockIdx.x * 64 + wm * 32 + (lane & 31);
+  const int col = blockIdx.y * 64 + wn * 32 + (lane & 31);
+  const int tap_z = MODE == 1 ? (int)blockIdx.z : 0;
+  const int half = lane >> 5;
+  const int ntap = MODE == 0 ? 9 : (MODE == 2 ? 4 : 1);
+  const int K = ntap * a.kc;
+  const int wtap = MODE == 1 ? 4 : ntap;  // taps per weight row
+  int pn = 0, py = 0, px = 0;
+  const bool prow = pix < P;
+  if (prow) {
+    pn = (int)(pix / ((int64_t)a.h * a.w));
+    const int r = (int)(pix - (int64_t)pn * a.h * a.w);
+    py = r / a.w;
+    px = r - py * a.w;
+  }
+  floatx16 acc = {};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const int kk = k0 + 8 * half;
+    bf16x8 A = zero8(), B = zero8();
+    if (kk < K) {
+      const int tap = MODE == 1 ? tap_z : kk / a.kc;
+      const int ch = kk - (MODE == 1 ? 0 : tap * a.kc);
+      if (prow) {
+        if constexpr (MODE == 0) {
+          const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+          if (yy >= 0 && yy < a.h && xx >= 0 && xx < a.w)
+            A = load8(a.x + ((int64_t)pn * a.h * a.w + (int64_t)yy * a.w + xx) * a.x_cs + a.x_co + ch);
+        } else if constexpr (MODE == 1) {
+          A = load8(a.x + pix * a.x_cs + a.x_co + ch);
+        } else {
+          const int H2 = 2 * a.h, W2 = 2 * a.w;
+          const int yy = 2 * py + (tap >> 1), xx = 2 * px + (tap & 1);
+          A = load8(a.x + ((int64_t)pn * H2 * W2 + (int64_t)yy * W2 + xx) * a.x_cs + a.x_co + ch);
+        }
+      }
+      if (col < a.nout) B = load8(a.wgt + ((int64_t)col * wtap + tap) * a.kc + ch);
+    }
+    acc = mfma(A, B, acc);
+  }
+  if (col >= a.nout) return;
+  const float bv = a.bias ? a.bias[col] : 0.f;
+  for (int r = 0; r < 16; ++r) {
+    const int64_t p = (int64_t)blockIdx.x * 64 + wm * 32 + c_row(r, lane);
+    if (p >= P) continue;
+    float v = acc[r] + bv;
+    if (a.relu) v = v > 0.f ? v : 0.f;
+    int64_t o;
+    if constexpr (MODE == 1) {
+      const int qn = (int)(p / ((int64_t)a.h * a.w));
+      const int rr = (int)(p - (int64_t)qn * a.h * a.w);
+      const int qy = rr / a.w, qx = rr - qy * a.w;
+      const int H2 = 2 * a.h, W2 = 2 * a.w;
+      o = (int64_t)qn * H2 * W2 + (int64_t)(2 * qy + (tap_z >> 1)) * W2 + 2 * qx + (tap_z & 1);
+    } else {
+      o = p;
+    }
+    a.y[o * a.y_cs + a.y_co + col] = f2bf(v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradients (split over pixels): partial[kb][m][n] = sum over this
+// block's pixel chunk of A(m, p) B(p, n).
+//   MODE 0, 3x3: m = co, n = (tap, ci): A = dy[p][co], B = x[p + off(tap)][ci]
+//   MODE 1, transposed 2x2, tap = blockIdx.z: m = co, n = ci:
+//          A = dy[2p + tap][co], B = x[p][ci]  (p over the input grid)
+// Operands are staged through LDS as [pixel][channel] tiles, 32 pixels at a
+// time, and read transposed into the MFMA fragments.
+// ---------------------------------------------------------------------------
+constexpr int kWgradPix = 512;  // pixels per block
+
+struct WgradArgs {
+  const uint16_t *x;
+  int n, h, w, cin, x_cs, x_co;   // x grid (input grid for MODE 1)
+  const uint16_t *dy;
+  int cout, dy_cs, dy_co;
+  float *partial;                 // [kblocks][ntap][cout][ncol]
+  int ncol;                       // MODE 0: 9 * cin; MODE 1: cin
+};
+
+template <int MODE>
+__global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
+  __shared__ uint16_t sA[32][64 + 8];  // [pixel][m]
+  __shared__ uint16_t sB[32][64 + 8];  // [pixel][n]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int half = lane >> 5;
+  const int64_t P = (int64_t)a.n * a.h * a.w;
+  const int64_t p_begin = (int64_t)blockIdx.x * kWgradPix;
+  const int m0 = blockIdx.y * 64;  // output channel block
+  const int tapz = MODE == 1 ? (int)(blockIdx.z % 4) : 0;
+  const int nblk = MODE == 1 ? (int)(blockIdx.z / 4) : (int)blockIdx.z;
+  const int n0 = nblk * 64;         // column block
+  floatx16 acc = {};
+  for (int pc = 0; pc < kWgradPix; pc += 32) {
+    // stage 32 pixels x 64 m and 32 pixels x 64 n
+    for (int e = tid; e < 32 * 64; e += 256) {
+      const int pl = e >> 6, c = e & 63;
+      const int64_t p = p_begin + pc + pl;
+      uint16_t va = 0, vb = 0;
+      if (p < P) {
+        const int pn = (int)(p / ((int64_t)a.h * a.w));
+        const int r = (int)(p - (int64_t)pn * a.h * a.w);
+        const int py = r / a.w, px = r - py * a.w;
+        const int m = m0 + c;
+        if (m < a.cout) {
+          if constexpr (MODE == 0) {
+            va = a.dy[p * a.dy_cs + a.dy_co + m];
+          } else {
+            const int H2 = 2 * a.h, W2 = 2 * a.w;
+            const int64_t q = (int64_t)pn * H2 * W2 + (int64_t)(2 * py + (tapz >> 1)) * W2 + 2 * px + (tapz & 1);
+            va = a.dy[q * a.dy_cs + a.dy_co + m];
+          }
+        }
+        const int nn = n0 + c;
+        if (nn < a.ncol) {
+          if constexpr (MODE == 0) {
+            const int tap = nn / a.cin, ci = nn - tap * a.cin;
+            const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+            if (yy >= 0 && yy < a.h && xx >= 0 && xx < a.w)
+              vb = a.x[((int64_t)pn * a.h * a.w + (int64_t)yy * a.w + xx) * a.x_cs + a.x_co + ci];
+          } else {
+            vb = a.x[p * a.x_cs + a.x_co + nn];
+          }
+        }
+      }
+      sA[pl][c] = va;
+      sB[pl][c] = vb;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < 32; ks += 16) {
+      uint16_t av[8], bv[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        av[j] = sA[ks + 8 * half + j][wm * 32 + (lane & 31)];
+        bv[j] = sB[ks + 8 * half + j][wn * 32 + (lane & 31)];
+      }
+      acc = mfma(pack8(av), pack8(bv), acc);
+    }
+    __syncthreads();
+  }
+  const int ntap = MODE == 1 ? 4 : 1;
+  const int nn = n0 + wn * 32 + (lane & 31);
+  if (nn >= a.ncol) return;
+  float *out = a.partial + ((int64_t)blockIdx.x * ntap + tapz) * (int64_t)a.cout * a.ncol;
+  for (int r = 0; r < 16; ++r) {
+    const int m = m0 + wm * 32 + c_row(r, lane);
+    if (m < a.cout) out[(int64_t)m * a.ncol + nn] = acc[r];
+  }
+}
+
+// dw[m][tap][n] (+)= sum over kblocks of partial[kb][tap][m][n], fixed order.
+// For MODE 0 ntap = 1 and n = (tap, ci) already.
+__global__ void wgrad_reduce(const float *partial, int kblocks, int ntap, int cout, int ncol, float *dw,
+                             int accumulate) {
+  const int64_t total = (int64_t)ntap * cout * ncol;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int tap = (int)(e / ((int64_t)cout * ncol));
+    const int64_t rem = e - (int64_t)tap * cout * ncol;
+    const int m = (int)(rem / ncol), n = (int)(rem - (int64_t)m * ncol);
+    float s = 0.f;
+    for (int kb = 0; kb < kblocks; ++kb) s += partial[(int64_t)kb * total + e];
+    const int64_t o = ((int64_t)m * ntap + tap) * ncol + n;  // [co][tap][ci]
+    dw[o] = accumulate ? dw[o] + s : s;
+  }
+}
+
+// bias gradient: db[c] (+)= sum_p dy[p][c] over a pixel grid, fixed order
+__global__ void bias_grad(const uint16_t *dy, int64_t P, int c, int cs, int co, float *db, int accumulate) {
+  const int ch = blockIdx.x;
+  float s = 0.f;
+  for (int64_t p = threadIdx.x; p < P; p += blockDim.x) s += bf2f(dy[p * cs + co + ch]);
+  __shared__ float red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) db[ch] = accumulate ? db[ch] + red[0] : red[0];
+}
+
+// wt[ci][ky][kx][co] = w[co][2-ky][2-kx][ci]
+__global__ void conv_flip(const uint16_t *w, int cout, int cin, uint16_t *wt) {
+  const int64_t total = (int64_t)cout * 9 * cin;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int co = (int)(e / (9 * cin));
+    const int r = (int)(e - (int64_t)co * 9 * cin);
+    const int tap = r / cin, ci = r - tap * cin;
+    wt[((int64_t)ci * 9 + (8 - tap)) * cout + co] = w[e];
+  }
+}
+
+// wt[ci][tap][co] = w[co][tap][ci] (2x2 taps)
+__global__ void up_rearrange(const uint16_t *w, int cout, int cin, uint16_t *wt) {
+  const int64_t total = (int64_t)cout * 4 * cin;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int co = (int)(e / (4 * cin));
+    const int r = (int)(e - (int64_t)co * 4 * cin);
+    const int tap = r / cin, ci = r - tap * cin;
+    wt[((int64_t)ci * 4 + tap) * cout + co] = w[e];
+  }
+}
+
+__global__ void relu_bwd_kernel(const uint16_t *y, int64_t n_pix, int c, int y_cs, int y_co, uint16_t *dy,
+                                int dy_cs, int dy_co) {
+  const int64_t total = n_pix * c;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / c;
+    const int ch = (int)(e - p * c);
+    if (!(bf2f(y[p * y_cs + y_co + ch]) > 0.f)) dy[p * dy_cs + dy_co + ch] = 0;
+  }
+}
+
+__global__ void maxpool_fwd_kernel(const uint16_t *x, int n, int h, int w, int c, int x_cs, int x_co, uint16_t *y,
+                                   int y_cs, int y_co) {
+  const int h2 = h / 2, w2 = w / 2;
+  const int64_t total = (int64_t)n * h2 * w2 * c;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int ch = (int)(e % c);
+    const int64_t q = e / c;
+    const int qn = (int)(q / ((int64_t)h2 * w2));
+    const int r = (int)(q - (int64_t)qn * h2 * w2);
+    const int qy = r / w2, qx = r - qy * w2;
+    float m = -INFINITY;
+    uint16_t best = 0;
+    for (int a = 0; a < 2; ++a)
+      for (int b = 0; b < 2; ++b) {
+        const uint16_t v = x[((int64_t)qn * h * w + (int64_t)(2 * qy + a) * w + 2 * qx + b) * x_cs + x_co + ch];
+        if (bf2f(v) > m) { m = bf2f(v); best = v; }
+      }
+    y[q * y_cs + y_co + ch] = best;
+  }
+}
+
+__global__ void maxpool_bwd_kernel(const uint16_t *x, int n, int h, int w, int c, int x_cs, int x_co,
+                                   const uint16_t *dy, int dy_cs, int dy_co, uint16_t *dx, int dx_cs, int dx_co,
+                                   int accumulate) {
+  const int h2 = h / 2, w2 = w / 2;
+  const int64_t total = (int64_t)n * h2 * w2 * c;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int ch = (int)(e % c);
+    const int64_t q = e / c;
+    const int qn = (int)(q / ((int64_t)h2 * w2));
+    const int r = (int)(q - (int64_t)qn * h2 * w2);
+    const int qy = r / w2, qx = r - qy * w2;
+    float m = -INFINITY;
+    int arg = 0;
+    for (int k = 0; k < 4; ++k) {
+      const float v = bf2f(x[((int64_t)qn * h * w + (int64_t)(2 * qy + k / 2) * w + 2 * qx + k % 2) * x_cs + x_co + ch]);
+      if (v > m) { m = v; arg = k; }
+    }
+    const uint16_t g = dy[q * dy_cs + dy_co + ch];
+    for (int k = 0; k < 4; ++k) {
+      uint16_t *d = dx + ((int64_t)qn * h * w + (int64_t)(2 * qy + k / 2) * w + 2 * qx + k % 2) * dx_cs + dx_co + ch;
+      if (accumulate) {
+        if (k == arg) *d = f2bf(bf2f(*d) + bf2f(g));
+      } else {
+        *d = k == arg ? g : 0;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ float head_logit(const uint16_t *x, int64_t p, int c, int x_cs, const float *w, float b) {
+  float z = b;
+  for (int ch = 0; ch < c; ++ch) z += w[ch] * bf2f(x[p * x_cs + ch]);
+  return z;
+}
+
+__global__ void head_fwd_kernel(const uint16_t *x, int64_t n_pix, int c, int x_cs, const float *w, const float *b,
+                                float *sat) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n_pix; p += (int64_t)gridDim.x * blockDim.x)
+    sat[p] = 1.f / (1.f + __expf(-head_logit(x, p, c, x_cs, w, b[0])));
+}
+
+// Per pixel: logit z, loss term l = softplus(z) - t z (binary cross-entropy
+// written on the logit), gradient g = (sigmoid(z) - t) * scale on masked
+// pixels (0 elsewhere), and dx = g w.  g and l go to scratch for the sums.
+__global__ void head_loss_pix(const uint16_t *x, int64_t n_pix, int c, int x_cs, const float *w, const float *b,
+                              const float *t, const uint8_t *mask, float scale, uint16_t *dx, float *g_out,
+                              float *l_out) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < n_pix; p += (int64_t)gridDim.x * blockDim.x) {
+    const float z = head_logit(x, p, c, x_cs, w, b[0]);
+    const bool on = mask[p] != 0;
+    const float sp = fmaxf(z, 0.f) + log1pf(__expf(-fabsf(z)));
+    const float s = 1.f / (1.f + __expf(-z));
+    const float g = on ? (s - t[p]) * scale : 0.f;
+    g_out[p] = g;
+    l_out[p] = on ? (sp - t[p] * z) * scale : 0.f;
+    if (dx)
+      for (int ch = 0; ch < c; ++ch) dx[p * c + ch] = f2bf(g * w[ch]);
+  }
+}
+
+// Block partials over a pixel chunk: threads = (256 / c) pixel lanes x c
+// channels.  out[block] = {sum l, sum g, sum g x[.][0..c)}.
+constexpr int kHeadPix = 4096;
+__global__ void head_loss_sums(const uint16_t *x, int64_t n_pix, int c, int x_cs, const float *g, const float *l,
+                               float *partial) {
+  __shared__ float red[256];
+  __shared__ float red_l[256], red_g[256];
+  const int lanes = 256 / c;
+  const int pl = threadIdx.x / c, ch = threadIdx.x - pl * c;
+  const int64_t p0 = (int64_t)blockIdx.x * kHeadPix;
+  float a = 0.f, sl = 0.f, sg = 0.f;
+  for (int k = pl; k < kHeadPix; k += lanes) {
+    const int64_t p = p0 + k;
+    if (p >= n_pix) break;
+    a += g[p] * bf2f(x[p * x_cs + ch]);
+    if (ch == 0) { sl += l[p]; sg += g[p]; }
+  }
+  red[threadIdx.x] = a;
+  red_l[threadIdx.x] = sl;
+  red_g[threadIdx.x] = sg;
+  __syncthreads();
+  if (threadIdx.x < (unsigned)c) {
+    float s = 0.f;
+    for (int q = 0; q < lanes; ++q) s += red[q * c + threadIdx.x];
+    partial[(int64_t)blockIdx.x * (2 + c) + 2 + threadIdx.x] = s;
+  }
+  if (threadIdx.x == 0) {
+    float s1 = 0.f, s2 = 0.f;
+    for (int q = 0; q < lanes; ++q) { s1 += red_l[q * c]; s2 += red_g[q * c]; }
+    partial[(int64_t)blockIdx.x * (2 + c)] = s1;
+    partial[(int64_t)blockIdx.x * (2 + c) + 1] = s2;
+  }
+}
+
+__global__ void head_loss_final(const float *partial, int blocks, int c, float *loss, float *dw, float *db) {
+  const int k = threadIdx.x;
+  if (k >= 2 + c) return;
+  float s = 0.f;
+  for (int b = 0; b < blocks; ++b) s += partial[(int64_t)b * (2 + c) + k];
+  if (k == 0) loss[0] = s;
+  else if (k == 1) { if (db) db[0] = s; }
+  else if (dw) dw[k - 2] = s;
+}
+
+__global__ void adam_kernel(float *p, const float *g, float *m, float *v, uint16_t *pb, int64_t n, float lr, float b1,
+                            float b2, float eps, float c1, float c2) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float pi = p[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    p[i] = pi;
+    if (pb) pb[i] = f2bf(pi);
+  }
+}
+
+__global__ void to_bf16_kernel(const float *x, uint16_t *y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = f2bf(x[i]);
+}
+__global__ void to_f32_kernel(const uint16_t *x, float *y, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = bf2f(x[i]);
+}
+
+static int grid1d(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (int)(b < 1 ? 1 : (b > 16384 ? 16384 : b));
+}
+static int launched() { return hipGetLastError() == hipSuccess ? 0 : -100; }
+static bool ok8(int v) { return v > 0 && v % 8 == 0; }
+
+}  // namespace unet
+
+using namespace unet;
+
+extern "C" {
+
+int unet_mfma_probe(const uint16_t *A, const uint16_t *B, float *C, void *s) {
+  mfma_probe_kernel<<<1, 64, 0, (hipStream_t)s>>>(A, B, C);
+  return launched();
+}
+
+int unet_conv3x3_fwd(const uint16_t *x, int n, int h, int w, int cin, int x_cs, int x_co, const uint16_t *wgt,
+                     const float *bias, int cout, uint16_t *y, int y_cs, int y_co, int relu, void *s) {
+  if (!x || !wgt || !y || n < 1 || h < 1 || w < 1 || !ok8(cin) || x_cs % 8 || x_co % 8 || x_co + cin > x_cs ||
+      cout < 1 || y_co + cout > y_cs)
+    return -1;
+  GemmArgs a{x, n, h, w, cin, x_cs, x_co, wgt, bias, cout, y, y_cs, y_co, relu};
+  const int64_t P = (int64_t)n * h * w;
+  dim3 g((unsigned)((P + 63) / 64), (unsigned)((cout + 63) / 64), 1);
+  igemm_fwd<0><<<g, 256, 0, (hipStream_t)s>>>(a);
+  return launched();
+}
+
+int unet_conv3x3_flip(const uint16_t *wgt, int cout, int cin, uint16_t *wt, void *s) {
+  if (!wgt || !wt || cout < 1 || cin < 1) return -1;
+  conv_flip<<<grid1d((int64_t)cout * 9 * cin), 256, 0, (hipStream_t)s>>>(wgt, cout, cin, wt);
+  return launched();
+}
+
+int64_t unet_wgrad_scratch_floats(int n, int h, int w, int cin, int cout, int taps) {
+  const int64_t P = (int64_t)n * h * w;
+  const int64_t kb = (P + kWgradPix - 1) / kWgradPix;
+  return kb * (int64_t)cout * cin * taps;
+}
+
+int unet_conv3x3_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs, int x_co, const uint16_t *dy,
+                       int cout, int dy_cs, int dy_co, float *dw, float *db, float *partial, int accumulate,
+                       void *s) {
+  if (!x || !dy || !dw || !partial || n < 1 || h < 1 || w < 1 || cin < 1 || cout < 1 || x_co + cin > x_cs ||
+      dy_co + cout > dy_cs)
+    return -1;
+  const int64_t P = (int64_t)n * h * w;
+  const int kb = (int)((P + kWgradPix - 1) / kWgradPix);
+  WgradArgs a{x, n, h, w, cin, x_cs, x_co, dy, cout, dy_cs, dy_co, partial, 9 * cin};
+  dim3 g((unsigned)kb, (unsigned)((cout + 63) / 64), (unsigned)((9 * cin + 63) / 64));
+  igemm_wgrad<0><<<g, 256, 0, (hipStream_t)s>>>(a);
+  wgrad_reduce<<<grid1d((int64_t)cout * 9 * cin), 256, 0, (hipStream_t)s>>>(partial, kb, 1, cout, 9 * cin, dw,
+                                                                             accumulate);
+  if (db) bias_grad<<<cout, 256, 0, (hipStream_t)s>>>(dy, P, cout, dy_cs, dy_co, db, accumulate);
+  return launched();
+}
+
+int unet_relu_bwd(const uint16_t *y, int n_pix, int c, int y_cs, int y_co, uint16_t *dy, int dy_cs, int dy_co,
+                  void *s) {
+  if (!y || !dy || n_pix < 1 || c < 1) return -1;
+  relu_bwd_kernel<<<grid1d((int64_t)n_pix * c), 256, 0, (hipStream_t)s>>>(y, n_pix, c, y_cs, y_co, dy, dy_cs, dy_co);
+  return launched();
+}
+
+int unet_maxpool_fwd(const uint16_t *x, int n, int h, int w, int c, int x_cs, int x_co, uint16_t *y, int y_cs,
+                     int y_co, void *s) {
+  if (!x || !y || n < 1 || h < 2 || w < 2 || (h & 1) || (w & 1) || c < 1) return -1;
+  maxpool_fwd_kernel<<<grid1d((int64_t)n * h * w * c / 4), 256, 0, (hipStream_t)s>>>(x, n, h, w, c, x_cs, x_co, y,
+                                                                                       y_cs, y_co);
+  return launched();
+}
+
+int unet_maxpool_bwd(const uint16_t *x, int n, int h, int w, int c, int x_cs, int x_co, const uint16_t *dy,
+                     int dy_cs, int dy_co, uint16_t *dx, int dx_cs, int dx_co, int accumulate, void *s) {
+  if (!x || !dy || !dx || n < 1 || h < 2 || w < 2 || (h & 1) || (w & 1) || c < 1) return -1;
+  maxpool_bwd_kernel<<<grid1d((int64_t)n * h * w * c / 4), 256, 0, (hipStream_t)s>>>(
+      x, n, h, w, c, x_cs, x_co, dy, dy_cs, dy_co, dx, dx_cs, dx_co, accumulate);
+  return launched();
+}
+
+int unet_upconv_fwd(const uint16_t *x, int n, int h, int w, int cin, int x_cs, int x_co, const uint16_t *wgt,
+                    const float *bias, int cout, uint16_t *y, int y_cs, int y_co, void *s) {
+  if (!x || !wgt || !y || n < 1 || h < 1 || w < 1 || !ok8(cin) || x_cs % 8 || x_co % 8 || cout < 1 ||
+      y_co + cout > y_cs)
+    return -1;
+  GemmArgs a{x, n, h, w, cin, x_cs, x_co, wgt, bias, cout, y, y_cs, y_co, 0};
+  const int64_t P = (int64_t)n * h * w;
+  dim3 g((unsigned)((P + 63) / 64), (unsigned)((cout + 63) / 64), 4);
+  igemm_fwd<1><<<g, 256, 0, (hipStream_t)s>>>(a);
+  return launched();
+}
+
+int unet_upconv_bwd_data(const uint16_t *dy, int n, int h, int w, int cout, int dy_cs, int dy_co,
+                         const uint16_t *wgt, int cin, uint16_t *wt, uint16_t *dx, int dx_cs, int dx_co, void *s) {
+  if (!dy || !wgt || !wt || !dx || n < 1 || h < 1 || w < 1 || !ok8(cout) || dy_cs % 8 || dy_co % 8 || cin < 1 ||
+      dx_co + cin > dx_cs)
+    return -1;
+  up_rearrange<<<grid1d((int64_t)cout * 4 * cin), 256, 0, (hipStream_t)s>>>(wgt, cout, cin, wt);
+  // A = dy over the 2h x 2w grid gathered at 2p + tap, output grid h x w
+  GemmArgs a{dy, n, h, w, cout, dy_cs, dy_co, wt, nullptr, cin, dx, dx_cs, dx_co, 0};
+  const int64_t P = (int64_t)n * h * w;
+  dim3 g((unsigned)((P + 63) / 64), (unsigned)((cin + 63) / 64), 1);
+  igemm_fwd<2><<<g, 256, 0, (hipStream_t)s>>>(a);
+  return launched();
+}
+
+int unet_upconv_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs, int x_co, const uint16_t *dy,
+                      int cout, int dy_cs, int dy_co, float *dw, float *db, float *partial, void *s) {
+  if (!x || !dy || !dw || !partial || n < 1 || h < 1 || w < 1 || cin < 1 || cout < 1) return -1;
+  const int64_t P = (int64_t)n * h * w;
+  const int kb = (int)((P + kWgradPix - 1) / kWgradPix);
+  WgradArgs a{x, n, h, w, cin, x_cs, x_co, dy, cout, dy_cs, dy_co, partial, cin};
+  dim3 g((unsigned)kb, (unsigned)((cout + 63) / 64), (unsigned)(4 * ((cin + 63) / 64)));
+  igemm_wgrad<1><<<g, 256, 0, (hipStream_t)s>>>(a);
+  wgrad_reduce<<<grid1d((int64_t)4 * cout * cin), 256, 0, (hipStream_t)s>>>(partial, kb, 4, cout, cin, dw, 0);
+  if (db) bias_grad<<<cout, 256, 0, (hipStream_t)s>>>(dy, 4 * P, cout, dy_cs, dy_co, db, 0);
+  return launched();
+}
+
+int unet_head_fwd(const uint16_t *x, int n_pix, int c, int x_cs, const float *w, const float *b, float *sat,
+                  void *s) {
+  if (!x || !w || !b || !sat || n_pix < 1 || c < 1 || c > 256 || 256 % c) return -1;
+  head_fwd_kernel<<<grid1d(n_pix), 256, 0, (hipStream_t)s>>>(x, n_pix, c, x_cs, w, b, sat);
+  return launched();
+}
+
+int64_t unet_head_scratch_floats(int n_pix, int c) {
+  const int64_t blocks = ((int64_t)n_pix + kHeadPix - 1) / kHeadPix;
+  return 2 * (int64_t)n_pix + blocks * (2 + c);
+}
+
+int unet_head_loss_bwd(const uint16_t *x, int n_pix, int c, int x_cs, const float *w, const float *b,
+                       const float *target, const uint8_t *mask, float scale, float *loss, uint16_t *dx,
+                       float *dw, float *db, float *partial, void *s) {
+  if (!x || !w || !b || !target || !mask || !loss || !partial || n_pix < 1 || c < 1 || c > 256 || 256 % c)
+    return -1;
+  float *g = partial, *l = partial + n_pix, *sums = partial + 2 * (int64_t)n_pix;
+  const int blocks = (int)(((int64_t)n_pix + kHeadPix - 1) / kHeadPix);
+  head_loss_pix<<<grid1d(n_pix), 256, 0, (hipStream_t)s>>>(x, n_pix, c, x_cs, w, b, target, mask, scale, dx, g, l);
+  head_loss_sums<<<blocks, 256, 0, (hipStream_t)s>>>(x, n_pix, c, x_cs, g, l, sums);
+  head_loss_final<<<1, 512, 0, (hipStream_t)s>>>(sums, blocks, c, loss, dw, db);
+  return launched();
+}
+
+int unet_adam(float *p, const float *g, float *m, float *v, uint16_t *p_bf16, int64_t count, float lr, float beta1,
+              float beta2, float eps, int step, void *s) {
+  if (!p || !g || !m || !v || count < 1 || step < 1) return -1;
+  const float c1 = 1.f - powf(beta1, (float)step), c2 = 1.f - powf(beta2, (float)step);
+  adam_kernel<<<grid1d(count), 256, 0, (hipStream_t)s>>>(p, g, m, v, p_bf16, count, lr, beta1, beta2, eps, c1, c2);
+  return launched();
+}
+
+int unet_to_bf16(const float *x, uint16_t *y, int64_t count, void *s) {
+  if (!x || !y || count < 1) return -1;
+  to_bf16_kernel<<<grid1d(count), 256, 0, (hipStream_t)s>>>(x, y, count);
+  return launched();
+}
+
+int unet_to_f32(const uint16_t *x, float *y, int64_t count, void *s) {
+  if (!x || !y || count < 1) return -1;
+  to_f32_kernel<<<grid1d(count), 256, 0, (hipStream_t)s>>>(x, y, count);
+  return launched();
+}
+
+}  // extern "C"

@@ -20,6 +20,31 @@ def _declared():
     return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", src)))
 
 
+def test_every_unet_symbol_is_exported():
+    from paper_2111_08666_amd import surrogate
+    src = open(os.path.join(ROOT, "include", "unet.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = sorted(set(re.findall(r"\b(unet_[a-z0-9_]+)\s*\(", src)))
+    L = surrogate.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(surrogate.EXPORTS) == names
+
+
+def test_unet_rejects_bad_arguments_before_launch():
+    """Channel counts that break the 16-byte operand loads, or slices outside
+    the tensor, are refused without touching a device."""
+    from paper_2111_08666_amd import surrogate
+    L = surrogate.lib()
+    fake = 4096  # never dereferenced: validation fails first
+    assert L.unet_conv3x3_fwd(fake, 1, 8, 8, 12, 16, 0, fake, None, 32, fake, 32, 0, 1, None) == -1
+    assert L.unet_conv3x3_fwd(fake, 1, 8, 8, 16, 16, 8, fake, None, 32, fake, 32, 0, 1, None) == -1
+    assert L.unet_conv3x3_fwd(None, 1, 8, 8, 16, 16, 0, fake, None, 32, fake, 32, 0, 1, None) == -1
+    assert L.unet_maxpool_fwd(fake, 1, 7, 8, 8, 8, 0, fake, 8, 0, None) == -1
+    assert L.unet_head_fwd(fake, 64, 24, 24, fake, fake, fake, None) == -1
+    assert L.unet_wgrad_scratch_floats(2, 16, 16, 32, 64, 9) == 1 * 64 * 32 * 9
+
+
 def test_every_declared_symbol_is_exported():
     L = lbm.lib()
     names = _declared()

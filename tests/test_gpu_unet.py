@@ -1,0 +1,324 @@
+"""U-Net kernels (BF16 MFMA, FP32 accumulation) against the FP64 oracle.
+
+Inputs are BF16-representable, so the oracle sees exactly the values the
+kernels see.  Stated bounds:
+  - FP32 outputs (weight/bias gradients, loss, Adam): |gpu - ora| <=
+    1e-5 * sum of |terms| (FP32 accumulation of BF16 products);
+  - BF16 outputs (activations, data gradients): |gpu - ora| <= 2^-8 |ora| +
+    1e-5 * sum of |terms| (one rounding to BF16 after FP32 accumulation);
+  - the whole network (activations and data gradients rounded to BF16 at
+    every layer): the logits within 3 % and every gradient tensor within 5 %
+    in relative Frobenius norm.  Measured: 0.1-4 %, largest where a weight
+    gradient's pixel sum cancels (small problems, first layer).  The test
+    checks the wiring (slices, concatenation order, pooling routes, flipped
+    weights): a wiring mistake gives errors of order one.
+"""
+import numpy as np
+import pytest
+
+import oracle.unet_oracle as U
+
+pytestmark = pytest.mark.gpu
+
+U_BF16 = 2.0 ** -8
+
+
+@pytest.fixture(scope="module")
+def S():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_08666_amd import surrogate
+    surrogate.lib()
+    return surrogate
+
+
+def rng(seed):
+    return np.random.default_rng(seed)
+
+
+def bf16_round(S, a):
+    return S.bf16_to_float(S.bf16_bits(a)).astype(np.float64)
+
+
+def dev_bits(S, a):
+    import torch
+    return torch.from_numpy(S.bf16_bits(a).view(np.int16)).cuda()
+
+
+def host_bf16(S, t):
+    return S.bf16_to_float(t.cpu().numpy().view(np.uint16)).astype(np.float64)
+
+
+def dev_f32(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def zeros16(*shape):
+    import torch
+    return torch.zeros(shape, dtype=torch.int16, device="cuda")
+
+
+def zeros32(*shape):
+    import torch
+    return torch.zeros(shape, dtype=torch.float32, device="cuda")
+
+
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def test_mfma_operand_layout(S):
+    """One v_mfma_f32_32x32x16_bf16 reproduces C = A B for the lane layout the
+    kernels assume."""
+    r = rng(1)
+    A = bf16_round(S, r.normal(size=(32, 16)))
+    B = bf16_round(S, r.normal(size=(16, 32)))
+    C = zeros32(32, 32)
+    Ad, Bd = dev_bits(S, A), dev_bits(S, B)   # keep the device copies alive until the sync
+    S.call("unet_mfma_probe", S.ptr(Ad), S.ptr(Bd), S.ptr(C), None)
+    sync()
+    ref = A @ B
+    bound = 1e-6 * (np.abs(A) @ np.abs(B))
+    assert np.all(np.abs(C.cpu().numpy() - ref) <= bound + 1e-30)
+
+
+def _conv_case(S, seed, n, h, w, cin, cout, x_cs, x_co, y_cs, y_co):
+    r = rng(seed)
+    xfull = bf16_round(S, r.normal(size=(n, h, w, x_cs)))
+    wt = bf16_round(S, r.normal(0, 0.2, size=(cout, 3, 3, cin)))
+    b = r.normal(0, 0.1, size=cout).astype(np.float32).astype(np.float64)
+    return xfull, wt, b
+
+
+@pytest.mark.parametrize("relu", [0, 1])
+@pytest.mark.parametrize("n,h,w,cin,cout,x_cs,x_co,y_cs,y_co", [
+    (2, 9, 13, 24, 40, 32, 8, 48, 8),      # ragged pixel tile, ragged channel tile, slices
+    (1, 16, 16, 8, 32, 8, 0, 32, 0),       # first-layer shape
+    (1, 5, 70, 64, 96, 64, 0, 96, 0),      # K = 576, two channel tiles
+])
+def test_conv3x3_forward(S, relu, n, h, w, cin, cout, x_cs, x_co, y_cs, y_co):
+    xfull, wt, b = _conv_case(S, 10 + cin, n, h, w, cin, cout, x_cs, x_co, y_cs, y_co)
+    x = xfull[..., x_co:x_co + cin]
+    y = zeros16(n, h, w, y_cs)
+    sentinel = 0x1234
+    y.fill_(sentinel)
+    xd, wd, bd = dev_bits(S, xfull), dev_bits(S, wt), dev_f32(b)
+    S.call("unet_conv3x3_fwd", S.ptr(xd), n, h, w, cin, x_cs, x_co,
+           S.ptr(wd), S.ptr(bd), cout, S.ptr(y), y_cs, y_co, relu, None)
+    sync()
+    got = host_bf16(S, y)
+    ref = U.conv3x3(x, wt, b)
+    terms = U.conv3x3(np.abs(x), np.abs(wt), np.abs(b))
+    if relu:
+        ref = U.relu(ref)
+    out = got[..., y_co:y_co + cout]
+    assert np.all(np.abs(out - ref) <= U_BF16 * np.abs(ref) + 1e-5 * terms)
+    # channels outside the slice are untouched
+    raw = y.cpu().numpy()
+    assert np.all(raw[..., :y_co] == sentinel) and np.all(raw[..., y_co + cout:] == sentinel)
+
+
+def test_conv3x3_data_and_weight_gradients(S):
+    n, h, w, cin, cout = 2, 20, 17, 16, 48          # 680 pixels -> two split-K blocks
+    r = rng(3)
+    x = bf16_round(S, r.normal(size=(n, h, w, cin)))
+    wt = bf16_round(S, r.normal(0, 0.2, size=(cout, 3, 3, cin)))
+    dy = bf16_round(S, r.normal(size=(n, h, w, cout)))
+    L = S.lib()
+    part = zeros32(L.unet_wgrad_scratch_floats(n, h, w, cin, cout, 9))
+    dw, db = zeros32(cout, 3, 3, cin), zeros32(cout)
+    dx = zeros16(n, h, w, cin)
+    flip = zeros16(cin, 3, 3, cout)
+    dxd, dyd, wd = dev_bits(S, x), dev_bits(S, dy), dev_bits(S, wt)
+    S.call("unet_conv3x3_wgrad", S.ptr(dxd), n, h, w, cin, cin, 0, S.ptr(dyd), cout, cout, 0,
+           S.ptr(dw), S.ptr(db), S.ptr(part), 0, None)
+    S.call("unet_conv3x3_flip", S.ptr(wd), cout, cin, S.ptr(flip), None)
+    S.call("unet_conv3x3_fwd", S.ptr(dyd), n, h, w, cout, cout, 0, S.ptr(flip), None, cin, S.ptr(dx),
+           cin, 0, 0, None)
+    sync()
+    rdx, rdw, rdb = U.conv3x3_grad(x, wt, dy)
+    tdx, tdw, _ = U.conv3x3_grad(np.abs(x), np.abs(wt), np.abs(dy))
+    assert np.all(np.abs(dw.cpu().numpy() - rdw) <= 1e-5 * tdw + 1e-30)
+    assert np.all(np.abs(db.cpu().numpy() - rdb) <= 1e-5 * np.abs(dy).sum(axis=(0, 1, 2)))
+    assert np.all(np.abs(host_bf16(S, dx) - rdx) <= U_BF16 * np.abs(rdx) + 1e-5 * tdx)
+    # accumulate = 1 adds a second identical contribution
+    S.call("unet_conv3x3_wgrad", S.ptr(dxd), n, h, w, cin, cin, 0, S.ptr(dyd), cout, cout, 0,
+           S.ptr(dw), S.ptr(db), S.ptr(part), 1, None)
+    sync()
+    assert np.all(np.abs(dw.cpu().numpy() - 2 * rdw) <= 2e-5 * tdw + 1e-30)
+
+
+def test_upconv_forward_and_gradients(S):
+    n, h, w, cin, cout = 2, 7, 12, 64, 32
+    r = rng(4)
+    x = bf16_round(S, r.normal(size=(n, h, w, cin)))
+    wt = bf16_round(S, r.normal(0, 0.2, size=(cout, 2, 2, cin)))
+    b = r.normal(0, 0.1, size=cout).astype(np.float32).astype(np.float64)
+    dy = bf16_round(S, r.normal(size=(n, 2 * h, 2 * w, cout)))
+    # outputs into the upper half of a 2*cout-channel tensor, as in the network
+    y = zeros16(n, 2 * h, 2 * w, 2 * cout)
+    xd, wd = dev_bits(S, x), dev_bits(S, wt)
+    bd = dev_f32(b)
+    S.call("unet_upconv_fwd", S.ptr(xd), n, h, w, cin, cin, 0, S.ptr(wd), S.ptr(bd), cout, S.ptr(y),
+           2 * cout, cout, None)
+    dyfull = np.zeros((n, 2 * h, 2 * w, 2 * cout))
+    dyfull[..., cout:] = dy
+    dyd = dev_bits(S, dyfull)
+    dx = zeros16(n, h, w, cin)
+    scratch = zeros16(4 * cin * cout)
+    S.call("unet_upconv_bwd_data", S.ptr(dyd), n, h, w, cout, 2 * cout, cout, S.ptr(wd), cin, S.ptr(scratch),
+           S.ptr(dx), cin, 0, None)
+    L = S.lib()
+    part = zeros32(L.unet_wgrad_scratch_floats(n, h, w, cin, cout, 4))
+    dw, db = zeros32(cout, 2, 2, cin), zeros32(cout)
+    S.call("unet_upconv_wgrad", S.ptr(xd), n, h, w, cin, cin, 0, S.ptr(dyd), cout, 2 * cout, cout, S.ptr(dw),
+           S.ptr(db), S.ptr(part), None)
+    sync()
+    ref = U.upconv2(x, wt, b)
+    terms = U.upconv2(np.abs(x), np.abs(wt), np.abs(b))
+    got = host_bf16(S, y)[..., cout:]
+    assert np.all(np.abs(got - ref) <= U_BF16 * np.abs(ref) + 1e-5 * terms)
+    assert np.all(host_bf16(S, y)[..., :cout] == 0)
+    rdx, rdw, rdb = U.upconv2_grad(x, wt, dy)
+    tdx, tdw, _ = U.upconv2_grad(np.abs(x), np.abs(wt), np.abs(dy))
+    assert np.all(np.abs(host_bf16(S, dx) - rdx) <= U_BF16 * np.abs(rdx) + 1e-5 * tdx)
+    assert np.all(np.abs(dw.cpu().numpy() - rdw) <= 1e-5 * tdw + 1e-30)
+    assert np.all(np.abs(db.cpu().numpy() - rdb) <= 1e-5 * np.abs(dy).sum(axis=(0, 1, 2)))
+
+
+def test_maxpool_relu_exact(S):
+    n, h, w, c = 2, 10, 14, 16
+    r = rng(5)
+    x = bf16_round(S, r.normal(size=(n, h, w, 2 * c)))
+    x[0, 0, 0, :] = x[0, 0, 1, :]          # a tie inside one window
+    y = zeros16(n, h // 2, w // 2, c)
+    xd = dev_bits(S, x)
+    S.call("unet_maxpool_fwd", S.ptr(xd), n, h, w, c, 2 * c, c, S.ptr(y), c, 0, None)
+    dy = bf16_round(S, r.normal(size=(n, h // 2, w // 2, c)))
+    base = bf16_round(S, r.normal(size=(n, h, w, c)))
+    dx0, dx1 = zeros16(n, h, w, c), dev_bits(S, base)
+    dyd = dev_bits(S, dy)
+    S.call("unet_maxpool_bwd", S.ptr(xd), n, h, w, c, 2 * c, c, S.ptr(dyd), c, 0, S.ptr(dx0), c, 0, 0, None)
+    S.call("unet_maxpool_bwd", S.ptr(xd), n, h, w, c, 2 * c, c, S.ptr(dyd), c, 0, S.ptr(dx1), c, 0, 1, None)
+    relu_y = dev_bits(S, x[..., :c])
+    g = dev_bits(S, base)
+    S.call("unet_relu_bwd", S.ptr(relu_y), n * h * w, c, c, 0, S.ptr(g), c, 0, None)
+    sync()
+    xs = x[..., c:]
+    assert np.array_equal(host_bf16(S, y), U.maxpool2(xs))
+    route = U.maxpool2_grad(xs, dy)
+    assert np.array_equal(host_bf16(S, dx0), route)
+    assert np.array_equal(host_bf16(S, dx1), bf16_round(S, base + route))
+    assert np.array_equal(host_bf16(S, g), np.where(x[..., :c] > 0, base, 0.0))
+
+
+def test_head_loss_and_gradients(S):
+    n_pix, c = 3000, 32
+    r = rng(6)
+    x = bf16_round(S, np.abs(r.normal(size=(n_pix, c))))
+    w = r.normal(0, 0.3, size=c).astype(np.float32).astype(np.float64)
+    b = np.array([0.1], np.float32).astype(np.float64)
+    t = r.uniform(size=n_pix).astype(np.float32).astype(np.float64)
+    mask = (r.uniform(size=n_pix) > 0.3).astype(np.uint8)
+    import torch
+    xd = dev_bits(S, x)
+    sat, loss = zeros32(n_pix), zeros32(1)
+    dx, dw, db = zeros16(n_pix, c), zeros32(c), zeros32(1)
+    L = S.lib()
+    part = zeros32(L.unet_head_scratch_floats(n_pix, c))
+    wd, bd, td = dev_f32(w), dev_f32(b), dev_f32(t)
+    md = torch.from_numpy(mask).cuda()
+    S.call("unet_head_fwd", S.ptr(xd), n_pix, c, c, S.ptr(wd), S.ptr(bd), S.ptr(sat), None)
+    S.call("unet_head_loss_bwd", S.ptr(xd), n_pix, c, c, S.ptr(wd), S.ptr(bd), S.ptr(td), S.ptr(md),
+           1.0 / mask.sum(), S.ptr(loss), S.ptr(dx), S.ptr(dw), S.ptr(db), S.ptr(part), None)
+    sync()
+    z = U.head(x, w, b[0])
+    assert np.allclose(sat.cpu().numpy(), U.sigmoid(z), rtol=1e-5, atol=1e-6)
+    assert abs(loss.item() - U.masked_bce(z, t, mask)) <= 1e-4 * abs(U.masked_bce(z, t, mask))
+    gz = U.masked_bce_grad(z, t, mask)
+    assert np.allclose(db.item(), gz.sum(), rtol=1e-4, atol=1e-6)
+    assert np.all(np.abs(dw.cpu().numpy() - gz @ x) <= 1e-4 * (np.abs(gz) @ x) + 1e-7)
+    ref_dx = gz[:, None] * w[None, :]
+    assert np.all(np.abs(host_bf16(S, dx) - ref_dx) <= (U_BF16 + 1e-5) * np.abs(ref_dx) + 1e-9)
+
+
+def test_adam_matches_oracle(S):
+    r = rng(7)
+    p = r.normal(size=1000).astype(np.float32)
+    pd, md, vd = dev_f32(p), zeros32(1000), zeros32(1000)
+    pb = zeros16(1000)
+    hp, hm, hv = p.astype(np.float64), np.zeros(1000), np.zeros(1000)
+    for step in range(1, 4):
+        g = r.normal(size=1000).astype(np.float32)
+        gd = dev_f32(g)
+        S.call("unet_adam", S.ptr(pd), S.ptr(gd), S.ptr(md), S.ptr(vd), S.ptr(pb), 1000, 1e-2, 0.9,
+               0.999, 1e-8, step, None)
+        hp, hm, hv = U.adam_step(hp, g.astype(np.float64), hm, hv, 1e-2, 0.9, 0.999, 1e-8, step)
+    sync()
+    assert np.allclose(pd.cpu().numpy(), hp, rtol=1e-6, atol=1e-6)
+    assert np.array_equal(host_bf16(S, pb), bf16_round(S, pd.cpu().numpy()))
+
+
+def _net_case(S, levels, n, hw, seed):
+    net = S.UNet(levels=levels, seed=seed)
+    p = net.get_params()
+    r = rng(seed)
+    for k in p:
+        if k.endswith(".b"):
+            p[k] = r.normal(0, 0.05, p[k].shape).astype(np.float32)
+    net.set_params(p)
+    x = np.zeros((n, hw, hw, S.IN_CH))
+    x[..., :3] = r.normal(size=(n, hw, hw, 3))
+    x = bf16_round(S, x)
+    t = r.uniform(size=(n, hw, hw))
+    mask = (r.uniform(size=(n, hw, hw)) > 0.25).astype(np.uint8)
+    # the oracle sees the weights the kernels see: BF16 weights, FP32 biases
+    po = {}
+    for k, v in p.items():
+        po[k] = bf16_round(S, v) if (k.endswith(".w") and not k.startswith("head")) else v.astype(np.float64)
+    return net, po, x, t, mask
+
+
+@pytest.mark.parametrize("levels,hw", [((32, 64), 32), ((32, 64, 128, 256), 64)])
+def test_network_forward_and_gradients(S, levels, hw):
+    import torch
+    n = 2
+    net, po, x, t, mask = _net_case(S, levels, n, hw, 11)
+    xd, td, md = dev_bits(S, x), dev_f32(t), torch.from_numpy(mask).cuda()
+    sat = net.forward(xd)
+    loss = net.backward(td, md)
+    sync()
+    z, a = U.forward(po, x, levels)
+    gz = U.masked_bce_grad(z, t, mask)
+    g = U.backward(po, a, gz, levels)
+    s_ref = U.sigmoid(z)
+    assert np.linalg.norm(sat.cpu().numpy() - s_ref) <= 3e-2 * np.linalg.norm(s_ref)
+    assert abs(loss.item() - U.masked_bce(z, t, mask)) <= 3e-2 * U.masked_bce(z, t, mask)
+    got = net.get_grads()
+    worst = {}
+    for k in g:
+        err = np.linalg.norm(got[k] - g[k]) / max(np.linalg.norm(g[k]), 1e-30)
+        worst[k] = err
+    print("[unet-grad] relative errors:", {k: f"{v:.1e}" for k, v in sorted(worst.items())}, flush=True)
+    assert max(worst.values()) <= 5e-2, worst
+
+
+def test_training_is_deterministic_and_learns(S):
+    import torch
+    net, _, x, t, mask = _net_case(S, (32, 64, 128, 256), 2, 64, 12)
+    t = (x[..., 0] + 0.5 * x[..., 1] > 0).astype(np.float64)   # a function of the input
+    xd, td, md = dev_bits(S, x), dev_f32(t), torch.from_numpy(mask).cuda()
+    net.forward(xd)
+    net.backward(td, md)
+    g1 = net.g.clone()
+    net.forward(xd)
+    net.backward(td, md)
+    assert torch.equal(g1, net.g)
+    losses = []
+    for _ in range(60):
+        losses.append(net.train_step(xd, td, md, lr=2e-3).item())
+    print(f"[unet-train] loss {losses[0]:.4f} -> {losses[-1]:.4f}", flush=True)
+    assert losses[-1] < 0.5 * losses[0]
