@@ -12,7 +12,6 @@ kernel time from HIP events on the solver's stream) and the FP64 oracle
 timed on the host cores as a CPU baseline.
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -29,15 +28,15 @@ BYTES_PER_NODE = {(9, 0): 2 * 9 * 2 * 4, (9, 1): 2 * (8 * 2 + 4) * 2,
 
 
 def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("lbm_kernels.hip", "lattice.h", "lbm_device.h"):
-        with open(os.path.join(ROOT, "paper_2111_08666_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2111_08666_amd.build import kernel_source_hash as h
+    return h()
 
 
 def workload(name):
+    """A Problem, or a list of Problems for a batched workload."""
     from paper_2111_08666_amd import inputs as I
+    if name == "batch64":
+        return I.batch_instances(64)
     if name == "d2q9_1024x512":
         return I.large_drainage(collision=1)
     if name == "d2q9_128x64":
@@ -102,10 +101,22 @@ def main():
 
     dev = torch.device("cuda:0")
     problem = workload(args.workload)
-    print(f"[bench] workload {args.workload}: {problem.nx}x{problem.ny}x{problem.nz}, "
-          f"fluid {problem.n_fluid}, collision {problem.collision}", file=sys.stderr, flush=True)
-    solver = lbm.Solver(problem, storage=args.storage, device=dev, math=args.math,
-                        strategy=args.strategy)
+    batch = isinstance(problem, list)
+    if batch:
+        problems = problem
+        solver = lbm.BatchSolver(problems, storage=args.storage, device=dev, math=args.math,
+                                 strategy=args.strategy)
+        problem = sorted(problems, key=lambda p: p.n_nodes)[len(problems) // 2]  # CPU-baseline sample
+        n_nodes, n_fluid = solver.n_nodes, solver.n_fluid
+        sizes = sorted({(p.nx, p.ny) for p in problems})
+        print(f"[bench] workload {args.workload}: {len(problems)} instances, {sizes[0]} .. {sizes[-1]}, "
+              f"{n_nodes} nodes, fluid {n_fluid}", file=sys.stderr, flush=True)
+    else:
+        print(f"[bench] workload {args.workload}: {problem.nx}x{problem.ny}x{problem.nz}, "
+              f"fluid {problem.n_fluid}, collision {problem.collision}", file=sys.stderr, flush=True)
+        solver = lbm.Solver(problem, storage=args.storage, device=dev, math=args.math,
+                            strategy=args.strategy)
+        n_nodes, n_fluid = problem.n_nodes, problem.n_fluid
     stream = solver.stream
     tune = None
     if not args.no_autotune and args.strategy == 0:
@@ -135,8 +146,9 @@ def main():
     ms_per_step = wall * 1e3 / steps
 
     # per-launch kernel durations: events bracketing single launches
+    n_samples = args.kernel_samples if not batch else min(args.kernel_samples, 50)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.kernel_samples)]
+           for _ in range(n_samples)]
     for a, b in evs:
         a.record(stream)
         solver.step(1)
@@ -145,10 +157,14 @@ def main():
     k_ms = sorted(a.elapsed_time(b) for a, b in evs)
     k_mean = sum(k_ms) / len(k_ms)
     obs = solver.observables()
+    if batch:
+        mass = [sum(o["mass"][c] for o in obs) for c in range(2)]
+    else:
+        mass = obs["mass"]
 
     kname, grid, block = solver.kernel_info()
     bpn = BYTES_PER_NODE[(problem.q, args.storage)]
-    alg_bytes = bpn * problem.n_fluid
+    alg_bytes = bpn * n_fluid
     achieved = alg_bytes / (k_mean * 1e-3) / 1e9
     traffic = traffic_for(kname, args.workload)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -157,7 +173,7 @@ def main():
                 "kernel_ms_mean": round(k_mean, 5), "kernel_ms_median": round(k_ms[len(k_ms) // 2], 5),
                 "alg_bytes_per_launch": alg_bytes, "bytes_per_fluid_node": bpn,
                 "graph_ms_per_step": round(e0.elapsed_time(e1) / steps, 5)}
-    mlups = problem.n_nodes * steps / wall / 1e6
+    mlups = n_nodes * steps / wall / 1e6
     out = {
         "metric": "MLUPS (2-component step) + % HBM roofline",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps,
@@ -166,13 +182,16 @@ def main():
         "dtype": ("f64 math, " if args.math == 0 else "f32 math, ")
                  + ("f32 storage" if args.storage == 0 else "bf16-deviation storage"),
         "data": "synthetic (seeded disc medium; the paper's geometry is not available)",
-        "config": {"workload": problem.name, "q": problem.q, "nx": problem.nx, "ny": problem.ny,
-                   "nz": problem.nz, "n_fluid": problem.n_fluid,
+        "config": {"workload": (f"batch of {len(problems)} D2Q9 drainage instances "
+                                f"{sizes[0][0]}x{sizes[0][1]} .. {sizes[-1][0]}x{sizes[-1][1]}"
+                                if batch else problem.name),
+                   "q": problem.q, "nx": None if batch else problem.nx, "ny": None if batch else problem.ny,
+                   "nz": None if batch else problem.nz, "n_nodes": n_nodes, "n_fluid": n_fluid,
                    "collision": ["SRT", "MRT", "TRT"][problem.collision],
                    "storage": "f32" if args.storage == 0 else "bf16-dev",
                    "launch": "eager" if args.eager else f"hipGraph x{chunk}",
-                   "mflups_fluid": round(problem.n_fluid * steps / wall / 1e6, 1),
-                   "mass_after": obs["mass"], "grid_blocks": grid, "block_threads": block,
+                   "mflups_fluid": round(n_fluid * steps / wall / 1e6, 1),
+                   "mass_after": mass, "grid_blocks": grid, "block_threads": block,
                    "autotune": tune.strip().splitlines() if tune else None},
         "roofline": roofline,
     }

@@ -41,7 +41,7 @@ typedef enum {
   LBM_EINVAL = -1,    /* bad argument; nothing was done */
   LBM_ENOMEM = -2,    /* workspace too small or misaligned */
   LBM_EDEVICE = -3,   /* a HIP call failed */
-  LBM_EUNSTABLE = -4, /* a density became non-finite or negative */
+  LBM_EUNSTABLE = -4, /* a density became non-finite */
   LBM_ESTATE = -5     /* call not valid in the current state */
 } lbm_status;
 
@@ -102,7 +102,9 @@ typedef struct {
                              nodes at least 3 nodes from any solid */
   double pc;              /* p_in - p_out */
   double n_in, n_out;
-  int32_t flags;          /* bit0 non-finite density, bit1 negative density */
+  int32_t flags;          /* bit0 non-finite density; bit1 a negative density (reported only:
+                             a slightly negative minor-phase density near strongly
+                             wetting walls is an artefact of the model, not a blow-up) */
   int32_t reserved;
 } lbm_obs;
 
@@ -134,7 +136,7 @@ lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
 lbm_status lbm_step_graph(lbm_ctx *ctx, int64_t n, int64_t reps);
 
 /* Observables at the current time; synchronises the stream.  Returns
- * LBM_EUNSTABLE (with *out filled) once a density is non-finite or negative;
+ * LBM_EUNSTABLE (with *out filled) once a density is non-finite (flags bit0);
  * later lbm_step calls then return LBM_EUNSTABLE too. */
 lbm_status lbm_observables(lbm_ctx *ctx, lbm_obs *out);
 
@@ -182,6 +184,13 @@ lbm_status lbm_batch_observables(lbm_batch *b, lbm_obs *out /* k entries */);
 lbm_status lbm_batch_get_density(lbm_batch *b, int32_t k, float *dst, int32_t dst_is_device);
 lbm_status lbm_batch_destroy(lbm_batch *b);
 const char *lbm_batch_last_error(const lbm_batch *b);
+/* lbm_kernel_info and lbm_autotune for a batch: one variant is chosen for
+ * the whole batch (every instance advances by variants x steps).  With the
+ * split strategy each instance is launched on its own; grid_blocks is then
+ * the largest instance's grid. */
+lbm_status lbm_batch_kernel_info(const lbm_batch *b, char *name, size_t name_len,
+                                 int64_t *grid_blocks, int32_t *block_threads);
+lbm_status lbm_batch_autotune(lbm_batch *b, int64_t steps, char *report, size_t report_len);
 
 #ifdef __cplusplus
 }

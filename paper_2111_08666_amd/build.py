@@ -15,6 +15,16 @@ FLAGS = [
 ]
 
 
+def kernel_source_hash() -> str:
+    """Hash of the step kernels' sources: counter measurements are tied to it."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.hip", "lattice.h", "lbm_device.h"):
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False, extra=()) -> str:
     cmd = [HIPCC, *FLAGS, *extra, "-x", "hip", *SOURCES, "-o", LIB + ".tmp"]
     if verbose:

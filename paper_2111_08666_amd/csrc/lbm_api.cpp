@@ -399,7 +399,7 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
 lbm_status batch_step(lbm_batch *b, int64_t n) {
   if (!b) return fail(nullptr, LBM_EINVAL, "NULL handle");
   if (n < 0) return fail(b, LBM_EINVAL, "n must be >= 0");
-  if (b->unstable) return fail(b, LBM_EUNSTABLE, "state is unstable (non-finite or negative density)");
+  if (b->unstable) return fail(b, LBM_EUNSTABLE, "state is unstable (non-finite density)");
   for (int64_t s = 0; s < n; ++s) {
     HIPCHK(b, launch_step(step_launch(b, b->parity), b->stream));
     b->parity ^= 1;
@@ -412,7 +412,7 @@ lbm_status batch_step_graph(lbm_batch *b, int64_t n, int64_t reps) {
   if (!b) return fail(nullptr, LBM_EINVAL, "NULL handle");
   if (n <= 0 || (n & 1) || reps < 0) return fail(b, LBM_EINVAL, "n must be even and > 0, reps >= 0");
   if (!b->stream) return fail(b, LBM_ESTATE, "graph capture needs a non-default stream");
-  if (b->unstable) return fail(b, LBM_EUNSTABLE, "state is unstable (non-finite or negative density)");
+  if (b->unstable) return fail(b, LBM_EUNSTABLE, "state is unstable (non-finite density)");
   if (!b->gexec || b->graph_n != n || b->graph_parity != b->parity) {
     if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
@@ -472,11 +472,11 @@ lbm_status batch_observables(lbm_batch *b, lbm_obs *out) {
   bool bad_state = false;
   for (int i = 0; i < b->k; ++i) {
     fill_obs(b, i, r.data() + (size_t)kObsFields * i, out + i);
-    if (out[i].flags) bad_state = true;
+    if (out[i].flags & 1) bad_state = true;  // a negative density (bit 1) is only reported
   }
   if (bad_state) {
     b->unstable = true;
-    return fail(b, LBM_EUNSTABLE, "non-finite or negative density");
+    return fail(b, LBM_EUNSTABLE, "non-finite density");
   }
   return LBM_OK;
 }
@@ -627,13 +627,19 @@ const char *lbm_last_error(const lbm_ctx *ctx) {
 lbm_status lbm_kernel_info(const lbm_ctx *ctx, char *name, size_t name_len, int64_t *grid_blocks,
                            int32_t *block_threads) {
   if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL handle");
-  const lbm_batch *b = ctx->b;
+  return lbm_batch_kernel_info(ctx->b, name, name_len, grid_blocks, block_threads);
+}
+
+lbm_status lbm_batch_kernel_info(const lbm_batch *b, char *name, size_t name_len, int64_t *grid_blocks,
+                                 int32_t *block_threads) {
+  if (!b) return fail(nullptr, LBM_EINVAL, "NULL handle");
   if (name && name_len)
     std::snprintf(name, name_len, "%s", step_kernel_name(b->q, b->collision, b->storage, b->math, b->strategy, b->ty));
   if (grid_blocks) {
-    if (b->strategy == LBM_SPLIT) {
-      const InstDev &h = b->h[0];
-      *grid_blocks = ((int64_t)((h.nx + 63) / 64) * h.ny * h.nz + 3) / 4;
+    if (b->strategy == LBM_SPLIT) {  // one launch per instance: the largest grid
+      int64_t g = 0;
+      for (const InstDev &h : b->h) g = std::max(g, ((int64_t)((h.nx + 63) / 64) * h.ny * h.nz + 3) / 4);
+      *grid_blocks = g;
     } else {
       *grid_blocks = b->n_blocks;
     }
@@ -644,7 +650,11 @@ lbm_status lbm_kernel_info(const lbm_ctx *ctx, char *name, size_t name_len, int6
 
 lbm_status lbm_autotune(lbm_ctx *ctx, int64_t steps, char *report, size_t report_len) {
   if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL handle");
-  lbm_batch *b = ctx->b;
+  return lbm_batch_autotune(ctx->b, steps, report, report_len);
+}
+
+lbm_status lbm_batch_autotune(lbm_batch *b, int64_t steps, char *report, size_t report_len) {
+  if (!b) return fail(nullptr, LBM_EINVAL, "NULL handle");
   if (steps < 2 || (steps & 1)) return fail(b, LBM_EINVAL, "steps must be even and >= 2");
   struct Cand { int strategy, ty; };
   std::vector<Cand> cands;

@@ -36,6 +36,14 @@ typedef __attribute__((address_space(1))) const uint16_t gcu16;
 __device__ __forceinline__ gcf *G(const float *p) { return (gcf *)p; }
 __device__ __forceinline__ gf *G(float *p) { return (gf *)p; }
 
+// Access at a wave-uniform base plus a per-lane 32-bit byte offset: the
+// compiler can then keep the base in scalar registers and address with one
+// 32-bit VGPR (global_load ... v_off, s[base]) instead of a 64-bit VGPR pair.
+typedef __attribute__((address_space(1))) const char gcc;
+typedef __attribute__((address_space(1))) char gc;
+__device__ __forceinline__ float ldg(gcf *base, uint32_t boff) { return *(gcf *)((gcc *)base + boff); }
+__device__ __forceinline__ void stg(gf *base, uint32_t boff, float v) { *(gf *)((gc *)base + boff) = v; }
+
 // ---------------------------------------------------------------------------
 // population access by storage kind; a node is addressed by its row block
 // offset `row` (y * ystride + z * zstride, in floats) and its x
@@ -75,10 +83,11 @@ __device__ __forceinline__ void pop_store(gf *__restrict__ b, int pitch, int64_t
                                           const float (&f0)[Q], const float (&f1)[Q], float rho1,
                                           float rho2) {
   if constexpr (ST == 0) {
+    const uint32_t bo = (uint32_t)x * 4u;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      b[row + (int64_t)i * pitch + x] = f0[i];
-      b[row + (int64_t)(Q + i) * pitch + x] = f1[i];
+      stg(b + row + (int64_t)i * pitch, bo, f0[i]);
+      stg(b + row + (int64_t)(Q + i) * pitch, bo, f1[i]);
     }
   } else {
     // collision conserves each component's node mass, so rho is stored as is
@@ -121,7 +130,16 @@ __device__ __forceinline__ void complete(const InstDev &d, gcf *__restrict__ fin
 // Source row offsets (in floats) for a node row (y, z): src[ey+1][ez+1] is
 // the row of (y - ey, z - ez) with periodic wrap.  Uniform across a wave when
 // y and z are.
-template <int Q>
+// A value the caller knows to be equal across the wave, marked as such so
+// that addresses built from it stay in scalar registers.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// UNI: the caller guarantees (y, z) is the same for every active lane.
+template <int Q, bool UNI = false>
 __device__ __forceinline__ void source_rows(const InstDev &d, int y, int z, int64_t (&src)[3][3]) {
   const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
   const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
@@ -129,7 +147,10 @@ __device__ __forceinline__ void source_rows(const InstDev &d, int y, int z, int6
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) src[a][b] = ys[a] * d.ystride + zs[b] * d.zstride;
+    for (int b = 0; b < 3; ++b) {
+      const int64_t v = ys[a] * d.ystride + zs[b] * d.zstride;
+      src[a][b] = UNI ? uniform64(v) : v;
+    }
 }
 
 // Source x for e_x = -1, 0, +1 (periodic wrap).
@@ -145,15 +166,16 @@ __device__ __forceinline__ void pull_row(const InstDev &d, gcf *__restrict__ fin
                                          const int64_t (&src)[3][3], const int (&xs)[3], float (&f0)[Q],
                                          float (&f1)[Q]) {
   using L = Lat<Q>;
-  const int pitch = d.pitch;
+  const int pitch = __builtin_amdgcn_readfirstlane(d.pitch);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int64_t row = src[L::ey[i] + 1][L::ez[i] + 1];
     const int sx = xs[L::ex[i] + 1];
     if constexpr (ST == 0) {
       gcf *b = fin + row + (int64_t)i * pitch;
-      f0[i] = b[(uint32_t)sx];
-      f1[i] = b[(int64_t)Q * pitch + (uint32_t)sx];
+      const uint32_t bo = (uint32_t)sx * 4u;
+      f0[i] = ldg(b, bo);
+      f1[i] = ldg(b + (int64_t)Q * pitch, bo);
     } else {
       const bool bb = (info >> i) & 1u;
       const int64_t r = bb ? src[1][1] : row;
@@ -178,9 +200,9 @@ __device__ __forceinline__ void store_ghosts(const InstDev &d, gf *__restrict__ 
     for (int i = 1; i < Q; ++i) {
       if (info & (1u << i)) {
         gf *b = fout + src[L::ey[i] + 1][L::ez[i] + 1] + (int64_t)i * pitch;
-        const uint32_t sx = (uint32_t)xs[L::ex[i] + 1];
-        b[sx] = f0[L::opp[i]];
-        b[(int64_t)Q * pitch + sx] = f1[L::opp[i]];
+        const uint32_t bo = (uint32_t)xs[L::ex[i] + 1] * 4u;
+        stg(b, bo, f0[L::opp[i]]);
+        stg(b + (int64_t)Q * pitch, bo, f1[L::opp[i]]);
       }
     }
   }
@@ -226,7 +248,7 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
   __shared__ V psi[kRH][64];
 
   const int bid = xcd_block();
-  const int inst = block_inst ? block_inst[bid] : 0;
+  const int inst = __builtin_amdgcn_readfirstlane(block_inst ? block_inst[bid] : 0);
   const InstDev &d = insts[inst];
   const int lb = bid - d.block_base;
   const int tx = lb % d.tiles_x, ty = lb / d.tiles_x;
@@ -277,7 +299,7 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
   float f0[KR][9], f1[KR][9], h0[9], h1[9];
   int64_t srow[KR + 1][3][3];
 #pragma unroll
-  for (int k = 0; k <= KR; ++k) source_rows<9>(d, gy[k], 0, srow[k]);
+  for (int k = 0; k <= KR; ++k) source_rows<9, true>(d, gy[k], 0, srow[k]);
 #pragma unroll
   for (int k = 0; k < KR; ++k)
     if (ST == 0 || !(info[k] & kSolid)) pull_row<9, ST>(d, fin, info[k], srow[k], xs, f0[k], f1[k]);
@@ -356,7 +378,7 @@ __global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ ins
     const R F1x = -G_ * rho1 * sx2 + rho1 * gxb, F1y = -G_ * rho1 * sy2 + rho1 * gyb;
     const R F2x = -G_ * rho2 * sx1 + rho2 * gxb, F2y = -G_ * rho2 * sy1 + rho2 * gyb;
     collide_node<9, COLL, R>(d, f0[k], f1[k], rho1, rho2, F1x, F1y, R(0), F2x, F2y, R(0));
-    pop_store<9, ST>(fout, d.pitch, gy_raw * d.ystride, gx, f0[k], f1[k], (float)rho1, (float)rho2);
+    pop_store<9, ST>(fout, d.pitch, uniform64(gy_raw * d.ystride), gx, f0[k], f1[k], (float)rho1, (float)rho2);
     store_ghosts<9, ST>(d, fout, inf, srow[k], xs, f0[k], f1[k]);
   }
 }
@@ -384,7 +406,7 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
   __shared__ V psi[kRing][kRH3][64];
 
   const int bid = xcd_block();
-  const int inst = block_inst ? block_inst[bid] : 0;
+  const int inst = __builtin_amdgcn_readfirstlane(block_inst ? block_inst[bid] : 0);
   const InstDev &d = insts[inst];
   const int lb = bid - d.block_base;
   const int tx = lb % d.tiles_x, ty = (lb / d.tiles_x) % d.tiles_y;
@@ -452,7 +474,7 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
       R rho1 = 0, rho2 = 0;
       if (!(inf[k] & kSolid)) {
         int64_t src[3][3];
-        source_rows<19>(d, gy[k], zz, src);
+        source_rows<19, true>(d, gy[k], zz, src);
         float a[19], b[19];
         pull_row<19, ST>(d, fin, inf[k], src, xs, a, b);
         if (inf[k] & (kInlet | kOutlet)) complete<19, ST, R>(d, fin, inf[k], gx, gy[k], zz, a, b);
@@ -500,7 +522,7 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
       const uint32_t inf = infop[gx + (int64_t)d.pitch * gy[k] + islab * z];
       if (inf & kSolid) continue;
       int64_t src[3][3];
-      source_rows<19>(d, gy[k], z, src);
+      source_rows<19, true>(d, gy[k], z, src);
       float a[19], b[19];
       pull_row<19, ST>(d, fin, inf, src, xs, a, b);
       if (inf & (kInlet | kOutlet)) complete<19, ST, R>(d, fin, inf, gx, gy[k], z, a, b);
@@ -526,7 +548,7 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
                                 -G_ * rho1 * sy2 + rho1 * gyb, -G_ * rho1 * sz2 + rho1 * gzb,
                                 -G_ * rho2 * sx1 + rho2 * gxb, -G_ * rho2 * sy1 + rho2 * gyb,
                                 -G_ * rho2 * sz1 + rho2 * gzb);
-      pop_store<19, ST>(fout, d.pitch, gy_raw[k] * d.ystride + z * d.zstride, gx, a, b, (float)rho1,
+      pop_store<19, ST>(fout, d.pitch, uniform64(gy_raw[k] * d.ystride + z * d.zstride), gx, a, b, (float)rho1,
                         (float)rho2);
       store_ghosts<19, ST>(d, fout, inf, src, xs, a, b);
     }
@@ -594,7 +616,7 @@ __global__ __launch_bounds__(256) void rho_kernel(const InstDev *__restrict__ in
   gcf *__restrict__ fin = G(d.f[parity]);
   int64_t src[3][3];
   int xs[3];
-  source_rows<Q>(d, y, z, src);
+  source_rows<Q, true>(d, y, z, src);  // one row per wave
   source_x(d, x, xs);
   float a[Q], b[Q];
   pull_row<Q, ST>(d, fin, info, src, xs, a, b);
@@ -670,7 +692,7 @@ __global__ __launch_bounds__(256) void collide_kernel(const InstDev *__restrict_
     if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
   }
   int64_t src[3][3];
-  source_rows<Q>(d, y, z, src);
+  source_rows<Q, true>(d, y, z, src);  // one row per wave
   float a[Q], b[Q];
   pull_row<Q, ST>(d, fin, info, src, xs, a, b);
   if (info & (kInlet | kOutlet)) complete<Q, ST, R>(d, fin, info, x, y, z, a, b);
@@ -678,7 +700,7 @@ __global__ __launch_bounds__(256) void collide_kernel(const InstDev *__restrict_
   collide_node<Q, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb, -G_ * rho1 * sy2 + rho1 * gyb,
                            -G_ * rho1 * sz2 + rho1 * gzb, -G_ * rho2 * sx1 + rho2 * gxb,
                            -G_ * rho2 * sy1 + rho2 * gyb, -G_ * rho2 * sz1 + rho2 * gzb);
-  pop_store<Q, ST>(fout, d.pitch, y * d.ystride + z * d.zstride, x, a, b, (float)rho1, (float)rho2);
+  pop_store<Q, ST>(fout, d.pitch, uniform64(y * d.ystride + z * d.zstride), x, a, b, (float)rho1, (float)rho2);
   store_ghosts<Q, ST>(d, fout, info, src, xs, a, b);
 }
 

@@ -299,6 +299,32 @@ def batch_instances(k_count=64, seed0=300, nx_range=(256, 1024), collision=1):
     return out
 
 
+def surrogate_mask(k: int, seed0: int = 40000, n: int = 256) -> np.ndarray:
+    """Solid map of surrogate instance k (radii 4-20, porosity 0.55)."""
+    return disc_medium(n, n, 4.0, 20.0, 0.55, seed0 + k, reservoir=8)
+
+
+def surrogate_instance(k: int, seed0: int = 40000, n: int = 256, collision: int = 1,
+                       mask: np.ndarray | None = None) -> Problem:
+    """Instance k of the surrogate's data set: an n x n disc medium (seed
+    seed0 + k) with a contact angle ~ U[30, 150] and a pressure step
+    log-uniform on [1e-4, 5e-3], drawn from their own stream so that instance
+    k does not depend on how many are generated.  `mask` may pass a solid map
+    already made by surrogate_mask(k, seed0, n)."""
+    rng = np.random.default_rng([seed0, k])
+    theta = float(rng.uniform(30.0, 150.0))
+    dp = float(10 ** rng.uniform(math.log10(1e-4), math.log10(5e-3)))
+    if mask is None:
+        mask = surrogate_mask(k, seed0, n)
+    rho0 = reservoir_front(mask, 8, 1.0, 0.027)
+    p = Problem(q=9, mask=mask, rho0=rho0, periodic=0, open_x=1, porous_x0=8, porous_x1=n - 8,
+                tau=TAU_M10, G=3.5, xi=xi_of_theta(theta), rho_in1=1.0 + 3 * dp, rho_out2=1.0,
+                collision=collision, name=f"surrogate{k}_{n}x{n}")
+    p.theta = theta
+    p.dp = dp
+    return p
+
+
 def as_dict(p: Problem) -> dict:
     d = asdict(p)
     d.pop("mask")

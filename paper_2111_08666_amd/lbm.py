@@ -25,7 +25,8 @@ EXPORTS = [
     "lbm_observables", "lbm_get_density", "lbm_save", "lbm_load", "lbm_get_step",
     "lbm_destroy", "lbm_last_error", "lbm_kernel_info", "lbm_autotune", "lbm_batch_workspace_bytes",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_step_graph", "lbm_batch_observables",
-    "lbm_batch_get_density", "lbm_batch_destroy", "lbm_batch_last_error",
+    "lbm_batch_get_density", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_kernel_info",
+    "lbm_batch_autotune",
 ]
 
 
@@ -109,11 +110,14 @@ def lib():
         L.lbm_batch_destroy.argtypes = [vp]
         L.lbm_batch_last_error.restype = C.c_char_p
         L.lbm_batch_last_error.argtypes = [vp]
+        L.lbm_batch_kernel_info.argtypes = [vp, C.c_char_p, sz, C.POINTER(i64), C.POINTER(i32)]
+        L.lbm_batch_autotune.argtypes = [vp, i64, C.c_char_p, sz]
         for name in ("lbm_create", "lbm_set_bc", "lbm_step", "lbm_step_graph", "lbm_observables",
                      "lbm_get_density", "lbm_save", "lbm_load", "lbm_destroy", "lbm_kernel_info",
                      "lbm_autotune",
                      "lbm_batch_create", "lbm_batch_step", "lbm_batch_step_graph",
-                     "lbm_batch_observables", "lbm_batch_get_density", "lbm_batch_destroy"):
+                     "lbm_batch_observables", "lbm_batch_get_density", "lbm_batch_destroy",
+                     "lbm_batch_kernel_info", "lbm_batch_autotune"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -321,10 +325,12 @@ class BatchSolver:
     def step_graph(self, n, reps=1):
         self._chk(lib().lbm_batch_step_graph(self._h, int(n), int(reps)))
 
-    def observables(self):
+    def observables(self, allow_unstable=False):
         k = len(self.problems)
         o = (Obs * k)()
-        self._chk(lib().lbm_batch_observables(self._h, o))
+        st = lib().lbm_batch_observables(self._h, o)
+        if not (st == LBM_EUNSTABLE and allow_unstable):
+            self._chk(st)
         return [x.to_dict() for x in o]
 
     def density(self, i) -> np.ndarray:
@@ -332,3 +338,23 @@ class BatchSolver:
         out = np.empty((2,) + p.mask.shape, dtype=np.float32)
         self._chk(lib().lbm_batch_get_density(self._h, int(i), out.ctypes.data, 0))
         return out
+
+    def autotune(self, steps=20) -> str:
+        rep = C.create_string_buffer(1024)
+        self._chk(lib().lbm_batch_autotune(self._h, int(steps), rep, 1024))
+        return rep.value.decode()
+
+    def kernel_info(self):
+        name = C.create_string_buffer(128)
+        g = C.c_int64()
+        b = C.c_int32()
+        self._chk(lib().lbm_batch_kernel_info(self._h, name, 128, C.byref(g), C.byref(b)))
+        return name.value.decode(), g.value, b.value
+
+    @property
+    def n_nodes(self):
+        return sum(p.n_nodes for p in self.problems)
+
+    @property
+    def n_fluid(self):
+        return sum(p.n_fluid for p in self.problems)

@@ -32,8 +32,12 @@ def main():
     from paper_2111_08666_amd import lbm
     t0 = time.time()
     p = workload(args.workload)
-    s = lbm.Solver(p, storage=args.storage, math=args.math, strategy=args.strategy,
-                   tile_rows=args.tile_rows)
+    if isinstance(p, list):
+        s = lbm.BatchSolver(p, storage=args.storage, math=args.math, strategy=args.strategy,
+                            tile_rows=args.tile_rows)
+    else:
+        s = lbm.Solver(p, storage=args.storage, math=args.math, strategy=args.strategy,
+                       tile_rows=args.tile_rows)
     print(f"[profile_run] {args.workload} ready in {time.time() - t0:.1f}s; kernel {s.kernel_info()}",
           flush=True)
     s.step(1)

@@ -68,6 +68,64 @@ def summarize(path):
     return "\n".join(out)
 
 
-if __name__ == "__main__":
-    for p in sys.argv[1:]:
+def _dispatch_values(path, counter):
+    """{kernel name: [per-dispatch value]} for one counter over a run's databases."""
+    vals = defaultdict(list)
+    for f in sorted(glob.glob(os.path.join(path, "**", "*.db"), recursive=True)):
+        cur = sqlite3.connect(f).cursor()
+        for name, _, v in cur.execute("select name, dispatch_id, sum(counter_value) from pmc_events "
+                                      "where counter_name = ? group by name, dispatch_id", (counter,)):
+            vals[name].append(v)
+    return vals
+
+
+def traffic(fetch_dir, write_dir, kernel, copy_mib):
+    """HBM bytes per launch of `kernel` (substring of the full name) from a
+    FETCH_SIZE run and a WRITE_SIZE run (KiB per dispatch), each scaled by
+    the factor that makes the largest copy dispatches of the same run read
+    and write `copy_mib` MiB."""
+    out = {}
+    for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        vals = _dispatch_values(d, counter)
+        kv = [v for n, vs in vals.items() if kernel in n for v in vs]
+        cv = sorted((v for n, vs in vals.items() if "copyBuffer" in n for v in vs), reverse=True)[:3]
+        if not kv or not cv:
+            raise SystemExit(f"no dispatches of {kernel!r} or of the calibration copy in {d}")
+        factor = copy_mib * 1024.0 / (sum(cv) / len(cv))
+        out[counter] = {"kib_per_dispatch": sum(kv) / len(kv), "dispatches": len(kv), "scale": factor,
+                        "bytes_per_launch": sum(kv) / len(kv) * 1024.0 * factor}
+    out["bytes_per_launch"] = out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"]
+    return out
+
+
+def main():
+    import argparse
+    import json
+    ap = argparse.ArgumentParser()
+    ap.add_argument("dirs", nargs="*")
+    ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--kernel", help="substring of the profiled kernel's full name")
+    ap.add_argument("--name", help="kernel name as the solver reports it")
+    ap.add_argument("--workload")
+    ap.add_argument("--copy-mib", type=int, default=1024)
+    ap.add_argument("--out", default="")
+    a = ap.parse_args()
+    for p in a.dirs:
         print(summarize(p))
+    if a.traffic:
+        from paper_2111_08666_amd.build import kernel_source_hash
+        rec = traffic(a.traffic[0], a.traffic[1], a.kernel, a.copy_mib)
+        rec["source_hash"] = kernel_source_hash()
+        print(json.dumps({f"{a.name}|{a.workload}": rec}, indent=1))
+        if a.out:
+            data = {}
+            if os.path.exists(a.out):
+                with open(a.out) as f:
+                    data = json.load(f)
+            data[f"{a.name}|{a.workload}"] = rec
+            with open(a.out, "w") as f:
+                json.dump(data, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main()

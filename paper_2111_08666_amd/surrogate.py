@@ -175,13 +175,28 @@ class UNet:
         return {k: host[o:o + n].reshape(self.shapes[k]).copy() for k, (o, n) in self.off.items()}
 
     def save(self, path):
-        np.savez(path, levels=np.array(self.levels), adam_t=self.adam_t, **self.get_params())
+        """Weights as the kernels use them: BF16 bit patterns for the
+        convolution weights, FP32 for biases and the head."""
+        params = self.get_params()
+        bits = self.pb.cpu().numpy().view(np.uint16)
+        out = {}
+        for k, v in params.items():
+            if k.endswith(".w") and not k.startswith("head"):
+                o, n = self.off[k]
+                out[k] = bits[o:o + n].reshape(self.shapes[k]).copy()
+            else:
+                out[k] = v.astype(np.float32)
+        np.savez(path, levels=np.array(self.levels), **out)
 
     @classmethod
     def load(cls, path, device="cuda:0"):
         with np.load(path, allow_pickle=False) as z:
             net = cls(levels=tuple(int(v) for v in z["levels"]), device=device)
-            net.set_params({k: z[k] for k in net.shapes})
+            params = {}
+            for k in net.shapes:
+                a = z[k]
+                params[k] = bf16_to_float(a) if a.dtype == np.uint16 else a
+            net.set_params(params)
         return net
 
     def _w(self, name):        # BF16 weight address
@@ -364,3 +379,56 @@ class UNet:
             else:  # one tap per output pixel
                 f += 2 * hh * ww * ci * co
         return f + 2 * h * w * self.levels[0]
+
+
+# ------------------------------------------------------------------ problem I/O
+THETA_MID, THETA_HALF = 90.0, 60.0          # contact-angle plane: (theta - 90) / 60
+LOGDP_MID, LOGDP_HALF = -3.15, 0.85         # pressure plane: (log10 dp + 3.15) / 0.85
+
+
+def features(mask: np.ndarray, theta: float, dp: float) -> np.ndarray:
+    """Network input (h, w, 8) float: solid mask, contact-angle plane,
+    pressure-step plane, five zero channels."""
+    h, w = mask.shape
+    x = np.zeros((h, w, IN_CH), np.float32)
+    x[..., 0] = mask
+    x[..., 1] = (theta - THETA_MID) / THETA_HALF
+    x[..., 2] = (np.log10(dp) - LOGDP_MID) / LOGDP_HALF
+    return x
+
+
+def saturation_field(rho: np.ndarray) -> np.ndarray:
+    """Per-node non-wetting fraction rho1 / (rho1 + rho2) (0 at solid nodes)."""
+    tot = rho[0] + rho[1]
+    return np.where(tot > 0, rho[0] / np.where(tot > 0, tot, 1.0), 0.0)
+
+
+def warm_start_density(problem, sat: np.ndarray, threshold: float = 0.5) -> np.ndarray:
+    """Initial densities from a predicted saturation field: inside the porous
+    window a fluid node is non-wetting-rich (rho1, rho2) = (major, minor)
+    where the prediction exceeds `threshold`, wetting-rich otherwise; the
+    reservoirs keep the cold-start state."""
+    rho = np.array(problem.rho0, dtype=np.float64, copy=True)
+    fluid = problem.mask == 0
+    major = float(rho[1][fluid].max())
+    minor = float(rho[0][fluid].min())
+    win = np.zeros_like(fluid)
+    win[:, problem.porous_x0:problem.porous_x1] = True
+    sel = fluid & win
+    nw = sel & (sat > threshold)
+    w = sel & ~(sat > threshold)
+    rho[0][nw], rho[1][nw] = major, minor
+    rho[0][w], rho[1][w] = minor, major
+    return rho
+
+
+def predict(net: "UNet", problems, batch: int = 8) -> np.ndarray:
+    """Saturation predictions (k, h, w) for problems with attributes theta, dp."""
+    import torch
+    out = []
+    for i in range(0, len(problems), batch):
+        chunk = problems[i:i + batch]
+        x = np.stack([features(p.mask, p.theta, p.dp) for p in chunk])
+        xb = torch.from_numpy(bf16_bits(x).view(np.int16)).to(net.device)
+        out.append(net.forward(xb).cpu().numpy().copy())
+    return np.concatenate(out)

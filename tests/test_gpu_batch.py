@@ -1,0 +1,83 @@
+"""The batched workload at full size: 64 uneven D2Q9 drainage instances
+(256x128 .. 1024x512), each with its own medium, contact angle and pressure
+step, advanced together by one launch per step in HIP graphs after the
+autotuner has picked the variant -- the configuration bench.py times.
+
+Per-instance error against the FP64 oracle after 200 steps at 1024 seeded
+fluid nodes per instance (tests/golden/batch64_step200_samples.npz, written
+by tests/golden/make_batch64_samples.py from the oracle alone):
+  FP32 storage: every sampled density within 1e-5 relative;
+  BF16-deviation storage: within 2e-2 (measured values printed).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_2111_08666_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+FIXTURE = os.path.join(HERE, "golden", "batch64_step200_samples.npz")
+
+
+@pytest.fixture(scope="module")
+def lbm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_08666_amd import lbm as L
+    L.lib()
+    return L
+
+
+@pytest.fixture(scope="module")
+def problems():
+    return I.batch_instances(64)
+
+
+@pytest.fixture(scope="module")
+def ref():
+    with np.load(FIXTURE, allow_pickle=False) as z:
+        return {k: z[k] for k in z.files}
+
+
+def _advance_like_bench(b, steps=200):
+    """Autotune (ordinary steps), then graph replays up to `steps`."""
+    rep = b.autotune(10)
+    done = 12 * len(rep.strip().splitlines())
+    rest = steps - done
+    assert rest > 0 and rest % 2 == 0
+    b.step_graph(2, rest // 2)
+    return rep
+
+
+@pytest.mark.parametrize("storage,bound", [(0, 1e-5), (1, 2e-2)])
+def test_batch64_per_instance_error_vs_oracle(lbm, problems, ref, storage, bound):
+    assert int(ref["steps"]) == 200
+    b = lbm.BatchSolver(problems, storage=storage)
+    rep = _advance_like_bench(b)
+    print(f"[batch64] storage={storage} autotune: {rep.strip().splitlines()}", flush=True)
+    errs = []
+    for k, p in enumerate(problems):
+        assert tuple(ref[f"shape{k}"]) == p.mask.shape
+        g = b.density(k).reshape(2, -1)[:, ref[f"idx{k}"]].astype(np.float64)
+        r = ref[f"rho{k}"]
+        errs.append(float(np.max(np.abs(g - r) / np.abs(r))))
+    errs = np.array(errs)
+    print(f"[batch64] storage={storage} per-instance max relative error: "
+          + " ".join(f"{e:.1e}" for e in errs), flush=True)
+    print(f"[batch64] storage={storage} worst {errs.max():.2e} median {np.median(errs):.2e}", flush=True)
+    assert errs.max() <= bound
+
+
+def test_batch64_equals_single_instance_runs(lbm, problems):
+    """Batching changes nothing: each instance of the batch is bitwise equal
+    to the same instance advanced alone with the same variant."""
+    b = lbm.BatchSolver(problems, strategy=lbm.FUSED, tile_rows=12)
+    b.step_graph(10, 3)
+    for k in (0, 17, 41, 63):
+        s = lbm.Solver(problems[k], strategy=lbm.FUSED, tile_rows=12)
+        s.step(30)
+        assert np.array_equal(b.density(k), s.density()), k
