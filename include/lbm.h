@@ -48,7 +48,7 @@ typedef enum {
 enum { LBM_SRT = 0, LBM_MRT = 1, LBM_TRT = 2 };            /* lbm_params.collision */
 enum { LBM_STORE_F32 = 0, LBM_STORE_BF16DEV = 1 };          /* lbm_params.storage */
 enum { LBM_MATH_F64 = 0, LBM_MATH_F32 = 1 };                /* lbm_params.math */
-enum { LBM_AUTO = 0, LBM_FUSED = 1, LBM_SPLIT = 2 };        /* lbm_params.strategy */
+enum { LBM_AUTO = 0, LBM_FUSED = 1, LBM_SPLIT = 2, LBM_COMPACT = 3 }; /* lbm_params.strategy */
 
 /* Problem geometry (Sec. 2.3 and Sec. 4.2: a solid map phi, periodic or
  * open axes, the inlet at x = 0 and the outlet at x = nx - 1). */
@@ -81,8 +81,14 @@ typedef struct {
   int32_t storage;        /* LBM_STORE_F32 or LBM_STORE_BF16DEV: how f* is held */
   int32_t math;           /* node arithmetic: LBM_MATH_F64 (default) or LBM_MATH_F32 */
   int32_t strategy;       /* LBM_AUTO, LBM_FUSED (one launch per step, halo
-                             densities recomputed per block) or LBM_SPLIT
-                             (density, solid-density and collide launches) */
+                             densities recomputed per block), LBM_SPLIT
+                             (density, solid-density and collide launches) or
+                             LBM_COMPACT (the split step over a compacted
+                             layout that stores fluid nodes only: thread per
+                             fluid node, bounce-back from the node's own
+                             slots).  The layout is fixed at creation:
+                             LBM_COMPACT cannot be switched to or from the
+                             others (lbm_autotune keeps it). */
   int32_t tile_rows;      /* fused D2Q9 tile height: 8, 12 or 16 (0 = 12) */
 } lbm_params;
 

@@ -21,6 +21,15 @@ constexpr int kTileX = 60;
 // 3D step tile: the same 64-lane rows, TY3 interior rows in y, marching in z.
 constexpr int kTileY3 = 8;
 
+// Compacted layout: the fluid nodes of each (y, z) row, in x order, get
+// consecutive compact indices c.  A 64-node word of a row is described by its
+// fluid bit mask and the compact index of its first fluid node, so the index
+// of fluid node (x, row) is pre + popcount(bits below x).
+struct RowWord {
+  unsigned long long bits;
+  long long pre;
+};
+
 // Device-side description of one instance (array in device memory).
 struct InstDev {
   float *f[2];            // ping-pong post-collision state (layout by storage)
@@ -35,6 +44,12 @@ struct InstDev {
   double tau1, tau2, G, chi1, chi2, gx, gy, gz;
   double rho_in1, rho_out2, rho_in2, rho_out1;
   double lambda, s_e, s_eps;
+  // compacted layout (compact != 0): f[s][i][c] planes of cpitch entries
+  const RowWord *cword;   // [ny * nz][pitch / 64]
+  const uint32_t *ckey;   // [nf]: dense node index x + pitch * (y + ny * z) of compact node c
+  const uint32_t *cbnd;   // [nbnd]: dense index of each solid node with a fluid neighbour
+  int64_t nf, nbnd;
+  int32_t cpitch, compact;
 };
 
 // Reduction record written per block by the observables kernel.
@@ -44,7 +59,8 @@ constexpr int kObsFields = 12;  // mass0 mass1 nfluid nwin swcount sumrw sumr pi
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, const float *rho0_dev,
                        int parity, hipStream_t s);
 // One step of every instance of a batch.  strategy 1: fused kernel (one
-// launch over a flat block table); 2: split step (three launches per instance).
+// launch over a flat block table); 2: split step (three launches per instance);
+// 3: compacted fluid-node step (three launches per instance, compact layout).
 struct StepLaunch {
   const InstDev *d_insts;
   const InstDev *h;            // host copies (grid sizes of the split kernels)

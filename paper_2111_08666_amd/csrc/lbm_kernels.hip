@@ -624,15 +624,11 @@ __global__ __launch_bounds__(256) void rho_kernel(const InstDev *__restrict__ in
   psi_st((gd *)d.psi, pi, sum_q<Q, double>(a), sum_q<Q, double>(b));
 }
 
+// Virtual solid density (Eq. 17) of solid node (x, y, z), dense index pi,
+// whose fluid neighbours are flagged in nb.
 template <int Q>
-__global__ __launch_bounds__(256) void psi_kernel(const InstDev *__restrict__ insts) {
+__device__ __forceinline__ void ivsd_node(const InstDev &d, int x, int y, int z, int64_t pi, uint32_t nb) {
   using L = Lat<Q>;
-  const InstDev &d = insts[0];
-  int x, y, z;
-  if (!wave_row(d, x, y, z)) return;
-  const int64_t pi = x + (int64_t)d.pitch * (y + (int64_t)d.ny * z);
-  const uint32_t nb = ((gcu32 *)d.info)[pi];
-  if (!(nb & kSolid) || !(nb & kLinkMask)) return;
   gd *__restrict__ psi = (gd *)d.psi;
   int xs[3];
   source_x(d, x, xs);  // xs[1 - e_x]: x + e_x with wrap
@@ -654,29 +650,36 @@ __global__ __launch_bounds__(256) void psi_kernel(const InstDev *__restrict__ in
   psi_st(psi, pi, d.chi1 * s1 * inv, d.chi2 * s2 * inv);
 }
 
-template <int Q, int COLL, int ST, typename R>
-__global__ __launch_bounds__(256) void collide_kernel(const InstDev *__restrict__ insts, int parity) {
-  using L = Lat<Q>;
+template <int Q>
+__global__ __launch_bounds__(256) void psi_kernel(const InstDev *__restrict__ insts) {
   const InstDev &d = insts[0];
   int x, y, z;
   if (!wave_row(d, x, y, z)) return;
   const int64_t pi = x + (int64_t)d.pitch * (y + (int64_t)d.ny * z);
-  const uint32_t info = ((gcu32 *)d.info)[pi];
-  if (info & kSolid) return;
+  const uint32_t nb = ((gcu32 *)d.info)[pi];
+  if (!(nb & kSolid) || !(nb & kLinkMask)) return;
+  ivsd_node<Q>(d, x, y, z, pi, nb);
+}
+
+// Densities at node pi and the pair sums sum_i w_i psi(x + e_i) e_i of the
+// interaction force (Eq. 13); at an open face the mirrored pairs with an x
+// component cancel.
+template <int Q, typename R>
+__device__ __forceinline__ void psi_force_sums(const InstDev &d, int x, int y, int z, int64_t pi,
+                                               uint32_t info, R &rho1, R &rho2, R &sx1, R &sy1, R &sz1,
+                                               R &sx2, R &sy2, R &sz2) {
+  using L = Lat<Q>;
   gcd *__restrict__ psi = (gcd *)d.psi;
-  gcf *__restrict__ fin = G(d.f[parity]);
-  gf *__restrict__ fout = G(d.f[parity ^ 1]);
   int xs[3];
   source_x(d, x, xs);
   const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
   const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
   const int yy[3] = {ym, y, yp}, zz[3] = {zm, z, zp};
-  // force: sum_i w_i psi(x + e_i) e_i by opposite pairs; at an open face the
-  // mirrored pairs with an x component cancel
   const Vec2<double> c = psi_ld(psi, pi);
-  const R rho1 = (R)c.x, rho2 = (R)c.y;
+  rho1 = (R)c.x;
+  rho2 = (R)c.y;
   const bool open_face = (info & (kInlet | kOutlet)) != 0;
-  R sx1 = 0, sy1 = 0, sz1 = 0, sx2 = 0, sy2 = 0, sz2 = 0;
+  sx1 = 0; sy1 = 0; sz1 = 0; sx2 = 0; sy2 = 0; sz2 = 0;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     if (L::opp[i] < i) continue;
@@ -691,6 +694,22 @@ __global__ __launch_bounds__(256) void collide_kernel(const InstDev *__restrict_
     if (L::ey[i]) { sy1 += L::ey[i] * d1; sy2 += L::ey[i] * d2; }
     if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
   }
+}
+
+template <int Q, int COLL, int ST, typename R>
+__global__ __launch_bounds__(256) void collide_kernel(const InstDev *__restrict__ insts, int parity) {
+  const InstDev &d = insts[0];
+  int x, y, z;
+  if (!wave_row(d, x, y, z)) return;
+  const int64_t pi = x + (int64_t)d.pitch * (y + (int64_t)d.ny * z);
+  const uint32_t info = ((gcu32 *)d.info)[pi];
+  if (info & kSolid) return;
+  gcf *__restrict__ fin = G(d.f[parity]);
+  gf *__restrict__ fout = G(d.f[parity ^ 1]);
+  int xs[3];
+  source_x(d, x, xs);
+  R rho1, rho2, sx1, sy1, sz1, sx2, sy2, sz2;
+  psi_force_sums<Q, R>(d, x, y, z, pi, info, rho1, rho2, sx1, sy1, sz1, sx2, sy2, sz2);
   int64_t src[3][3];
   source_rows<Q, true>(d, y, z, src);  // one row per wave
   float a[Q], b[Q];
@@ -702,6 +721,114 @@ __global__ __launch_bounds__(256) void collide_kernel(const InstDev *__restrict_
                            -G_ * rho2 * sy1 + rho2 * gyb, -G_ * rho2 * sz1 + rho2 * gzb);
   pop_store<Q, ST>(fout, d.pitch, uniform64(y * d.ystride + z * d.zstride), x, a, b, (float)rho1, (float)rho2);
   store_ghosts<Q, ST>(d, fout, info, src, xs, a, b);
+}
+
+// ---------------------------------------------------------------------------
+// Compacted fluid-node step.  Thread per fluid node (nothing is spent on solid
+// nodes, whose populations are not stored).  The state is f*[s][i][c] over
+// the compact index c; a pull from a fluid source reads the source's compact
+// index (popcount rank in its row), a pull across a solid link reads the
+// node's own f*_opp(i) (half-way bounce-back without ghost slots).  Densities
+// and the virtual solid density go through the dense psi array as in the
+// split step, and the force and collision are the split step's arithmetic.
+// ---------------------------------------------------------------------------
+// Compact index of fluid node (x, row), row = y + ny * z.  For a solid
+// position it is the index of the next fluid node (at most nf).
+__device__ __forceinline__ int64_t crank(const InstDev &d, int x, int64_t row) {
+  const RowWord w = d.cword[row * (d.pitch >> 6) + (x >> 6)];
+  const unsigned long long below = (1ull << (x & 63)) - 1ull;
+  return w.pre + __popcll(w.bits & below);
+}
+
+__device__ __forceinline__ void ckey_xyz(const InstDev &d, uint32_t key, int &x, int &y, int &z) {
+  const uint32_t r = key / (uint32_t)d.pitch;
+  x = (int)(key - r * (uint32_t)d.pitch);
+  y = (int)(r % (uint32_t)d.ny);
+  z = (int)(r / (uint32_t)d.ny);
+}
+
+// Pull + inlet/outlet completion of fluid node c at (x, y, z).
+template <int Q, int ST, typename R>
+__device__ __forceinline__ void cgather(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int x, int y,
+                                        int z, int64_t c, float (&f0)[Q], float (&f1)[Q]) {
+  using L = Lat<Q>;
+  const int cp = d.cpitch;
+  int xs[3];
+  source_x(d, x, xs);  // indexed by e_x + 1: x - e_x with wrap
+  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
+  const int ys[3] = {yp, y, ym}, zs[3] = {zp, z, zm};  // indexed by e + 1: y - e_y, z - e_z
+  const int64_t last = d.nf - 1;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int64_t sc = c;
+    int pi = i;
+    if (i != 0) {
+      if ((info >> i) & 1u) {
+        pi = L::opp[i];
+      } else {
+        // a missing link at an open face wraps onto an arbitrary node; the
+        // completion below overwrites it
+        sc = crank(d, xs[L::ex[i] + 1], ys[L::ey[i] + 1] + (int64_t)d.ny * zs[L::ez[i] + 1]);
+        sc = sc < last ? sc : last;
+      }
+    }
+    f0[i] = pop_get<Q, ST>(fin, cp, 0, pi, 0, (int)sc);
+    f1[i] = pop_get<Q, ST>(fin, cp, 1, pi, 0, (int)sc);
+  }
+  if (info & (kInlet | kOutlet)) {
+    const int t = y + d.ny * z;
+    const int64_t nt = (int64_t)d.ny * d.nz;
+    gcf *frz = G(d.frozen);
+    complete_boundary<Q, R>(
+        d, info, f0, f1, [&](int s, int i) { return pop_get<Q, ST>(fin, cp, s, i, 0, (int)c); },
+        [&](int s, int i) { return frz[(int64_t)(s * Q + i) * nt + t]; });
+  }
+}
+
+template <int Q, int ST>
+__global__ __launch_bounds__(256) void crho_kernel(const InstDev *__restrict__ insts, int parity) {
+  const InstDev &d = insts[0];
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d.nf) return;
+  const uint32_t key = d.ckey[c];
+  int x, y, z;
+  ckey_xyz(d, key, x, y, z);
+  const uint32_t info = ((gcu32 *)d.info)[key];
+  float a[Q], b[Q];
+  cgather<Q, ST, double>(d, G(d.f[parity]), info, x, y, z, c, a, b);
+  psi_st((gd *)d.psi, key, sum_q<Q, double>(a), sum_q<Q, double>(b));
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void cpsi_kernel(const InstDev *__restrict__ insts) {
+  const InstDev &d = insts[0];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d.nbnd) return;
+  const uint32_t key = d.cbnd[j];
+  int x, y, z;
+  ckey_xyz(d, key, x, y, z);
+  ivsd_node<Q>(d, x, y, z, key, ((gcu32 *)d.info)[key]);
+}
+
+template <int Q, int COLL, int ST, typename R>
+__global__ __launch_bounds__(256) void ccollide_kernel(const InstDev *__restrict__ insts, int parity) {
+  const InstDev &d = insts[0];
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= d.nf) return;
+  const uint32_t key = d.ckey[c];
+  int x, y, z;
+  ckey_xyz(d, key, x, y, z);
+  const uint32_t info = ((gcu32 *)d.info)[key];
+  R rho1, rho2, sx1, sy1, sz1, sx2, sy2, sz2;
+  psi_force_sums<Q, R>(d, x, y, z, key, info, rho1, rho2, sx1, sy1, sz1, sx2, sy2, sz2);
+  float a[Q], b[Q];
+  cgather<Q, ST, R>(d, G(d.f[parity]), info, x, y, z, c, a, b);
+  const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
+  collide_node<Q, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb, -G_ * rho1 * sy2 + rho1 * gyb,
+                           -G_ * rho1 * sz2 + rho1 * gzb, -G_ * rho2 * sx1 + rho2 * gxb,
+                           -G_ * rho2 * sy1 + rho2 * gyb, -G_ * rho2 * sz1 + rho2 * gzb);
+  pop_store<Q, ST>(G(d.f[parity ^ 1]), d.cpitch, 0, (int)c, a, b, (float)rho1, (float)rho2);
 }
 
 // ---------------------------------------------------------------------------
@@ -726,6 +853,10 @@ __global__ void init_kernel(const InstDev *__restrict__ insts, const float *__re
     for (int i = 0; i < Q; ++i) {
       a[i] = (float)(Lat<Q>::w[i] * (double)r1);
       c[i] = (float)(Lat<Q>::w[i] * (double)r2);
+    }
+    if (d.compact) {
+      pop_store<Q, ST>(b, d.cpitch, 0, (int)crank(d, x, y + (int64_t)d.ny * z), a, c, r1, r2);
+      continue;
     }
     pop_store<Q, ST>(b, d.pitch, y * d.ystride + z * d.zstride, x, a, c, r1, r2);
     int64_t src[3][3];
@@ -762,7 +893,8 @@ __global__ __launch_bounds__(256) void obs_kernel(const InstDev *__restrict__ in
     const uint32_t inf = d.info[x + (int64_t)d.pitch * yz];
     if (inf & kSolid) continue;
     float a[Q], b[Q];
-    gather<Q, ST, double>(d, fin, inf, x, y, z, a, b);
+    if (d.compact) cgather<Q, ST, double>(d, fin, inf, x, y, z, crank(d, x, yz), a, b);
+    else gather<Q, ST, double>(d, fin, inf, x, y, z, a, b);
     const double r1 = sum_q<Q, double>(a), r2 = sum_q<Q, double>(b);
     if (!isfinite(r1) || !isfinite(r2)) flags |= 1;
     if (r1 < 0.0 || r2 < 0.0) flags |= 2;
@@ -835,7 +967,8 @@ __global__ void density_kernel(const InstDev *__restrict__ insts, int parity, fl
     float r1 = 0.f, r2 = 0.f;
     if (!(inf & kSolid)) {
       float a[Q], b[Q];
-      gather<Q, ST, double>(d, fin, inf, x, y, z, a, b);
+      if (d.compact) cgather<Q, ST, double>(d, fin, inf, x, y, z, crank(d, x, yz), a, b);
+      else gather<Q, ST, double>(d, fin, inf, x, y, z, a, b);
       r1 = (float)sum_q<Q, double>(a);
       r2 = (float)sum_q<Q, double>(b);
     }
@@ -901,12 +1034,29 @@ static void launch_split_q(int q, const InstDev *d, const InstDev &h, int parity
   }
 }
 
+template <int COLL, int ST, typename R>
+static void launch_compact_q(int q, const InstDev *d, const InstDev &h, int parity, hipStream_t s) {
+  if (h.nf == 0) return;  // no fluid: nothing moves
+  const dim3 g((unsigned)((h.nf + 255) / 256)), gb((unsigned)((h.nbnd + 255) / 256)), b(256);
+  if (q == 9) {
+    crho_kernel<9, ST><<<g, b, 0, s>>>(d, parity);
+    if (h.nbnd) cpsi_kernel<9><<<gb, b, 0, s>>>(d);
+    ccollide_kernel<9, COLL, ST, R><<<g, b, 0, s>>>(d, parity);
+  } else if constexpr (COLL != 1) {
+    crho_kernel<19, ST><<<g, b, 0, s>>>(d, parity);
+    if (h.nbnd) cpsi_kernel<19><<<gb, b, 0, s>>>(d);
+    ccollide_kernel<19, COLL, ST, R><<<g, b, 0, s>>>(d, parity);
+  }
+}
+
 template <typename R>
 static void launch_r(const StepLaunch &L, hipStream_t s) {
 #define LBM_DISPATCH(COLL, ST)                                                                    \
   do {                                                                                            \
     if (L.strategy == 2) {                                                                        \
       for (int i = 0; i < L.k; ++i) launch_split_q<COLL, ST, R>(L.q, L.d_insts + i, L.h[i], L.parity, s); \
+    } else if (L.strategy == 3) {                                                                 \
+      for (int i = 0; i < L.k; ++i) launch_compact_q<COLL, ST, R>(L.q, L.d_insts + i, L.h[i], L.parity, s); \
     } else {                                                                                      \
       launch_fused_q<COLL, ST, R>(L.q, L.ty, L.d_insts, L.block_inst, L.n_blocks, L.parity, s);   \
     }                                                                                             \
@@ -937,6 +1087,9 @@ const char *step_kernel_name(int q, int collision, int storage, int math, int st
   static thread_local char buf[128];
   if (strategy == 2)
     snprintf(buf, sizeof buf, "collide_kernel<%d,%s,%s,%s> (+rho_kernel, psi_kernel)", q, coll[collision],
+             st[storage], mt[math]);
+  else if (strategy == 3)
+    snprintf(buf, sizeof buf, "ccollide_kernel<%d,%s,%s,%s> (+crho_kernel, cpsi_kernel)", q, coll[collision],
              st[storage], mt[math]);
   else if (q == 9)
     snprintf(buf, sizeof buf, "step_d2q9<%s,%s,%s,%d>", coll[collision], st[storage], mt[math], ty);

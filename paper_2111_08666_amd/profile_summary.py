@@ -87,13 +87,19 @@ def traffic(fetch_dir, write_dir, kernel, copy_mib):
     out = {}
     for counter, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         vals = _dispatch_values(d, counter)
-        kv = [v for n, vs in vals.items() if kernel in n for v in vs]
         cv = sorted((v for n, vs in vals.items() if "copyBuffer" in n for v in vs), reverse=True)[:3]
-        if not kv or not cv:
-            raise SystemExit(f"no dispatches of {kernel!r} or of the calibration copy in {d}")
+        if not cv:
+            raise SystemExit(f"no calibration copy in {d}")
         factor = copy_mib * 1024.0 / (sum(cv) / len(cv))
-        out[counter] = {"kib_per_dispatch": sum(kv) / len(kv), "dispatches": len(kv), "scale": factor,
-                        "bytes_per_launch": sum(kv) / len(kv) * 1024.0 * factor}
+        kib, disp = 0.0, []
+        for part in kernel.split("+"):   # a step of several kernels: sum their means
+            kv = [v for n, vs in vals.items() if part.strip() in n for v in vs]
+            if not kv:
+                raise SystemExit(f"no dispatches of {part!r} in {d}")
+            kib += sum(kv) / len(kv)
+            disp.append(len(kv))
+        out[counter] = {"kib_per_launch": kib, "dispatches": disp, "scale": factor,
+                        "bytes_per_launch": kib * 1024.0 * factor}
     out["bytes_per_launch"] = out["FETCH_SIZE"]["bytes_per_launch"] + out["WRITE_SIZE"]["bytes_per_launch"]
     return out
 
@@ -104,7 +110,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("dirs", nargs="*")
     ap.add_argument("--traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
-    ap.add_argument("--kernel", help="substring of the profiled kernel's full name")
+    ap.add_argument("--kernel", help="substring of the profiled kernel's full name ('a+b+c': a step of "
+                                     "several kernels)")
     ap.add_argument("--name", help="kernel name as the solver reports it")
     ap.add_argument("--workload")
     ap.add_argument("--copy-mib", type=int, default=1024)

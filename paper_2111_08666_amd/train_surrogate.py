@@ -189,7 +189,11 @@ def cmd_train(a):
     flops = 3 * net.flops_per_image(x.shape[1], x.shape[2]) * a.batch
     it = 0
     history = []
+    t_start = time.time()
     for ep in range(a.epochs):
+        if a.max_minutes and time.time() - t_start > 60 * a.max_minutes:
+            log(f"[train] time budget of {a.max_minutes} min reached after {ep} epochs")
+            break
         perm = rng.permutation(tr)
         torch.cuda.synchronize()
         te = time.time()
@@ -307,6 +311,7 @@ def main():
     t.add_argument("--val-frac", type=float, default=0.05)
     t.add_argument("--seed", type=int, default=0)
     t.add_argument("--workers", type=int, default=8)
+    t.add_argument("--max-minutes", type=float, default=0.0, help="stop starting epochs after this")
     t.add_argument("--out", required=True)
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)

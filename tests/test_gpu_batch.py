@@ -6,7 +6,8 @@ autotuner has picked the variant -- the configuration bench.py times.
 Per-instance error against the FP64 oracle after 200 steps at 1024 seeded
 fluid nodes per instance (tests/golden/batch64_step200_samples.npz, written
 by tests/golden/make_batch64_samples.py from the oracle alone):
-  FP32 storage: every sampled density within 1e-5 relative;
+  FP32 storage: every sampled density within 1e-5 relative, with FP64 and
+  with FP32 node arithmetic;
   BF16-deviation storage: within 2e-2 (measured values printed).
 """
 import os
@@ -53,12 +54,12 @@ def _advance_like_bench(b, steps=200):
     return rep
 
 
-@pytest.mark.parametrize("storage,bound", [(0, 1e-5), (1, 2e-2)])
-def test_batch64_per_instance_error_vs_oracle(lbm, problems, ref, storage, bound):
+@pytest.mark.parametrize("storage,math,bound", [(0, 0, 1e-5), (1, 0, 2e-2), (0, 1, 1e-5)])
+def test_batch64_per_instance_error_vs_oracle(lbm, problems, ref, storage, math, bound):
     assert int(ref["steps"]) == 200
-    b = lbm.BatchSolver(problems, storage=storage)
+    b = lbm.BatchSolver(problems, storage=storage, math=math)
     rep = _advance_like_bench(b)
-    print(f"[batch64] storage={storage} autotune: {rep.strip().splitlines()}", flush=True)
+    print(f"[batch64] storage={storage} math={math} autotune: {rep.strip().splitlines()}", flush=True)
     errs = []
     for k, p in enumerate(problems):
         assert tuple(ref[f"shape{k}"]) == p.mask.shape
@@ -66,9 +67,10 @@ def test_batch64_per_instance_error_vs_oracle(lbm, problems, ref, storage, bound
         r = ref[f"rho{k}"]
         errs.append(float(np.max(np.abs(g - r) / np.abs(r))))
     errs = np.array(errs)
-    print(f"[batch64] storage={storage} per-instance max relative error: "
+    print(f"[batch64] storage={storage} math={math} per-instance max relative error: "
           + " ".join(f"{e:.1e}" for e in errs), flush=True)
-    print(f"[batch64] storage={storage} worst {errs.max():.2e} median {np.median(errs):.2e}", flush=True)
+    print(f"[batch64] storage={storage} math={math} worst {errs.max():.2e} median {np.median(errs):.2e}",
+          flush=True)
     assert errs.max() <= bound
 
 

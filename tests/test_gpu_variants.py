@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from cases import problems
 from paper_2111_08666_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
@@ -69,12 +70,15 @@ def _series(p, solver, checkpoints):
     return errs
 
 
-@pytest.mark.parametrize("strategy", ["fused", "split"])
+STRATEGIES = {"fused": 1, "split": 2, "compact": 3}
+
+
+@pytest.mark.parametrize("strategy", sorted(STRATEGIES))
 @pytest.mark.parametrize("name", sorted(P3))
 def test_d3q19_density_parity_200_steps(lbm, name, strategy):
     p = P3[name]
     print(f"[parity3d] {name} {p.mask.shape} {strategy}", flush=True)
-    s = lbm.Solver(p, strategy=lbm.FUSED if strategy == "fused" else lbm.SPLIT)
+    s = lbm.Solver(p, strategy=STRATEGIES[strategy])
     errs = _series(p, s, CHECKPOINTS)
     print(f"[parity3d] {name} {strategy} errors {['%.1e' % e for e in errs]}", flush=True)
     assert max(errs) <= REL_TOL, errs
@@ -111,11 +115,26 @@ def test_fp32_math_error_is_bounded(lbm, q):
     assert max(errs) <= F32_MATH_BOUND, errs
 
 
-@pytest.mark.parametrize("strategy", ["fused", "split"])
+P2D = problems()
+
+
+@pytest.mark.parametrize("name", sorted(P2D))
+def test_fp32_math_d2q9_error_is_stated(lbm, name):
+    """FP32 node arithmetic on every D2Q9 parity case.  It does not hold the
+    default's 1e-5 bar everywhere (drainage amplifies rounding differences:
+    3.6e-5 on the SRT drainage case), so it is an option with the stated
+    bound, and FP64 node arithmetic stays the default."""
+    p = P2D[name]
+    errs = _series(p, lbm.Solver(p, math=lbm.MATH_F32), CHECKPOINTS)
+    print(f"[fp32-math-2d] {name} errors {['%.1e' % e for e in errs]}", flush=True)
+    assert max(errs) <= F32_MATH_BOUND, errs
+
+
+@pytest.mark.parametrize("strategy", sorted(STRATEGIES))
 @pytest.mark.parametrize("q", [9, 19])
 def test_bf16_deviation_storage_error_is_bounded(lbm, q, strategy):
     p = _drain2d() if q == 9 else P3["d3_drain_trt"]
-    s = lbm.Solver(p, storage=lbm.STORE_BF16DEV, strategy=lbm.FUSED if strategy == "fused" else lbm.SPLIT)
+    s = lbm.Solver(p, storage=lbm.STORE_BF16DEV, strategy=STRATEGIES[strategy])
     errs = _series(p, s, CHECKPOINTS)
     print(f"[bf16-dev] q={q} {strategy} errors {['%.1e' % e for e in errs]}", flush=True)
     assert max(errs) <= BF16_BOUND, errs
@@ -149,3 +168,12 @@ def test_bf16_batch_matches_single(lbm):
         s = lbm.Solver(p, storage=lbm.STORE_BF16DEV)
         s.step(30)
         assert np.array_equal(b.density(i), s.density())
+
+
+def test_d3q19_compact_equals_split_bitwise(lbm):
+    p = P3["d3_drain_trt"]
+    a = lbm.Solver(p, strategy=lbm.SPLIT)
+    b = lbm.Solver(p, strategy=lbm.COMPACT)
+    a.step(40)
+    b.step_graph(20, 2)
+    assert np.array_equal(a.density(), b.density())
