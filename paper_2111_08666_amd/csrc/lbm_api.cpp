@@ -70,13 +70,22 @@ Tiling make_tiling(int q, int nx, int ny, int nz, int ty) {
   return t;
 }
 
+// The compacted layout addresses one component's populations with 32-bit
+// byte offsets: q * cpitch * 4 must stay below 2^32.
+bool compact_fits(const lbm_geometry &g) {
+  int64_t nf = 0;
+  for (int64_t n = 0; n < (int64_t)g.nx * g.ny * g.nz; ++n) nf += g.solid[n] == 0;
+  return (int64_t)g.q * (nf + 64) * 4 < ((int64_t)1 << 32);
+}
+
 // The step a context starts with.  Measured on MI355X: the fused kernel is
 // fastest in 2D (single instances and batches); in 3D the compacted layout
 // beats the dense split step (5.1 against 7.7 ms per step at 384^3, porosity
 // 0.42), since it spends nothing on solid nodes.
 int resolve_strategy(const lbm_geometry &g, const lbm_params &p) {
   if (p.strategy != LBM_AUTO) return p.strategy;
-  return g.q == 19 ? LBM_COMPACT : LBM_FUSED;
+  if (g.q == 19) return compact_fits(g) ? LBM_COMPACT : LBM_SPLIT;
+  return LBM_FUSED;
 }
 
 Layout make_layout(const lbm_geometry &g, const lbm_params &p) {
@@ -91,7 +100,7 @@ Layout make_layout(const lbm_geometry &g, const lbm_params &p) {
   L.frozen_bytes = align_up((size_t)2 * g.q * g.ny * g.nz * sizeof(float));
   L.psi_bytes = align_up((size_t)L.pitch * g.ny * g.nz * 2 * sizeof(double));
   L.compact = resolve_strategy(g, p) == LBM_COMPACT;
-  if (L.compact) {
+  if (L.compact) {  // validate() keeps q * cpitch * 4 bytes below 2^32
     int64_t nf = 0;
     for (int64_t n = 0; n < L.n_nodes; ++n) nf += g.solid[n] == 0;
     L.nf = nf;
@@ -160,6 +169,8 @@ bool validate(const lbm_geometry *g, const lbm_params *p, const double *rho0, st
   if (p->strategy < LBM_AUTO || p->strategy > LBM_COMPACT) return bad(err, "unknown strategy");
   if (p->strategy == LBM_COMPACT && p->collision == LBM_MRT && g->q != 9)
     return bad(err, "MRT is defined for D2Q9 only");
+  if (p->strategy == LBM_COMPACT && !compact_fits(*g))
+    return bad(err, "too many fluid nodes for the compacted layout (use LBM_SPLIT)");
   if (p->tile_rows != 0 && p->tile_rows != 8 && p->tile_rows != 12 && p->tile_rows != 16)
     return bad(err, "tile_rows must be 0, 8, 12 or 16");
   const double vals[] = {p->rho_in1, p->rho_out2, p->rho_in2, p->rho_out1, p->g[0], p->g[1], p->g[2]};

@@ -773,8 +773,16 @@ __device__ __forceinline__ void cgather(const InstDev &d, gcf *__restrict__ fin,
         sc = sc < last ? sc : last;
       }
     }
-    f0[i] = pop_get<Q, ST>(fin, cp, 0, pi, 0, (int)sc);
-    f1[i] = pop_get<Q, ST>(fin, cp, 1, pi, 0, (int)sc);
+    if constexpr (ST == 0) {
+      // component planes from a wave-uniform base, 32-bit byte offsets (the
+      // host keeps Q * cpitch * 4 below 2^32)
+      const uint32_t bo = ((uint32_t)pi * (uint32_t)cp + (uint32_t)sc) * 4u;
+      f0[i] = ldg(fin, bo);
+      f1[i] = ldg(fin + (int64_t)Q * cp, bo);
+    } else {
+      f0[i] = pop_get<Q, ST>(fin, cp, 0, pi, 0, (int)sc);
+      f1[i] = pop_get<Q, ST>(fin, cp, 1, pi, 0, (int)sc);
+    }
   }
   if (info & (kInlet | kOutlet)) {
     const int t = y + d.ny * z;
