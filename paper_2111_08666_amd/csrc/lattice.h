@@ -277,6 +277,9 @@ __device__ __forceinline__ void collide_node(const InstDev &d, float (&f0)[Q], f
     if (L::ey[i]) jy += L::ey[i] * dsum;
     if (L::ez[i]) jz += L::ez[i] * dsum;
   }
+  // the FP64 copies made for the momentum are not kept for the collision
+#pragma unroll
+  for (int i = 0; i < Q; ++i) asm volatile("" : "+v"(f0[i]), "+v"(f1[i]));
   const R rho = rho1 + rho2, inv_rho = rcp<R>(rho);
   const R h = d.half_shift ? R(0.5) : R(0);
   const R ux = (jx + h * (F1x + F2x)) * inv_rho;

@@ -238,8 +238,9 @@ __device__ __forceinline__ int xcd_block() {
 // Phase 3: force (Eq. 13 with the open-face mirror) and collision for the
 //          interior nodes, whose pulled populations stayed in registers.
 // ---------------------------------------------------------------------------
+// The 8-row tile fits 128 registers (four waves per SIMD) without spilling.
 template <int COLL, int ST, typename R, int TY>
-__global__ __launch_bounds__(256) void step_d2q9(const InstDev *__restrict__ insts,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TY == 8 ? 4 : 1))) void step_d2q9(const InstDev *__restrict__ insts,
                                                   const int32_t *__restrict__ block_inst, int parity) {
   using L = Lat<9>;
   using V = Vec2<R>;
@@ -740,6 +741,14 @@ __device__ __forceinline__ int64_t crank(const InstDev &d, int x, int64_t row) {
   return w.pre + __popcll(w.bits & below);
 }
 
+// Does some link of the lattice pull from row offset (dy, dz)?
+template <int Q>
+__device__ __forceinline__ constexpr bool row_used(int dy, int dz) {
+  for (int i = 1; i < Q; ++i)
+    if (Lat<Q>::ey[i] == dy && Lat<Q>::ez[i] == dz) return true;
+  return false;
+}
+
 __device__ __forceinline__ void ckey_xyz(const InstDev &d, uint32_t key, int &x, int &y, int &z) {
   const uint32_t r = key / (uint32_t)d.pitch;
   x = (int)(key - r * (uint32_t)d.pitch);
@@ -759,6 +768,24 @@ __device__ __forceinline__ void cgather(const InstDev &d, gcf *__restrict__ fin,
   const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
   const int ys[3] = {yp, y, ym}, zs[3] = {zp, z, zm};  // indexed by e + 1: y - e_y, z - e_z
   const int64_t last = d.nf - 1;
+  // Rank rk and fluid bit fl at column x of every source row (one row word
+  // each; the node's own row is rk = c, fl = 1).  A fluid source at x - 1 has
+  // rank rk - 1, one at x + 1 rank rk + fl; wrapped x sources are looked up.
+  int64_t rk[3][3];
+  int fl[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      rk[a][b] = c;
+      fl[a][b] = 1;
+      if ((a == 1 && b == 1) || !row_used<Q>(a - 1, b - 1)) continue;
+      const int64_t row = ys[a] + (int64_t)d.ny * zs[b];
+      const RowWord w = d.cword[row * (d.pitch >> 6) + (x >> 6)];
+      rk[a][b] = w.pre + __popcll(w.bits & ((1ull << (x & 63)) - 1ull));
+      fl[a][b] = (int)((w.bits >> (x & 63)) & 1ull);
+    }
+  const bool x_edge = x == 0 || x == d.nx - 1;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     int64_t sc = c;
@@ -767,10 +794,17 @@ __device__ __forceinline__ void cgather(const InstDev &d, gcf *__restrict__ fin,
       if ((info >> i) & 1u) {
         pi = L::opp[i];
       } else {
-        // a missing link at an open face wraps onto an arbitrary node; the
-        // completion below overwrites it
-        sc = crank(d, xs[L::ex[i] + 1], ys[L::ey[i] + 1] + (int64_t)d.ny * zs[L::ez[i] + 1]);
-        sc = sc < last ? sc : last;
+        const int a = L::ey[i] + 1, b = L::ez[i] + 1;
+        if (L::ex[i] == 0) {
+          sc = rk[a][b];
+        } else if (!x_edge) {
+          sc = L::ex[i] > 0 ? rk[a][b] - 1 : rk[a][b] + fl[a][b];
+        } else {
+          // wrapped source: periodic x, or a missing link at an open face
+          // (an arbitrary node, overwritten by the completion below)
+          sc = crank(d, xs[L::ex[i] + 1], ys[a] + (int64_t)d.ny * zs[b]);
+          sc = sc < last ? sc : last;
+        }
       }
     }
     if constexpr (ST == 0) {
@@ -797,7 +831,7 @@ __device__ __forceinline__ void cgather(const InstDev &d, gcf *__restrict__ fin,
 template <int Q, int ST>
 __global__ __launch_bounds__(256) void crho_kernel(const InstDev *__restrict__ insts, int parity) {
   const InstDev &d = insts[0];
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
   if (c >= d.nf) return;
   const uint32_t key = d.ckey[c];
   int x, y, z;
@@ -822,7 +856,7 @@ __global__ __launch_bounds__(256) void cpsi_kernel(const InstDev *__restrict__ i
 template <int Q, int COLL, int ST, typename R>
 __global__ __launch_bounds__(256) void ccollide_kernel(const InstDev *__restrict__ insts, int parity) {
   const InstDev &d = insts[0];
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
   if (c >= d.nf) return;
   const uint32_t key = d.ckey[c];
   int x, y, z;
@@ -830,6 +864,9 @@ __global__ __launch_bounds__(256) void ccollide_kernel(const InstDev *__restrict
   const uint32_t info = ((gcu32 *)d.info)[key];
   R rho1, rho2, sx1, sy1, sz1, sx2, sy2, sz2;
   psi_force_sums<Q, R>(d, x, y, z, key, info, rho1, rho2, sx1, sy1, sz1, sx2, sy2, sz2);
+  // keep the psi loads and the pulls apart: both in flight at once would
+  // double the live registers and halve the waves per SIMD
+  __builtin_amdgcn_sched_barrier(0);
   float a[Q], b[Q];
   cgather<Q, ST, R>(d, G(d.f[parity]), info, x, y, z, c, a, b);
   const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
@@ -945,17 +982,30 @@ __global__ __launch_bounds__(256) void obs_kernel(const InstDev *__restrict__ in
   }
 }
 
+// One block of 256 threads per field: thread t sums blocks t, t + 256, ...
+// in order, then a fixed tree over the threads -- deterministic.
 __global__ void obs_final(const double *__restrict__ partials, int n_blocks, double *__restrict__ out) {
-  const int k = threadIdx.x;
-  if (k >= kObsFields) return;
+  __shared__ double red[256];
+  __shared__ int fred[256];
+  const int k = blockIdx.x, t = threadIdx.x;
   double s = 0.0;
   int fl = 0;
-  for (int b = 0; b < n_blocks; ++b) {
+  for (int b = t; b < n_blocks; b += 256) {
     const double v = partials[(int64_t)b * kObsFields + k];
     if (k == kObsFields - 1) fl |= (int)v;
     else s += v;
   }
-  out[k] = (k == kObsFields - 1) ? (double)fl : s;
+  red[t] = s;
+  fred[t] = fl;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      red[t] += red[t + o];
+      fred[t] |= fred[t + o];
+    }
+    __syncthreads();
+  }
+  if (t == 0) out[k] = (k == kObsFields - 1) ? (double)fred[0] : red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1115,7 +1165,7 @@ hipError_t launch_observables(const InstDev *d_inst, const InstDev &h, int parit
     if (h.storage == 0) obs_kernel<19, 0><<<n_blocks, 256, 0, s>>>(d_inst, parity, partials);
     else obs_kernel<19, 1><<<n_blocks, 256, 0, s>>>(d_inst, parity, partials);
   }
-  obs_final<<<1, 64, 0, s>>>(partials, n_blocks, result);
+  obs_final<<<kObsFields, 256, 0, s>>>(partials, n_blocks, result);
   return hipGetLastError();
 }
 

@@ -86,68 +86,114 @@ struct GemmArgs {
   int relu;
 };
 
-template <int MODE>
+// Wave tile TM x TN MFMA tiles (32 x 32 each): per K step a lane loads TM A
+// fragments and TN B fragments for TM * TN products.  The four waves of a
+// block are stacked along the pixels: block tile (128 TM) x (32 TN).
+template <int MODE, int TM, int TN>
 __global__ __launch_bounds__(256) void igemm_fwd(GemmArgs a) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
   const int64_t P = (int64_t)a.n * a.h * a.w;  // rows of A (pixels of the A grid)
-  const int64_t pix = (int64_t)blockIdx.x * 64 + wm * 32 + (lane & 31);
-  const int col = blockIdx.y * 64 + wn * 32 + (lane & 31);
+  const int64_t pix0 = ((int64_t)blockIdx.x * 4 + wave) * (32 * TM);
+  const int col0 = blockIdx.y * (32 * TN);
   const int tap_z = MODE == 1 ? (int)blockIdx.z : 0;
   const int half = lane >> 5;
   const int ntap = MODE == 0 ? 9 : (MODE == 2 ? 4 : 1);
-  const int K = ntap * a.kc;
   const int wtap = MODE == 1 ? 4 : ntap;  // taps per weight row
-  int pn = 0, py = 0, px = 0;
-  const bool prow = pix < P;
-  if (prow) {
-    pn = (int)(pix / ((int64_t)a.h * a.w));
-    const int r = (int)(pix - (int64_t)pn * a.h * a.w);
-    py = r / a.w;
-    px = r - py * a.w;
+  const int K = ntap * a.kc;
+  int pn[TM], py[TM], px[TM];
+  bool prow[TM];
+#pragma unroll
+  for (int t = 0; t < TM; ++t) {
+    const int64_t pix = pix0 + 32 * t + (lane & 31);
+    prow[t] = pix < P;
+    pn[t] = py[t] = px[t] = 0;
+    if (prow[t]) {
+      pn[t] = (int)(pix / ((int64_t)a.h * a.w));
+      const int r = (int)(pix - (int64_t)pn[t] * a.h * a.w);
+      py[t] = r / a.w;
+      px[t] = r - py[t] * a.w;
+    }
   }
-  floatx16 acc = {};
+  floatx16 acc[TM][TN];
+#pragma unroll
+  for (int t = 0; t < TM; ++t)
+#pragma unroll
+    for (int u = 0; u < TN; ++u) acc[t][u] = floatx16{};
   for (int k0 = 0; k0 < K; k0 += 16) {
     const int kk = k0 + 8 * half;
-    bf16x8 A = zero8(), B = zero8();
+    bf16x8 A[TM], B[TN];
+#pragma unroll
+    for (int t = 0; t < TM; ++t) A[t] = zero8();
+#pragma unroll
+    for (int u = 0; u < TN; ++u) B[u] = zero8();
     if (kk < K) {
       const int tap = MODE == 1 ? tap_z : kk / a.kc;
       const int ch = kk - (MODE == 1 ? 0 : tap * a.kc);
-      if (prow) {
+#pragma unroll
+      for (int t = 0; t < TM; ++t) {
+        if (!prow[t]) continue;
         if constexpr (MODE == 0) {
-          const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+          const int yy = py[t] + tap / 3 - 1, xx = px[t] + tap % 3 - 1;
           if (yy >= 0 && yy < a.h && xx >= 0 && xx < a.w)
-            A = load8(a.x + ((int64_t)pn * a.h * a.w + (int64_t)yy * a.w + xx) * a.x_cs + a.x_co + ch);
+            A[t] = load8(a.x + ((int64_t)pn[t] * a.h * a.w + (int64_t)yy * a.w + xx) * a.x_cs + a.x_co + ch);
         } else if constexpr (MODE == 1) {
-          A = load8(a.x + pix * a.x_cs + a.x_co + ch);
+          const int64_t pix = pix0 + 32 * t + (lane & 31);
+          A[t] = load8(a.x + pix * a.x_cs + a.x_co + ch);
         } else {
           const int H2 = 2 * a.h, W2 = 2 * a.w;
-          const int yy = 2 * py + (tap >> 1), xx = 2 * px + (tap & 1);
-          A = load8(a.x + ((int64_t)pn * H2 * W2 + (int64_t)yy * W2 + xx) * a.x_cs + a.x_co + ch);
+          const int yy = 2 * py[t] + (tap >> 1), xx = 2 * px[t] + (tap & 1);
+          A[t] = load8(a.x + ((int64_t)pn[t] * H2 * W2 + (int64_t)yy * W2 + xx) * a.x_cs + a.x_co + ch);
         }
       }
-      if (col < a.nout) B = load8(a.wgt + ((int64_t)col * wtap + tap) * a.kc + ch);
+#pragma unroll
+      for (int u = 0; u < TN; ++u) {
+        const int col = col0 + 32 * u + (lane & 31);
+        if (col < a.nout) B[u] = load8(a.wgt + ((int64_t)col * wtap + tap) * a.kc + ch);
+      }
     }
-    acc = mfma(A, B, acc);
+#pragma unroll
+    for (int t = 0; t < TM; ++t)
+#pragma unroll
+      for (int u = 0; u < TN; ++u) acc[t][u] = mfma(A[t], B[u], acc[t][u]);
   }
-  if (col >= a.nout) return;
-  const float bv = a.bias ? a.bias[col] : 0.f;
-  for (int r = 0; r < 16; ++r) {
-    const int64_t p = (int64_t)blockIdx.x * 64 + wm * 32 + c_row(r, lane);
-    if (p >= P) continue;
-    float v = acc[r] + bv;
-    if (a.relu) v = v > 0.f ? v : 0.f;
-    int64_t o;
-    if constexpr (MODE == 1) {
-      const int qn = (int)(p / ((int64_t)a.h * a.w));
-      const int rr = (int)(p - (int64_t)qn * a.h * a.w);
-      const int qy = rr / a.w, qx = rr - qy * a.w;
-      const int H2 = 2 * a.h, W2 = 2 * a.w;
-      o = (int64_t)qn * H2 * W2 + (int64_t)(2 * qy + (tap_z >> 1)) * W2 + 2 * qx + (tap_z & 1);
-    } else {
-      o = p;
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    const int col = col0 + 32 * u + (lane & 31);
+    if (col >= a.nout) continue;
+    const float bv = a.bias ? a.bias[col] : 0.f;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t p = pix0 + 32 * t + c_row(r, lane);
+        if (p >= P) continue;
+        float v = acc[t][u][r] + bv;
+        if (a.relu) v = v > 0.f ? v : 0.f;
+        int64_t o;
+        if constexpr (MODE == 1) {
+          const int qn = (int)(p / ((int64_t)a.h * a.w));
+          const int rr = (int)(p - (int64_t)qn * a.h * a.w);
+          const int qy = rr / a.w, qx = rr - qy * a.w;
+          const int H2 = 2 * a.h, W2 = 2 * a.w;
+          o = (int64_t)qn * H2 * W2 + (int64_t)(2 * qy + (tap_z >> 1)) * W2 + 2 * qx + (tap_z & 1);
+        } else {
+          o = p;
+        }
+        a.y[o * a.y_cs + a.y_co + col] = f2bf(v);
+      }
     }
-    a.y[o * a.y_cs + a.y_co + col] = f2bf(v);
+  }
+}
+
+// Launch with the wave tile chosen by the output channel count.
+template <int MODE>
+static void launch_igemm(const GemmArgs &a, int64_t P, int taps_z, hipStream_t s) {
+  if (a.nout >= 64) {
+    dim3 g((unsigned)((P + 255) / 256), (unsigned)((a.nout + 63) / 64), (unsigned)taps_z);
+    igemm_fwd<MODE, 2, 2><<<g, 256, 0, s>>>(a);
+  } else {
+    dim3 g((unsigned)((P + 511) / 512), (unsigned)((a.nout + 31) / 32), (unsigned)taps_z);
+    igemm_fwd<MODE, 4, 1><<<g, 256, 0, s>>>(a);
   }
 }
 
@@ -157,10 +203,14 @@ __global__ __launch_bounds__(256) void igemm_fwd(GemmArgs a) {
 //   MODE 0, 3x3: m = co, n = (tap, ci): A = dy[p][co], B = x[p + off(tap)][ci]
 //   MODE 1, transposed 2x2, tap = blockIdx.z: m = co, n = ci:
 //          A = dy[2p + tap][co], B = x[p][ci]  (p over the input grid)
-// Operands are staged through LDS as [pixel][channel] tiles, 32 pixels at a
-// time, and read transposed into the MFMA fragments.
+// Per stage, 64 pixels x 64 channels of each operand are loaded as 16-byte
+// vectors (8 channels of one pixel) and written channel-major to LDS, so an
+// MFMA operand fragment (8 consecutive pixels of one channel) is one 128-bit
+// LDS read.  Channel counts, strides and offsets are multiples of 8.
 // ---------------------------------------------------------------------------
-constexpr int kWgradPix = 512;  // pixels per block
+constexpr int kWgradPix = 4096;  // pixels per block (split-K chunk)
+constexpr int kStagePix = 64;    // pixels per LDS stage
+constexpr int kStageLd = kStagePix + 8;
 
 struct WgradArgs {
   const uint16_t *x;
@@ -173,8 +223,8 @@ struct WgradArgs {
 
 template <int MODE>
 __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
-  __shared__ uint16_t sA[32][64 + 8];  // [pixel][m]
-  __shared__ uint16_t sB[32][64 + 8];  // [pixel][n]
+  __shared__ __attribute__((aligned(16))) uint16_t sA[64][kStageLd];  // [m][pixel]
+  __shared__ __attribute__((aligned(16))) uint16_t sB[64][kStageLd];  // [n][pixel]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
   const int half = lane >> 5;
@@ -185,51 +235,58 @@ __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
   const int nblk = MODE == 1 ? (int)(blockIdx.z / 4) : (int)blockIdx.z;
   const int n0 = nblk * 64;         // column block
   floatx16 acc = {};
-  for (int pc = 0; pc < kWgradPix; pc += 32) {
-    // stage 32 pixels x 64 m and 32 pixels x 64 n
-    for (int e = tid; e < 32 * 64; e += 256) {
-      const int pl = e >> 6, c = e & 63;
-      const int64_t p = p_begin + pc + pl;
-      uint16_t va = 0, vb = 0;
-      if (p < P) {
+  const int64_t p_end = p_begin + kWgradPix < P ? p_begin + kWgradPix : P;
+  for (int64_t pc = p_begin; pc < p_end; pc += kStagePix) {
+    // stage: 64 pixels x 8 channel groups of 8 per operand = 512 vectors, 2 per thread
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int e = tid + 256 * r;
+      const int pl = e >> 3, cg = (e & 7) * 8;
+      const int64_t p = pc + pl;
+      uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
+      if (p < p_end) {
         const int pn = (int)(p / ((int64_t)a.h * a.w));
-        const int r = (int)(p - (int64_t)pn * a.h * a.w);
-        const int py = r / a.w, px = r - py * a.w;
-        const int m = m0 + c;
+        const int rr = (int)(p - (int64_t)pn * a.h * a.w);
+        const int py = rr / a.w, px = rr - py * a.w;
+        const int m = m0 + cg;
         if (m < a.cout) {
+          int64_t q;
           if constexpr (MODE == 0) {
-            va = a.dy[p * a.dy_cs + a.dy_co + m];
+            q = p;
           } else {
             const int H2 = 2 * a.h, W2 = 2 * a.w;
-            const int64_t q = (int64_t)pn * H2 * W2 + (int64_t)(2 * py + (tapz >> 1)) * W2 + 2 * px + (tapz & 1);
-            va = a.dy[q * a.dy_cs + a.dy_co + m];
+            q = (int64_t)pn * H2 * W2 + (int64_t)(2 * py + (tapz >> 1)) * W2 + 2 * px + (tapz & 1);
           }
+          va = *reinterpret_cast<const uint4 *>(a.dy + q * a.dy_cs + a.dy_co + m);
         }
-        const int nn = n0 + c;
+        const int nn = n0 + cg;
         if (nn < a.ncol) {
           if constexpr (MODE == 0) {
             const int tap = nn / a.cin, ci = nn - tap * a.cin;
             const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
             if (yy >= 0 && yy < a.h && xx >= 0 && xx < a.w)
-              vb = a.x[((int64_t)pn * a.h * a.w + (int64_t)yy * a.w + xx) * a.x_cs + a.x_co + ci];
+              vb = *reinterpret_cast<const uint4 *>(
+                  a.x + ((int64_t)pn * a.h * a.w + (int64_t)yy * a.w + xx) * a.x_cs + a.x_co + ci);
           } else {
-            vb = a.x[p * a.x_cs + a.x_co + nn];
+            vb = *reinterpret_cast<const uint4 *>(a.x + p * a.x_cs + a.x_co + nn);
           }
         }
       }
-      sA[pl][c] = va;
-      sB[pl][c] = vb;
+      const uint32_t wa[4] = {va.x, va.y, va.z, va.w}, wb[4] = {vb.x, vb.y, vb.z, vb.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        sA[cg + 2 * k][pl] = (uint16_t)(wa[k] & 0xffffu);
+        sA[cg + 2 * k + 1][pl] = (uint16_t)(wa[k] >> 16);
+        sB[cg + 2 * k][pl] = (uint16_t)(wb[k] & 0xffffu);
+        sB[cg + 2 * k + 1][pl] = (uint16_t)(wb[k] >> 16);
+      }
     }
     __syncthreads();
 #pragma unroll
-    for (int ks = 0; ks < 32; ks += 16) {
-      uint16_t av[8], bv[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        av[j] = sA[ks + 8 * half + j][wm * 32 + (lane & 31)];
-        bv[j] = sB[ks + 8 * half + j][wn * 32 + (lane & 31)];
-      }
-      acc = mfma(pack8(av), pack8(bv), acc);
+    for (int ks = 0; ks < kStagePix; ks += 16) {
+      const uint4 av = *reinterpret_cast<const uint4 *>(&sA[wm * 32 + (lane & 31)][ks + 8 * half]);
+      const uint4 bv = *reinterpret_cast<const uint4 *>(&sB[wn * 32 + (lane & 31)][ks + 8 * half]);
+      acc = mfma(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), acc);
     }
     __syncthreads();
   }
@@ -259,19 +316,41 @@ __global__ void wgrad_reduce(const float *partial, int kblocks, int ntap, int co
   }
 }
 
-// bias gradient: db[c] (+)= sum_p dy[p][c] over a pixel grid, fixed order
-__global__ void bias_grad(const uint16_t *dy, int64_t P, int c, int cs, int co, float *db, int accumulate) {
-  const int ch = blockIdx.x;
-  float s = 0.f;
-  for (int64_t p = threadIdx.x; p < P; p += blockDim.x) s += bf2f(dy[p * cs + co + ch]);
+// Bias gradient db[c] (+)= sum_p dy[p][c] in two fixed-order passes: block
+// partials over chunks of kBiasPix pixels (threads = 4 pixel lanes x 64
+// channels, coalesced along the channels of a pixel), then the sum over blocks.
+constexpr int kBiasPix = 2048;
+__global__ void bias_partial(const uint16_t *dy, int64_t P, int c, int cs, int co, float *partial) {
   __shared__ float red[256];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+  const int pl = threadIdx.x >> 6, cl = threadIdx.x & 63;
+  const int64_t p0 = (int64_t)blockIdx.x * kBiasPix;
+  const int64_t p1 = p0 + kBiasPix < P ? p0 + kBiasPix : P;
+  for (int c0 = 0; c0 < c; c0 += 64) {
+    const int ch = c0 + cl;
+    float s = 0.f;
+    if (ch < c)
+      for (int64_t p = p0 + pl; p < p1; p += 4) s += bf2f(dy[p * cs + co + ch]);
+    red[threadIdx.x] = s;
+    __syncthreads();
+    if (pl == 0 && ch < c)
+      partial[(int64_t)blockIdx.x * c + ch] = ((red[cl] + red[64 + cl]) + red[128 + cl]) + red[192 + cl];
     __syncthreads();
   }
-  if (threadIdx.x == 0) db[ch] = accumulate ? db[ch] + red[0] : red[0];
+}
+
+__global__ void bias_final(const float *partial, int blocks, int c, float *db, int accumulate) {
+  const int ch = blockIdx.x * blockDim.x + threadIdx.x;
+  if (ch >= c) return;
+  float s = 0.f;
+  for (int b = 0; b < blocks; ++b) s += partial[(int64_t)b * c + ch];
+  db[ch] = accumulate ? db[ch] + s : s;
+}
+
+static void bias_grad(const uint16_t *dy, int64_t P, int c, int cs, int co, float *db, float *partial,
+                      int accumulate, hipStream_t s) {
+  const int blocks = (int)((P + kBiasPix - 1) / kBiasPix);
+  bias_partial<<<blocks, 256, 0, s>>>(dy, P, c, cs, co, partial);
+  bias_final<<<(c + 63) / 64, 64, 0, s>>>(partial, blocks, c, db, accumulate);
 }
 
 // wt[ci][ky][kx][co] = w[co][2-ky][2-kx][ci]
@@ -478,9 +557,7 @@ int unet_conv3x3_fwd(const uint16_t *x, int n, int h, int w, int cin, int x_cs, 
       cout < 1 || y_co + cout > y_cs)
     return -1;
   GemmArgs a{x, n, h, w, cin, x_cs, x_co, wgt, bias, cout, y, y_cs, y_co, relu};
-  const int64_t P = (int64_t)n * h * w;
-  dim3 g((unsigned)((P + 63) / 64), (unsigned)((cout + 63) / 64), 1);
-  igemm_fwd<0><<<g, 256, 0, (hipStream_t)s>>>(a);
+  launch_igemm<0>(a, (int64_t)n * h * w, 1, (hipStream_t)s);
   return launched();
 }
 
@@ -493,14 +570,17 @@ int unet_conv3x3_flip(const uint16_t *wgt, int cout, int cin, uint16_t *wt, void
 int64_t unet_wgrad_scratch_floats(int n, int h, int w, int cin, int cout, int taps) {
   const int64_t P = (int64_t)n * h * w;
   const int64_t kb = (P + kWgradPix - 1) / kWgradPix;
-  return kb * (int64_t)cout * cin * taps;
+  const int64_t dy_pix = taps == 4 ? 4 * P : P;  // the bias partials reuse the scratch
+  const int64_t wpart = kb * (int64_t)cout * cin * taps;
+  const int64_t bpart = (dy_pix + kBiasPix - 1) / kBiasPix * (int64_t)cout;
+  return wpart > bpart ? wpart : bpart;
 }
 
 int unet_conv3x3_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs, int x_co, const uint16_t *dy,
                        int cout, int dy_cs, int dy_co, float *dw, float *db, float *partial, int accumulate,
                        void *s) {
-  if (!x || !dy || !dw || !partial || n < 1 || h < 1 || w < 1 || cin < 1 || cout < 1 || x_co + cin > x_cs ||
-      dy_co + cout > dy_cs)
+  if (!x || !dy || !dw || !partial || n < 1 || h < 1 || w < 1 || !ok8(cin) || !ok8(cout) || x_cs % 8 ||
+      x_co % 8 || dy_cs % 8 || dy_co % 8 || x_co + cin > x_cs || dy_co + cout > dy_cs)
     return -1;
   const int64_t P = (int64_t)n * h * w;
   const int kb = (int)((P + kWgradPix - 1) / kWgradPix);
@@ -509,7 +589,7 @@ int unet_conv3x3_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs
   igemm_wgrad<0><<<g, 256, 0, (hipStream_t)s>>>(a);
   wgrad_reduce<<<grid1d((int64_t)cout * 9 * cin), 256, 0, (hipStream_t)s>>>(partial, kb, 1, cout, 9 * cin, dw,
                                                                              accumulate);
-  if (db) bias_grad<<<cout, 256, 0, (hipStream_t)s>>>(dy, P, cout, dy_cs, dy_co, db, accumulate);
+  if (db) bias_grad(dy, P, cout, dy_cs, dy_co, db, partial, accumulate, (hipStream_t)s);
   return launched();
 }
 
@@ -542,9 +622,7 @@ int unet_upconv_fwd(const uint16_t *x, int n, int h, int w, int cin, int x_cs, i
       y_co + cout > y_cs)
     return -1;
   GemmArgs a{x, n, h, w, cin, x_cs, x_co, wgt, bias, cout, y, y_cs, y_co, 0};
-  const int64_t P = (int64_t)n * h * w;
-  dim3 g((unsigned)((P + 63) / 64), (unsigned)((cout + 63) / 64), 4);
-  igemm_fwd<1><<<g, 256, 0, (hipStream_t)s>>>(a);
+  launch_igemm<1>(a, (int64_t)n * h * w, 4, (hipStream_t)s);
   return launched();
 }
 
@@ -556,22 +634,22 @@ int unet_upconv_bwd_data(const uint16_t *dy, int n, int h, int w, int cout, int 
   up_rearrange<<<grid1d((int64_t)cout * 4 * cin), 256, 0, (hipStream_t)s>>>(wgt, cout, cin, wt);
   // A = dy over the 2h x 2w grid gathered at 2p + tap, output grid h x w
   GemmArgs a{dy, n, h, w, cout, dy_cs, dy_co, wt, nullptr, cin, dx, dx_cs, dx_co, 0};
-  const int64_t P = (int64_t)n * h * w;
-  dim3 g((unsigned)((P + 63) / 64), (unsigned)((cin + 63) / 64), 1);
-  igemm_fwd<2><<<g, 256, 0, (hipStream_t)s>>>(a);
+  launch_igemm<2>(a, (int64_t)n * h * w, 1, (hipStream_t)s);
   return launched();
 }
 
 int unet_upconv_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs, int x_co, const uint16_t *dy,
                       int cout, int dy_cs, int dy_co, float *dw, float *db, float *partial, void *s) {
-  if (!x || !dy || !dw || !partial || n < 1 || h < 1 || w < 1 || cin < 1 || cout < 1) return -1;
+  if (!x || !dy || !dw || !partial || n < 1 || h < 1 || w < 1 || !ok8(cin) || !ok8(cout) || x_cs % 8 ||
+      x_co % 8 || dy_cs % 8 || dy_co % 8 || x_co + cin > x_cs || dy_co + cout > dy_cs)
+    return -1;
   const int64_t P = (int64_t)n * h * w;
   const int kb = (int)((P + kWgradPix - 1) / kWgradPix);
   WgradArgs a{x, n, h, w, cin, x_cs, x_co, dy, cout, dy_cs, dy_co, partial, cin};
   dim3 g((unsigned)kb, (unsigned)((cout + 63) / 64), (unsigned)(4 * ((cin + 63) / 64)));
   igemm_wgrad<1><<<g, 256, 0, (hipStream_t)s>>>(a);
   wgrad_reduce<<<grid1d((int64_t)4 * cout * cin), 256, 0, (hipStream_t)s>>>(partial, kb, 4, cout, cin, dw, 0);
-  if (db) bias_grad<<<cout, 256, 0, (hipStream_t)s>>>(dy, 4 * P, cout, dy_cs, dy_co, db, 0);
+  if (db) bias_grad(dy, 4 * P, cout, dy_cs, dy_co, db, partial, 0, (hipStream_t)s);
   return launched();
 }
 
