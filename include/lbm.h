@@ -48,7 +48,8 @@ typedef enum {
 enum { LBM_SRT = 0, LBM_MRT = 1, LBM_TRT = 2 };            /* lbm_params.collision */
 enum { LBM_STORE_F32 = 0, LBM_STORE_BF16DEV = 1 };          /* lbm_params.storage */
 enum { LBM_MATH_F64 = 0, LBM_MATH_F32 = 1 };                /* lbm_params.math */
-enum { LBM_AUTO = 0, LBM_FUSED = 1, LBM_SPLIT = 2, LBM_COMPACT = 3 }; /* lbm_params.strategy */
+enum { LBM_AUTO = 0, LBM_FUSED = 1, LBM_SPLIT = 2, LBM_COMPACT = 3,
+       LBM_FUSED_LIST = 4 };                                /* lbm_params.strategy */
 
 /* Problem geometry (Sec. 2.3 and Sec. 4.2: a solid map phi, periodic or
  * open axes, the inlet at x = 0 and the outlet at x = nx - 1). */
@@ -86,7 +87,9 @@ typedef struct {
                              LBM_COMPACT (the split step over a compacted
                              layout that stores fluid nodes only: thread per
                              fluid node, bounce-back from the node's own
-                             slots).  The layout is fixed at creation:
+                             slots); LBM_FUSED_LIST (D2Q9: the fused
+                             step whose collision phase runs over a per-tile
+                             list of fluid nodes).  The layout is fixed at creation:
                              LBM_COMPACT cannot be switched to or from the
                              others (lbm_autotune keeps it). */
   int32_t tile_rows;      /* fused D2Q9 tile height: 8, 12 or 16 (0 = 12) */

@@ -166,7 +166,8 @@ bool validate(const lbm_geometry *g, const lbm_params *p, const double *rho0, st
   if (p->bc_set < 1 || p->bc_set > 3) return bad(err, "bc_set must be 1, 2 or 3");
   if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_BF16DEV) return bad(err, "unknown storage");
   if (p->math != LBM_MATH_F64 && p->math != LBM_MATH_F32) return bad(err, "unknown math precision");
-  if (p->strategy < LBM_AUTO || p->strategy > LBM_COMPACT) return bad(err, "unknown strategy");
+  if (p->strategy < LBM_AUTO || p->strategy > LBM_FUSED_LIST) return bad(err, "unknown strategy");
+  if (p->strategy == LBM_FUSED_LIST && g->q != 9) return bad(err, "the listed fused step is D2Q9 only");
   if (p->strategy == LBM_COMPACT && p->collision == LBM_MRT && g->q != 9)
     return bad(err, "MRT is defined for D2Q9 only");
   if (p->strategy == LBM_COMPACT && !compact_fits(*g))
@@ -763,6 +764,7 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int64_t steps, char *report, size_t 
   } else {
     if (b->q == 9) {
       for (int ty : {8, 12, 16}) cands.push_back({LBM_FUSED, ty});
+      for (int ty : {8, 12, 16}) cands.push_back({LBM_FUSED_LIST, ty});
     } else {
       cands.push_back({LBM_FUSED, 12});
     }

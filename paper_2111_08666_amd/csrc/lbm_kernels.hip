@@ -385,6 +385,172 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TY == 8 ? 4
 }
 
 // ---------------------------------------------------------------------------
+// D2Q9 fused step with a listed collision phase.  Phases 1 and 2 as above,
+// except that a pulled node keeps only its densities.  Phase 3 runs over a
+// per-tile list of the fluid interior nodes (row-major, built from ballots
+// and a fixed-order prefix in LDS), one list entry per thread: no lane waits
+// on a solid node.  Each entry pulls its populations again (L2 hits: phase 1
+// just read them) with per-lane rows.
+// ---------------------------------------------------------------------------
+template <int COLL, int ST, typename R, int TY>
+__global__ __launch_bounds__(256) void step_d2q9_list(const InstDev *__restrict__ insts,
+                                                      const int32_t *__restrict__ block_inst, int parity) {
+  using L = Lat<9>;
+  using V = Vec2<R>;
+  constexpr int KR = TY / 4;
+  constexpr int kRH = TY + 4;
+  __shared__ V psi[kRH][64];
+  __shared__ uint16_t list[TY * 64];
+  __shared__ int cnt[TY];
+
+  const int bid = xcd_block();
+  const int inst = __builtin_amdgcn_readfirstlane(block_inst ? block_inst[bid] : 0);
+  const InstDev &d = insts[inst];
+  const int lb = bid - d.block_base;
+  const int tx = lb % d.tiles_x, ty = lb / d.tiles_x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  gcf *__restrict__ fin = G(d.f[parity]);
+  gf *__restrict__ fout = G(d.f[parity ^ 1]);
+  gcu32 *__restrict__ infop = (gcu32 *)d.info;
+  const int nx = d.nx, ny = d.ny;
+  const bool px = d.periodic & 1, py = d.periodic & 2;
+
+  int gx = tx * kTileX - 2 + lane;
+  const bool col_store = lane >= 2 && lane < 62 && gx < nx;
+  bool col_in = true;
+  if (gx < 0 || gx >= nx) {
+    if (px) gx += gx < 0 ? nx : -nx;
+    else col_in = false;
+  }
+  const int gxa = col_in ? gx : (gx < 0 ? 0 : nx - 1);
+  int xs[3];
+  source_x(d, gxa, xs);
+
+  int rows[KR + 1], gy[KR + 1];
+  bool row_in[KR + 1];
+#pragma unroll
+  for (int k = 0; k <= KR; ++k) {
+    rows[k] = k < KR ? 2 + wave + 4 * k : (wave < 2 ? wave : TY + wave);
+    int y = ty * TY - 2 + rows[k];
+    bool in = true;
+    if (y < 0 || y >= ny) {
+      if (py) y += y < 0 ? ny : -ny;
+      else in = false;
+    }
+    gy[k] = in ? y : 0;
+    row_in[k] = in;
+  }
+
+  uint32_t infos[KR + 1];
+#pragma unroll
+  for (int k = 0; k <= KR; ++k)
+    infos[k] = (row_in[k] && col_in) ? infop[gx + (int64_t)d.pitch * gy[k]] : kSolid;
+
+  // Phase 1: densities of every region node -> LDS; fluid interior counts
+#pragma unroll
+  for (int k = 0; k <= KR; ++k) {
+    const uint32_t info = infos[k];
+    R rho1 = 0, rho2 = 0;
+    if (ST == 0 || !(info & kSolid)) {
+      int64_t src[3][3];
+      source_rows<9, true>(d, gy[k], 0, src);
+      float a[9], b[9];
+      pull_row<9, ST>(d, fin, info, src, xs, a, b);
+      if (!(info & kSolid)) {
+        if (info & (kInlet | kOutlet)) complete<9, ST, R>(d, fin, info, gx, gy[k], 0, a, b);
+        rho1 = sum_q<9, R>(a);
+        rho2 = sum_q<9, R>(b);
+      }
+    }
+    psi[rows[k]][lane] = V{rho1, rho2};
+    if (k < KR) {
+      const bool fluid = row_in[k] && col_store && ty * TY - 2 + rows[k] < ny && !(info & kSolid);
+      const unsigned long long m = __ballot(fluid);
+      if (lane == 0) cnt[rows[k] - 2] = __popcll(m);
+    }
+  }
+  __syncthreads();
+
+  // Phase 2: virtual solid density; list of fluid interior nodes (row-major)
+#pragma unroll
+  for (int k = 0; k <= KR; ++k) {
+    const int r = rows[k];
+    const uint32_t info = infos[k];
+    if (k < KR) {
+      const bool fluid = row_in[k] && col_store && ty * TY - 2 + r < ny && !(info & kSolid);
+      const unsigned long long m = __ballot(fluid);
+      int base = 0;
+      for (int q = 0; q < r - 2; ++q) base += cnt[q];
+      if (fluid) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)((r << 6) | lane);
+    }
+    if (!row_in[k] || !col_in || !(info & kSolid) || r < 1 || r > kRH - 2 || lane < 1 || lane > 62) continue;
+    if (!(info & kLinkMask)) continue;
+    R s1 = 0, s2 = 0, den = 0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      if (info & (1u << i)) {
+        const V p = psi[r + L::ey[i]][lane + L::ex[i]];
+        const R w = (R)L::w[i];
+        s1 += w * p.x;
+        s2 += w * p.y;
+        den += w;
+      }
+    }
+    const R inv = rcp<R>(den);
+    psi[r][lane] = V{(R)d.chi1 * s1 * inv, (R)d.chi2 * s2 * inv};
+  }
+  int total = 0;
+#pragma unroll
+  for (int q = 0; q < TY; ++q) total += cnt[q];
+  __syncthreads();
+
+  // Phase 3: force + collision over the list
+  const R w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+  for (int t = threadIdx.x; t < total; t += 256) {
+    const int e = list[t];
+    const int r = e >> 6, ln = e & 63;
+    const int x = tx * kTileX - 2 + ln, y = ty * TY - 2 + r;
+    const uint32_t inf = infop[x + (int64_t)d.pitch * y];
+    int64_t src[3][3];
+    int xsl[3];
+    source_rows<9>(d, y, 0, src);
+    source_x(d, x, xsl);
+    float f0[9], f1[9];
+    pull_row<9, ST>(d, fin, inf, src, xsl, f0, f1);
+    if (inf & (kInlet | kOutlet)) complete<9, ST, R>(d, fin, inf, x, y, 0, f0, f1);
+    const V c = psi[r][ln];
+    const R rho1 = c.x, rho2 = c.y;
+    R sx1, sy1, sx2, sy2;
+    {
+      const V p2 = psi[r + 1][ln], p4 = psi[r - 1][ln];
+      if (inf & (kInlet | kOutlet)) {
+        sx1 = 0;
+        sx2 = 0;
+        sy1 = w1 * (p2.x - p4.x);
+        sy2 = w1 * (p2.y - p4.y);
+      } else {
+        const V p1 = psi[r][ln + 1], p3 = psi[r][ln - 1];
+        const V p5 = psi[r + 1][ln + 1], p7 = psi[r - 1][ln - 1];
+        const V p6 = psi[r + 1][ln - 1], p8 = psi[r - 1][ln + 1];
+        const R a57 = p5.x - p7.x, a68 = p6.x - p8.x;
+        const R b57 = p5.y - p7.y, b68 = p6.y - p8.y;
+        sx1 = w1 * (p1.x - p3.x) + w5 * (a57 - a68);
+        sy1 = w1 * (p2.x - p4.x) + w5 * (a57 + a68);
+        sx2 = w1 * (p1.y - p3.y) + w5 * (b57 - b68);
+        sy2 = w1 * (p2.y - p4.y) + w5 * (b57 + b68);
+      }
+    }
+    const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy;
+    const R F1x = -G_ * rho1 * sx2 + rho1 * gxb, F1y = -G_ * rho1 * sy2 + rho1 * gyb;
+    const R F2x = -G_ * rho2 * sx1 + rho2 * gxb, F2y = -G_ * rho2 * sy1 + rho2 * gyb;
+    collide_node<9, COLL, R>(d, f0, f1, rho1, rho2, F1x, F1y, R(0), F2x, F2y, R(0));
+    pop_store<9, ST>(fout, d.pitch, y * d.ystride, x, f0, f1, (float)rho1, (float)rho2);
+    store_ghosts<9, ST>(d, fout, inf, src, xsl, f0, f1);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // D3Q19 fused step.  A block owns a 60 x kTileY3 column of (x, y) and marches
 // through a chunk of z.  Per plane it keeps densities of the 64 x (kTileY3+4)
 // region in an LDS ring of five planes (z-2 .. z+2): at plane z it forms rho of
@@ -1078,6 +1244,16 @@ static void launch_fused_q(int q, int ty, const InstDev *d, const int32_t *bi, i
 }
 
 template <int COLL, int ST, typename R>
+static void launch_fused_list_q(int q, int ty, const InstDev *d, const int32_t *bi, int64_t nb, int parity,
+                                hipStream_t s) {
+  const dim3 g((unsigned)nb), b(256);
+  if (q != 9) return;
+  if (ty == 8) step_d2q9_list<COLL, ST, R, 8><<<g, b, 0, s>>>(d, bi, parity);
+  else if (ty == 16) step_d2q9_list<COLL, ST, R, 16><<<g, b, 0, s>>>(d, bi, parity);
+  else step_d2q9_list<COLL, ST, R, 12><<<g, b, 0, s>>>(d, bi, parity);
+}
+
+template <int COLL, int ST, typename R>
 static void launch_split_q(int q, const InstDev *d, const InstDev &h, int parity, hipStream_t s) {
   const int64_t waves = (int64_t)((h.nx + 63) / 64) * h.ny * h.nz;
   const dim3 g((unsigned)((waves + 3) / 4)), b(256);
@@ -1115,6 +1291,8 @@ static void launch_r(const StepLaunch &L, hipStream_t s) {
       for (int i = 0; i < L.k; ++i) launch_split_q<COLL, ST, R>(L.q, L.d_insts + i, L.h[i], L.parity, s); \
     } else if (L.strategy == 3) {                                                                 \
       for (int i = 0; i < L.k; ++i) launch_compact_q<COLL, ST, R>(L.q, L.d_insts + i, L.h[i], L.parity, s); \
+    } else if (L.strategy == 4) {                                                                 \
+      launch_fused_list_q<COLL, ST, R>(L.q, L.ty, L.d_insts, L.block_inst, L.n_blocks, L.parity, s); \
     } else {                                                                                      \
       launch_fused_q<COLL, ST, R>(L.q, L.ty, L.d_insts, L.block_inst, L.n_blocks, L.parity, s);   \
     }                                                                                             \
@@ -1149,6 +1327,8 @@ const char *step_kernel_name(int q, int collision, int storage, int math, int st
   else if (strategy == 3)
     snprintf(buf, sizeof buf, "ccollide_kernel<%d,%s,%s,%s> (+crho_kernel, cpsi_kernel)", q, coll[collision],
              st[storage], mt[math]);
+  else if (strategy == 4)
+    snprintf(buf, sizeof buf, "step_d2q9_list<%s,%s,%s,%d>", coll[collision], st[storage], mt[math], ty);
   else if (q == 9)
     snprintf(buf, sizeof buf, "step_d2q9<%s,%s,%s,%d>", coll[collision], st[storage], mt[math], ty);
   else

@@ -219,6 +219,7 @@ struct WgradArgs {
   int cout, dy_cs, dy_co;
   float *partial;                 // [kblocks][ntap][cout][ncol]
   int ncol;                       // MODE 0: 9 * cin; MODE 1: cin
+  float *bpartial;                // [kblocks][ntap][cout] bias partial sums, or NULL
 };
 
 template <int MODE>
@@ -235,6 +236,9 @@ __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
   const int nblk = MODE == 1 ? (int)(blockIdx.z / 4) : (int)blockIdx.z;
   const int n0 = nblk * 64;         // column block
   floatx16 acc = {};
+  // the blocks of the first column block also sum dy over their pixels (bias)
+  const bool bias_blk = a.bpartial && nblk == 0 && tid < 64;
+  float bacc = 0.f;
   const int64_t p_end = p_begin + kWgradPix < P ? p_begin + kWgradPix : P;
   for (int64_t pc = p_begin; pc < p_end; pc += kStagePix) {
     // stage: 64 pixels x 8 channel groups of 8 per operand = 512 vectors, 2 per thread
@@ -282,6 +286,15 @@ __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
       }
     }
     __syncthreads();
+    if (bias_blk) {
+#pragma unroll
+      for (int q = 0; q < kStagePix; q += 8) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(&sA[tid][q]);
+        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bacc += bf2f((uint16_t)(w4[k] & 0xffffu)) + bf2f((uint16_t)(w4[k] >> 16));
+      }
+    }
 #pragma unroll
     for (int ks = 0; ks < kStagePix; ks += 16) {
       const uint4 av = *reinterpret_cast<const uint4 *>(&sA[wm * 32 + (lane & 31)][ks + 8 * half]);
@@ -291,6 +304,8 @@ __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
     __syncthreads();
   }
   const int ntap = MODE == 1 ? 4 : 1;
+  if (bias_blk && m0 + tid < a.cout)
+    a.bpartial[((int64_t)blockIdx.x * ntap + tapz) * a.cout + m0 + tid] = bacc;
   const int nn = n0 + wn * 32 + (lane & 31);
   if (nn >= a.ncol) return;
   float *out = a.partial + ((int64_t)blockIdx.x * ntap + tapz) * (int64_t)a.cout * a.ncol;
@@ -316,42 +331,15 @@ __global__ void wgrad_reduce(const float *partial, int kblocks, int ntap, int co
   }
 }
 
-// Bias gradient db[c] (+)= sum_p dy[p][c] in two fixed-order passes: block
-// partials over chunks of kBiasPix pixels (threads = 4 pixel lanes x 64
-// channels, coalesced along the channels of a pixel), then the sum over blocks.
-constexpr int kBiasPix = 2048;
-__global__ void bias_partial(const uint16_t *dy, int64_t P, int c, int cs, int co, float *partial) {
-  __shared__ float red[256];
-  const int pl = threadIdx.x >> 6, cl = threadIdx.x & 63;
-  const int64_t p0 = (int64_t)blockIdx.x * kBiasPix;
-  const int64_t p1 = p0 + kBiasPix < P ? p0 + kBiasPix : P;
-  for (int c0 = 0; c0 < c; c0 += 64) {
-    const int ch = c0 + cl;
-    float s = 0.f;
-    if (ch < c)
-      for (int64_t p = p0 + pl; p < p1; p += 4) s += bf2f(dy[p * cs + co + ch]);
-    red[threadIdx.x] = s;
-    __syncthreads();
-    if (pl == 0 && ch < c)
-      partial[(int64_t)blockIdx.x * c + ch] = ((red[cl] + red[64 + cl]) + red[128 + cl]) + red[192 + cl];
-    __syncthreads();
-  }
-}
-
-__global__ void bias_final(const float *partial, int blocks, int c, float *db, int accumulate) {
+// db[c] (+)= sum over the weight-gradient blocks' bias partials, fixed order.
+__global__ void bias_reduce(const float *bpartial, int64_t nparts, int c, float *db, int accumulate) {
   const int ch = blockIdx.x * blockDim.x + threadIdx.x;
   if (ch >= c) return;
   float s = 0.f;
-  for (int b = 0; b < blocks; ++b) s += partial[(int64_t)b * c + ch];
+  for (int64_t b = 0; b < nparts; ++b) s += bpartial[b * c + ch];
   db[ch] = accumulate ? db[ch] + s : s;
 }
 
-static void bias_grad(const uint16_t *dy, int64_t P, int c, int cs, int co, float *db, float *partial,
-                      int accumulate, hipStream_t s) {
-  const int blocks = (int)((P + kBiasPix - 1) / kBiasPix);
-  bias_partial<<<blocks, 256, 0, s>>>(dy, P, c, cs, co, partial);
-  bias_final<<<(c + 63) / 64, 64, 0, s>>>(partial, blocks, c, db, accumulate);
-}
 
 // wt[ci][ky][kx][co] = w[co][2-ky][2-kx][ci]
 __global__ void conv_flip(const uint16_t *w, int cout, int cin, uint16_t *wt) {
@@ -570,10 +558,9 @@ int unet_conv3x3_flip(const uint16_t *wgt, int cout, int cin, uint16_t *wt, void
 int64_t unet_wgrad_scratch_floats(int n, int h, int w, int cin, int cout, int taps) {
   const int64_t P = (int64_t)n * h * w;
   const int64_t kb = (P + kWgradPix - 1) / kWgradPix;
-  const int64_t dy_pix = taps == 4 ? 4 * P : P;  // the bias partials reuse the scratch
   const int64_t wpart = kb * (int64_t)cout * cin * taps;
-  const int64_t bpart = (dy_pix + kBiasPix - 1) / kBiasPix * (int64_t)cout;
-  return wpart > bpart ? wpart : bpart;
+  const int64_t bpart = kb * (taps == 4 ? 4 : 1) * (int64_t)cout;  // bias partials follow
+  return wpart + bpart;
 }
 
 int unet_conv3x3_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs, int x_co, const uint16_t *dy,
@@ -584,12 +571,13 @@ int unet_conv3x3_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs
     return -1;
   const int64_t P = (int64_t)n * h * w;
   const int kb = (int)((P + kWgradPix - 1) / kWgradPix);
-  WgradArgs a{x, n, h, w, cin, x_cs, x_co, dy, cout, dy_cs, dy_co, partial, 9 * cin};
+  const int64_t wpart = (int64_t)kb * cout * 9 * cin;
+  WgradArgs a{x, n, h, w, cin, x_cs, x_co, dy, cout, dy_cs, dy_co, partial, 9 * cin, db ? partial + wpart : nullptr};
   dim3 g((unsigned)kb, (unsigned)((cout + 63) / 64), (unsigned)((9 * cin + 63) / 64));
   igemm_wgrad<0><<<g, 256, 0, (hipStream_t)s>>>(a);
   wgrad_reduce<<<grid1d((int64_t)cout * 9 * cin), 256, 0, (hipStream_t)s>>>(partial, kb, 1, cout, 9 * cin, dw,
                                                                              accumulate);
-  if (db) bias_grad(dy, P, cout, dy_cs, dy_co, db, partial, accumulate, (hipStream_t)s);
+  if (db) bias_reduce<<<(cout + 63) / 64, 64, 0, (hipStream_t)s>>>(partial + wpart, kb, cout, db, accumulate);
   return launched();
 }
 
@@ -645,11 +633,12 @@ int unet_upconv_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs,
     return -1;
   const int64_t P = (int64_t)n * h * w;
   const int kb = (int)((P + kWgradPix - 1) / kWgradPix);
-  WgradArgs a{x, n, h, w, cin, x_cs, x_co, dy, cout, dy_cs, dy_co, partial, cin};
+  const int64_t wpart = (int64_t)kb * 4 * cout * cin;
+  WgradArgs a{x, n, h, w, cin, x_cs, x_co, dy, cout, dy_cs, dy_co, partial, cin, db ? partial + wpart : nullptr};
   dim3 g((unsigned)kb, (unsigned)((cout + 63) / 64), (unsigned)(4 * ((cin + 63) / 64)));
   igemm_wgrad<1><<<g, 256, 0, (hipStream_t)s>>>(a);
   wgrad_reduce<<<grid1d((int64_t)4 * cout * cin), 256, 0, (hipStream_t)s>>>(partial, kb, 4, cout, cin, dw, 0);
-  if (db) bias_grad(dy, 4 * P, cout, dy_cs, dy_co, db, partial, 0, (hipStream_t)s);
+  if (db) bias_reduce<<<(cout + 63) / 64, 64, 0, (hipStream_t)s>>>(partial + wpart, (int64_t)kb * 4, cout, db, 0);
   return launched();
 }
 

@@ -42,7 +42,7 @@ def test_unet_rejects_bad_arguments_before_launch():
     assert L.unet_conv3x3_fwd(None, 1, 8, 8, 16, 16, 0, fake, None, 32, fake, 32, 0, 1, None) == -1
     assert L.unet_maxpool_fwd(fake, 1, 7, 8, 8, 8, 0, fake, 8, 0, None) == -1
     assert L.unet_head_fwd(fake, 64, 24, 24, fake, fake, fake, None) == -1
-    assert L.unet_wgrad_scratch_floats(2, 16, 16, 32, 64, 9) == 1 * 64 * 32 * 9
+    assert L.unet_wgrad_scratch_floats(2, 16, 16, 32, 64, 9) == 1 * 64 * 32 * 9 + 1 * 64  # weights + bias
 
 
 def test_every_declared_symbol_is_exported():

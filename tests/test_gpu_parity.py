@@ -44,7 +44,7 @@ def _rel_err(g, o, mask):
     return float((np.abs(g.astype(np.float64) - o) / np.abs(o))[:, fluid].max())
 
 
-STRATEGIES = {"fused": 1, "split": 2, "compact": 3}
+STRATEGIES = {"fused": 1, "split": 2, "compact": 3, "fused_list": 4}
 
 
 @pytest.mark.parametrize("strategy", sorted(STRATEGIES))
@@ -65,11 +65,12 @@ def test_density_parity_200_steps(lbm, name, strategy):
     print(f"[parity] {name} {strategy}: worst relative density error {worst:.2e}", flush=True)
 
 
+@pytest.mark.parametrize("strategy", [1, 4])
 @pytest.mark.parametrize("tile_rows", [8, 16])
-def test_fused_tile_heights_match_oracle(lbm, tile_rows):
+def test_fused_tile_heights_match_oracle(lbm, tile_rows, strategy):
     p = PROBLEMS["drain_mrt"]
     ref = _oracle_series(p, (77,))
-    s = lbm.Solver(p, strategy=lbm.FUSED, tile_rows=tile_rows)
+    s = lbm.Solver(p, strategy=strategy, tile_rows=tile_rows)
     s.step(77)
     assert _rel_err(s.density(), ref[77], p.mask) <= REL_TOL
 
@@ -81,7 +82,7 @@ def test_autotune_keeps_the_physics(lbm):
     s = lbm.Solver(p)
     rep = s.autotune(4)
     n_var = len(rep.strip().splitlines())
-    assert n_var == 4  # three tile heights and the split step
+    assert n_var == 7  # three tile heights, fused and listed, and the split step
     total = s.t
     assert total == n_var * (4 + 2)
     s.step(200 - total)
@@ -223,3 +224,15 @@ def test_compact_checkpoint_and_batch(lbm):
         s = lbm.Solver(q, strategy=lbm.COMPACT)
         s.step(40)
         assert np.array_equal(bt.density(i), s.density()), i
+
+
+@pytest.mark.parametrize("storage", [0, 1])
+def test_listed_fused_step_equals_fused_step_bitwise(lbm, storage):
+    """Listing the fluid nodes moves work between lanes, not arithmetic."""
+    for name in ("drain_mrt", "set2", "droplet_periodic", "tiny_poiseuille"):
+        p = PROBLEMS[name]
+        a = lbm.Solver(p, strategy=lbm.FUSED, tile_rows=8, storage=storage)
+        b = lbm.Solver(p, strategy=lbm.FUSED_LIST, tile_rows=8, storage=storage)
+        a.step(41)
+        b.step(41)
+        assert np.array_equal(a.density(), b.density()), name
