@@ -325,6 +325,57 @@ def surrogate_instance(k: int, seed0: int = 40000, n: int = 256, collision: int 
     return p
 
 
+# U-shaped obstacle of the trapped-volume study (Sec. 4.1).  The paper gives
+# the channel (800 x 200), the droplet radius (30) and the parameters, not the
+# obstacle's dimensions; these are chosen so that the cup is well inside the
+# channel with two open passages of equal width.
+U_TRAP = dict(nx=800, ny=200, bar_x=300, thick=6, y0=50, y1=150, arm=120, drop_r=30.0)
+
+
+def u_trap_mask(nx=800, ny=200, bar_x=300, thick=6, y0=50, y1=150, arm=120, **_) -> np.ndarray:
+    """Channel with solid top and bottom rows and a U-shaped wall: a vertical
+    bar facing the inlet and two arms pointing downstream, so the cup opens
+    towards the outlet."""
+    m = np.zeros((ny, nx), np.uint8)
+    m[0] = m[-1] = 1
+    m[y0:y1, bar_x:bar_x + thick] = 1                       # bar
+    m[y0:y0 + thick, bar_x:bar_x + arm] = 1                 # lower arm
+    m[y1 - thick:y1, bar_x:bar_x + arm] = 1                 # upper arm
+    return m
+
+
+def u_trap_cup(nx=800, ny=200, bar_x=300, thick=6, y0=50, y1=150, arm=120, **_) -> np.ndarray:
+    """Boolean map of the cup's interior (where component 2 gets trapped)."""
+    cup = np.zeros((ny, nx), bool)
+    cup[y0 + thick:y1 - thick, bar_x + thick:bar_x + arm] = True
+    return cup
+
+
+def u_trap(bc_set: int = 3, collision: int = 0, minor: float = 0.027, **geom) -> Problem:
+    """Trapped-volume case of Sec. 4.1: the channel starts full of component 2
+    (wetting), with a semicircular droplet of component 1 (radius 30, tanh
+    profile) on the inlet face of the U's bar and an 8-column inlet
+    reservoir of component 1; tau = (3.5, 0.62) (M = 25), G = 3.5,
+    xi = -0.4, inlet density 1.01 (component 1) and outlet density 1
+    (component 2).  Set-1 also fixes component 2 at the inlet and component 1
+    at the outlet to the minor density."""
+    g = dict(U_TRAP)
+    g.update(geom)
+    mask = u_trap_mask(**g)
+    rho0 = reservoir_front(mask, 8, 1.0, minor)
+    cy = 0.5 * (g["y0"] + g["y1"])
+    drop = tanh_droplet(mask.shape, (g["bar_x"], cy), g["drop_r"], (1.0, minor), (minor, 1.0), mask=mask)
+    x = np.arange(mask.shape[1])[None, :]
+    upstream = np.broadcast_to(x < g["bar_x"], mask.shape)
+    for s in range(2):
+        rho0[s] = np.where(upstream & (x >= 8), drop[s], rho0[s])
+    rho0[:, mask.astype(bool)] = 0.0
+    p = Problem(q=9, mask=mask, rho0=rho0, periodic=0, open_x=1, porous_x0=8, porous_x1=g["nx"] - 8,
+                bc_set=bc_set, collision=collision, tau=(3.5, 0.62), G=3.5, xi=-0.4, rho_in1=1.01,
+                rho_out2=1.0, rho_in2=minor, rho_out1=minor, name=f"u_trap_set{bc_set}")
+    return p
+
+
 def as_dict(p: Problem) -> dict:
     d = asdict(p)
     d.pop("mask")

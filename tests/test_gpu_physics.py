@@ -1,0 +1,156 @@
+"""The paper's benchmarks run on the GPU at the paper's own domain sizes,
+each as one batch through the library, and measured on the fields it
+returns:
+
+  - Laplace law (Sec. 3.2, Fig. 4): 192 x 192 periodic box, droplets of
+    three radii at three viscosity ratios; the slope of dP against 1/R is
+    the surface tension, printed as 0.0692 at G = 3.5 and independent of M.
+  - Contact angle (Sec. 3.3, Figs. 6-7): 192 x 96 channel, periodic x,
+    semicircular droplet of radius 30 on the bottom wall, xi swept over the
+    values the paper labels, at M = 1, 25 and 1/25.
+  - Trapped volume (Sec. 4.1): the U-shaped obstacle under the three
+    boundary-condition sets; under Set-3 the water in the cup survives.
+
+The oracle pins the same physics on half-size domains (test_oracle_physics);
+these runs reach the full sizes that the oracle cannot finish in seconds."""
+import numpy as np
+import pytest
+
+from measure import contact_angle, laplace_point
+from paper_2111_08666_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+# tau = 3.5 gives nu = 1 and tau = 0.62 gives nu = 0.04 (Sec. 4.1): M = 25
+TAUS = {"M1": (1.0, 1.0), "M25": (3.5, 0.62), "M1/25": (0.62, 3.5)}
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_08666_amd import lbm
+    return lbm
+
+
+def _run(L, probs, steps):
+    b = L.BatchSolver(probs)
+    try:
+        b.step_graph(1000, steps // 1000)
+        obs = b.observables()
+        return [b.density(i).astype(np.float64) for i in range(len(probs))], obs
+    finally:
+        b.close()
+
+
+@pytest.fixture(scope="module")
+def laplace(L):
+    n, G = 192, 3.5
+    cases = [(m, r0) for m in TAUS for r0 in (20, 30, 40)]
+    probs = [I.Problem(q=9, mask=np.zeros((n, n), np.uint8),
+                       rho0=I.tanh_droplet((n, n), (n / 2 - 0.5, n / 2 - 0.5), r0, (1.0, 0.027),
+                                           (0.027, 1.0)),
+                       periodic=3, open_x=0, tau=TAUS[m], G=G, collision=0, name=f"laplace_{m}_{r0}")
+             for m, r0 in cases]
+    fields, _ = _run(L, probs, 30000)
+    pts = {}
+    for (m, r0), r in zip(cases, fields):
+        pts.setdefault(m, []).append(laplace_point(r, G))
+    slopes = {m: float(np.polyfit(np.array(p)[:, 0], np.array(p)[:, 1], 1)[0]) for m, p in pts.items()}
+    print(f"[laplace 192^2] points {pts}", flush=True)
+    print(f"[laplace 192^2] slopes {slopes}", flush=True)
+    return slopes
+
+
+def test_laplace_full_size(paper, laplace):
+    """gamma = 0.0692 within 5 % at every viscosity ratio, and the three
+    slopes within 5 % of gamma of each other (Sec. 3.2 prints no spread; the
+    measured one is about 4 %: 0.0680, 0.0666 and 0.0694 for M = 1, 25 and
+    1/25)."""
+    gamma = paper["surface_tension_G3.5"]["value"]
+    for m, s in laplace.items():
+        assert abs(s - gamma) / gamma < 0.05, (m, s)
+    vals = list(laplace.values())
+    assert (max(vals) - min(vals)) / gamma < 0.05
+
+
+XIS = (-0.6, -0.3, 0.0, 0.3, 0.5, 0.7)
+
+
+@pytest.fixture(scope="module")
+def angles(L):
+    nx, ny, r0 = 192, 96, 30
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[0] = mask[-1] = 1
+    rho0 = I.tanh_droplet((ny, nx), (nx / 2, 0.5), r0, (1.0, 0.027), (0.027, 1.0), mask=mask)
+    cases = [(m, xi) for m in TAUS for xi in XIS]
+    probs = [I.Problem(q=9, mask=mask, rho0=rho0.copy(), periodic=1, open_x=0, tau=TAUS[m], G=3.5,
+                       xi=xi, collision=0, name=f"angle_{m}_{xi}") for m, xi in cases]
+    fields, _ = _run(L, probs, 40000)
+    out = {c: contact_angle(r) for c, r in zip(cases, fields)}
+    for m in TAUS:
+        print(f"[contact angle 192x96] {m}: " +
+              " ".join(f"xi={xi:+.1f}:{out[(m, xi)]:.1f}" for xi in XIS), flush=True)
+    return out
+
+
+def test_contact_angle_printed_pairs_full_size(paper, angles):
+    """Fig. 7's labelled pairs at M = 1 within 5 degrees for |xi| <= 0.5.
+    At the extremes (-0.6, 0.7) the labels depart from the paper's own cubic
+    fit by 12.6 and 6.5 degrees, and Sec. 3.3 notes that the angle there
+    depends on M; these two are held to the fit, within 7 degrees."""
+    a, b, c, d = paper["contact_angle_fit"]["coeffs_high_to_low"]
+    for xi, theta in paper["contact_angle_pairs"]["pairs"]:
+        got = angles[("M1", xi)]
+        if abs(xi) <= 0.5:
+            assert abs(got - theta) < 5.0, (xi, got, theta)
+        else:
+            fit = ((a * xi + b) * xi + c) * xi + d
+            assert abs(got - fit) < 7.0, (xi, got, fit)
+
+
+def test_contact_angle_monotone_in_xi(angles):
+    """theta grows with xi at every viscosity ratio (Fig. 6)."""
+    for m in TAUS:
+        th = [angles[(m, xi)] for xi in XIS]
+        assert all(a < b for a, b in zip(th, th[1:])), (m, th)
+
+
+def test_contact_angle_independent_of_viscosity_ratio(angles):
+    """Away from the extremes the angle barely moves with M (Sec. 3.3):
+    within 5 degrees of the M = 1 value for |xi| <= 0.5."""
+    for m in ("M25", "M1/25"):
+        for xi in XIS:
+            if abs(xi) <= 0.5:
+                assert abs(angles[(m, xi)] - angles[("M1", xi)]) < 5.0, (m, xi)
+
+
+def test_trapped_volume_set3(L):
+    """Sec. 4.1: the U-shaped obstacle (800 x 200, M = 25, xi = -0.4, inlet
+    density 1.01, outlet 1) with the three boundary sets in one batch.
+    Under Set-3 the invading component passes the U and drains the channel
+    (window saturation near 0.1 after about 80000 steps with this obstacle)
+    while the water in the cup keeps its mass within 5 % at every record."""
+    sets = (1, 2, 3)
+    probs = [I.u_trap(bc_set=s) for s in sets]
+    cup = I.u_trap_cup(**I.U_TRAP)
+    b = L.BatchSolver(probs)
+    try:
+        cup2 = {s: [] for s in sets}
+        sw = {}
+        for rec in range(10):
+            if rec:
+                b.step_graph(1000, 10)
+            obs = b.observables()
+            for i, s in enumerate(sets):
+                cup2[s].append(float(b.density(i)[1][cup].astype(np.float64).sum()))
+                sw[s] = obs[i]["s_w"]
+    finally:
+        b.close()
+    ratios = {s: [c / cup2[s][0] for c in cup2[s]] for s in sets}
+    print(f"[trapped] cup water / initial every 10000 steps: "
+          f"{ {s: [round(r, 4) for r in ratios[s]] for s in sets} }", flush=True)
+    print(f"[trapped] window S_w after 90000 steps: {sw}", flush=True)
+    assert all(abs(r - 1.0) < 0.05 for r in ratios[3])
+    assert sw[3] < 0.15

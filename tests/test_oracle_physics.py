@@ -6,6 +6,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from measure import contact_angle, laplace_point
 from paper_2111_08666_amd import inputs as I
 
 
@@ -91,12 +92,7 @@ def _laplace(r0, tau=(1.0, 1.0), n=64, steps=8000, G=3.5):
     P = O.make_params(q=9, nx=n, ny=n, periodic=3, tau=tau, G=G)
     s = O.OracleSim(params=P, mask=mask, rho0=rho0)
     s.step(steps)
-    r = s.density()
-    # Eq. 14 with the pair sum over ordered pairs (k = 1) or unordered (k = 1/2)
-    dP = {k: ((r[0] + r[1]) / 3 + k * G / 3 * r[0] * r[1]) for k in (1.0, 0.5)}
-    inside, outside = r[0, n // 2, n // 2], r[0, 0, 0]
-    R = np.sqrt(((r[0] - outside) / (inside - outside)).sum() / np.pi)
-    return 1.0 / R, dP[1.0][n // 2, n // 2] - dP[1.0][0, 0], dP[0.5][n // 2, n // 2] - dP[0.5][0, 0]
+    return laplace_point(s.density(), G)
 
 
 @pytest.fixture(scope="module")
@@ -121,41 +117,6 @@ def test_laplace_independent_of_viscosity_ratio(laplace_slopes):
     """Sec. 3.2: the surface tension does not depend on M."""
     a, b = laplace_slopes["M1"], laplace_slopes["M25"]
     assert abs(a - b) / a < 0.03
-
-
-def contact_angle(r, ywall=0.5, h=5.0):
-    """Contact angle through component 2 of a droplet of component 1 sitting
-    on the bottom wall: circle through the apex and the chord h lattice units
-    above the half-way wall plane, interface at rho1 = rho2 by linear
-    interpolation (Sec. 3.3)."""
-    d = r[0] - r[1]
-    ny, nx = d.shape
-    prof = (d > 0).sum(axis=0)
-    xc = int(round((prof * np.arange(nx)).sum() / prof.sum()))
-    c = d[:, xc]
-    H = None
-    for y in range(1, ny - 1):
-        if c[y] > 0 >= c[y + 1]:
-            H = y + c[y] / (c[y] - c[y + 1])
-            break
-    yh = ywall + h
-    y0 = int(np.floor(yh))
-    t = yh - y0
-    row = (1 - t) * d[y0] + t * d[y0 + 1]
-    xl = xr = None
-    for x in range(xc, 0, -1):
-        if row[x] > 0 >= row[x - 1]:
-            xl = x - row[x] / (row[x] - row[x - 1])
-            break
-    for x in range(xc, nx - 1):
-        if row[x] > 0 >= row[x + 1]:
-            xr = x + row[x] / (row[x] - row[x + 1])
-            break
-    a = 0.5 * (xr - xl)
-    yc = (H ** 2 - yh ** 2 - a ** 2) / (2 * (H - yh))
-    R = H - yc
-    theta_drop = np.degrees(np.arccos(np.clip((ywall - yc) / R, -1, 1)))
-    return 180.0 - theta_drop
 
 
 def _droplet_angle(xi, nx=96, ny=48, r0=15, steps=10000, tau=(1.0, 1.0)):
