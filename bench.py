@@ -85,7 +85,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=100, help="steps per captured graph")
     ap.add_argument("--storage", type=int, default=0, help="0 FP32, 1 BF16 deviations")
     ap.add_argument("--math", type=int, default=0, help="node arithmetic: 0 FP64, 1 FP32")
-    ap.add_argument("--strategy", type=int, default=0, help="0 auto, 1 fused, 2 split")
+    ap.add_argument("--strategy", type=int, default=0,
+                    help="0 auto (autotuned), 1 fused, 2 split, 3 compact, 4 fused with listed collision")
+    ap.add_argument("--tile-rows", type=int, default=0, help="fused tile height 8, 12 or 16 (0: 12)")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--eager", action="store_true", help="plain launches instead of graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -105,7 +107,7 @@ def main():
     if batch:
         problems = problem
         solver = lbm.BatchSolver(problems, storage=args.storage, device=dev, math=args.math,
-                                 strategy=args.strategy)
+                                 strategy=args.strategy, tile_rows=args.tile_rows)
         problem = sorted(problems, key=lambda p: p.n_nodes)[len(problems) // 2]  # CPU-baseline sample
         n_nodes, n_fluid = solver.n_nodes, solver.n_fluid
         sizes = sorted({(p.nx, p.ny) for p in problems})
@@ -115,7 +117,7 @@ def main():
         print(f"[bench] workload {args.workload}: {problem.nx}x{problem.ny}x{problem.nz}, "
               f"fluid {problem.n_fluid}, collision {problem.collision}", file=sys.stderr, flush=True)
         solver = lbm.Solver(problem, storage=args.storage, device=dev, math=args.math,
-                            strategy=args.strategy)
+                            strategy=args.strategy, tile_rows=args.tile_rows)
         n_nodes, n_fluid = problem.n_nodes, problem.n_fluid
     stream = solver.stream
     tune = None

@@ -49,7 +49,7 @@ enum { LBM_SRT = 0, LBM_MRT = 1, LBM_TRT = 2 };            /* lbm_params.collisi
 enum { LBM_STORE_F32 = 0, LBM_STORE_BF16DEV = 1 };          /* lbm_params.storage */
 enum { LBM_MATH_F64 = 0, LBM_MATH_F32 = 1 };                /* lbm_params.math */
 enum { LBM_AUTO = 0, LBM_FUSED = 1, LBM_SPLIT = 2, LBM_COMPACT = 3,
-       LBM_FUSED_LIST = 4 };                                /* lbm_params.strategy */
+       LBM_FUSED_LIST = 4, LBM_COMPACT_FUSED = 5 };         /* lbm_params.strategy */
 
 /* Problem geometry (Sec. 2.3 and Sec. 4.2: a solid map phi, periodic or
  * open axes, the inlet at x = 0 and the outlet at x = nx - 1). */
@@ -89,9 +89,13 @@ typedef struct {
                              fluid node, bounce-back from the node's own
                              slots); LBM_FUSED_LIST (D2Q9: the fused
                              step whose collision phase runs over a per-tile
-                             list of fluid nodes).  The layout is fixed at creation:
-                             LBM_COMPACT cannot be switched to or from the
-                             others (lbm_autotune keeps it). */
+                             list of fluid nodes, their pulled populations
+                             parked in LDS; nx up to about 1.8 million);
+                             LBM_COMPACT_FUSED (D2Q9: the fused tile step
+                             over the compacted layout of LBM_COMPACT).
+                             The layout is fixed at creation: the compacted
+                             strategies cannot be switched to or from the
+                             others (lbm_autotune stays within the layout). */
   int32_t tile_rows;      /* fused D2Q9 tile height: 8, 12 or 16 (0 = 12) */
 } lbm_params;
 

@@ -78,6 +78,13 @@ bool compact_fits(const lbm_geometry &g) {
   return (int64_t)g.q * (nf + 64) * 4 < ((int64_t)1 << 32);
 }
 
+// The listed D2Q9 step addresses its stores as a 32-bit byte offset from the
+// tile's first row: 16 row blocks of 18 pitched rows must span < 2^31 bytes.
+bool list_fits(int32_t nx) { return (int64_t)16 * 18 * round_up(nx, 64) * 4 < ((int64_t)1 << 31); }
+
+// Strategies that run on the compacted layout.
+bool compact_strategy(int s) { return s == LBM_COMPACT || s == LBM_COMPACT_FUSED; }
+
 // The step a context starts with.  Measured on MI355X: the fused kernel is
 // fastest in 2D (single instances and batches); in 3D the compacted layout
 // beats the dense split step (5.1 against 7.7 ms per step at 384^3, porosity
@@ -99,7 +106,7 @@ Layout make_layout(const lbm_geometry &g, const lbm_params &p) {
   L.info_bytes = align_up((size_t)L.pitch * g.ny * g.nz * sizeof(uint32_t));
   L.frozen_bytes = align_up((size_t)2 * g.q * g.ny * g.nz * sizeof(float));
   L.psi_bytes = align_up((size_t)L.pitch * g.ny * g.nz * 2 * sizeof(double));
-  L.compact = resolve_strategy(g, p) == LBM_COMPACT;
+  L.compact = compact_strategy(resolve_strategy(g, p));
   if (L.compact) {  // validate() keeps q * cpitch * 4 bytes below 2^32
     int64_t nf = 0;
     for (int64_t n = 0; n < L.n_nodes; ++n) nf += g.solid[n] == 0;
@@ -166,11 +173,13 @@ bool validate(const lbm_geometry *g, const lbm_params *p, const double *rho0, st
   if (p->bc_set < 1 || p->bc_set > 3) return bad(err, "bc_set must be 1, 2 or 3");
   if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_BF16DEV) return bad(err, "unknown storage");
   if (p->math != LBM_MATH_F64 && p->math != LBM_MATH_F32) return bad(err, "unknown math precision");
-  if (p->strategy < LBM_AUTO || p->strategy > LBM_FUSED_LIST) return bad(err, "unknown strategy");
+  if (p->strategy < LBM_AUTO || p->strategy > LBM_COMPACT_FUSED) return bad(err, "unknown strategy");
+  if (p->strategy == LBM_COMPACT_FUSED && g->q != 9) return bad(err, "the compacted fused step is D2Q9 only");
   if (p->strategy == LBM_FUSED_LIST && g->q != 9) return bad(err, "the listed fused step is D2Q9 only");
+  if (p->strategy == LBM_FUSED_LIST && !list_fits(g->nx)) return bad(err, "nx too large for the listed fused step");
   if (p->strategy == LBM_COMPACT && p->collision == LBM_MRT && g->q != 9)
     return bad(err, "MRT is defined for D2Q9 only");
-  if (p->strategy == LBM_COMPACT && !compact_fits(*g))
+  if (compact_strategy(p->strategy) && !compact_fits(*g))
     return bad(err, "too many fluid nodes for the compacted layout (use LBM_SPLIT)");
   if (p->tile_rows != 0 && p->tile_rows != 8 && p->tile_rows != 12 && p->tile_rows != 16)
     return bad(err, "tile_rows must be 0, 8, 12 or 16");
@@ -328,7 +337,7 @@ size_t batch_bytes(int32_t k, const lbm_geometry *g, const lbm_params *p, int64_
 
 // Tilings, block table and descriptors for a step variant; synchronises.
 lbm_status apply_plan(lbm_batch *b, int strategy, int ty) {
-  if (b->compact != (strategy == LBM_COMPACT))
+  if (b->compact != compact_strategy(strategy))
     return fail(b, LBM_EINVAL, "the compact step and the compacted layout go together");
   std::vector<int32_t> table;
   int64_t base = 0;
@@ -379,7 +388,7 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
     if (g[i].q != g[0].q || p[i].storage != p[0].storage || p[i].collision != p[0].collision ||
         p[i].math != p[0].math)
       return fail(nullptr, LBM_EINVAL, "all instances must share q, storage, collision and math");
-    if ((resolve_strategy(g[i], p[i]) == LBM_COMPACT) != (resolve_strategy(g[0], p[0]) == LBM_COMPACT))
+    if (compact_strategy(resolve_strategy(g[i], p[i])) != compact_strategy(resolve_strategy(g[0], p[0])))
       return fail(nullptr, LBM_EINVAL, "all instances or none must use the compacted layout");
   }
   int64_t nb;
@@ -483,7 +492,7 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
   // default plan: the split step for D3Q19 (its per-block working set does
   // not fit the L2), the fused step otherwise
   int strategy = resolve_strategy(g[0], p[0]);
-  b->compact = strategy == LBM_COMPACT;
+  b->compact = compact_strategy(strategy);
   if (strategy == LBM_SPLIT && (b->collision == LBM_MRT && b->q != 9)) strategy = LBM_FUSED;
   const lbm_status ps = apply_plan(b, strategy, p[0].tile_rows ? p[0].tile_rows : 12);
   if (ps != LBM_OK) { delete b; return ps; }
@@ -761,10 +770,15 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int64_t steps, char *report, size_t 
   std::vector<Cand> cands;
   if (b->compact) {
     cands.push_back({LBM_COMPACT, 12});
+    if (b->q == 9)
+      for (int ty : {8, 12, 16}) cands.push_back({LBM_COMPACT_FUSED, ty});
   } else {
     if (b->q == 9) {
       for (int ty : {8, 12, 16}) cands.push_back({LBM_FUSED, ty});
-      for (int ty : {8, 12, 16}) cands.push_back({LBM_FUSED_LIST, ty});
+      bool fits = true;
+      for (const InstDev &h : b->h) fits = fits && list_fits(h.nx);
+      if (fits)
+        for (int ty : {8, 12, 16}) cands.push_back({LBM_FUSED_LIST, ty});
     } else {
       cands.push_back({LBM_FUSED, 12});
     }

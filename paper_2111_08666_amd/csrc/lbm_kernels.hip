@@ -228,6 +228,81 @@ __device__ __forceinline__ int xcd_block() {
   return xcd * q8 + min(xcd, r8) + (b >> 3);
 }
 
+// Compact index of fluid node (x, row), row = y + ny * z.  For a solid
+// position it is the index of the next fluid node (at most nf).
+__device__ __forceinline__ int64_t crank(const InstDev &d, int x, int64_t row) {
+  const RowWord w = d.cword[row * (d.pitch >> 6) + (x >> 6)];
+  const unsigned long long below = (1ull << (x & 63)) - 1ull;
+  return w.pre + __popcll(w.bits & below);
+}
+
+// Pull of D2Q9 fluid node (x, y) in the compacted layout (f*[s][i][c] over
+// fluid nodes); c receives the node's compact index.
+// The rank of column x in each source row gives every fluid source's index
+// (x - 1: rank - 1; x + 1: rank + the column's fluid bit); bounce-back reads
+// the node's own opposite slot; wrapped x sources are ranked directly.
+template <int ST>
+__device__ __forceinline__ void cpull9(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int x, int y,
+                                       const int (&xs)[3], int32_t &c, float (&f0)[9], float (&f1)[9]) {
+  using L = Lat<9>;
+  const int cp = d.cpitch, ny = d.ny;
+  const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};  // y - e_y, by e_y + 1
+  const int64_t wpr = d.pitch >> 6;
+  const unsigned long long below = (1ull << (x & 63)) - 1ull;
+  int32_t rk[3];
+  int fl[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const RowWord w = d.cword[ys[a] * wpr + (x >> 6)];
+    rk[a] = (int32_t)(w.pre + __popcll(w.bits & below));
+    fl[a] = (int)((w.bits >> (x & 63)) & 1ull);
+  }
+  c = rk[1];
+  const bool x_edge = x == 0 || x == d.nx - 1;
+  const int32_t last = (int32_t)(d.nf - 1);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    int32_t sc = c;
+    int pi = i;
+    if (i != 0) {
+      if ((info >> i) & 1u) {
+        pi = L::opp[i];
+      } else {
+        const int a = L::ey[i] + 1;
+        if (L::ex[i] == 0) {
+          sc = rk[a];
+        } else if (!x_edge) {
+          sc = L::ex[i] > 0 ? rk[a] - 1 : rk[a] + fl[a];
+        } else {
+          // wrapped source: periodic x, or a missing link at an open face
+          // (an arbitrary node, overwritten by the completion below)
+          const int32_t r = (int32_t)crank(d, xs[L::ex[i] + 1], ys[a]);
+          sc = r < last ? r : last;
+        }
+      }
+    }
+    if constexpr (ST == 0) {
+      const uint32_t bo = ((uint32_t)pi * (uint32_t)cp + (uint32_t)sc) * 4u;
+      f0[i] = ldg(fin, bo);
+      f1[i] = ldg(fin + (int64_t)9 * cp, bo);
+    } else {
+      f0[i] = pop_get<9, ST>(fin, cp, 0, pi, 0, (int)sc);
+      f1[i] = pop_get<9, ST>(fin, cp, 1, pi, 0, (int)sc);
+    }
+  }
+}
+
+// Inlet/outlet completion of a D2Q9 node pulled by cpull9 (compact index c).
+template <int ST, typename R>
+__device__ __forceinline__ void ccomplete9(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int y,
+                                           int32_t c, float (&f0)[9], float (&f1)[9]) {
+  gcf *frz = G(d.frozen);
+  const int cp = d.cpitch, ny = d.ny;
+  complete_boundary<9, R>(
+      d, info, f0, f1, [&](int s, int i) { return pop_get<9, ST>(fin, cp, s, i, 0, (int)c); },
+      [&](int s, int i) { return frz[(int64_t)(s * 9 + i) * ny + y]; });
+}
+
 // ---------------------------------------------------------------------------
 // D2Q9 fused step.  Block = 4 waves over a region of 64 columns x (TY + 4)
 // rows: 60 x TY interior nodes plus a 2-node halo.  Wave w owns interior rows
@@ -238,15 +313,27 @@ __device__ __forceinline__ int xcd_block() {
 // Phase 3: force (Eq. 13 with the open-face mirror) and collision for the
 //          interior nodes, whose pulled populations stayed in registers.
 // ---------------------------------------------------------------------------
-// The 8-row tile fits 128 registers (four waves per SIMD) without spilling.
-template <int COLL, int ST, typename R, int TY>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TY == 8 ? 4 : 1))) void step_d2q9(const InstDev *__restrict__ insts,
-                                                  const int32_t *__restrict__ block_inst, int parity) {
+// Occupancy: TY = 8 fits 128 registers (four waves per SIMD) with every
+// pulled row in registers.  TY = 12 parks the last interior row of each wave
+// in LDS between the phases, which fits it in 128 registers and 35 KB of LDS
+// (four blocks per CU) instead of three waves per SIMD.
+template <int TY> struct FusedShape {
+  static constexpr int kParked = TY == 12 ? 1 : 0;  // interior rows per wave kept in LDS
+  static constexpr int kWaves = TY == 16 ? 1 : 4;
+};
+
+// CL = 1: the same step over the compacted layout (fluid nodes only stored,
+// pulls by rank, bounce-back from the node's own slots, no ghost slots).
+template <int COLL, int ST, typename R, int TY, int CL = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FusedShape<TY>::kWaves))) void step_d2q9(
+    const InstDev *__restrict__ insts, const int32_t *__restrict__ block_inst, int parity) {
   using L = Lat<9>;
   using V = Vec2<R>;
   constexpr int KR = TY / 4;        // interior rows per wave
   constexpr int kRH = TY + 4;       // region rows
+  constexpr int KP = FusedShape<TY>::kParked;
   __shared__ V psi[kRH][64];
+  __shared__ float park[KP > 0 ? KP * 4 : 1][18][64];  // [row slot * 4 + wave][component * 9 + link][lane]
 
   const int bid = xcd_block();
   const int inst = __builtin_amdgcn_readfirstlane(block_inst ? block_inst[bid] : 0);
@@ -299,23 +386,45 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TY == 8 ? 4
   // flight).
   float f0[KR][9], f1[KR][9], h0[9], h1[9];
   int64_t srow[KR + 1][3][3];
+  int32_t cidx[KR + 1];  // compact indices (CL)
+  if constexpr (CL) {
 #pragma unroll
-  for (int k = 0; k <= KR; ++k) source_rows<9, true>(d, gy[k], 0, srow[k]);
+    for (int k = 0; k <= KR; ++k) {
+      float(&a)[9] = k < KR ? f0[k < KR ? k : 0] : h0;
+      float(&b)[9] = k < KR ? f1[k < KR ? k : 0] : h1;
+      cidx[k] = 0;
+      if (!(info[k] & kSolid)) cpull9<ST>(d, fin, info[k], gx, gy[k], xs, cidx[k], a, b);
+    }
+  } else {
 #pragma unroll
-  for (int k = 0; k < KR; ++k)
-    if (ST == 0 || !(info[k] & kSolid)) pull_row<9, ST>(d, fin, info[k], srow[k], xs, f0[k], f1[k]);
-  if (ST == 0 || !(info[KR] & kSolid)) pull_row<9, ST>(d, fin, info[KR], srow[KR], xs, h0, h1);
+    for (int k = 0; k <= KR; ++k) source_rows<9, true>(d, gy[k], 0, srow[k]);
+#pragma unroll
+    for (int k = 0; k < KR; ++k)
+      if (ST == 0 || !(info[k] & kSolid)) pull_row<9, ST>(d, fin, info[k], srow[k], xs, f0[k], f1[k]);
+    if (ST == 0 || !(info[KR] & kSolid)) pull_row<9, ST>(d, fin, info[KR], srow[KR], xs, h0, h1);
+  }
 #pragma unroll
   for (int k = 0; k <= KR; ++k) {
     R rho1 = 0, rho2 = 0;
     if (!(info[k] & kSolid)) {
       float(&a)[9] = k < KR ? f0[k < KR ? k : 0] : h0;
       float(&b)[9] = k < KR ? f1[k < KR ? k : 0] : h1;
-      if (info[k] & (kInlet | kOutlet)) complete<9, ST, R>(d, fin, info[k], gx, gy[k], 0, a, b);
+      if (info[k] & (kInlet | kOutlet)) {
+        if constexpr (CL) ccomplete9<ST, R>(d, fin, info[k], gy[k], cidx[k], a, b);
+        else complete<9, ST, R>(d, fin, info[k], gx, gy[k], 0, a, b);
+      }
       rho1 = sum_q<9, R>(a);
       rho2 = sum_q<9, R>(b);
     }
     psi[rows[k]][lane] = V{rho1, rho2};
+    if (k >= KR - KP && k < KR) {
+      float(&pk)[18][64] = park[(k - (KR - KP)) * 4 + wave];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        pk[i][lane] = f0[k < KR ? k : 0][i];
+        pk[9 + i][lane] = f1[k < KR ? k : 0][i];
+      }
+    }
   }
   __syncthreads();
 
@@ -378,19 +487,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TY == 8 ? 4
     const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy;
     const R F1x = -G_ * rho1 * sx2 + rho1 * gxb, F1y = -G_ * rho1 * sy2 + rho1 * gyb;
     const R F2x = -G_ * rho2 * sx1 + rho2 * gxb, F2y = -G_ * rho2 * sy1 + rho2 * gyb;
+    if (k >= KR - KP) {
+      const float(&pk)[18][64] = park[(k - (KR - KP)) * 4 + wave];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        f0[k][i] = pk[i][lane];
+        f1[k][i] = pk[9 + i][lane];
+      }
+    }
     collide_node<9, COLL, R>(d, f0[k], f1[k], rho1, rho2, F1x, F1y, R(0), F2x, F2y, R(0));
-    pop_store<9, ST>(fout, d.pitch, uniform64(gy_raw * d.ystride), gx, f0[k], f1[k], (float)rho1, (float)rho2);
-    store_ghosts<9, ST>(d, fout, inf, srow[k], xs, f0[k], f1[k]);
+    if constexpr (CL) {
+      pop_store<9, ST>(fout, d.cpitch, 0, cidx[k], f0[k], f1[k], (float)rho1, (float)rho2);
+    } else {
+      pop_store<9, ST>(fout, d.pitch, uniform64(gy_raw * d.ystride), gx, f0[k], f1[k], (float)rho1, (float)rho2);
+      store_ghosts<9, ST>(d, fout, inf, srow[k], xs, f0[k], f1[k]);
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
-// D2Q9 fused step with a listed collision phase.  Phases 1 and 2 as above,
-// except that a pulled node keeps only its densities.  Phase 3 runs over a
-// per-tile list of the fluid interior nodes (row-major, built from ballots
-// and a fixed-order prefix in LDS), one list entry per thread: no lane waits
-// on a solid node.  Each entry pulls its populations again (L2 hits: phase 1
-// just read them) with per-lane rows.
+// D2Q9 fused step with a listed collision phase.  Phases 1 and 2 as in the
+// fused step; in phase 1 every interior fluid node also parks its pulled
+// (and completed) populations and its info word in LDS, dense by interior
+// position.  Phase 3 runs over a per-tile list of the fluid interior nodes
+// (row-major, built from ballots and a fixed-order prefix in LDS), one list
+// entry per thread, so no lane spends the collision on a solid node.  The
+// arithmetic is the fused step's, value for value.
+// LDS: populations 72 B per interior node (34.6 KB at TY = 8) + densities.
 // ---------------------------------------------------------------------------
 template <int COLL, int ST, typename R, int TY>
 __global__ __launch_bounds__(256) void step_d2q9_list(const InstDev *__restrict__ insts,
@@ -399,8 +522,11 @@ __global__ __launch_bounds__(256) void step_d2q9_list(const InstDev *__restrict_
   using V = Vec2<R>;
   constexpr int KR = TY / 4;
   constexpr int kRH = TY + 4;
+  constexpr int kN = TY * kTileX;   // interior nodes of a tile
   __shared__ V psi[kRH][64];
-  __shared__ uint16_t list[TY * 64];
+  __shared__ float pops[18][kN];    // [component * 9 + link][interior position]
+  __shared__ uint32_t pinfo[kN];
+  __shared__ uint16_t list[kN];     // interior positions of the fluid nodes, row-major
   __shared__ int cnt[TY];
 
   const int bid = xcd_block();
@@ -441,55 +567,66 @@ __global__ __launch_bounds__(256) void step_d2q9_list(const InstDev *__restrict_
     gy[k] = in ? y : 0;
     row_in[k] = in;
   }
-
-  uint32_t infos[KR + 1];
+  uint32_t info[KR + 1];
 #pragma unroll
   for (int k = 0; k <= KR; ++k)
-    infos[k] = (row_in[k] && col_in) ? infop[gx + (int64_t)d.pitch * gy[k]] : kSolid;
+    info[k] = (row_in[k] && col_in) ? infop[gx + (int64_t)d.pitch * gy[k]] : kSolid;
 
-  // Phase 1: densities of every region node -> LDS; fluid interior counts
+  // Phase 1: pull every row of this thread, then complete, sum, and park the
+  // interior fluid nodes' populations
+  {
+    float f0[KR + 1][9], f1[KR + 1][9];
+    int64_t srow[KR + 1][3][3];
 #pragma unroll
-  for (int k = 0; k <= KR; ++k) {
-    const uint32_t info = infos[k];
-    R rho1 = 0, rho2 = 0;
-    if (ST == 0 || !(info & kSolid)) {
-      int64_t src[3][3];
-      source_rows<9, true>(d, gy[k], 0, src);
-      float a[9], b[9];
-      pull_row<9, ST>(d, fin, info, src, xs, a, b);
-      if (!(info & kSolid)) {
-        if (info & (kInlet | kOutlet)) complete<9, ST, R>(d, fin, info, gx, gy[k], 0, a, b);
-        rho1 = sum_q<9, R>(a);
-        rho2 = sum_q<9, R>(b);
+    for (int k = 0; k <= KR; ++k) source_rows<9, true>(d, gy[k], 0, srow[k]);
+#pragma unroll
+    for (int k = 0; k <= KR; ++k)
+      if (ST == 0 || !(info[k] & kSolid)) pull_row<9, ST>(d, fin, info[k], srow[k], xs, f0[k], f1[k]);
+#pragma unroll
+    for (int k = 0; k <= KR; ++k) {
+      R rho1 = 0, rho2 = 0;
+      if (!(info[k] & kSolid)) {
+        if (info[k] & (kInlet | kOutlet)) complete<9, ST, R>(d, fin, info[k], gx, gy[k], 0, f0[k], f1[k]);
+        rho1 = sum_q<9, R>(f0[k]);
+        rho2 = sum_q<9, R>(f1[k]);
       }
-    }
-    psi[rows[k]][lane] = V{rho1, rho2};
-    if (k < KR) {
-      const bool fluid = row_in[k] && col_store && ty * TY - 2 + rows[k] < ny && !(info & kSolid);
-      const unsigned long long m = __ballot(fluid);
-      if (lane == 0) cnt[rows[k] - 2] = __popcll(m);
+      psi[rows[k]][lane] = V{rho1, rho2};
+      if (k < KR) {
+        const bool fluid = row_in[k] && col_store && ty * TY - 2 + rows[k] < ny && !(info[k] & kSolid);
+        if (fluid) {
+          const int pos = (rows[k] - 2) * kTileX + lane - 2;
+#pragma unroll
+          for (int i = 0; i < 9; ++i) {
+            pops[i][pos] = f0[k][i];
+            pops[9 + i][pos] = f1[k][i];
+          }
+          pinfo[pos] = info[k];
+        }
+        const unsigned long long m = __ballot(fluid);
+        if (lane == 0) cnt[rows[k] - 2] = __popcll(m);
+      }
     }
   }
   __syncthreads();
 
-  // Phase 2: virtual solid density; list of fluid interior nodes (row-major)
+  // Phase 2: virtual solid density; the list of fluid interior nodes
 #pragma unroll
   for (int k = 0; k <= KR; ++k) {
     const int r = rows[k];
-    const uint32_t info = infos[k];
+    const uint32_t nb = info[k];
     if (k < KR) {
-      const bool fluid = row_in[k] && col_store && ty * TY - 2 + r < ny && !(info & kSolid);
+      const bool fluid = row_in[k] && col_store && ty * TY - 2 + r < ny && !(nb & kSolid);
       const unsigned long long m = __ballot(fluid);
       int base = 0;
       for (int q = 0; q < r - 2; ++q) base += cnt[q];
-      if (fluid) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)((r << 6) | lane);
+      if (fluid) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)((r - 2) * kTileX + lane - 2);
     }
-    if (!row_in[k] || !col_in || !(info & kSolid) || r < 1 || r > kRH - 2 || lane < 1 || lane > 62) continue;
-    if (!(info & kLinkMask)) continue;
+    if (!row_in[k] || !col_in || !(nb & kSolid) || r < 1 || r > kRH - 2 || lane < 1 || lane > 62) continue;
+    if (!(nb & kLinkMask)) continue;
     R s1 = 0, s2 = 0, den = 0;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
-      if (info & (1u << i)) {
+      if (nb & (1u << i)) {
         const V p = psi[r + L::ey[i]][lane + L::ex[i]];
         const R w = (R)L::w[i];
         s1 += w * p.x;
@@ -505,20 +642,25 @@ __global__ __launch_bounds__(256) void step_d2q9_list(const InstDev *__restrict_
   for (int q = 0; q < TY; ++q) total += cnt[q];
   __syncthreads();
 
-  // Phase 3: force + collision over the list
+  // Phase 3: force + collision over the list.  Stores address the tile's
+  // first interior row (wave-uniform) plus a 32-bit byte offset; the host
+  // keeps TY row blocks within 2^31 bytes for this strategy.
   const R w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+  gf *const tile_out = fout + uniform64((int64_t)ty * TY * d.ystride);
+  const int pitch = __builtin_amdgcn_readfirstlane(d.pitch);
+  const uint32_t ystride = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)d.ystride);
   for (int t = threadIdx.x; t < total; t += 256) {
-    const int e = list[t];
-    const int r = e >> 6, ln = e & 63;
-    const int x = tx * kTileX - 2 + ln, y = ty * TY - 2 + r;
-    const uint32_t inf = infop[x + (int64_t)d.pitch * y];
-    int64_t src[3][3];
-    int xsl[3];
-    source_rows<9>(d, y, 0, src);
-    source_x(d, x, xsl);
+    const int pos = list[t];
+    const int ri = pos / kTileX, ci = pos - ri * kTileX;
+    const int r = ri + 2, ln = ci + 2;
+    const int x = tx * kTileX + ci, y = ty * TY + ri;
+    const uint32_t inf = pinfo[pos];
     float f0[9], f1[9];
-    pull_row<9, ST>(d, fin, inf, src, xsl, f0, f1);
-    if (inf & (kInlet | kOutlet)) complete<9, ST, R>(d, fin, inf, x, y, 0, f0, f1);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      f0[i] = pops[i][pos];
+      f1[i] = pops[9 + i][pos];
+    }
     const V c = psi[r][ln];
     const R rho1 = c.x, rho2 = c.y;
     R sx1, sy1, sx2, sy2;
@@ -545,8 +687,23 @@ __global__ __launch_bounds__(256) void step_d2q9_list(const InstDev *__restrict_
     const R F1x = -G_ * rho1 * sx2 + rho1 * gxb, F1y = -G_ * rho1 * sy2 + rho1 * gyb;
     const R F2x = -G_ * rho2 * sx1 + rho2 * gxb, F2y = -G_ * rho2 * sy1 + rho2 * gyb;
     collide_node<9, COLL, R>(d, f0, f1, rho1, rho2, F1x, F1y, R(0), F2x, F2y, R(0));
-    pop_store<9, ST>(fout, d.pitch, y * d.ystride, x, f0, f1, (float)rho1, (float)rho2);
-    store_ghosts<9, ST>(d, fout, inf, src, xsl, f0, f1);
+    if constexpr (ST == 0) {
+      const uint32_t bo = ((uint32_t)ri * ystride + (uint32_t)x) * 4u;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        stg(tile_out + (int64_t)i * pitch, bo, f0[i]);
+        stg(tile_out + (int64_t)(9 + i) * pitch, bo, f1[i]);
+      }
+    } else {
+      pop_store<9, ST>(fout, d.pitch, y * d.ystride, x, f0, f1, (float)rho1, (float)rho2);
+    }
+    if (inf & kLinkMask) {
+      int64_t src[3][3];
+      int xsl[3];
+      source_rows<9>(d, y, 0, src);
+      source_x(d, x, xsl);
+      store_ghosts<9, ST>(d, fout, inf, src, xsl, f0, f1);
+    }
   }
 }
 
@@ -899,13 +1056,6 @@ __global__ __launch_bounds__(256) void collide_kernel(const InstDev *__restrict_
 // and the virtual solid density go through the dense psi array as in the
 // split step, and the force and collision are the split step's arithmetic.
 // ---------------------------------------------------------------------------
-// Compact index of fluid node (x, row), row = y + ny * z.  For a solid
-// position it is the index of the next fluid node (at most nf).
-__device__ __forceinline__ int64_t crank(const InstDev &d, int x, int64_t row) {
-  const RowWord w = d.cword[row * (d.pitch >> 6) + (x >> 6)];
-  const unsigned long long below = (1ull << (x & 63)) - 1ull;
-  return w.pre + __popcll(w.bits & below);
-}
 
 // Does some link of the lattice pull from row offset (dy, dz)?
 template <int Q>
@@ -1232,9 +1382,13 @@ hipError_t launch_init(const InstDev *d_inst, const InstDev &h, const float *rho
 
 template <int COLL, int ST, typename R>
 static void launch_fused_q(int q, int ty, const InstDev *d, const int32_t *bi, int64_t nb, int parity,
-                           hipStream_t s) {
+                           hipStream_t s, bool compact = false) {
   const dim3 g((unsigned)nb), b(256);
-  if (q == 9) {
+  if (q == 9 && compact) {
+    if (ty == 8) step_d2q9<COLL, ST, R, 8, 1><<<g, b, 0, s>>>(d, bi, parity);
+    else if (ty == 16) step_d2q9<COLL, ST, R, 16, 1><<<g, b, 0, s>>>(d, bi, parity);
+    else step_d2q9<COLL, ST, R, 12, 1><<<g, b, 0, s>>>(d, bi, parity);
+  } else if (q == 9) {
     if (ty == 8) step_d2q9<COLL, ST, R, 8><<<g, b, 0, s>>>(d, bi, parity);
     else if (ty == 16) step_d2q9<COLL, ST, R, 16><<<g, b, 0, s>>>(d, bi, parity);
     else step_d2q9<COLL, ST, R, 12><<<g, b, 0, s>>>(d, bi, parity);
@@ -1293,6 +1447,8 @@ static void launch_r(const StepLaunch &L, hipStream_t s) {
       for (int i = 0; i < L.k; ++i) launch_compact_q<COLL, ST, R>(L.q, L.d_insts + i, L.h[i], L.parity, s); \
     } else if (L.strategy == 4) {                                                                 \
       launch_fused_list_q<COLL, ST, R>(L.q, L.ty, L.d_insts, L.block_inst, L.n_blocks, L.parity, s); \
+    } else if (L.strategy == 5) {                                                                 \
+      launch_fused_q<COLL, ST, R>(L.q, L.ty, L.d_insts, L.block_inst, L.n_blocks, L.parity, s, true); \
     } else {                                                                                      \
       launch_fused_q<COLL, ST, R>(L.q, L.ty, L.d_insts, L.block_inst, L.n_blocks, L.parity, s);   \
     }                                                                                             \
@@ -1329,6 +1485,8 @@ const char *step_kernel_name(int q, int collision, int storage, int math, int st
              st[storage], mt[math]);
   else if (strategy == 4)
     snprintf(buf, sizeof buf, "step_d2q9_list<%s,%s,%s,%d>", coll[collision], st[storage], mt[math], ty);
+  else if (strategy == 5)
+    snprintf(buf, sizeof buf, "step_d2q9<%s,%s,%s,%d,compact>", coll[collision], st[storage], mt[math], ty);
   else if (q == 9)
     snprintf(buf, sizeof buf, "step_d2q9<%s,%s,%s,%d>", coll[collision], st[storage], mt[math], ty);
   else

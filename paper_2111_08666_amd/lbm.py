@@ -18,7 +18,7 @@ LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, 
 SRT, MRT, TRT = 0, 1, 2
 STORE_F32, STORE_BF16DEV = 0, 1
 MATH_F64, MATH_F32 = 0, 1
-AUTO, FUSED, SPLIT, COMPACT, FUSED_LIST = 0, 1, 2, 3, 4
+AUTO, FUSED, SPLIT, COMPACT, FUSED_LIST, COMPACT_FUSED = 0, 1, 2, 3, 4, 5
 
 EXPORTS = [
     "lbm_workspace_bytes", "lbm_create", "lbm_set_bc", "lbm_step", "lbm_step_graph",

@@ -44,7 +44,7 @@ def _rel_err(g, o, mask):
     return float((np.abs(g.astype(np.float64) - o) / np.abs(o))[:, fluid].max())
 
 
-STRATEGIES = {"fused": 1, "split": 2, "compact": 3, "fused_list": 4}
+STRATEGIES = {"fused": 1, "split": 2, "compact": 3, "fused_list": 4, "compact_fused": 5}
 
 
 @pytest.mark.parametrize("strategy", sorted(STRATEGIES))
@@ -65,7 +65,7 @@ def test_density_parity_200_steps(lbm, name, strategy):
     print(f"[parity] {name} {strategy}: worst relative density error {worst:.2e}", flush=True)
 
 
-@pytest.mark.parametrize("strategy", [1, 4])
+@pytest.mark.parametrize("strategy", [1, 4, 5])
 @pytest.mark.parametrize("tile_rows", [8, 16])
 def test_fused_tile_heights_match_oracle(lbm, tile_rows, strategy):
     p = PROBLEMS["drain_mrt"]
@@ -224,6 +224,56 @@ def test_compact_checkpoint_and_batch(lbm):
         s = lbm.Solver(q, strategy=lbm.COMPACT)
         s.step(40)
         assert np.array_equal(bt.density(i), s.density()), i
+
+
+@pytest.mark.parametrize("tile_rows", [8, 12, 16])
+@pytest.mark.parametrize("storage", [0, 1])
+@pytest.mark.parametrize("name", ["drain_mrt", "set2", "droplet_periodic", "tiny_poiseuille", "drain_srt"])
+def test_compacted_fused_step_equals_fused_step_bitwise(lbm, name, storage, tile_rows):
+    """The fused tile step over the compacted layout pulls by rank and
+    bounces back from the node's own slots instead of ghost slots: the same
+    values, so the same densities bit for bit, with eager steps and graph
+    replays, and the same observables."""
+    p = PROBLEMS[name]
+    a = lbm.Solver(p, strategy=lbm.FUSED, tile_rows=tile_rows, storage=storage)
+    b = lbm.Solver(p, strategy=lbm.COMPACT_FUSED, tile_rows=tile_rows, storage=storage)
+    assert "compact" in b.kernel_info()[0]
+    for n in (1, 36, 63):
+        a.step(n)
+        if n % 2 == 0:
+            b.step_graph(n, 1)
+        else:
+            b.step(n)
+        assert np.array_equal(a.density(), b.density()), (name, n)
+    assert a.observables() == b.observables()
+
+
+def test_compacted_fused_checkpoint_batch_and_autotune(lbm):
+    """Checkpoints, batches of uneven instances and the autotuner (which
+    stays within the compacted layout) with the compacted fused step."""
+    p = PROBLEMS["drain_srt"]
+    a = lbm.Solver(p, strategy=lbm.COMPACT_FUSED, tile_rows=8)
+    a.step(21)
+    blob = a.save()
+    a.step(30)
+    ref = a.density()
+    b = lbm.Solver(p, strategy=lbm.COMPACT_FUSED, tile_rows=8)
+    b.load(blob)
+    b.step(30)
+    assert np.array_equal(b.density(), ref)
+    ps = [PROBLEMS["drain_mrt"], PROBLEMS["droplet_wall_mrt"]]
+    bt = lbm.BatchSolver(ps, strategy=lbm.COMPACT_FUSED, tile_rows=12)
+    bt.step_graph(10, 4)
+    for i, q in enumerate(ps):
+        s = lbm.Solver(q, strategy=lbm.FUSED, tile_rows=12)
+        s.step(40)
+        assert np.array_equal(bt.density(i), s.density()), i
+    c = lbm.Solver(PROBLEMS["drain_trt"], strategy=lbm.COMPACT_FUSED)
+    rep = c.autotune(4)
+    assert len(rep.strip().splitlines()) == 4  # the compact split step and three tile heights
+    c.step(200 - c.t)
+    ref = _oracle_series(PROBLEMS["drain_trt"], (200,))
+    assert _rel_err(c.density(), ref[200], PROBLEMS["drain_trt"].mask) <= REL_TOL
 
 
 @pytest.mark.parametrize("storage", [0, 1])
