@@ -112,6 +112,36 @@ def test_observables_match_oracle(lbm, name):
     assert b["flags"] == 0
 
 
+@pytest.mark.parametrize("name,steps", [("drain_srt", 20000), ("small_drainage_G0.9", 5000)])
+def test_steady_state_saturation_and_capillary_pressure(lbm, name, steps):
+    """Saturation and capillary pressure within 1 % of the oracle's: the
+    127x37 drainage at its steady state (its window saturation moves by less
+    than 1e-5 per 1000 steps from 17000 steps on), and the 128x64 G = 0.9
+    case at the end of its 5000-step run."""
+    p = PROBLEMS[name]
+    o = O.OracleSim(p)
+    s = lbm.Solver(p)
+    o.step(steps - 1000)
+    s.step_graph(1000, (steps - 1000) // 1000)
+    a0 = o.observables()
+    o.step(1000)
+    s.step_graph(1000, 1)
+    a, b = o.observables(), s.observables()
+    sw_a = a["sw_count"] / a["n_window"]
+    sw_b = b["sw_count"] / b["n_window"]
+    sww_a = a["sum_rho_w"] / a["sum_rho"]
+    sww_b = b["sum_rho_w"] / b["sum_rho"]
+    drift = abs(sw_a - a0["sw_count"] / a0["n_window"])
+    print(f"[steady] {name} {steps} steps: S_w {sw_b:.6f} (oracle {sw_a:.6f}), weighted {sww_b:.6f} "
+          f"({sww_a:.6f}), P_c {b['pc']:.6e} ({a['pc']:.6e}); oracle S_w change over the last 1000 steps "
+          f"{drift:.1e}", flush=True)
+    if name == "drain_srt":
+        assert drift < 1e-5
+    assert abs(sw_b - sw_a) <= 0.01 * sw_a
+    assert abs(sww_b - sww_a) <= 0.01 * sww_a
+    assert abs(b["pc"] - a["pc"]) <= 0.01 * abs(a["pc"])
+
+
 def test_run_twice_is_bitwise_identical(lbm):
     p = PROBLEMS["drain_mrt"]
     a, b = lbm.Solver(p), lbm.Solver(p)
