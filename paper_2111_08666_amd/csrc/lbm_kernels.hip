@@ -220,6 +220,14 @@ __device__ __forceinline__ void gather(const InstDev &d, gcf *__restrict__ fin, 
   if (info & (kInlet | kOutlet)) complete<Q, ST, R>(d, fin, info, x, y, z, f0, f1);
 }
 
+// Periodic image of a tile-region coordinate.  A tile's halo (and the
+// unused tail of the last tile) can lie more than one period away when the
+// periodic extent is smaller than the tile, so this is a true modulo.
+__device__ __forceinline__ int wrap_index(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
 // Blocks are dealt round-robin to the 8 XCDs; renumber them so each XCD
 // works on a contiguous range of tiles and neighbouring tiles share its L2.
 __device__ __forceinline__ int xcd_block() {
@@ -353,7 +361,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FusedShape<
   const bool col_store = lane >= 2 && lane < 62 && gx < nx;
   bool col_in = true;
   if (gx < 0 || gx >= nx) {
-    if (px) gx += gx < 0 ? nx : -nx;
+    if (px) gx = wrap_index(gx, nx);
     else col_in = false;
   }
   const int gxa = col_in ? gx : (gx < 0 ? 0 : nx - 1);
@@ -369,7 +377,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FusedShape<
     int y = ty * TY - 2 + rows[k];
     bool in = true;
     if (y < 0 || y >= ny) {
-      if (py) y += y < 0 ? ny : -ny;
+      if (py) y = wrap_index(y, ny);
       else in = false;
     }
     gy[k] = in ? y : 0;
@@ -546,7 +554,7 @@ __global__ __launch_bounds__(256) void step_d2q9_list(const InstDev *__restrict_
   const bool col_store = lane >= 2 && lane < 62 && gx < nx;
   bool col_in = true;
   if (gx < 0 || gx >= nx) {
-    if (px) gx += gx < 0 ? nx : -nx;
+    if (px) gx = wrap_index(gx, nx);
     else col_in = false;
   }
   const int gxa = col_in ? gx : (gx < 0 ? 0 : nx - 1);
@@ -561,7 +569,7 @@ __global__ __launch_bounds__(256) void step_d2q9_list(const InstDev *__restrict_
     int y = ty * TY - 2 + rows[k];
     bool in = true;
     if (y < 0 || y >= ny) {
-      if (py) y += y < 0 ? ny : -ny;
+      if (py) y = wrap_index(y, ny);
       else in = false;
     }
     gy[k] = in ? y : 0;
@@ -750,7 +758,7 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
   const bool col_store = lane >= 2 && lane < 62 && gx < nx;
   bool col_in = true;
   if (gx < 0 || gx >= nx) {
-    if (px) gx += gx < 0 ? nx : -nx;
+    if (px) gx = wrap_index(gx, nx);
     else col_in = false;
   }
   const int gxa = col_in ? gx : (gx < 0 ? 0 : nx - 1);
@@ -766,7 +774,7 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
     gy_raw[k] = y;
     bool in = true;
     if (y < 0 || y >= ny) {
-      if (py) y += y < 0 ? ny : -ny;
+      if (py) y = wrap_index(y, ny);
       else in = false;
     }
     gy[k] = in ? y : 0;
@@ -777,7 +785,7 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
   auto wrap_z = [&](int zp, int &zz) __attribute__((always_inline)) -> bool {
     zz = zp;
     if (zz < 0 || zz >= nz) {
-      if (pz) { zz += zz < 0 ? nz : -nz; return true; }
+      if (pz) { zz = wrap_index(zz, nz); return true; }
       zz = 0;
       return false;
     }
