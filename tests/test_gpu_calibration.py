@@ -1,0 +1,142 @@
+"""Calibration sweeps on the GPU, each one batch through the library: the
+miscibility test and the surface tension against G (Sec. 3.1, Figs. 2-3),
+the contact angle against xi at other G (Sec. 3.3 at G = 3.5 only), and the
+contact angle of a sessile droplet in 3D (D3Q19).  The measured tables are
+printed; the assertions are the trends and values the paper states.
+
+Miscibility (Sec. 3.1): 192 x 192 periodic box, droplet of radius 40 (Eq. 29
+with W = 5, inside 1, outside 0.02), M = 1, 25 and 1/25, 30000 steps;
+densities at the droplet centre, and gamma = dP * R from the centre-corner
+pressure difference and the droplet's area radius."""
+import numpy as np
+import pytest
+
+from measure import contact_angle, laplace_point
+from paper_2111_08666_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TAUS = {"M1": (1.0, 1.0), "M25": (3.5, 0.62), "M1/25": (0.62, 3.5)}
+GS = (1.5, 2.0, 2.5, 3.0, 3.5, 4.0, 4.5)
+
+
+@pytest.fixture(scope="module")
+def L():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2111_08666_amd import lbm
+    return lbm
+
+
+def _fields(L, probs, steps):
+    b = L.BatchSolver(probs)
+    try:
+        b.step_graph(1000, steps // 1000)
+        return [b.density(i).astype(np.float64) for i in range(len(probs))]
+    finally:
+        b.close()
+
+
+@pytest.fixture(scope="module")
+def miscibility(L):
+    n = 192
+    cases = [(m, G) for m in TAUS for G in GS]
+    probs = [I.Problem(q=9, mask=np.zeros((n, n), np.uint8),
+                       rho0=I.tanh_droplet((n, n), (n / 2 - 0.5, n / 2 - 0.5), 40, (1.0, 0.02), (0.02, 1.0)),
+                       periodic=3, open_x=0, tau=TAUS[m], G=G, collision=0, name=f"misc_{m}_{G}")
+             for m, G in cases]
+    out = {}
+    for (m, G), r in zip(cases, _fields(L, probs, 30000)):
+        inv_r, dp, _ = laplace_point(r, G)
+        out[(m, G)] = {"rho1": r[0, n // 2, n // 2], "rho2": r[1, n // 2, n // 2], "gamma": dp / inv_r}
+    for m in TAUS:
+        print(f"[miscibility 192^2] {m}: " + "  ".join(
+            f"G={G}: rho1 {out[(m, G)]['rho1']:.4f} rho2 {out[(m, G)]['rho2']:.4f} "
+            f"gamma {out[(m, G)]['gamma']:.4f}" for G in GS), flush=True)
+    return out
+
+
+def test_segregation_grows_with_G(miscibility):
+    """Fig. 2: the centre-density contrast grows with G at every M."""
+    for m in TAUS:
+        c = [miscibility[(m, G)]["rho1"] - miscibility[(m, G)]["rho2"] for G in GS]
+        assert all(a <= b + 1e-6 for a, b in zip(c, c[1:])), (m, c)
+
+
+def test_miscible_below_the_critical_G(paper, miscibility):
+    """Sec. 3.1: below G = 2.5 the components mix (the droplet centre holds
+    a comparable amount of both), above it they separate."""
+    g_crit = paper["miscibility_threshold_G"]["value"]
+    for m in TAUS:
+        for G in GS:
+            r = miscibility[(m, G)]
+            if G < g_crit - 0.25:
+                assert r["rho2"] > 0.3 * r["rho1"], (m, G, r)
+            elif G > g_crit + 0.25:
+                assert r["rho2"] < 0.1 * r["rho1"], (m, G, r)
+
+
+def test_dissolved_density_at_G35(paper, miscibility):
+    """At G = 3.5 the dissolved density is 0.027 (Sec. 3.2, within 25 %) at
+    every M.  (The printed gamma = 0.0692 is the slope of the Laplace
+    regression, checked as such in test_gpu_physics; a single droplet's
+    dP * R also carries the regression's intercept and reads 0.065-0.068.)"""
+    for m in TAUS:
+        r = miscibility[(m, 3.5)]
+        assert abs(r["rho2"] - paper["dissolved_density_G3.5"]["value"]) < 0.25 * 0.027, (m, r)
+
+
+def test_surface_tension_grows_with_G_and_not_with_M(miscibility):
+    """Fig. 3: gamma grows with G.  Sec. 3.1 says changing M makes no major
+    change and prints no number; measured, M = 25 and 1/25 stay within 7.1 %
+    of the M = 1 value wherever the components are immiscible (G >= 3);
+    bounded here at 10 %."""
+    for m in TAUS:
+        g = [miscibility[(m, G)]["gamma"] for G in GS if G >= 3.0]
+        assert all(a < b for a, b in zip(g, g[1:])), (m, g)
+    for G in GS:
+        if G >= 3.0:
+            ref = miscibility[("M1", G)]["gamma"]
+            for m in ("M25", "M1/25"):
+                assert abs(miscibility[(m, G)]["gamma"] - ref) < 0.10 * ref, (m, G)
+
+
+def _sessile(q, xi, G, nx=192, ny=96, nz=None, r0=30):
+    shape = (ny, nx) if q == 9 else (nz, ny, nx)
+    mask = np.zeros(shape, np.uint8)
+    mask[..., 0, :] = 1
+    mask[..., -1, :] = 1
+    center = (nx / 2, 0.5) if q == 9 else (nx / 2, 0.5, nz / 2)
+    minor = 0.027 if G == 3.5 else (0.05 if G == 3.0 else 0.012)
+    rho0 = I.tanh_droplet(shape, center, r0, (1.0, minor), (minor, 1.0), mask=mask)
+    return I.Problem(q=q, mask=mask, rho0=rho0, periodic=1 if q == 9 else 5, open_x=0, tau=(1.0, 1.0),
+                     G=G, xi=xi, collision=0 if q == 9 else 2, name=f"sessile{q}_{G}_{xi}")
+
+
+XIS = (-0.3, 0.0, 0.3)
+
+
+def test_contact_angle_table_at_other_G(L):
+    """xi -> theta at G = 3.0 and 4.0 (192 x 96, M = 1, 40000 steps): 90
+    degrees at xi = 0 and monotone in xi.  The paper calibrates G = 3.5
+    only; the table is printed for use at the other G."""
+    cases = [(G, xi) for G in (3.0, 4.0) for xi in XIS]
+    fields = _fields(L, [_sessile(9, xi, G) for G, xi in cases], 40000)
+    th = {c: contact_angle(r) for c, r in zip(cases, fields)}
+    for G in (3.0, 4.0):
+        print(f"[contact angle 192x96] G={G}: " + " ".join(f"xi={xi:+.1f}:{th[(G, xi)]:.1f}" for xi in XIS),
+              flush=True)
+        assert abs(th[(G, 0.0)] - 90.0) < 3.0
+        assert th[(G, -0.3)] < th[(G, 0.0)] < th[(G, 0.3)]
+
+
+def test_contact_angle_in_3d(L):
+    """Sessile droplet in 3D (D3Q19 TRT, 96 x 48 x 96, radius 20, G = 3.5,
+    20000 steps), angle measured in the droplet's mid-plane: 90 degrees at
+    xi = 0 and monotone in xi; printed next to the 2D calibration."""
+    fields = _fields(L, [_sessile(19, xi, 3.5, nx=96, ny=48, nz=96, r0=20) for xi in XIS], 20000)
+    th = {xi: contact_angle(r[:, 48]) for xi, r in zip(XIS, fields)}
+    print("[contact angle 3D 96x48x96] " + " ".join(f"xi={xi:+.1f}:{th[xi]:.1f}" for xi in XIS), flush=True)
+    assert abs(th[0.0] - 90.0) < 4.0
+    assert th[-0.3] < th[0.0] < th[0.3]
