@@ -185,9 +185,130 @@ __global__ __launch_bounds__(256) void igemm_fwd(GemmArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// 3x3 convolution with LDS staging.  The reduction runs over 16-channel
+// groups, and within a group over the nine taps (k = (group, tap, channel)):
+// per group the block stages its input rows with a one-pixel halo (zero
+// outside the image) and the group's weights of its output channels in LDS
+// once, and all nine taps of all four waves read their MFMA fragments from
+// there.  Wave tile TM x TN MFMA tiles (32 x 32 each); the four waves are
+// stacked along the pixels, so a block covers 128 TM consecutive pixels --
+// whole image rows (16 <= w <= 256, w divides the block, h * w a multiple of
+// it) -- and 32 TN output channels.  Needs the reduction channels to be a
+// multiple of 16.
+// ---------------------------------------------------------------------------
+constexpr int conv_block_pix(int tm) { return 128 * tm; }
+// largest staged region over the allowed widths: (pixels / w + 2) rows of w + 2
+constexpr int conv_halo_pix(int bp) {
+  int m = 0;
+  for (int w = 16; w <= 256; w *= 2) {
+    const int v = (bp / w + 2) * (w + 2);
+    if (bp % w == 0 && v > m) m = v;
+  }
+  return m;
+}
+
+template <int TM, int TN>
+__global__ __launch_bounds__(256) void conv3x3_lds(GemmArgs a) {
+  constexpr int BP = conv_block_pix(TM), BC = 32 * TN;
+  __shared__ uint4 sA[conv_halo_pix(BP) * 2];  // [region pixel][channel half of the group]
+  __shared__ uint4 sB[BC * 9 * 2];             // [output channel][tap][channel half]
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int half = lane >> 5;
+  const int w = a.w, h = a.h, rw = w + 2;
+  const int64_t p0 = (int64_t)blockIdx.x * BP;
+  const int img = (int)(p0 / ((int64_t)h * w));
+  const int y0 = (int)((p0 - (int64_t)img * h * w) / w);  // first image row of the block
+  const int rows = BP / w + 2;                            // staged rows, halo included
+  const int col0 = blockIdx.y * BC;
+  const int64_t img_base = (int64_t)img * h * w;
+  floatx16 acc[TM][TN];
+#pragma unroll
+  for (int t = 0; t < TM; ++t)
+#pragma unroll
+    for (int u = 0; u < TN; ++u) acc[t][u] = floatx16{};
+  // this lane's pixels within the block (row-major over the block's rows)
+  int pr[TM], pc[TM];
+#pragma unroll
+  for (int t = 0; t < TM; ++t) {
+    const int q = wave * 32 * TM + 32 * t + (lane & 31);
+    pr[t] = q / w;
+    pc[t] = q - pr[t] * w;
+  }
+  const int groups = a.kc / 16;
+  for (int g = 0; g < groups; ++g) {
+    const int ch = g * 16;
+    for (int e = tid; e < rows * rw * 2; e += 256) {
+      const int q = e >> 1, hf = e & 1;
+      const int ry = q / rw, rx = q - ry * rw;
+      const int y = y0 - 1 + ry, x = rx - 1;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (y >= 0 && y < h && x >= 0 && x < w)
+        v = *reinterpret_cast<const uint4 *>(a.x + (img_base + (int64_t)y * w + x) * a.x_cs + a.x_co + ch + 8 * hf);
+      sA[e] = v;
+    }
+    for (int e = tid; e < BC * 9 * 2; e += 256) {
+      const int co = e / 18, rem = e - co * 18;
+      const int tap = rem >> 1, hf = rem & 1;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (col0 + co < a.nout)
+        v = *reinterpret_cast<const uint4 *>(a.wgt + ((int64_t)(col0 + co) * 9 + tap) * a.kc + ch + 8 * hf);
+      sB[e] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+      const int dy = tap / 3, dx = tap % 3;
+      bf16x8 A[TM], B[TN];
+#pragma unroll
+      for (int t = 0; t < TM; ++t)
+        A[t] = __builtin_bit_cast(bf16x8, sA[((pr[t] + dy) * rw + pc[t] + dx) * 2 + half]);
+#pragma unroll
+      for (int u = 0; u < TN; ++u)
+        B[u] = __builtin_bit_cast(bf16x8, sB[((32 * u + (lane & 31)) * 9 + tap) * 2 + half]);
+#pragma unroll
+      for (int t = 0; t < TM; ++t)
+#pragma unroll
+        for (int u = 0; u < TN; ++u) acc[t][u] = mfma(A[t], B[u], acc[t][u]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < TN; ++u) {
+    const int col = col0 + 32 * u + (lane & 31);
+    if (col >= a.nout) continue;
+    const float bv = a.bias ? a.bias[col] : 0.f;
+#pragma unroll
+    for (int t = 0; t < TM; ++t) {
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t p = p0 + wave * 32 * TM + 32 * t + c_row(r, lane);
+        float v = acc[t][u][r] + bv;
+        if (a.relu) v = v > 0.f ? v : 0.f;
+        a.y[p * a.y_cs + a.y_co + col] = f2bf(v);
+      }
+    }
+  }
+}
+
+// Can the LDS-staged kernel with block of bp pixels run this convolution?
+static bool conv_lds_fits(const GemmArgs &a, int bp) {
+  return a.kc % 16 == 0 && a.w >= 16 && a.w <= 256 && bp % a.w == 0 && ((int64_t)a.h * a.w) % bp == 0;
+}
+
 // Launch with the wave tile chosen by the output channel count.
 template <int MODE>
 static void launch_igemm(const GemmArgs &a, int64_t P, int taps_z, hipStream_t s) {
+  if (MODE == 0 && a.nout <= 32 && conv_lds_fits(a, conv_block_pix(4))) {
+    dim3 g((unsigned)(P / conv_block_pix(4)), 1);
+    conv3x3_lds<4, 1><<<g, 256, 0, s>>>(a);
+    return;
+  }
+  if (MODE == 0 && conv_lds_fits(a, conv_block_pix(2))) {
+    dim3 g((unsigned)(P / conv_block_pix(2)), (unsigned)((a.nout + 63) / 64));
+    conv3x3_lds<2, 2><<<g, 256, 0, s>>>(a);
+    return;
+  }
   if (a.nout >= 64) {
     dim3 g((unsigned)((P + 255) / 256), (unsigned)((a.nout + 63) / 64), (unsigned)taps_z);
     igemm_fwd<MODE, 2, 2><<<g, 256, 0, s>>>(a);

@@ -98,6 +98,11 @@ def _conv_case(S, seed, n, h, w, cin, cout, x_cs, x_co, y_cs, y_co):
     (2, 9, 13, 24, 40, 32, 8, 48, 8),      # ragged pixel tile, ragged channel tile, slices
     (1, 16, 16, 8, 32, 8, 0, 32, 0),       # first-layer shape
     (1, 5, 70, 64, 96, 64, 0, 96, 0),      # K = 576, two channel tiles
+    # LDS-staged path (16-channel groups, whole rows per 256- or 512-pixel block)
+    (2, 16, 32, 32, 48, 40, 8, 64, 8),     # 8 rows per block, ragged channel tile, slices
+    (1, 8, 256, 16, 64, 16, 0, 64, 0),     # one row of 256 per block
+    (1, 256, 1, 16, 40, 16, 0, 40, 0),     # one-pixel-wide image (the gather path)
+    (2, 16, 32, 32, 24, 32, 0, 32, 8),     # at most 32 output channels: 512-pixel blocks
 ])
 def test_conv3x3_forward(S, relu, n, h, w, cin, cout, x_cs, x_co, y_cs, y_co):
     xfull, wt, b = _conv_case(S, 10 + cin, n, h, w, cin, cout, x_cs, x_co, y_cs, y_co)
