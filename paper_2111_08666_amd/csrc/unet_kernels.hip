@@ -324,13 +324,15 @@ static void launch_igemm(const GemmArgs &a, int64_t P, int taps_z, hipStream_t s
 //   MODE 0, 3x3: m = co, n = (tap, ci): A = dy[p][co], B = x[p + off(tap)][ci]
 //   MODE 1, transposed 2x2, tap = blockIdx.z: m = co, n = ci:
 //          A = dy[2p + tap][co], B = x[p][ci]  (p over the input grid)
-// Per stage, 64 pixels x 64 channels of each operand are loaded as 16-byte
-// vectors (8 channels of one pixel) and written channel-major to LDS, so an
-// MFMA operand fragment (8 consecutive pixels of one channel) is one 128-bit
-// LDS read.  Channel counts, strides and offsets are multiples of 8.
+// Per stage of 128 pixels, each thread loads an 8-pixel x 8-channel block of
+// one operand (eight 16-byte vectors), transposes it in registers (byte
+// permutes) and writes it channel-major to LDS as eight 16-byte vectors, so
+// an MFMA operand fragment (8 consecutive pixels of one channel) is one
+// 128-bit LDS read and neither side of LDS sees bank conflicts.  Channel
+// counts, strides and offsets are multiples of 8.
 // ---------------------------------------------------------------------------
 constexpr int kWgradPix = 4096;  // pixels per block (split-K chunk)
-constexpr int kStagePix = 64;    // pixels per LDS stage
+constexpr int kStagePix = 128;   // pixels per LDS stage
 constexpr int kStageLd = kStagePix + 8;
 
 struct WgradArgs {
@@ -342,6 +344,23 @@ struct WgradArgs {
   int ncol;                       // MODE 0: 9 * cin; MODE 1: cin
   float *bpartial;                // [kblocks][ntap][cout] bias partial sums, or NULL
 };
+
+// 8 x 8 transpose of 16-bit values: in[p] holds channels 0..7 of pixel p,
+// out[c] receives pixels 0..7 of channel c.
+__device__ __forceinline__ void transpose8x8(const uint4 (&in)[8], uint4 (&out)[8]) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    uint32_t lo[4], hi[4];  // channel 2j and 2j + 1, pixel pairs i
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t a = (&in[2 * i].x)[j], b = (&in[2 * i + 1].x)[j];
+      lo[i] = __builtin_amdgcn_perm(b, a, 0x05040100u);
+      hi[i] = __builtin_amdgcn_perm(b, a, 0x07060302u);
+    }
+    out[2 * j] = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+    out[2 * j + 1] = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+  }
+}
 
 template <int MODE>
 __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
@@ -356,24 +375,27 @@ __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
   const int tapz = MODE == 1 ? (int)(blockIdx.z % 4) : 0;
   const int nblk = MODE == 1 ? (int)(blockIdx.z / 4) : (int)blockIdx.z;
   const int n0 = nblk * 64;         // column block
+  // staging role: threads 0-127 stage A, 128-255 stage B; channel group cg
+  // (8 channels) and pixel block pb (8 pixels) of the stage
+  const bool stage_b = tid >= 128;
+  const int cg = (tid & 127) >> 4, pb = tid & 15;
   floatx16 acc = {};
   // the blocks of the first column block also sum dy over their pixels (bias)
   const bool bias_blk = a.bpartial && nblk == 0 && tid < 64;
   float bacc = 0.f;
   const int64_t p_end = p_begin + kWgradPix < P ? p_begin + kWgradPix : P;
   for (int64_t pc = p_begin; pc < p_end; pc += kStagePix) {
-    // stage: 64 pixels x 8 channel groups of 8 per operand = 512 vectors, 2 per thread
+    uint4 v[8], t[8];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const int e = tid + 256 * r;
-      const int pl = e >> 3, cg = (e & 7) * 8;
-      const int64_t p = pc + pl;
-      uint4 va = make_uint4(0, 0, 0, 0), vb = make_uint4(0, 0, 0, 0);
-      if (p < p_end) {
-        const int pn = (int)(p / ((int64_t)a.h * a.w));
-        const int rr = (int)(p - (int64_t)pn * a.h * a.w);
-        const int py = rr / a.w, px = rr - py * a.w;
-        const int m = m0 + cg;
+    for (int r = 0; r < 8; ++r) {
+      const int64_t p = pc + pb * 8 + r;
+      v[r] = make_uint4(0, 0, 0, 0);
+      if (p >= p_end) continue;
+      const int pn = (int)(p / ((int64_t)a.h * a.w));
+      const int rr = (int)(p - (int64_t)pn * a.h * a.w);
+      const int py = rr / a.w, px = rr - py * a.w;
+      if (!stage_b) {
+        const int m = m0 + cg * 8;
         if (m < a.cout) {
           int64_t q;
           if constexpr (MODE == 0) {
@@ -382,36 +404,33 @@ __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
             const int H2 = 2 * a.h, W2 = 2 * a.w;
             q = (int64_t)pn * H2 * W2 + (int64_t)(2 * py + (tapz >> 1)) * W2 + 2 * px + (tapz & 1);
           }
-          va = *reinterpret_cast<const uint4 *>(a.dy + q * a.dy_cs + a.dy_co + m);
+          v[r] = *reinterpret_cast<const uint4 *>(a.dy + q * a.dy_cs + a.dy_co + m);
         }
-        const int nn = n0 + cg;
+      } else {
+        const int nn = n0 + cg * 8;
         if (nn < a.ncol) {
           if constexpr (MODE == 0) {
             const int tap = nn / a.cin, ci = nn - tap * a.cin;
             const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
             if (yy >= 0 && yy < a.h && xx >= 0 && xx < a.w)
-              vb = *reinterpret_cast<const uint4 *>(
+              v[r] = *reinterpret_cast<const uint4 *>(
                   a.x + ((int64_t)pn * a.h * a.w + (int64_t)yy * a.w + xx) * a.x_cs + a.x_co + ci);
           } else {
-            vb = *reinterpret_cast<const uint4 *>(a.x + p * a.x_cs + a.x_co + nn);
+            v[r] = *reinterpret_cast<const uint4 *>(a.x + p * a.x_cs + a.x_co + nn);
           }
         }
       }
-      const uint32_t wa[4] = {va.x, va.y, va.z, va.w}, wb[4] = {vb.x, vb.y, vb.z, vb.w};
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        sA[cg + 2 * k][pl] = (uint16_t)(wa[k] & 0xffffu);
-        sA[cg + 2 * k + 1][pl] = (uint16_t)(wa[k] >> 16);
-        sB[cg + 2 * k][pl] = (uint16_t)(wb[k] & 0xffffu);
-        sB[cg + 2 * k + 1][pl] = (uint16_t)(wb[k] >> 16);
-      }
     }
+    transpose8x8(v, t);
+    uint16_t(*dst)[kStageLd] = stage_b ? sB : sA;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) *reinterpret_cast<uint4 *>(&dst[cg * 8 + c][pb * 8]) = t[c];
     __syncthreads();
     if (bias_blk) {
 #pragma unroll
       for (int q = 0; q < kStagePix; q += 8) {
-        const uint4 v = *reinterpret_cast<const uint4 *>(&sA[tid][q]);
-        const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
+        const uint4 u = *reinterpret_cast<const uint4 *>(&sA[tid][q]);
+        const uint32_t w4[4] = {u.x, u.y, u.z, u.w};
 #pragma unroll
         for (int k = 0; k < 4; ++k) bacc += bf2f((uint16_t)(w4[k] & 0xffffu)) + bf2f((uint16_t)(w4[k] >> 16));
       }
