@@ -455,6 +455,18 @@ __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
   }
 }
 
+// sum_{k < count} p[k * stride] in a fixed order: eight interleaved partial
+// sums (k mod 8) combined pairwise, so the loads of a thread overlap.
+__device__ __forceinline__ float strided_sum(const float *p, int64_t count, int64_t stride) {
+  float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  int64_t k = 0;
+  for (; k + 8 <= count; k += 8)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] += p[(k + j) * stride];
+  for (int j = 0; k + j < count; ++j) acc[j] += p[(k + j) * stride];
+  return ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+}
+
 // dw[m][tap][n] (+)= sum over kblocks of partial[kb][tap][m][n], fixed order.
 // For MODE 0 ntap = 1 and n = (tap, ci) already.
 __global__ void wgrad_reduce(const float *partial, int kblocks, int ntap, int cout, int ncol, float *dw,
@@ -464,8 +476,7 @@ __global__ void wgrad_reduce(const float *partial, int kblocks, int ntap, int co
     const int tap = (int)(e / ((int64_t)cout * ncol));
     const int64_t rem = e - (int64_t)tap * cout * ncol;
     const int m = (int)(rem / ncol), n = (int)(rem - (int64_t)m * ncol);
-    float s = 0.f;
-    for (int kb = 0; kb < kblocks; ++kb) s += partial[(int64_t)kb * total + e];
+    const float s = strided_sum(partial + e, kblocks, total);
     const int64_t o = ((int64_t)m * ntap + tap) * ncol + n;  // [co][tap][ci]
     dw[o] = accumulate ? dw[o] + s : s;
   }
@@ -475,8 +486,7 @@ __global__ void wgrad_reduce(const float *partial, int kblocks, int ntap, int co
 __global__ void bias_reduce(const float *bpartial, int64_t nparts, int c, float *db, int accumulate) {
   const int ch = blockIdx.x * blockDim.x + threadIdx.x;
   if (ch >= c) return;
-  float s = 0.f;
-  for (int64_t b = 0; b < nparts; ++b) s += bpartial[b * c + ch];
+  const float s = strided_sum(bpartial + ch, nparts, c);
   db[ch] = accumulate ? db[ch] + s : s;
 }
 
@@ -565,6 +575,18 @@ __global__ void maxpool_bwd_kernel(const uint16_t *x, int n, int h, int w, int c
 
 __device__ __forceinline__ float head_logit(const uint16_t *x, int64_t p, int c, int x_cs, const float *w, float b) {
   float z = b;
+  if ((c & 7) == 0 && (x_cs & 7) == 0) {  // 16-byte vectors of 8 channels
+    for (int c8 = 0; c8 < c; c8 += 8) {
+      const uint4 v = *reinterpret_cast<const uint4 *>(x + p * x_cs + c8);
+      const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        z += w[c8 + 2 * k] * bf2f((uint16_t)(u[k] & 0xffffu));
+        z += w[c8 + 2 * k + 1] * bf2f((uint16_t)(u[k] >> 16));
+      }
+    }
+    return z;
+  }
   for (int ch = 0; ch < c; ++ch) z += w[ch] * bf2f(x[p * x_cs + ch]);
   return z;
 }
@@ -589,8 +611,17 @@ __global__ void head_loss_pix(const uint16_t *x, int64_t n_pix, int c, int x_cs,
     const float g = on ? (s - t[p]) * scale : 0.f;
     g_out[p] = g;
     l_out[p] = on ? (sp - t[p] * z) * scale : 0.f;
-    if (dx)
+    if (dx && (c & 7) == 0) {
+      for (int c8 = 0; c8 < c; c8 += 8) {
+        uint32_t u[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+          u[k] = (uint32_t)f2bf(g * w[c8 + 2 * k]) | ((uint32_t)f2bf(g * w[c8 + 2 * k + 1]) << 16);
+        *reinterpret_cast<uint4 *>(dx + p * c + c8) = make_uint4(u[0], u[1], u[2], u[3]);
+      }
+    } else if (dx) {
       for (int ch = 0; ch < c; ++ch) dx[p * c + ch] = f2bf(g * w[ch]);
+    }
   }
 }
 
@@ -623,6 +654,50 @@ __global__ void head_loss_sums(const uint16_t *x, int64_t n_pix, int c, int x_cs
   if (threadIdx.x == 0) {
     float s1 = 0.f, s2 = 0.f;
     for (int q = 0; q < lanes; ++q) { s1 += red_l[q * c]; s2 += red_g[q * c]; }
+    partial[(int64_t)blockIdx.x * (2 + c)] = s1;
+    partial[(int64_t)blockIdx.x * (2 + c) + 1] = s2;
+  }
+}
+
+// Vector form of head_loss_sums (c and x_cs multiples of 8): threads =
+// (256 / (c / 8)) pixel lanes x (c / 8) channel groups of eight, each with
+// eight accumulators fed by one 16-byte load per pixel.
+__global__ void head_loss_sums_v(const uint16_t *x, int64_t n_pix, int c, int x_cs, const float *g, const float *l,
+                                 float *partial) {
+  __shared__ float red[256 * 8];
+  __shared__ float red_l[256], red_g[256];
+  const int groups = c / 8, lanes = 256 / groups;
+  const int pl = threadIdx.x / groups, cg = threadIdx.x - pl * groups;
+  const int64_t p0 = (int64_t)blockIdx.x * kHeadPix;
+  float a[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+  float sl = 0.f, sg = 0.f;
+  for (int k = pl; k < kHeadPix; k += lanes) {
+    const int64_t p = p0 + k;
+    if (p >= n_pix) break;
+    const float gv = g[p];
+    const uint4 v = *reinterpret_cast<const uint4 *>(x + p * x_cs + cg * 8);
+    const uint32_t u[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      a[2 * q] += gv * bf2f((uint16_t)(u[q] & 0xffffu));
+      a[2 * q + 1] += gv * bf2f((uint16_t)(u[q] >> 16));
+    }
+    if (cg == 0) { sl += l[p]; sg += gv; }
+  }
+#pragma unroll
+  for (int j = 0; j < 8; ++j) red[threadIdx.x * 8 + j] = a[j];
+  red_l[threadIdx.x] = sl;
+  red_g[threadIdx.x] = sg;
+  __syncthreads();
+  if (threadIdx.x < (unsigned)c) {
+    const int ch = threadIdx.x, g8 = ch >> 3, j = ch & 7;
+    float s = 0.f;
+    for (int q = 0; q < lanes; ++q) s += red[(q * groups + g8) * 8 + j];
+    partial[(int64_t)blockIdx.x * (2 + c) + 2 + ch] = s;
+  }
+  if (threadIdx.x == 0) {
+    float s1 = 0.f, s2 = 0.f;
+    for (int q = 0; q < lanes; ++q) { s1 += red_l[q * groups]; s2 += red_g[q * groups]; }
     partial[(int64_t)blockIdx.x * (2 + c)] = s1;
     partial[(int64_t)blockIdx.x * (2 + c) + 1] = s2;
   }
@@ -802,7 +877,10 @@ int unet_head_loss_bwd(const uint16_t *x, int n_pix, int c, int x_cs, const floa
   float *g = partial, *l = partial + n_pix, *sums = partial + 2 * (int64_t)n_pix;
   const int blocks = (int)(((int64_t)n_pix + kHeadPix - 1) / kHeadPix);
   head_loss_pix<<<grid1d(n_pix), 256, 0, (hipStream_t)s>>>(x, n_pix, c, x_cs, w, b, target, mask, scale, dx, g, l);
-  head_loss_sums<<<blocks, 256, 0, (hipStream_t)s>>>(x, n_pix, c, x_cs, g, l, sums);
+  if ((c & 7) == 0 && (x_cs & 7) == 0)
+    head_loss_sums_v<<<blocks, 256, 0, (hipStream_t)s>>>(x, n_pix, c, x_cs, g, l, sums);
+  else
+    head_loss_sums<<<blocks, 256, 0, (hipStream_t)s>>>(x, n_pix, c, x_cs, g, l, sums);
   head_loss_final<<<1, 512, 0, (hipStream_t)s>>>(sums, blocks, c, loss, dw, db);
   return launched();
 }

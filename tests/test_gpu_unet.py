@@ -220,8 +220,8 @@ def test_maxpool_relu_exact(S):
     assert np.array_equal(host_bf16(S, g), np.where(x[..., :c] > 0, base, 0.0))
 
 
-def test_head_loss_and_gradients(S):
-    n_pix, c = 3000, 32
+@pytest.mark.parametrize("n_pix,c", [(3000, 32), (5000, 64), (1000, 4)])  # 16-byte vector and scalar paths
+def test_head_loss_and_gradients(S, n_pix, c):
     r = rng(6)
     x = bf16_round(S, np.abs(r.normal(size=(n_pix, c))))
     w = r.normal(0, 0.3, size=c).astype(np.float32).astype(np.float64)
