@@ -362,69 +362,74 @@ __device__ __forceinline__ void transpose8x8(const uint4 (&in)[8], uint4 (&out)[
   }
 }
 
-template <int MODE>
+// Block tile (32 MT) x (32 NT) of C with MT * NT = 4 waves, each one 32 x 32
+// MFMA tile: (2, 2) in general, (1, 4) when the output channels fit 32.
+template <int MODE, int MT, int NT>
 __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[64][kStageLd];  // [m][pixel]
-  __shared__ __attribute__((aligned(16))) uint16_t sB[64][kStageLd];  // [n][pixel]
+  static_assert(MT * NT == 4, "four waves");
+  __shared__ __attribute__((aligned(16))) uint16_t sA[32 * MT][kStageLd];  // [m][pixel]
+  __shared__ __attribute__((aligned(16))) uint16_t sB[32 * NT][kStageLd];  // [n][pixel]
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave & 1, wn = wave >> 1;
+  const int wm = wave % MT, wn = wave / MT;
   const int half = lane >> 5;
   const int64_t P = (int64_t)a.n * a.h * a.w;
   const int64_t p_begin = (int64_t)blockIdx.x * kWgradPix;
-  const int m0 = blockIdx.y * 64;  // output channel block
+  const int m0 = blockIdx.y * 32 * MT;  // output channel block
   const int tapz = MODE == 1 ? (int)(blockIdx.z % 4) : 0;
   const int nblk = MODE == 1 ? (int)(blockIdx.z / 4) : (int)blockIdx.z;
-  const int n0 = nblk * 64;         // column block
-  // staging role: threads 0-127 stage A, 128-255 stage B; channel group cg
-  // (8 channels) and pixel block pb (8 pixels) of the stage
-  const bool stage_b = tid >= 128;
-  const int cg = (tid & 127) >> 4, pb = tid & 15;
+  const int n0 = nblk * 32 * NT;        // column block
   floatx16 acc = {};
   // the blocks of the first column block also sum dy over their pixels (bias)
-  const bool bias_blk = a.bpartial && nblk == 0 && tid < 64;
+  const bool bias_blk = a.bpartial && nblk == 0 && tid < 32 * MT;
   float bacc = 0.f;
   const int64_t p_end = p_begin + kWgradPix < P ? p_begin + kWgradPix : P;
   for (int64_t pc = p_begin; pc < p_end; pc += kStagePix) {
-    uint4 v[8], t[8];
+    // staging: 8-pixel x 8-channel blocks, 64 MT of A then 64 NT of B
+    for (int e = tid; e < 64 * (MT + NT); e += 256) {
+      const bool stage_b = e >= 64 * MT;
+      const int eo = stage_b ? e - 64 * MT : e;
+      const int cg = eo >> 4, pb = eo & 15;
+      uint4 v[8], t[8];
 #pragma unroll
-    for (int r = 0; r < 8; ++r) {
-      const int64_t p = pc + pb * 8 + r;
-      v[r] = make_uint4(0, 0, 0, 0);
-      if (p >= p_end) continue;
-      const int pn = (int)(p / ((int64_t)a.h * a.w));
-      const int rr = (int)(p - (int64_t)pn * a.h * a.w);
-      const int py = rr / a.w, px = rr - py * a.w;
-      if (!stage_b) {
-        const int m = m0 + cg * 8;
-        if (m < a.cout) {
-          int64_t q;
-          if constexpr (MODE == 0) {
-            q = p;
-          } else {
-            const int H2 = 2 * a.h, W2 = 2 * a.w;
-            q = (int64_t)pn * H2 * W2 + (int64_t)(2 * py + (tapz >> 1)) * W2 + 2 * px + (tapz & 1);
+      for (int r = 0; r < 8; ++r) {
+        const int64_t p = pc + pb * 8 + r;
+        v[r] = make_uint4(0, 0, 0, 0);
+        if (p >= p_end) continue;
+        const int pn = (int)(p / ((int64_t)a.h * a.w));
+        const int rr = (int)(p - (int64_t)pn * a.h * a.w);
+        const int py = rr / a.w, px = rr - py * a.w;
+        if (!stage_b) {
+          const int m = m0 + cg * 8;
+          if (m < a.cout) {
+            int64_t q;
+            if constexpr (MODE == 0) {
+              q = p;
+            } else {
+              const int H2 = 2 * a.h, W2 = 2 * a.w;
+              q = (int64_t)pn * H2 * W2 + (int64_t)(2 * py + (tapz >> 1)) * W2 + 2 * px + (tapz & 1);
+            }
+            v[r] = *reinterpret_cast<const uint4 *>(a.dy + q * a.dy_cs + a.dy_co + m);
           }
-          v[r] = *reinterpret_cast<const uint4 *>(a.dy + q * a.dy_cs + a.dy_co + m);
-        }
-      } else {
-        const int nn = n0 + cg * 8;
-        if (nn < a.ncol) {
-          if constexpr (MODE == 0) {
-            const int tap = nn / a.cin, ci = nn - tap * a.cin;
-            const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
-            if (yy >= 0 && yy < a.h && xx >= 0 && xx < a.w)
-              v[r] = *reinterpret_cast<const uint4 *>(
-                  a.x + ((int64_t)pn * a.h * a.w + (int64_t)yy * a.w + xx) * a.x_cs + a.x_co + ci);
-          } else {
-            v[r] = *reinterpret_cast<const uint4 *>(a.x + p * a.x_cs + a.x_co + nn);
+        } else {
+          const int nn = n0 + cg * 8;
+          if (nn < a.ncol) {
+            if constexpr (MODE == 0) {
+              const int tap = nn / a.cin, ci = nn - tap * a.cin;
+              const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
+              if (yy >= 0 && yy < a.h && xx >= 0 && xx < a.w)
+                v[r] = *reinterpret_cast<const uint4 *>(
+                    a.x + ((int64_t)pn * a.h * a.w + (int64_t)yy * a.w + xx) * a.x_cs + a.x_co + ci);
+            } else {
+              v[r] = *reinterpret_cast<const uint4 *>(a.x + p * a.x_cs + a.x_co + nn);
+            }
           }
         }
       }
-    }
-    transpose8x8(v, t);
-    uint16_t(*dst)[kStageLd] = stage_b ? sB : sA;
+      transpose8x8(v, t);
+      uint16_t(*dst)[kStageLd] = stage_b ? sB : sA;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) *reinterpret_cast<uint4 *>(&dst[cg * 8 + c][pb * 8]) = t[c];
+      for (int c = 0; c < 8; ++c) *reinterpret_cast<uint4 *>(&dst[cg * 8 + c][pb * 8]) = t[c];
+    }
     __syncthreads();
     if (bias_blk) {
 #pragma unroll
@@ -788,8 +793,13 @@ int unet_conv3x3_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs
   const int kb = (int)((P + kWgradPix - 1) / kWgradPix);
   const int64_t wpart = (int64_t)kb * cout * 9 * cin;
   WgradArgs a{x, n, h, w, cin, x_cs, x_co, dy, cout, dy_cs, dy_co, partial, 9 * cin, db ? partial + wpart : nullptr};
-  dim3 g((unsigned)kb, (unsigned)((cout + 63) / 64), (unsigned)((9 * cin + 63) / 64));
-  igemm_wgrad<0><<<g, 256, 0, (hipStream_t)s>>>(a);
+  if (cout <= 32) {
+    dim3 g((unsigned)kb, 1, (unsigned)((9 * cin + 127) / 128));
+    igemm_wgrad<0, 1, 4><<<g, 256, 0, (hipStream_t)s>>>(a);
+  } else {
+    dim3 g((unsigned)kb, (unsigned)((cout + 63) / 64), (unsigned)((9 * cin + 63) / 64));
+    igemm_wgrad<0, 2, 2><<<g, 256, 0, (hipStream_t)s>>>(a);
+  }
   wgrad_reduce<<<grid1d((int64_t)cout * 9 * cin), 256, 0, (hipStream_t)s>>>(partial, kb, 1, cout, 9 * cin, dw,
                                                                              accumulate);
   if (db) bias_reduce<<<(cout + 63) / 64, 64, 0, (hipStream_t)s>>>(partial + wpart, kb, cout, db, accumulate);
@@ -850,8 +860,13 @@ int unet_upconv_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs,
   const int kb = (int)((P + kWgradPix - 1) / kWgradPix);
   const int64_t wpart = (int64_t)kb * 4 * cout * cin;
   WgradArgs a{x, n, h, w, cin, x_cs, x_co, dy, cout, dy_cs, dy_co, partial, cin, db ? partial + wpart : nullptr};
-  dim3 g((unsigned)kb, (unsigned)((cout + 63) / 64), (unsigned)(4 * ((cin + 63) / 64)));
-  igemm_wgrad<1><<<g, 256, 0, (hipStream_t)s>>>(a);
+  if (cout <= 32) {
+    dim3 g((unsigned)kb, 1, (unsigned)(4 * ((cin + 127) / 128)));
+    igemm_wgrad<1, 1, 4><<<g, 256, 0, (hipStream_t)s>>>(a);
+  } else {
+    dim3 g((unsigned)kb, (unsigned)((cout + 63) / 64), (unsigned)(4 * ((cin + 63) / 64)));
+    igemm_wgrad<1, 2, 2><<<g, 256, 0, (hipStream_t)s>>>(a);
+  }
   wgrad_reduce<<<grid1d((int64_t)4 * cout * cin), 256, 0, (hipStream_t)s>>>(partial, kb, 4, cout, cin, dw, 0);
   if (db) bias_reduce<<<(cout + 63) / 64, 64, 0, (hipStream_t)s>>>(partial + wpart, (int64_t)kb * 4, cout, db, 0);
   return launched();

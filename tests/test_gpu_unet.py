@@ -126,8 +126,9 @@ def test_conv3x3_forward(S, relu, n, h, w, cin, cout, x_cs, x_co, y_cs, y_co):
     assert np.all(raw[..., :y_co] == sentinel) and np.all(raw[..., y_co + cout:] == sentinel)
 
 
-def test_conv3x3_data_and_weight_gradients(S):
-    n, h, w, cin, cout = 2, 20, 17, 16, 48          # 680 pixels -> two split-K blocks
+@pytest.mark.parametrize("cin,cout", [(16, 48), (24, 24)])  # 64 x 64 and 32 x 128 weight-gradient tiles
+def test_conv3x3_data_and_weight_gradients(S, cin, cout):
+    n, h, w = 2, 20, 17                              # 680 pixels -> two split-K blocks
     r = rng(3)
     x = bf16_round(S, r.normal(size=(n, h, w, cin)))
     wt = bf16_round(S, r.normal(0, 0.2, size=(cout, 3, 3, cin)))
