@@ -711,8 +711,7 @@ __global__ void head_loss_sums_v(const uint16_t *x, int64_t n_pix, int c, int x_
 __global__ void head_loss_final(const float *partial, int blocks, int c, float *loss, float *dw, float *db) {
   const int k = threadIdx.x;
   if (k >= 2 + c) return;
-  float s = 0.f;
-  for (int b = 0; b < blocks; ++b) s += partial[(int64_t)b * (2 + c) + k];
+  const float s = strided_sum(partial + k, blocks, 2 + c);
   if (k == 0) loss[0] = s;
   else if (k == 1) { if (db) db[0] = s; }
   else if (dw) dw[k - 2] = s;
