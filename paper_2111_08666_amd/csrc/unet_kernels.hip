@@ -549,6 +549,28 @@ __global__ void maxpool_fwd_kernel(const uint16_t *x, int n, int h, int w, int c
   }
 }
 
+// Vector form (channel counts, strides and offsets multiples of 8): one
+// 16-byte vector of 8 channels per thread.
+__global__ void relu_bwd_vec(const uint16_t *y, int64_t n_pix, int c8, int y_cs, int y_co, uint16_t *dy, int dy_cs,
+                             int dy_co) {
+  const int64_t total = n_pix * c8;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t p = e / c8;
+    const int ch = (int)(e - p * c8) * 8;
+    const uint4 yv = *reinterpret_cast<const uint4 *>(y + p * y_cs + y_co + ch);
+    uint4 *dp = reinterpret_cast<uint4 *>(dy + p * dy_cs + dy_co + ch);
+    uint4 g = *dp;
+    const uint32_t yy[4] = {yv.x, yv.y, yv.z, yv.w};
+    uint32_t gg[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (!(bf2f((uint16_t)(yy[k] & 0xffffu)) > 0.f)) gg[k] &= 0xffff0000u;
+      if (!(bf2f((uint16_t)(yy[k] >> 16)) > 0.f)) gg[k] &= 0x0000ffffu;
+    }
+    *dp = make_uint4(gg[0], gg[1], gg[2], gg[3]);
+  }
+}
+
 __global__ void maxpool_bwd_kernel(const uint16_t *x, int n, int h, int w, int c, int x_cs, int x_co,
                                    const uint16_t *dy, int dy_cs, int dy_co, uint16_t *dx, int dx_cs, int dx_co,
                                    int accumulate) {
@@ -808,7 +830,12 @@ int unet_conv3x3_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs
 int unet_relu_bwd(const uint16_t *y, int n_pix, int c, int y_cs, int y_co, uint16_t *dy, int dy_cs, int dy_co,
                   void *s) {
   if (!y || !dy || n_pix < 1 || c < 1) return -1;
-  relu_bwd_kernel<<<grid1d((int64_t)n_pix * c), 256, 0, (hipStream_t)s>>>(y, n_pix, c, y_cs, y_co, dy, dy_cs, dy_co);
+  if (c % 8 == 0 && y_cs % 8 == 0 && y_co % 8 == 0 && dy_cs % 8 == 0 && dy_co % 8 == 0)
+    relu_bwd_vec<<<grid1d((int64_t)n_pix * (c / 8)), 256, 0, (hipStream_t)s>>>(y, n_pix, c / 8, y_cs, y_co, dy,
+                                                                                dy_cs, dy_co);
+  else
+    relu_bwd_kernel<<<grid1d((int64_t)n_pix * c), 256, 0, (hipStream_t)s>>>(y, n_pix, c, y_cs, y_co, dy, dy_cs,
+                                                                            dy_co);
   return launched();
 }
 

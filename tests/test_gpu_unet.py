@@ -212,7 +212,12 @@ def test_maxpool_relu_exact(S):
     relu_y = dev_bits(S, x[..., :c])
     g = dev_bits(S, base)
     S.call("unet_relu_bwd", S.ptr(relu_y), n * h * w, c, c, 0, S.ptr(g), c, 0, None)
+    # 12 channels: the element-wise path (the 16-channel call above takes 16-byte vectors)
+    relu_y12 = dev_bits(S, np.ascontiguousarray(x[..., :12]))
+    g12 = dev_bits(S, np.ascontiguousarray(base[..., :12]))
+    S.call("unet_relu_bwd", S.ptr(relu_y12), n * h * w, 12, 12, 0, S.ptr(g12), 12, 0, None)
     sync()
+    assert np.array_equal(host_bf16(S, g12), np.where(x[..., :12] > 0, base[..., :12], 0.0))
     xs = x[..., c:]
     assert np.array_equal(host_bf16(S, y), U.maxpool2(xs))
     route = U.maxpool2_grad(xs, dy)
