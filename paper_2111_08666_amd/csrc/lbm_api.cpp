@@ -85,10 +85,11 @@ bool list_fits(int32_t nx) { return (int64_t)16 * 18 * round_up(nx, 64) * 4 < ((
 // Strategies that run on the compacted layout.
 bool compact_strategy(int s) { return s == LBM_COMPACT || s == LBM_COMPACT_FUSED; }
 
-// The step a context starts with.  Measured on MI355X: the fused kernel is
-// fastest in 2D (single instances and batches); in 3D the compacted layout
-// beats the dense split step (5.1 against 7.7 ms per step at 384^3, porosity
-// 0.42), since it spends nothing on solid nodes.
+// The step a context starts with.  Measured on MI355X: in 2D the dense fused
+// kernel is fastest on single instances (the autotuner may still pick the
+// listed variant on batches); in 3D the compacted layout beats the dense split
+// step (3.7 against 7.7 ms per step at 384^3, porosity 0.42), since it spends
+// nothing on solid nodes.
 int resolve_strategy(const lbm_geometry &g, const lbm_params &p) {
   if (p.strategy != LBM_AUTO) return p.strategy;
   if (g.q == 19) return compact_fits(g) ? LBM_COMPACT : LBM_SPLIT;
