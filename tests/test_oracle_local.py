@@ -254,3 +254,24 @@ def test_viscosity_reading_matches_printed_pairs(paper):
         assert abs(CS2 * (tau - 0.5) - nu) < 1e-15
     (t1, _), (t2, _) = paper["viscosity_from_tau"]["pairs"]
     assert abs((t1 - 0.5) / (t2 - 0.5) - paper["viscosity_from_tau"]["viscosity_ratio"]) < 1e-12
+
+
+def test_mrt_momentum_rate_moves_components_not_the_total():
+    """The MRT component-momentum rate s_j (s_nu, or s_q with mrt_sj_mode = 1)
+    leaves the total momentum change at F but changes how the two
+    components share it: each component's momentum relaxes towards
+    rho^s u at rate s_j."""
+    rng = np.random.default_rng(9)
+    e, _, _ = O.lattice(9)
+    e = e.astype(float)
+    outs = []
+    for sj in (0, 1):
+        P = _params(9, 1)
+        P.mrt_sj_mode = sj
+        fin, F = _random_node(9, np.random.default_rng(9))
+        out = O.collide_node(P, fin, F)
+        j0, j1 = fin @ e, out @ e
+        assert np.abs(j1.sum(axis=0) - (j0.sum(axis=0) + F.sum(axis=0))).max() < 1e-15
+        outs.append(j1)
+    # the per-component momenta differ between the two rates
+    assert np.abs(outs[0] - outs[1]).max() > 1e-6
