@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -402,6 +403,7 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
   if (nb > 0x7fffffff) return fail(nullptr, LBM_EINVAL, "too many blocks");
 
   lbm_batch *b = new lbm_batch();
+  std::unique_ptr<lbm_batch> owner(b);  // freed on every error return below
   b->k = k;
   b->q = g[0].q;
   b->storage = p[0].storage;
@@ -496,8 +498,8 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
   b->compact = compact_strategy(strategy);
   if (strategy == LBM_SPLIT && (b->collision == LBM_MRT && b->q != 9)) strategy = LBM_FUSED;
   const lbm_status ps = apply_plan(b, strategy, p[0].tile_rows ? p[0].tile_rows : 12);
-  if (ps != LBM_OK) { delete b; return ps; }
-  *out = b;
+  if (ps != LBM_OK) return ps;
+  *out = owner.release();
   return LBM_OK;
 }
 
