@@ -95,7 +95,12 @@ typedef struct {
                              over the compacted layout of LBM_COMPACT).
                              The layout is fixed at creation: the compacted
                              strategies cannot be switched to or from the
-                             others (lbm_autotune stays within the layout). */
+                             others (lbm_autotune stays within the layout).
+                             LBM_AUTO: D3Q19 compacted; D2Q9 dense fused
+                             while the two population buffers of all
+                             instances of the context or batch fit in the
+                             256 MB last-level cache, else compacted fused
+                             (every instance must then be LBM_AUTO). */
   int32_t tile_rows;      /* fused D2Q9 tile height: 8, 12 or 16 (0 = 12) */
 } lbm_params;
 

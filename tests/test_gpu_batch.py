@@ -83,3 +83,20 @@ def test_batch64_equals_single_instance_runs(lbm, problems):
         s = lbm.Solver(problems[k], strategy=lbm.FUSED, tile_rows=12)
         s.step(30)
         assert np.array_equal(b.density(k), s.density()), k
+
+
+def test_auto_layout_follows_the_cache_size(lbm, problems):
+    """AUTO keeps the dense layout while both population buffers of a context
+    fit in the 256 MB last-level cache and compacts beyond it: the 64
+    instances (2.4 GB dense) step on the compacted fused kernel, one
+    1024x512 instance (75 MB) on the dense one; an explicit strategy is
+    kept."""
+    b = lbm.BatchSolver(problems)
+    assert "compact" in b.kernel_info()[0]
+    b.close()
+    b = lbm.BatchSolver(problems, strategy=lbm.FUSED)
+    assert "compact" not in b.kernel_info()[0]
+    b.close()
+    s = lbm.Solver(I.large_drainage())
+    assert "compact" not in s.kernel_info()[0]
+    s.close()
