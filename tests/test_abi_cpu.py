@@ -117,3 +117,34 @@ def test_build_entry_resolves_both_builders(monkeypatch):
     monkeypatch.setattr(ob, "build", lambda verbose=False: calls.append("oracle"))
     g.build()
     assert calls == ["hip", "oracle"]
+
+
+def _ws(problems, strategy):
+    keep = []
+    k = len(problems)
+    strategies = strategy if isinstance(strategy, list) else [strategy] * k
+    g = (lbm.Geometry * k)(*[lbm.make_geometry(p, keep) for p in problems])
+    prm = (lbm.Params * k)(*[lbm.make_params(p, strategy=s) for p, s in zip(problems, strategies)])
+    n = lbm.lib().lbm_batch_workspace_bytes(k, g, prm)
+    assert n > 0
+    return n
+
+
+def _open_box(nx, ny):
+    return I.Problem(q=9, mask=np.zeros((ny, nx), np.uint8), rho0=np.full((2, ny, nx), 0.5), periodic=3,
+                     open_x=0, name=f"box{nx}x{ny}")
+
+
+def test_auto_layout_by_population_footprint():
+    """AUTO's D2Q9 layout, read from the workspace it asks for (no device
+    call): dense while both population buffers fit in 256 MB (two buffers of
+    18 * 1024 floats per row: 1820 rows), compacted beyond; a batch is judged
+    on its total, and an explicit strategy anywhere keeps the dense layout."""
+    small, big = _open_box(1024, 1700), _open_box(1024, 1900)
+    assert _ws([small], lbm.AUTO) == _ws([small], lbm.FUSED) != _ws([small], lbm.COMPACT_FUSED)
+    assert _ws([big], lbm.AUTO) == _ws([big], lbm.COMPACT_FUSED) != _ws([big], lbm.FUSED)
+    pair = [small, _open_box(1024, 200)]   # together past 256 MB
+    assert _ws(pair, lbm.AUTO) == _ws(pair, lbm.COMPACT_FUSED) != _ws(pair, lbm.FUSED)
+    assert _ws(pair, [lbm.AUTO, lbm.FUSED]) == _ws(pair, lbm.FUSED)
+    one = [I.large_drainage()]
+    assert _ws(one, lbm.AUTO) == _ws(one, lbm.FUSED)
