@@ -92,6 +92,8 @@ def main():
     ap.add_argument("--eager", action="store_true", help="plain launches instead of graphs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-samples", type=int, default=300)
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="skip the time-to-steady comparison of a cold start and the U-Net warm start")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -181,7 +183,7 @@ def main():
                 "alg_bytes_per_launch": alg_bytes, "bytes_per_fluid_node": bpn}
     mlups = n_nodes * steps / wall / 1e6
     out = {
-        "metric": "MLUPS (2-component step) + % HBM roofline",
+        "metric": "MLUPS (2-component step) + % HBM roofline; time-to-steady w/ vs w/o warm start",
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -203,6 +205,16 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem)
+    if not args.no_warm_start:
+        # after the timed region: held-out instances run to steady state from
+        # the cold start and from the trained network's prediction
+        from paper_2111_08666_amd import bench_warmstart
+        w = bench_warmstart.measure(log=lambda m: print(m, file=sys.stderr, flush=True))
+        out["time_to_steady"] = {
+            "cold_over_warm_steps_median": w["value"], "unit": "x", "workload": w["config"]["workload"],
+            "criterion": "window saturation change < 1e-6 per 1000 steps; cold and warm S within 0.01",
+            "settled_both": w["settled_both"], "agree_within_s_tol": w["agree_within_s_tol"],
+            "steps_total": w["steps_total"], "wall_s": w["wall_s"], "cap": w["config"]["cap"]}
     print(json.dumps(out), flush=True)
 
 

@@ -27,19 +27,16 @@ if ROOT not in sys.path:
 WEIGHTS = os.path.join(ROOT, "paper_2111_08666_amd", "weights", "unet_drainage256.npz")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--first", type=int, default=2000)
-    ap.add_argument("--count", type=int, default=32)
-    ap.add_argument("--cap", type=int, default=300000)
-    ap.add_argument("--s-tol", type=float, default=0.01)
-    a = ap.parse_args()
+def measure(first=2000, count=32, cap=300000, s_tol=0.01, log=None):
+    """Runs the comparison and returns the result record (see the module
+    docstring); `log` receives the progress lines."""
     import torch
     from paper_2111_08666_amd import inputs as I
     from paper_2111_08666_amd import surrogate as S
     from paper_2111_08666_amd import train_surrogate as T
 
-    probs = [p for p in (I.surrogate_instance(k) for k in range(a.first, a.first + a.count)) if p.theta < 90.0]
+    log = log or (lambda m: print(m, file=sys.stderr, flush=True))
+    probs = [p for p in (I.surrogate_instance(k) for k in range(first, first + count)) if p.theta < 90.0]
     net = S.UNet.load(WEIGHTS)
     S.predict(net, probs[:1])  # first call loads the kernels
     torch.cuda.synchronize()
@@ -52,23 +49,23 @@ def main():
         q = I.Problem(**{f: getattr(p, f) for f in p.__dataclass_fields__})
         q.rho0 = S.warm_start_density(p, s)
         warm.append(q)
-    print(f"[warmstart] {len(probs)} instances; inference {infer_s * 1e3:.1f} ms", file=sys.stderr, flush=True)
+    log(f"[warmstart] {len(probs)} instances; inference {infer_s * 1e3:.1f} ms")
     t0 = time.time()
-    cs, cc, cS, _, _ = T.run_to_steady(probs, a.cap, tag=" cold")
+    cs, cc, cS, _, _ = T.run_to_steady(probs, cap, tag=" cold")
     cold_s = time.time() - t0
     t0 = time.time()
-    ws, wc, wS, _, _ = T.run_to_steady(warm, a.cap, tag=" warm")
+    ws, wc, wS, _, _ = T.run_to_steady(warm, cap, tag=" warm")
     warm_s = time.time() - t0
     both = [i for i in range(len(probs)) if cc[i] and wc[i]]
-    agree = [i for i in both if abs(cS[i] - wS[i]) <= a.s_tol]
+    agree = [i for i in both if abs(cS[i] - wS[i]) <= s_tol]
     ratios = [cs[i] / ws[i] for i in agree]
-    out = {
+    return {
         "metric": "time to steady state, cold start / U-Net warm start (steps, median over settled instances)",
         "value": round(float(np.median(ratios)), 3) if ratios else None, "unit": "x",
         "higher_is_better": True,
         "config": {"workload": f"{len(probs)} held-out D2Q9 drainage instances 256x256, contact angle < 90 deg",
-                   "indices": [a.first, a.first + a.count], "cap": a.cap, "check": 1000, "tol": 1e-6,
-                   "s_tol": a.s_tol},
+                   "indices": [first, first + count], "cap": cap, "check": 1000, "tol": 1e-6,
+                   "s_tol": s_tol},
         "settled_both": len(both), "agree_within_s_tol": len(agree),
         "cold_steps": cs, "warm_steps": ws,
         "abs_dS": [round(abs(cS[i] - wS[i]), 5) for i in range(len(probs))],
@@ -76,7 +73,16 @@ def main():
         "wall_s": {"cold_batch": round(cold_s, 2), "warm_batch": round(warm_s, 2),
                    "inference": round(infer_s, 4)},
     }
-    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--first", type=int, default=2000)
+    ap.add_argument("--count", type=int, default=32)
+    ap.add_argument("--cap", type=int, default=300000)
+    ap.add_argument("--s-tol", type=float, default=0.01)
+    a = ap.parse_args()
+    print(json.dumps(measure(a.first, a.count, a.cap, a.s_tol)), flush=True)
 
 
 if __name__ == "__main__":
