@@ -100,3 +100,36 @@ def test_auto_layout_follows_the_cache_size(lbm, problems):
     s = lbm.Solver(I.large_drainage())
     assert "compact" not in s.kernel_info()[0]
     s.close()
+
+
+SMALL = os.path.join(HERE, "golden", "batch64_small_step10k_obs.npz")
+
+
+def test_batch64_small_instances_saturation_and_pc_vs_oracle(lbm, problems):
+    """The eight smallest of the 64 instances after 10 000 steps of the
+    whole batch, advanced as bench.py runs it (autotune, then graph
+    replays), against the FP64 oracle's observables
+    (tests/golden/batch64_small_step10k_obs.npz, written by
+    tests/golden/make_batch_small_obs.py from the oracle alone): window
+    saturation and capillary pressure within 1 %, FP32 storage."""
+    with np.load(SMALL, allow_pickle=False) as z:
+        ref = {k: z[k] for k in z.files}
+    steps = int(ref["steps"])
+    b = lbm.BatchSolver(problems)
+    try:
+        _advance_like_bench(b, steps)
+        obs = b.observables()
+        kernel = b.kernel_info()[0]
+    finally:
+        b.close()
+    rows = []
+    for k in (int(i) for i in ref["index"]):
+        o = obs[k]
+        e_s = abs(o["s_w"] - float(ref[f"s_w{k}"])) / float(ref[f"s_w{k}"])
+        e_sw = abs(o["s_w_weighted"] - float(ref[f"s_w_weighted{k}"])) / float(ref[f"s_w_weighted{k}"])
+        e_pc = abs(o["pc"] - float(ref[f"pc{k}"])) / abs(float(ref[f"pc{k}"]))
+        rows.append((k, e_s, e_sw, e_pc))
+    print(f"[batch64-small] {kernel}, {steps} steps, relative errors (instance: S_w, S_w weighted, P_c): "
+          + "  ".join(f"{k}: {a:.1e} {b_:.1e} {c:.1e}" for k, a, b_, c in rows), flush=True)
+    for k, a, b_, c in rows:
+        assert a <= 0.01 and b_ <= 0.01 and c <= 0.01, (k, a, b_, c)
