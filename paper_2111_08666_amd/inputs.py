@@ -148,6 +148,32 @@ def sphere_medium(nx: int, ny: int, nz: int, r_min: float, r_max: float,
 # ---------------------------------------------------------------------------
 # initial densities
 # ---------------------------------------------------------------------------
+def close_narrow_throats(mask: np.ndarray) -> np.ndarray:
+    """2D mask with its under-resolved pores closed, for long runs that
+    reverse the flow:
+    - every one-node-wide passage (a fluid node with solid on both sides
+      along x or along y), repeated until none is left;
+    - every fluid region not side-connected (4-connectivity) to the region
+      that holds the inlet column (pockets reached only through diagonal
+      links where two discs nearly touch).
+    A diffuse interface (about five nodes wide) cannot resolve such pores;
+    with strong wetting the wetting density in them can grow without bound."""
+    from scipy import ndimage
+    m = mask.astype(bool).copy()
+    while True:
+        pad = np.pad(m, 1, constant_values=False)
+        sx = pad[1:-1, :-2] & pad[1:-1, 2:]
+        sy = pad[:-2, 1:-1] & pad[2:, 1:-1]
+        fill = ~m & (sx | sy)
+        if not fill.any():
+            break
+        m |= fill
+    lab, _ = ndimage.label(~m)  # 4-connectivity
+    keep = np.unique(lab[:, 0][lab[:, 0] > 0])
+    m |= ~np.isin(lab, keep)
+    return m.astype(np.uint8)
+
+
 def reservoir_front(mask: np.ndarray, front_x: int, rho_major: float = 1.0,
                     rho_minor: float = 0.01) -> np.ndarray:
     """Sharp initial front (Sec. 4.2.1): component 1 (non-wetting, invading)

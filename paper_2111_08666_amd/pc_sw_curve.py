@@ -1,8 +1,8 @@
-"""Capillary pressure - water saturation curve of the 1024x512 disc medium:
-primary drainage, then imbibition, by stepwise pressure increments
-(Sec. 4.2, Figs. 10 and 12), on one GPU.
+"""Capillary pressure - water saturation curve of the 1024x512 disc medium
+(its one-node throats closed): primary drainage, then imbibition, by
+stepwise pressure increments (Sec. 4.2, Figs. 10 and 12), on one GPU.
 
-    python -m paper_2111_08666_amd.pc_sw_curve [--steps 200000] [--audit 1000] [--out curve.json]
+    python -m paper_2111_08666_amd.pc_sw_curve [--size 1024x512] [--steps 200000] [--audit 1000] [--out curve.json]
 
 Drainage raises the inlet density of component 1 (the invading oil) over
 ten levels, rho_in1 = 1 + 3 dP with dP from 1e-3 to 2e-2 (geometric), each
@@ -45,19 +45,59 @@ def schedule():
     return s
 
 
+def study_problem(nx=1024, ny=512):
+    """The drainage medium (1024x512: the benchmark's; other sizes: the same
+    recipe, radii 4-20, porosity 0.55, seed 2) with its under-resolved pores
+    closed (inputs.close_narrow_throats).  In the unmodified 1024x512
+    medium the first imbibition increment went non-finite twice: the water
+    density grew to 3.9 in a one-node throat at x = 236, then (throats
+    closed) to 1.4 beside a negative oil density in a 2x2 pocket reached
+    only through diagonal links at x = 625."""
+    if (nx, ny) == (1024, 512):
+        p = I.large_drainage()
+    else:
+        p = I.drainage_2d(nx=nx, ny=ny, r=(4.0, 20.0), porosity=0.55, seed=2, G=3.5,
+                          theta=I.theta_of_xi(-0.4), tau=I.TAU_M10, rho_in1=1.0 + 3 * 1e-3, rho_out2=1.0,
+                          minor=0.027, collision=1, name=f"d2q9_{nx}x{ny}_drainage_M10")
+        p.xi = -0.4
+    p.mask = I.close_narrow_throats(p.mask)
+    p.rho0 = I.reservoir_front(p.mask, p.porous_x0, 1.0, 0.027)
+    p.name += "_throats_closed"
+    return p
+
+
+def _reservoir_fraction(rho, fl, cols, c):
+    """Mean share of component c over the fluid nodes of columns `cols`."""
+    r = rho[:, :, cols]
+    f = fl[:, cols]
+    return float((r[c][f] / (r[0][f] + r[1][f])).mean())
+
+
 def run(steps=200000, audit=1000, problem=None, log=print):
+    """Breakthrough ends a phase: drainage when component 1 makes up a
+    quarter of the outlet reservoir, imbibition when component 2 makes up a
+    quarter of the inlet reservoir (checked at every audit).  Past it the
+    displacing phase reaches the face where Set-3 imposes the other
+    component's density, and a node holding both near density 1 is not
+    stable."""
     if steps % audit:
         raise ValueError("steps must be a multiple of the audit interval")
-    p = problem if problem is not None else I.large_drainage()
+    p = problem if problem is not None else study_problem()
     s = lbm.Solver(p)
+    fl = p.mask == 0
+    res_in = slice(0, p.porous_x0)
+    res_out = slice(p.porous_x1, p.nx)
     rec = []
     t0 = time.time()
+    done = set()
     try:
         kernel = s.kernel_info()[0]
         for k, (phase, rin, rout) in enumerate(schedule()):
+            if phase in done:
+                continue
             s.set_bc(rin, rout)
-            m1, m2, flags, sw_hist = [], [], 0, []
-            for _ in range(steps // audit):
+            m1, m2, flags, sw_hist, through = [], [], 0, [], False
+            for a in range(steps // audit):
                 s.step_graph(audit, 1)
                 o = s.observables(allow_unstable=True)
                 m1.append(o["mass"][0])
@@ -65,6 +105,14 @@ def run(steps=200000, audit=1000, problem=None, log=print):
                 flags |= o["flags"]
                 sw_hist.append(o["s_w_weighted"])
                 if o["flags"] & 1:
+                    break
+                rho = s.density()
+                if phase == "drainage":
+                    through = _reservoir_fraction(rho, fl, res_out, 0) > 0.25
+                else:
+                    through = _reservoir_fraction(rho, fl, res_in, 1) > 0.25
+                if through:
+                    done.add(phase)
                     break
             o = s.observables(allow_unstable=True)
             rho = s.density().astype(np.float64)
@@ -83,11 +131,11 @@ def run(steps=200000, audit=1000, problem=None, log=print):
                  "mass_audit": {"n": len(m1), "mass1_min": min(m1), "mass1_max": max(m1),
                                 "mass2_min": min(m2), "mass2_max": max(m2),
                                 "finite": bool(np.all(np.isfinite(m1 + m2))), "flags": flags},
-                 "column_means": inlet, "non_finite": where}
+                 "column_means": inlet, "non_finite": where, "breakthrough": through}
             rec.append(r)
             log(f"[pc_sw] {k:2d} {phase:10s} rho_in1 {rin:.4f} rho_out2 {rout:.4f}: P_c {r['pc']:+.5f} "
-                f"S_w {r['s_w']:.4f} (weighted {r['s_w_weighted']:.4f}) flags {flags} "
-                f"({time.time() - t0:.0f}s)")
+                f"S_w {r['s_w']:.4f} (weighted {r['s_w_weighted']:.4f}) flags {flags}"
+                f"{' breakthrough' if through else ''} ({time.time() - t0:.0f}s)")
             if flags & 1:
                 break
     finally:
@@ -101,10 +149,12 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=200000)
     ap.add_argument("--audit", type=int, default=1000)
+    ap.add_argument("--size", default="1024x512", help="medium size NXxNY (1024x512: the benchmark's)")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
-    res = run(a.steps, a.audit, log=log)
+    nx, ny = (int(v) for v in a.size.split("x"))
+    res = run(a.steps, a.audit, problem=study_problem(nx, ny), log=log)
     print(json.dumps(res), flush=True)
     if a.out:
         with open(a.out, "w") as f:

@@ -42,3 +42,25 @@ def test_batch_instances_are_uneven_and_in_range():
     assert len(sizes) > 1 and all(p.nx % 64 == 0 and p.ny == p.nx // 2 for p in b)
     for p in b:
         assert 30 <= p.theta <= 150 and 1e-4 <= p.dp <= 5e-3
+
+
+def test_close_narrow_throats():
+    """One-node passages along x or y are filled until none is left; wider
+    passages stay open, and no fluid node is left between two solid ones."""
+    m = np.zeros((9, 12), np.uint8)
+    m[1, :] = 1
+    m[3, :] = 1          # row 2: a one-node channel along x
+    m[7, :] = 1          # rows 4-6: a three-node channel
+    m[4:7, 8] = 1
+    m[4:7, 10] = 1       # column 9 of rows 4-6: a one-node channel along y
+    out = I.close_narrow_throats(m)
+    assert np.all(out >= m)
+    assert out[2].all() and out[4:7, 9].all()
+    assert not out[4:7, :8].any() and not out[0].any() and not out[8].any()
+    pad = np.pad(out.astype(bool), 1)
+    fluid = ~out.astype(bool)
+    assert not np.any(fluid & ((pad[1:-1, :-2] & pad[1:-1, 2:]) | (pad[:-2, 1:-1] & pad[2:, 1:-1])))
+    assert np.array_equal(I.close_narrow_throats(out), out)
+    p = I.large_drainage()
+    closed = I.close_narrow_throats(p.mask)
+    assert np.all(closed >= p.mask) and 0 < int(closed.sum() - p.mask.sum()) < 0.01 * p.n_fluid
