@@ -235,27 +235,50 @@ __global__ __launch_bounds__(256) void conv3x3_lds(GemmArgs a) {
     pr[t] = q / w;
     pc[t] = q - pr[t] * w;
   }
+  // Software pipeline over the 16-channel groups: the next group's global
+  // loads go to registers before this group's taps run, and are parked in
+  // LDS after the barrier that ends them.  Each thread's staged elements
+  // keep their place from group to group; only the channel offset moves.
+  constexpr int KA = (conv_halo_pix(BP) * 2 + 255) / 256, KB = (BC * 9 * 2 + 255) / 256;
+  const int nA = rows * rw * 2;
+  constexpr uint32_t kNone = 0xffffffffu;  // element outside the image or the weights
+  uint32_t offA[KA], offB[KB];              // element offsets (host keeps them below 2^32 - 1)
+#pragma unroll
+  for (int i = 0; i < KA; ++i) {
+    const int e = tid + 256 * i, q = e >> 1, hf = e & 1;
+    const int ry = q / rw, rx = q - ry * rw;
+    const int y = y0 - 1 + ry, x = rx - 1;
+    offA[i] = (e < nA && y >= 0 && y < h && x >= 0 && x < w)
+                  ? (uint32_t)((img_base + (int64_t)y * w + x) * a.x_cs + a.x_co + 8 * hf)
+                  : kNone;
+  }
+#pragma unroll
+  for (int i = 0; i < KB; ++i) {
+    const int e = tid + 256 * i, co = e / 18, rem = e - co * 18;
+    const int tap = rem >> 1, hf = rem & 1;
+    offB[i] = (e < BC * 9 * 2 && col0 + co < a.nout) ? (uint32_t)(((int64_t)(col0 + co) * 9 + tap) * a.kc + 8 * hf)
+                                                     : kNone;
+  }
+  uint4 ra[KA], rb[KB];
+  auto fetch = [&](int ch) {
+#pragma unroll
+    for (int i = 0; i < KA; ++i)
+      ra[i] = offA[i] != kNone ? *reinterpret_cast<const uint4 *>(a.x + offA[i] + ch) : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < KB; ++i)
+      rb[i] = offB[i] != kNone ? *reinterpret_cast<const uint4 *>(a.wgt + offB[i] + ch) : make_uint4(0, 0, 0, 0);
+  };
   const int groups = a.kc / 16;
+  fetch(0);
   for (int g = 0; g < groups; ++g) {
-    const int ch = g * 16;
-    for (int e = tid; e < rows * rw * 2; e += 256) {
-      const int q = e >> 1, hf = e & 1;
-      const int ry = q / rw, rx = q - ry * rw;
-      const int y = y0 - 1 + ry, x = rx - 1;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (y >= 0 && y < h && x >= 0 && x < w)
-        v = *reinterpret_cast<const uint4 *>(a.x + (img_base + (int64_t)y * w + x) * a.x_cs + a.x_co + ch + 8 * hf);
-      sA[e] = v;
-    }
-    for (int e = tid; e < BC * 9 * 2; e += 256) {
-      const int co = e / 18, rem = e - co * 18;
-      const int tap = rem >> 1, hf = rem & 1;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (col0 + co < a.nout)
-        v = *reinterpret_cast<const uint4 *>(a.wgt + ((int64_t)(col0 + co) * 9 + tap) * a.kc + ch + 8 * hf);
-      sB[e] = v;
-    }
+#pragma unroll
+    for (int i = 0; i < KA; ++i)
+      if (tid + 256 * i < nA) sA[tid + 256 * i] = ra[i];
+#pragma unroll
+    for (int i = 0; i < KB; ++i)
+      if (tid + 256 * i < BC * 9 * 2) sB[tid + 256 * i] = rb[i];
     __syncthreads();
+    if (g + 1 < groups) fetch((g + 1) * 16);
 #pragma unroll
     for (int tap = 0; tap < 9; ++tap) {
       const int dy = tap / 3, dx = tap % 3;
@@ -293,7 +316,11 @@ __global__ __launch_bounds__(256) void conv3x3_lds(GemmArgs a) {
 
 // Can the LDS-staged kernel with block of bp pixels run this convolution?
 static bool conv_lds_fits(const GemmArgs &a, int bp) {
-  return a.kc % 16 == 0 && a.w >= 16 && a.w <= 256 && bp % a.w == 0 && ((int64_t)a.h * a.w) % bp == 0;
+  // element offsets of the input and the weights must fit 32 bits
+  const bool small = (int64_t)a.n * a.h * a.w * a.x_cs < ((int64_t)1 << 32) - 1 &&
+                     (int64_t)a.nout * 9 * a.kc < ((int64_t)1 << 32) - 1;
+  return small && a.kc % 16 == 0 && a.w >= 16 && a.w <= 256 && bp % a.w == 0 &&
+         ((int64_t)a.h * a.w) % bp == 0;
 }
 
 // Launch with the wave tile chosen by the output channel count.
