@@ -417,14 +417,24 @@ __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
       const int eo = stage_b ? e - 64 * MT : e;
       const int cg = eo >> 4, pb = eo & 15;
       uint4 v[8], t[8];
+      // image, row and column of the first of the 8 consecutive pixels; the
+      // others follow by increments (wrapping at row and image ends)
+      const int64_t pfirst = pc + pb * 8;
+      int pn = (int)(pfirst / ((int64_t)a.h * a.w));
+      const int rr0 = (int)(pfirst - (int64_t)pn * a.h * a.w);
+      int py = rr0 / a.w, px = rr0 - py * a.w;
 #pragma unroll
       for (int r = 0; r < 8; ++r) {
-        const int64_t p = pc + pb * 8 + r;
+        const int64_t p = pfirst + r;
+        if (r > 0 && ++px == a.w) {
+          px = 0;
+          if (++py == a.h) {
+            py = 0;
+            ++pn;
+          }
+        }
         v[r] = make_uint4(0, 0, 0, 0);
         if (p >= p_end) continue;
-        const int pn = (int)(p / ((int64_t)a.h * a.w));
-        const int rr = (int)(p - (int64_t)pn * a.h * a.w);
-        const int py = rr / a.w, px = rr - py * a.w;
         if (!stage_b) {
           const int m = m0 + cg * 8;
           if (m < a.cout) {
