@@ -410,16 +410,22 @@ __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
   const bool bias_blk = a.bpartial && nblk == 0 && tid < 32 * MT;
   float bacc = 0.f;
   const int64_t p_end = p_begin + kWgradPix < P ? p_begin + kWgradPix : P;
-  for (int64_t pc = p_begin; pc < p_end; pc += kStagePix) {
-    // staging: 8-pixel x 8-channel blocks, 64 MT of A then 64 NT of B
-    for (int e = tid; e < 64 * (MT + NT); e += 256) {
+  // staging: 8-pixel x 8-channel blocks, 64 MT of A then 64 NT of B; a
+  // thread owns entries tid and tid + 256.  The next stage's loads go to
+  // registers before this stage's products run; the transpose and the LDS
+  // stores follow the barrier that ends them.
+  constexpr int kEntries = 64 * (MT + NT), NE = (kEntries + 255) / 256;
+  uint4 v[NE][8];
+  auto load_stage = [&](int64_t pcs) {
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+      const int e = tid + 256 * j;
       const bool stage_b = e >= 64 * MT;
       const int eo = stage_b ? e - 64 * MT : e;
       const int cg = eo >> 4, pb = eo & 15;
-      uint4 v[8], t[8];
       // image, row and column of the first of the 8 consecutive pixels; the
       // others follow by increments (wrapping at row and image ends)
-      const int64_t pfirst = pc + pb * 8;
+      const int64_t pfirst = pcs + pb * 8;
       int pn = (int)(pfirst / ((int64_t)a.h * a.w));
       const int rr0 = (int)(pfirst - (int64_t)pn * a.h * a.w);
       int py = rr0 / a.w, px = rr0 - py * a.w;
@@ -433,8 +439,8 @@ __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
             ++pn;
           }
         }
-        v[r] = make_uint4(0, 0, 0, 0);
-        if (p >= p_end) continue;
+        v[j][r] = make_uint4(0, 0, 0, 0);
+        if (e >= kEntries || p >= p_end) continue;
         if (!stage_b) {
           const int m = m0 + cg * 8;
           if (m < a.cout) {
@@ -445,7 +451,7 @@ __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
               const int H2 = 2 * a.h, W2 = 2 * a.w;
               q = (int64_t)pn * H2 * W2 + (int64_t)(2 * py + (tapz >> 1)) * W2 + 2 * px + (tapz & 1);
             }
-            v[r] = *reinterpret_cast<const uint4 *>(a.dy + q * a.dy_cs + a.dy_co + m);
+            v[j][r] = *reinterpret_cast<const uint4 *>(a.dy + q * a.dy_cs + a.dy_co + m);
           }
         } else {
           const int nn = n0 + cg * 8;
@@ -454,20 +460,33 @@ __global__ __launch_bounds__(256) void igemm_wgrad(WgradArgs a) {
               const int tap = nn / a.cin, ci = nn - tap * a.cin;
               const int yy = py + tap / 3 - 1, xx = px + tap % 3 - 1;
               if (yy >= 0 && yy < a.h && xx >= 0 && xx < a.w)
-                v[r] = *reinterpret_cast<const uint4 *>(
+                v[j][r] = *reinterpret_cast<const uint4 *>(
                     a.x + ((int64_t)pn * a.h * a.w + (int64_t)yy * a.w + xx) * a.x_cs + a.x_co + ci);
             } else {
-              v[r] = *reinterpret_cast<const uint4 *>(a.x + p * a.x_cs + a.x_co + nn);
+              v[j][r] = *reinterpret_cast<const uint4 *>(a.x + p * a.x_cs + a.x_co + nn);
             }
           }
         }
       }
-      transpose8x8(v, t);
+    }
+  };
+  if (p_begin < p_end) load_stage(p_begin);
+  for (int64_t pc = p_begin; pc < p_end; pc += kStagePix) {
+#pragma unroll
+    for (int j = 0; j < NE; ++j) {
+      const int e = tid + 256 * j;
+      if (e >= kEntries) continue;
+      const bool stage_b = e >= 64 * MT;
+      const int eo = stage_b ? e - 64 * MT : e;
+      const int cg = eo >> 4, pb = eo & 15;
+      uint4 t[8];
+      transpose8x8(v[j], t);
       uint16_t(*dst)[kStageLd] = stage_b ? sB : sA;
 #pragma unroll
       for (int c = 0; c < 8; ++c) *reinterpret_cast<uint4 *>(&dst[cg * 8 + c][pb * 8]) = t[c];
     }
     __syncthreads();
+    if (pc + kStagePix < p_end) load_stage(pc + kStagePix);
     if (bias_blk) {
 #pragma unroll
       for (int q = 0; q < kStagePix; q += 8) {
