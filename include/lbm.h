@@ -17,7 +17,8 @@
  *  - All GPU work is enqueued on the caller's HIP stream (hipStream_t passed
  *    as void*; NULL = the default stream), in stream order.  Only
  *    lbm_observables, lbm_get_density with a host destination, lbm_save,
- *    lbm_load and the create calls synchronise that stream.
+ *    lbm_load, lbm_set_bc, the autotune calls and the create calls
+ *    synchronise that stream.
  *  - Every call returns an lbm_status; on failure lbm_last_error() returns a
  *    message.  Invalid arguments are rejected before any device work.
  *  - A context is not thread-safe; distinct contexts are independent.
@@ -129,7 +130,9 @@ typedef struct {
 typedef struct lbm_ctx lbm_ctx;
 typedef struct lbm_batch lbm_batch;
 
-/* Size in bytes of the device workspace lbm_create needs (0 if invalid). */
+/* Size in bytes of the device workspace lbm_create needs (0 if invalid).
+ * It depends on the layout the strategy implies (dense, or compacted to the
+ * fluid nodes; see LBM_AUTO), so pass the same params to lbm_create. */
 size_t lbm_workspace_bytes(const lbm_geometry *geom, const lbm_params *params);
 
 /* Create a solver.  rho_init: host, 2*nx*ny*nz doubles (component 1 then 2;
@@ -143,14 +146,22 @@ lbm_status lbm_create(const lbm_geometry *geom, const lbm_params *params,
                       const double *rho_init, void *workspace, size_t ws_bytes,
                       void *hip_stream, lbm_ctx **out);
 
-/* Change the Zou-He densities (a pressure increment, Sec. 4.2); stream-ordered. */
+/* Change the Zou-He densities rho_in of component 1 at x = 0 and rho_out
+ * of component 2 at x = nx - 1 (Eqs. 22-25 and 18-21; a pressure increment
+ * of Sec. 4.2).  Both must be finite and > 0.  Takes effect from the next
+ * step, captured graphs included; synchronises the stream. */
 lbm_status lbm_set_bc(lbm_ctx *ctx, double rho_in1, double rho_out2);
 
-/* Enqueue n time steps (one fused kernel launch each).  Asynchronous. */
+/* Enqueue n time steps of Sec. 2 (streaming with bounce-back, Set-3 faces,
+ * densities, solid densities of Eq. 17, forces of Eq. 13, collision of
+ * Eqs. 1-11): one kernel launch per step for the fused strategies, three for
+ * the split and compacted ones.  Asynchronous.  LBM_EUNSTABLE once
+ * lbm_observables has seen a non-finite density. */
 lbm_status lbm_step(lbm_ctx *ctx, int64_t n);
 
-/* Capture n steps into a HIP graph once and replay it `reps` times; for
- * launch-bound small domains.  n must be even.  Asynchronous. */
+/* Capture n steps into a HIP graph once (again when n changes) and replay
+ * it `reps` times; for launch-bound small domains.  n must be even; the
+ * stream must not be the default stream (LBM_ESTATE).  Asynchronous. */
 lbm_status lbm_step_graph(lbm_ctx *ctx, int64_t n, int64_t reps);
 
 /* Observables at the current time; synchronises the stream.  Returns
@@ -168,7 +179,10 @@ lbm_status lbm_get_density(lbm_ctx *ctx, float *dst, int32_t dst_is_device);
 lbm_status lbm_save(lbm_ctx *ctx, void *host_blob, size_t *bytes);
 lbm_status lbm_load(lbm_ctx *ctx, const void *host_blob, size_t bytes);
 
+/* Steps taken since creation (as restored by lbm_load); -1 for NULL. */
 int64_t lbm_get_step(const lbm_ctx *ctx);
+/* Free the context (host memory only; the workspace stays the caller's).
+ * Call it after the stream's pending work is done or abandoned. */
 lbm_status lbm_destroy(lbm_ctx *ctx);
 
 /* Last error message of ctx (or of the calling thread's last failed create
@@ -176,13 +190,15 @@ lbm_status lbm_destroy(lbm_ctx *ctx);
 const char *lbm_last_error(const lbm_ctx *ctx);
 
 /* Name, grid size (blocks) and block size of the step kernel the context
- * launches (the collide kernel for the split strategy); for profiling. */
+ * launches (the collide kernel for the split and compacted strategies); for
+ * profiling. */
 lbm_status lbm_kernel_info(const lbm_ctx *ctx, char *name, size_t name_len,
                            int64_t *grid_blocks, int32_t *block_threads);
 
-/* Time every step variant that can run this context (fused with each tile
- * height, split) for `steps` steps each (even, >= 2) with HIP events and keep
- * the fastest.  The timed steps are ordinary steps: the state advances by
+/* Time every step variant the context's layout allows (dense: fused and
+ * listed at each tile height, split; compacted: the compacted step, and in
+ * 2D the compacted fused step at each tile height) for `steps` steps each
+ * (even, >= 2) with HIP events and keep the fastest.  The timed steps are ordinary steps: the state advances by
  * (number of variants) x steps.  report (optional) receives one line per
  * variant with its milliseconds per step.  Synchronises the stream. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int64_t steps, char *report, size_t report_len);
@@ -190,7 +206,10 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int64_t steps, char *report, size_t report
 /* ---- batches: many instances of uneven size advanced together ----------
  * One launch per step covers every instance through a flat table of
  * (instance, tile) blocks; steps can be captured in one HIP graph.  All
- * instances must share q and storage.  rho_inits[k] as for lbm_create. */
+ * instances must share q, storage, collision, math and layout (with
+ * LBM_AUTO the batch's total decides the layout).  rho_inits[k] as for
+ * lbm_create; each instance has its own geometry, parameters and
+ * observables.  The calls mirror the single-context ones. */
 size_t lbm_batch_workspace_bytes(int32_t k, const lbm_geometry *geoms, const lbm_params *params);
 lbm_status lbm_batch_create(int32_t k, const lbm_geometry *geoms, const lbm_params *params,
                             const double *const *rho_inits, void *workspace,
@@ -204,8 +223,8 @@ lbm_status lbm_batch_destroy(lbm_batch *b);
 const char *lbm_batch_last_error(const lbm_batch *b);
 /* lbm_kernel_info and lbm_autotune for a batch: one variant is chosen for
  * the whole batch (every instance advances by variants x steps).  With the
- * split strategy each instance is launched on its own; grid_blocks is then
- * the largest instance's grid. */
+ * split and compacted strategies each instance is launched on its own;
+ * grid_blocks is then the largest instance's grid. */
 lbm_status lbm_batch_kernel_info(const lbm_batch *b, char *name, size_t name_len,
                                  int64_t *grid_blocks, int32_t *block_threads);
 lbm_status lbm_batch_autotune(lbm_batch *b, int64_t steps, char *report, size_t report_len);
