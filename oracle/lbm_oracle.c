@@ -20,8 +20,11 @@
  * the Laplace law, the flat-interface dissolved density, contact-angle
  * symmetry and the paper's calibration pairs, exact mass bookkeeping.
  * The outlet rule of Eq. 26 (frozen reading), the boundary-pressure window
- * and the saturation count have no printed value that discriminates them:
- * parity unpinned for those three definitions.
+ * and the saturations are pinned by constructed states with closed-form
+ * answers.  The pressure form of Eq. 14 (READING below: the pair sum over
+ * ordered pairs) has no printed value and no experiment here that tells the
+ * readings apart (coexisting bulks relax to mirror-image compositions):
+ * parity unpinned for that form.
  */
 #include "lbm_oracle.h"
 

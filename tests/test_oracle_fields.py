@@ -236,3 +236,56 @@ def test_invalid_inputs_are_rejected():
         O.OracleSim(params=O.make_params(nx=6, ny=6, periodic=1), mask=mask, rho0=rho0)
     with pytest.raises(ValueError, match="xi"):
         O.OracleSim(params=O.make_params(nx=6, ny=6, periodic=3, xi=1.0), mask=mask, rho0=rho0)
+
+
+def test_saturations_of_a_two_region_state_are_area_fractions():
+    """Window saturations (Sec. 4.2; count and density-weighted readings)
+    against closed forms.  A walled channel, periodic in x, holds water
+    (majority 1, minority m) at k <= x < x1 + 2 and oil elsewhere; the
+    window [x0, x1) contains only the front at k.  Streaming the initial
+    rest equilibria permutes populations, the front nodes keep their
+    majority, and both window edges see the same state on either side, so
+    at t = 0:
+      count    = (x1 - k) / (x1 - x0)
+      weighted = ((x1 - k) + (k - x0) m) / ((x1 - x0)(1 + m))
+    A window bound off by one, or the comparison reversed, fails this."""
+    nx, ny, m = 40, 9, 0.03
+    x0, x1, k = 5, 35, 17
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[0] = mask[-1] = 1
+    rho0 = np.zeros((2, ny, nx))
+    rho0[0], rho0[1] = 1.0, m
+    rho0[0, :, k:x1 + 2], rho0[1, :, k:x1 + 2] = m, 1.0
+    rho0[:, mask.astype(bool)] = 0
+    P = O.make_params(q=9, nx=nx, ny=ny, periodic=1, open_x=0, G=3.5, porous_x0=x0, porous_x1=x1)
+    o = O.OracleSim(params=P, mask=mask, rho0=rho0).observables()
+    nyf = ny - 2
+    assert o["n_window"] == (x1 - x0) * nyf
+    assert o["s_w"] == (x1 - k) / (x1 - x0)
+    want = ((x1 - k) + (k - x0) * m) / ((x1 - x0) * (1 + m))
+    assert abs(o["s_w_weighted"] - want) < 1e-14
+
+
+def test_face_pressure_window_excludes_nodes_within_two_of_solid():
+    """Face pressures (Eq. 14, READING: face nodes at least 3 lattice units
+    from every solid).  Walls at y = 0 and y = ny - 1; component 2 has
+    density m_near in the rows next to the walls and m_far elsewhere.  Rows
+    3 .. ny - 4 of the inlet face pull only from far rows, so they hold
+    exactly (rho_in, m_far); rows 1-2 and ny-3..ny-2 do not.  P_in is their
+    Eq. 14 pressure and n_in counts them: a window of 2 lu (or none) would
+    average in the mixed rows."""
+    nx, ny, rin, m_far, m_near, G = 12, 14, 1.02, 0.03, 0.2, 3.5
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[0] = mask[-1] = 1
+    rho0 = np.zeros((2, ny, nx))
+    rho0[0] = rin
+    rho0[1] = m_far
+    rho0[1, 1], rho0[1, ny - 2] = m_near, m_near
+    rho0[:, mask.astype(bool)] = 0
+    P = O.make_params(q=9, nx=nx, ny=ny, periodic=0, open_x=1, G=G, rho_in1=rin, rho_out2=m_far)
+    o = O.OracleSim(params=P, mask=mask, rho0=rho0).observables()
+    assert o["n_in"] == ny - 6 and o["n_out"] == ny - 6
+    want = CS2 * (rin + m_far) + CS2 * G * rin * m_far
+    assert abs(o["p_in"] - want) < 1e-15
+    assert abs(o["p_out"] - want) < 1e-15 and abs(o["pc"]) < 1e-15
+
