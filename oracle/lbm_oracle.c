@@ -21,10 +21,9 @@
  * symmetry and the paper's calibration pairs, exact mass bookkeeping.
  * The outlet rule of Eq. 26 (frozen reading), the boundary-pressure window
  * and the saturations are pinned by constructed states with closed-form
- * answers.  The pressure form of Eq. 14 (READING below: the pair sum over
- * ordered pairs) has no printed value and no experiment here that tells the
- * readings apart (coexisting bulks relax to mirror-image compositions):
- * parity unpinned for that form.
+ * answers; the pressure form of Eq. 14 (READING below: the pair sum over
+ * ordered pairs) by the hydrostatic balance of a mixture at rest under a
+ * body force.
  */
 #include "lbm_oracle.h"
 
