@@ -30,6 +30,7 @@ template <typename R> struct Vec2 { R x, y; };
 typedef __attribute__((address_space(1))) float gf;
 typedef __attribute__((address_space(1))) const float gcf;
 typedef __attribute__((address_space(1))) const uint32_t gcu32;
+typedef __attribute__((address_space(1))) uint32_t gu32;
 typedef __attribute__((address_space(1))) uint16_t gu16;
 typedef __attribute__((address_space(1))) const uint16_t gcu16;
 
@@ -48,14 +49,21 @@ __device__ __forceinline__ void stg(gf *base, uint32_t boff, float v) { *(gf *)(
 // population access by storage kind; a node is addressed by its row block
 // offset `row` (y * ystride + z * zstride, in floats) and its x
 // FP32:  row block = [s][i][pitch] floats
-// BF16:  row block = [s][pitch] float densities, then [s][i-1][pitch] bf16
-//        deviations d_i = f*_i - w_i rho (i >= 1); f*_0 = rho - sum_i f*_i.
+// BF16:  row block = [pitch] (rho1, rho2) float pairs, then [i-1][pitch]
+//        32-bit words holding both components' bf16 deviations
+//        d_i = f*_i - w_i rho (i >= 1; component 1 in the low half);
+//        f*_0 = rho - sum_i f*_i.  A pull of link i reads one float pair
+//        and one word for both components.
 // ---------------------------------------------------------------------------
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const v2f gcv2f;
+typedef __attribute__((address_space(1))) v2f gv2f;
+
 template <int Q>
 __device__ __forceinline__ float bf16_pop(gcf *__restrict__ b, int pitch, int s, int i, int64_t row, int x,
                                           float r) {
   gcu16 *dv = (gcu16 *)b;
-  const int64_t k = 2 * row + (int64_t)(4 + s * (Q - 1) + i - 1) * pitch + x;
+  const int64_t k = 2 * (row + (int64_t)(1 + i) * pitch + x) + s;
   return __builtin_fmaf((float)Lat<Q>::w[i], r, bf16_to_f32(dv[k]));
 }
 
@@ -64,7 +72,7 @@ __device__ __forceinline__ float pop_get(gcf *__restrict__ b, int pitch, int s, 
   if constexpr (ST == 0) {
     return b[row + (int64_t)(s * Q + i) * pitch + x];
   } else {
-    const float r = b[row + (int64_t)s * pitch + x];
+    const float r = b[row + 2 * (int64_t)x + s];
     if (i == 0) {
       // the rest population closes the node's mass: rho - sum of the others,
       // reconstructed exactly as a pull elsewhere reconstructs them
@@ -74,6 +82,39 @@ __device__ __forceinline__ float pop_get(gcf *__restrict__ b, int pitch, int s, 
       return r - sum;
     }
     return bf16_pop<Q>(b, pitch, s, i, row, x, r);
+  }
+}
+
+// Both components' link i of one node (the same values as two pop_get
+// calls, from one float-pair and one word load per link in BF16).
+template <int Q, int ST>
+__device__ __forceinline__ void pop_get2(gcf *__restrict__ b, int pitch, int i, int64_t row, int x, float &f0,
+                                         float &f1) {
+  if constexpr (ST == 0) {
+    f0 = pop_get<Q, 0>(b, pitch, 0, i, row, x);
+    f1 = pop_get<Q, 0>(b, pitch, 1, i, row, x);
+  } else {
+    const v2f r = *(gcv2f *)(b + row + 2 * (int64_t)x);
+    auto link = [&](int j, float &g0, float &g1) {
+      const uint32_t u = *(gcu32 *)(b + row + (int64_t)(1 + j) * pitch + x);
+      const float w = (float)Lat<Q>::w[j];
+      g0 = __builtin_fmaf(w, r.x, bf16_to_f32((uint16_t)(u & 0xffffu)));
+      g1 = __builtin_fmaf(w, r.y, bf16_to_f32((uint16_t)(u >> 16)));
+    };
+    if (i == 0) {
+      float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+      for (int j = 1; j < Q; ++j) {
+        float g0, g1;
+        link(j, g0, g1);
+        s0 += g0;
+        s1 += g1;
+      }
+      f0 = r.x - s0;
+      f1 = r.y - s1;
+    } else {
+      link(i, f0, f1);
+    }
   }
 }
 
@@ -91,14 +132,12 @@ __device__ __forceinline__ void pop_store(gf *__restrict__ b, int pitch, int64_t
     }
   } else {
     // collision conserves each component's node mass, so rho is stored as is
-    b[row + x] = rho1;
-    b[row + pitch + x] = rho2;
-    gu16 *dv = (gu16 *)b;
+    *(gv2f *)(b + row + 2 * (int64_t)x) = v2f{rho1, rho2};
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const float w = (float)Lat<Q>::w[i];
-      dv[2 * row + (int64_t)(4 + i - 1) * pitch + x] = f32_to_bf16(f0[i] - w * rho1);
-      dv[2 * row + (int64_t)(4 + Q - 1 + i - 1) * pitch + x] = f32_to_bf16(f1[i] - w * rho2);
+      const uint32_t u = (uint32_t)f32_to_bf16(f0[i] - w * rho1) | ((uint32_t)f32_to_bf16(f1[i] - w * rho2) << 16);
+      *(gu32 *)(b + row + (int64_t)(1 + i) * pitch + x) = u;
     }
   }
 }
@@ -181,8 +220,7 @@ __device__ __forceinline__ void pull_row(const InstDev &d, gcf *__restrict__ fin
       const int64_t r = bb ? src[1][1] : row;
       const int x = bb ? xs[1] : sx;
       const int pi = bb ? L::opp[i] : i;
-      f0[i] = pop_get<Q, 1>(fin, pitch, 0, pi, r, x);
-      f1[i] = pop_get<Q, 1>(fin, pitch, 1, pi, r, x);
+      pop_get2<Q, 1>(fin, pitch, pi, r, x, f0[i], f1[i]);
     }
   }
 }
@@ -294,8 +332,7 @@ __device__ __forceinline__ void cpull9(const InstDev &d, gcf *__restrict__ fin, 
       f0[i] = ldg(fin, bo);
       f1[i] = ldg(fin + (int64_t)9 * cp, bo);
     } else {
-      f0[i] = pop_get<9, ST>(fin, cp, 0, pi, 0, (int)sc);
-      f1[i] = pop_get<9, ST>(fin, cp, 1, pi, 0, (int)sc);
+      pop_get2<9, ST>(fin, cp, pi, 0, (int)sc, f0[i], f1[i]);
     }
   }
 }
@@ -1138,8 +1175,7 @@ __device__ __forceinline__ void cgather(const InstDev &d, gcf *__restrict__ fin,
       f0[i] = ldg(fin, bo);
       f1[i] = ldg(fin + (int64_t)Q * cp, bo);
     } else {
-      f0[i] = pop_get<Q, ST>(fin, cp, 0, pi, 0, (int)sc);
-      f1[i] = pop_get<Q, ST>(fin, cp, 1, pi, 0, (int)sc);
+      pop_get2<Q, ST>(fin, cp, pi, 0, (int)sc, f0[i], f1[i]);
     }
   }
   if (info & (kInlet | kOutlet)) {
