@@ -102,7 +102,8 @@ Layout make_layout(const lbm_geometry &g, const lbm_params &p) {
   Layout L{};
   L.pitch = (int32_t)round_up(g.nx, 64);
   L.n_nodes = (int64_t)g.nx * g.ny * g.nz;
-  // row block per (y, z): FP32 2Q populations; BF16 2 densities + 2(Q-1) bf16 deviations
+  // row block per (y, z): FP32 2Q populations; BF16 a (rho1, rho2) pair per node + Q-1 words
+  // of both components' bf16 deviations (Q + 1 floats per node either way for BF16)
   L.ystride = (int64_t)(p.storage == LBM_STORE_F32 ? 2 * g.q : g.q + 1) * L.pitch;
   L.zstride = L.ystride * g.ny;
   L.buf_bytes = align_up((size_t)L.zstride * g.nz * sizeof(float));
@@ -116,7 +117,7 @@ Layout make_layout(const lbm_geometry &g, const lbm_params &p) {
     L.nf = nf;
     L.nsolid = L.n_nodes - nf;
     L.cpitch = (int32_t)round_up(std::max<int64_t>(nf, 1), 64);
-    // FP32: 2Q planes; BF16: 2 density planes (float) + 2(Q-1) deviation planes (bf16)
+    // FP32: 2Q planes; BF16: a plane of (rho1, rho2) pairs + Q-1 planes of deviation words
     L.buf_bytes = align_up((size_t)(p.storage == LBM_STORE_F32 ? 2 * g.q : g.q + 1) * L.cpitch * sizeof(float));
     L.cword_bytes = align_up((size_t)g.ny * g.nz * (L.pitch / 64) * sizeof(RowWord));
     L.ckey_bytes = align_up((size_t)std::max<int64_t>(nf, 1) * sizeof(uint32_t));

@@ -31,7 +31,6 @@ typedef __attribute__((address_space(1))) float gf;
 typedef __attribute__((address_space(1))) const float gcf;
 typedef __attribute__((address_space(1))) const uint32_t gcu32;
 typedef __attribute__((address_space(1))) uint32_t gu32;
-typedef __attribute__((address_space(1))) uint16_t gu16;
 typedef __attribute__((address_space(1))) const uint16_t gcu16;
 
 __device__ __forceinline__ gcf *G(const float *p) { return (gcf *)p; }
