@@ -148,3 +148,36 @@ def test_auto_layout_by_population_footprint():
     assert _ws(pair, [lbm.AUTO, lbm.FUSED]) == _ws(pair, lbm.FUSED)
     one = [I.large_drainage()]
     assert _ws(one, lbm.AUTO) == _ws(one, lbm.FUSED)
+
+
+def _create_raw(q, nx, ny, nz, solid, strategy=lbm.AUTO):
+    """lbm_create on a bare geometry (all fluid, closed) with default
+    parameters; returns (status, message).  Validation fails before any
+    device call, so no workspace is passed."""
+    L = lbm.lib()
+    g = lbm.Geometry()
+    g.q, g.nx, g.ny, g.nz = q, nx, ny, nz
+    g.solid = solid.ctypes.data
+    p = lbm.make_params(I.Problem(q=q, mask=np.zeros((1, 1), np.uint8), rho0=np.ones((2, 1, 1)), open_x=0),
+                        strategy=strategy)
+    h = C.c_void_p()
+    rho = np.ones(2, np.float64)
+    st = L.lbm_create(C.byref(g), C.byref(p), rho.ctypes.data, None, 0, None, C.byref(h))
+    return st, L.lbm_last_error(None).decode(), L.lbm_workspace_bytes(C.byref(g), C.byref(p))
+
+
+def test_size_limits_are_rejected_with_their_reason():
+    """The limits the kernels' index arithmetic needs, checked on the host
+    before anything is read past the sizes: more than 2^31 nodes; a
+    compacted 3D layout whose link planes pass 32-bit byte offsets (more
+    than about 56 M fluid nodes); a listed fused step wider than its 32-bit
+    store offsets allow."""
+    one = np.zeros(1, np.uint8)   # never read: the size check comes first
+    st, err, ws = _create_raw(19, 2048, 2048, 1024, one)
+    assert st == lbm.LBM_EINVAL and "grid too large" in err and ws == 0
+    big = np.zeros(400 * 400 * 360, np.uint8)   # 57.6 M fluid nodes
+    st, err, ws = _create_raw(19, 400, 400, 360, big, strategy=lbm.COMPACT)
+    assert st == lbm.LBM_EINVAL and "compacted layout" in err and ws == 0
+    wide = np.zeros(2_000_000 * 3, np.uint8)
+    st, err, ws = _create_raw(9, 2_000_000, 3, 1, wide, strategy=lbm.FUSED_LIST)
+    assert st == lbm.LBM_EINVAL and "listed fused step" in err and ws == 0
