@@ -161,14 +161,15 @@ def test_graph_replay_matches_eager(lbm):
     assert np.array_equal(a.density(), b.density())
 
 
-def test_checkpoint_resume_is_bitwise(lbm):
+@pytest.mark.parametrize("storage", [0, 1])
+def test_checkpoint_resume_is_bitwise(lbm, storage):
     p = PROBLEMS["drain_srt"]
-    a = lbm.Solver(p)
+    a = lbm.Solver(p, storage=storage)
     a.step(31)
     blob = a.save()
     a.step(40)
     ref = a.density()
-    b = lbm.Solver(p)
+    b = lbm.Solver(p, storage=storage)
     b.load(blob)
     assert b.t == 31
     b.step(40)
