@@ -36,13 +36,17 @@ def ref():
         return {k: z[k] for k in z.files}
 
 
-@pytest.mark.parametrize("name,make", [("d2q9", I.large_drainage), ("d3q19", I.drainage_3d)])
-def test_full_size_workload_matches_oracle_samples(lbm, ref, name, make):
+@pytest.mark.parametrize("name,make,math", [("d2q9", I.large_drainage, 0), ("d2q9", I.large_drainage, 1),
+                                            ("d3q19", I.drainage_3d, 0)])
+def test_full_size_workload_matches_oracle_samples(lbm, ref, name, make, math):
+    """math = 1: FP32 node arithmetic on the MRT drainage, held to the same
+    1e-5 bar (FP32 arithmetic misses it on some SRT/TRT parity cases, so it
+    is not the default)."""
     if f"{name}_rho" not in ref:
         pytest.skip(f"no {name} samples in the fixture")
     steps = int(ref[f"{name}_steps"])
     p = make()
-    s = lbm.Solver(p)
+    s = lbm.Solver(p, math=math)
     try:
         rep = s.autotune(10)
         rest = steps - s.t
@@ -55,7 +59,7 @@ def test_full_size_workload_matches_oracle_samples(lbm, ref, name, make):
         s.close()
     want = ref[f"{name}_rho"]
     err = float(np.max(np.abs(got - want) / np.abs(want)))
-    print(f"[fullsize] {name} {p.nx}x{p.ny}x{p.nz} ({kernel}; autotune: {len(rep.strip().splitlines())} "
+    print(f"[fullsize] {name} math={math} {p.nx}x{p.ny}x{p.nz} ({kernel}; autotune: {len(rep.strip().splitlines())} "
           f"variants), {steps} steps: worst relative error over {want.shape[1]} nodes x 2 components "
           f"{err:.2e}", flush=True)
     assert err <= REL_TOL
