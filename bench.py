@@ -94,6 +94,9 @@ def main():
     ap.add_argument("--kernel-samples", type=int, default=300)
     ap.add_argument("--no-warm-start", action="store_true",
                     help="skip the time-to-steady comparison of a cold start and the U-Net warm start")
+    ap.add_argument("--f32-alt", choices=("auto", "on", "off"), default="auto",
+                    help="also time the same workload with FP32 node arithmetic (auto: on where its full-size "
+                         "parity within 1e-5 is tested: d2q9_1024x512, batch64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -203,6 +206,34 @@ def main():
                    "autotune": tune.strip().splitlines() if tune else None},
         "roofline": roofline,
     }
+    alt = args.f32_alt == "on" or (args.f32_alt == "auto" and args.math == 0 and args.storage == 0
+                                   and args.workload in ("d2q9_1024x512", "batch64"))
+    if alt:
+        # the same workload and protocol with FP32 node arithmetic; reported
+        # beside the FP64-arithmetic value, which stays the headline
+        solver.close()
+        kw = dict(storage=args.storage, device=dev, math=1, strategy=args.strategy, tile_rows=args.tile_rows)
+        solver = lbm.BatchSolver(problems, **kw) if batch else lbm.Solver(problem, **kw)
+        if not args.no_autotune and args.strategy == 0:
+            solver.autotune(10)
+        stream = solver.stream
+        run(max(chunk, args.warmup - args.warmup % chunk))
+        torch.cuda.synchronize()
+        a0 = torch.cuda.Event(enable_timing=True)
+        a1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        a0.record(stream)
+        run(steps)
+        a1.record(stream)
+        torch.cuda.synchronize()
+        awall = time.perf_counter() - t0
+        astep = a0.elapsed_time(a1) / steps
+        out["f32_arithmetic"] = {
+            "value": round(n_nodes * steps / awall / 1e6, 1), "unit": "MLUPS",
+            "ms_per_step": round(awall * 1e3 / steps, 5), "kernel": solver.kernel_info()[0],
+            "roofline_frac": round(alg_bytes / (astep * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "parity": "full-size samples within 1e-5 of the FP64 oracle (tests/test_gpu_fullsize.py, "
+                      "tests/test_gpu_batch.py)"}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem)
     if not args.no_warm_start:
