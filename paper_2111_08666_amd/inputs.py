@@ -22,7 +22,7 @@ Arrays are numpy, C order, with x the fastest index: a 2D field has shape
 from __future__ import annotations
 
 import math
-from dataclasses import dataclass, field, asdict
+from dataclasses import dataclass, asdict
 
 import numpy as np
 

@@ -8,7 +8,6 @@ import csv
 import glob
 import os
 import sqlite3
-import sys
 from collections import defaultdict
 
 

@@ -18,7 +18,6 @@ on fields the solver generated with
     python -m paper_2111_08666_amd.train_surrogate gen ..."""
 import os
 
-import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu

@@ -2,7 +2,6 @@
 correlation, adjoint identities, central finite differences and Adam's
 closed form (CPU only)."""
 import numpy as np
-import pytest
 from scipy import signal
 
 import oracle.unet_oracle as U
