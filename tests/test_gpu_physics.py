@@ -154,3 +154,20 @@ def test_trapped_volume_set3(L):
     print(f"[trapped] window S_w after 90000 steps: {sw}", flush=True)
     assert all(abs(r - 1.0) < 0.05 for r in ratios[3])
     assert sw[3] < 0.15
+
+
+def test_pressure_increment_protocol_drainage(L):
+    """The Sec. 4.2 protocol (paper_2111_08666_amd/pc_sw_curve.py) on a
+    256 x 128 medium of the benchmark recipe, 20 000 steps per increment:
+    through the ten drainage increments no density turns non-finite or
+    negative, the measured capillary pressure rises with every increment,
+    and the water saturation does not rise."""
+    from paper_2111_08666_amd import pc_sw_curve as PC
+    res = PC.run(steps=20000, audit=1000, problem=PC.study_problem(256, 128), log=lambda m: print(m, flush=True))
+    drain = [r for r in res["increments"] if r["phase"] == "drainage"]
+    assert len(drain) >= 2
+    assert all(r["mass_audit"]["flags"] == 0 and r["mass_audit"]["finite"] for r in drain)
+    pc = [r["pc"] for r in drain]
+    assert all(a < b for a, b in zip(pc, pc[1:])), pc
+    sw = [r["s_w_weighted"] for r in drain]
+    assert all(b <= a + 1e-4 for a, b in zip(sw, sw[1:])), sw
