@@ -45,7 +45,7 @@ def schedule():
     return s
 
 
-def study_problem(nx=1024, ny=512):
+def study_problem(nx=1024, ny=512, xi=-0.4):
     """The drainage medium (1024x512: the benchmark's; other sizes: the same
     recipe, radii 4-20, porosity 0.55, seed 2) with its under-resolved pores
     closed (inputs.close_narrow_throats).  In the unmodified 1024x512
@@ -57,9 +57,9 @@ def study_problem(nx=1024, ny=512):
         p = I.large_drainage()
     else:
         p = I.drainage_2d(nx=nx, ny=ny, r=(4.0, 20.0), porosity=0.55, seed=2, G=3.5,
-                          theta=I.theta_of_xi(-0.4), tau=I.TAU_M10, rho_in1=1.0 + 3 * 1e-3, rho_out2=1.0,
+                          theta=I.theta_of_xi(xi), tau=I.TAU_M10, rho_in1=1.0 + 3 * 1e-3, rho_out2=1.0,
                           minor=0.027, collision=1, name=f"d2q9_{nx}x{ny}_drainage_M10")
-        p.xi = -0.4
+    p.xi = xi
     p.mask = I.close_narrow_throats(p.mask)
     p.rho0 = I.reservoir_front(p.mask, p.porous_x0, 1.0, 0.027)
     p.name += "_throats_closed"
@@ -150,11 +150,13 @@ def main():
     ap.add_argument("--steps", type=int, default=200000)
     ap.add_argument("--audit", type=int, default=1000)
     ap.add_argument("--size", default="1024x512", help="medium size NXxNY (1024x512: the benchmark's)")
+    ap.add_argument("--xi", type=float, default=-0.4,
+                    help="adhesion (-0.4: about 50 degrees, Sec. 4.2.1; -0.55: about 22; 0.2: about 110)")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     nx, ny = (int(v) for v in a.size.split("x"))
-    res = run(a.steps, a.audit, problem=study_problem(nx, ny), log=log)
+    res = run(a.steps, a.audit, problem=study_problem(nx, ny, a.xi), log=log)
     print(json.dumps(res), flush=True)
     if a.out:
         with open(a.out, "w") as f:
