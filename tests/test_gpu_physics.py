@@ -171,3 +171,25 @@ def test_pressure_increment_protocol_drainage(L):
     assert all(a < b for a, b in zip(pc, pc[1:])), pc
     sw = [r["s_w_weighted"] for r in drain]
     assert all(b <= a + 1e-4 for a, b in zip(sw, sw[1:])), sw
+
+
+def test_wettability_trends_of_the_pressure_protocol(L):
+    """The protocol at three adhesions on the 256 x 128 medium (50 000 steps
+    per increment): drainage leaves clearly less water in the oil-wet medium
+    (xi = 0.2, about 110 degrees) than in the water-wet ones (xi = -0.4,
+    -0.55), and lowering P_c to zero brings water back (spontaneous
+    imbibition) only in the water-wet media (Sec. 4.2.1-4.2.2)."""
+    from paper_2111_08666_amd import pc_sw_curve as PC
+    out = {}
+    for xi in (-0.55, -0.4, 0.2):
+        res = PC.run(steps=50000, audit=1000, problem=PC.study_problem(256, 128, xi), log=lambda m: None)
+        inc = res["increments"]
+        assert all(r["mass_audit"]["flags"] & 1 == 0 for r in inc), xi
+        drained = [r for r in inc if r["phase"] == "drainage"][-1]["s_w"]
+        at_zero = [r for r in inc if r["phase"] == "imbibition" and r["rho_in1"] == 1.0 and r["rho_out2"] == 1.0]
+        out[xi] = (drained, at_zero[0]["s_w"] if at_zero else 1.0)
+        print(f"[wettability] xi={xi}: S_w after drainage {out[xi][0]:.4f}, at P_c = 0 {out[xi][1]:.4f}", flush=True)
+    assert out[0.2][0] < min(out[-0.4][0], out[-0.55][0]) - 0.05
+    for xi in (-0.55, -0.4):
+        assert out[xi][1] > out[xi][0] + 0.01
+    assert out[0.2][1] <= out[0.2][0] + 0.01
