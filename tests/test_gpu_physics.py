@@ -193,3 +193,16 @@ def test_wettability_trends_of_the_pressure_protocol(L):
     for xi in (-0.55, -0.4):
         assert out[xi][1] > out[xi][0] + 0.01
     assert out[0.2][1] <= out[0.2][0] + 0.01
+
+
+def test_drainage_run_records(L):
+    """paper_2111_08666_amd/drainage_run.py on the 128 x 64 workload for
+    2000 steps: a record every 500 steps, no flag, the window saturation
+    falling as the non-wetting component enters, and both masses finite."""
+    from paper_2111_08666_amd import drainage_run as D
+    res = D.run("d2q9_128x64", 2000, 500, log=lambda m: None)
+    recs = res["records"]
+    assert res["steps"] == 2000 and len(recs) == 5
+    assert all(r["flags"] == 0 and np.all(np.isfinite(r["mass"])) for r in recs)
+    sw = [r["s_w_weighted"] for r in recs]
+    assert all(b < a for a, b in zip(sw, sw[1:])), sw
