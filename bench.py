@@ -232,8 +232,10 @@ def main():
             "value": round(n_nodes * steps / awall / 1e6, 1), "unit": "MLUPS",
             "ms_per_step": round(awall * 1e3 / steps, 5), "kernel": solver.kernel_info()[0],
             "roofline_frac": round(alg_bytes / (astep * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "parity": "full-size samples within 1e-5 of the FP64 oracle (tests/test_gpu_fullsize.py, "
-                      "tests/test_gpu_batch.py)"}
+            "parity": ("full-size samples within 1e-5 of the FP64 oracle (tests/test_gpu_fullsize.py, "
+                       "tests/test_gpu_batch.py)" if args.workload in ("d2q9_1024x512", "batch64")
+                       else "stated bound 2e-4 relative to the FP64 oracle; the 1e-5 bar is not claimed "
+                            "for this workload")}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(problem)
     if not args.no_warm_start:
