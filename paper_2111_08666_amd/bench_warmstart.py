@@ -75,6 +75,14 @@ def measure(first=2000, count=32, cap=300000, s_tol=0.01, log=None):
     }
 
 
+def summary(w):
+    """The record's headline fields, as bench.py reports them."""
+    return {"cold_over_warm_steps_median": w["value"], "unit": "x", "workload": w["config"]["workload"],
+            "criterion": "window saturation change < 1e-6 per 1000 steps; cold and warm S within 0.01",
+            "settled_both": w["settled_both"], "agree_within_s_tol": w["agree_within_s_tol"],
+            "steps_total": w["steps_total"], "wall_s": w["wall_s"], "cap": w["config"]["cap"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--first", type=int, default=2000)

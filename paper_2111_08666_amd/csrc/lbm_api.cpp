@@ -72,11 +72,13 @@ Tiling make_tiling(int q, int nx, int ny, int nz, int ty) {
 }
 
 // The compacted layout addresses one component's populations with 32-bit
-// byte offsets: q * cpitch * 4 must stay below 2^32.
+// byte offsets (q * cpitch * 4 below 2^32), and keys each fluid node by its
+// 32-bit dense index x + pitch * (y + ny * z) (pitch * ny * nz below 2^32).
 bool compact_fits(const lbm_geometry &g) {
   int64_t nf = 0;
   for (int64_t n = 0; n < (int64_t)g.nx * g.ny * g.nz; ++n) nf += g.solid[n] == 0;
-  return (int64_t)g.q * (nf + 64) * 4 < ((int64_t)1 << 32);
+  const int64_t dense = round_up(g.nx, 64) * (int64_t)g.ny * g.nz;
+  return (int64_t)g.q * (nf + 64) * 4 < ((int64_t)1 << 32) && dense < ((int64_t)1 << 32);
 }
 
 // The listed D2Q9 step addresses its stores as a 32-bit byte offset from the
@@ -152,6 +154,20 @@ void build_compact(const lbm_geometry &g, const Layout &L, const std::vector<uin
         }
       }
     }
+}
+
+// FNV-1a hash of what fixes an instance's node tables (solid map, axes),
+// stored in checkpoints so that a state is only restored onto its geometry.
+uint64_t geometry_hash(const lbm_geometry &g) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void *p, size_t n) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) { h ^= c[i]; h *= 1099511628211ull; }
+  };
+  const int32_t hd[6] = {g.q, g.nx, g.ny, g.nz, (int32_t)g.periodic, g.open_x};
+  mix(hd, sizeof hd);
+  mix(g.solid, (size_t)g.nx * g.ny * g.nz);
+  return h;
 }
 
 bool bad(std::string &err, const std::string &msg) {
@@ -280,6 +296,7 @@ struct lbm_batch {
   bool compact = false;  // compacted layout: only the compact step runs on it
   std::vector<InstDev> h;
   std::vector<Layout> lay;
+  std::vector<uint64_t> geom_hash;
   InstDev *d_insts = nullptr;
   int32_t *d_block_inst = nullptr;
   int64_t table_cap = 0;
@@ -497,6 +514,7 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
     }
     b->h.push_back(h);
     b->lay.push_back(L);
+    b->geom_hash.push_back(geometry_hash(g[i]));
     // held (frozen) links: rest equilibria of the initial densities
     const int64_t N = L.n_nodes;
     const int64_t nt = (int64_t)g[i].ny * g[i].nz;
@@ -635,12 +653,23 @@ lbm_status batch_density(lbm_batch *b, int32_t i, float *dst, int32_t dst_is_dev
   return LBM_OK;
 }
 
+// Checkpoint blob: header, the boundary densities, the held (Eq. 26/27)
+// links, then the current population buffer.  The header records the layout
+// and the geometry, and lbm_load restores a blob only onto a context with
+// the same ones.
 struct CkptHeader {
   char magic[8];
   int32_t version, k, q, storage;
-  int32_t parity, pad;
+  int32_t parity, compact;
+  int32_t nx, ny, nz, pitch;
+  int32_t cpitch, pad;
   int64_t step;
+  uint64_t buf_bytes, frozen_bytes, geom_hash;
+  double rho_in1, rho_out2;
 };
+constexpr int32_t kCkptVersion = 2;
+
+size_t ckpt_bytes(const Layout &L) { return sizeof(CkptHeader) + L.frozen_bytes + L.buf_bytes; }
 
 }  // namespace
 
@@ -704,18 +733,23 @@ lbm_status lbm_save(lbm_ctx *ctx, void *host_blob, size_t *bytes) {
   if (!ctx || !bytes) return fail(nullptr, LBM_EINVAL, "NULL argument");
   lbm_batch *b = ctx->b;
   const Layout &L = b->lay[0];
-  const size_t need = sizeof(CkptHeader) + L.buf_bytes + sizeof(InstDev);
+  const size_t need = ckpt_bytes(L);
   if (!host_blob) { *bytes = need; return LBM_OK; }
   if (*bytes < need) return fail(b, LBM_EINVAL, "checkpoint buffer too small");
+  const InstDev &h = b->h[0];
   CkptHeader hd{};
   std::memcpy(hd.magic, "LBMCKPT", 8);
-  hd.version = 1; hd.k = 1; hd.q = b->q; hd.storage = b->storage;
-  hd.parity = b->parity; hd.step = b->step;
+  hd.version = kCkptVersion; hd.k = 1; hd.q = b->q; hd.storage = b->storage;
+  hd.parity = b->parity; hd.compact = L.compact ? 1 : 0;
+  hd.nx = h.nx; hd.ny = h.ny; hd.nz = h.nz; hd.pitch = L.pitch; hd.cpitch = L.cpitch;
+  hd.step = b->step;
+  hd.buf_bytes = L.buf_bytes; hd.frozen_bytes = L.frozen_bytes; hd.geom_hash = b->geom_hash[0];
+  hd.rho_in1 = h.rho_in1; hd.rho_out2 = h.rho_out2;
   char *p = reinterpret_cast<char *>(host_blob);
   std::memcpy(p, &hd, sizeof(hd));
-  std::memcpy(p + sizeof(hd), &b->h[0], sizeof(InstDev));
-  HIPCHK(b, hipMemcpyAsync(p + sizeof(hd) + sizeof(InstDev), b->h[0].f[b->parity], L.buf_bytes,
-                           hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(b, hipMemcpyAsync(p + sizeof(hd), h.frozen, L.frozen_bytes, hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(b, hipMemcpyAsync(p + sizeof(hd) + L.frozen_bytes, h.f[b->parity], L.buf_bytes, hipMemcpyDeviceToHost,
+                           b->stream));
   HIPCHK(b, hipStreamSynchronize(b->stream));
   *bytes = need;
   return LBM_OK;
@@ -725,22 +759,29 @@ lbm_status lbm_load(lbm_ctx *ctx, const void *host_blob, size_t bytes) {
   if (!ctx || !host_blob) return fail(nullptr, LBM_EINVAL, "NULL argument");
   lbm_batch *b = ctx->b;
   const Layout &L = b->lay[0];
-  const size_t need = sizeof(CkptHeader) + L.buf_bytes + sizeof(InstDev);
-  if (bytes < need) return fail(b, LBM_EINVAL, "checkpoint too small");
+  const size_t need = ckpt_bytes(L);
+  if (bytes < sizeof(CkptHeader)) return fail(b, LBM_EINVAL, "checkpoint too small");
   CkptHeader hd;
   std::memcpy(&hd, host_blob, sizeof(hd));
-  InstDev saved;
-  std::memcpy(&saved, reinterpret_cast<const char *>(host_blob) + sizeof(hd), sizeof(InstDev));
   const InstDev &cur = b->h[0];
-  if (std::memcmp(hd.magic, "LBMCKPT", 8) || hd.version != 1 || hd.q != b->q || hd.storage != b->storage ||
-      saved.nx != cur.nx || saved.ny != cur.ny || saved.nz != cur.nz)
-    return fail(b, LBM_EINVAL, "checkpoint does not match this context");
+  if (std::memcmp(hd.magic, "LBMCKPT", 8) || hd.version != kCkptVersion || hd.k != 1)
+    return fail(b, LBM_EINVAL, "not a checkpoint of this library version");
+  if (bytes != need || hd.q != b->q || hd.storage != b->storage || hd.compact != (L.compact ? 1 : 0) ||
+      hd.nx != cur.nx || hd.ny != cur.ny || hd.nz != cur.nz || hd.pitch != L.pitch || hd.cpitch != L.cpitch ||
+      hd.buf_bytes != L.buf_bytes || hd.frozen_bytes != L.frozen_bytes || hd.geom_hash != b->geom_hash[0])
+    return fail(b, LBM_EINVAL, "checkpoint does not match this context (lattice, storage, layout or geometry)");
+  if (hd.parity != 0 && hd.parity != 1) return fail(b, LBM_EINVAL, "corrupt checkpoint (buffer parity)");
+  if (hd.step < 0 || !std::isfinite(hd.rho_in1) || !std::isfinite(hd.rho_out2))
+    return fail(b, LBM_EINVAL, "corrupt checkpoint (step or boundary densities)");
+  const char *p = reinterpret_cast<const char *>(host_blob);
   b->parity = hd.parity;
   b->step = hd.step;
-  b->h[0].rho_in1 = saved.rho_in1;
-  b->h[0].rho_out2 = saved.rho_out2;
-  HIPCHK(b, hipMemcpyAsync(b->h[0].f[b->parity], reinterpret_cast<const char *>(host_blob) + sizeof(hd) + sizeof(InstDev),
-                           L.buf_bytes, hipMemcpyHostToDevice, b->stream));
+  b->h[0].rho_in1 = hd.rho_in1;
+  b->h[0].rho_out2 = hd.rho_out2;
+  HIPCHK(b, hipMemcpyAsync((void *)b->h[0].frozen, p + sizeof(hd), L.frozen_bytes, hipMemcpyHostToDevice,
+                           b->stream));
+  HIPCHK(b, hipMemcpyAsync(b->h[0].f[b->parity], p + sizeof(hd) + L.frozen_bytes, L.buf_bytes,
+                           hipMemcpyHostToDevice, b->stream));
   HIPCHK(b, hipMemcpyAsync(b->d_insts, &b->h[0], sizeof(InstDev), hipMemcpyHostToDevice, b->stream));
   HIPCHK(b, hipStreamSynchronize(b->stream));
   b->unstable = false;

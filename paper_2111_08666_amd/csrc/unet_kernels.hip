@@ -829,6 +829,10 @@ static bool ok8(int v) { return v > 0 && v % 8 == 0; }
 
 using namespace unet;
 
+// A channel slice [co, co + c) of a tensor with cs channels per pixel lies
+// inside the tensor.
+static bool slice_ok(int co, int c, int cs) { return co >= 0 && c >= 1 && (int64_t)co + c <= cs; }
+
 extern "C" {
 
 int unet_mfma_probe(const uint16_t *A, const uint16_t *B, float *C, void *s) {
@@ -838,8 +842,8 @@ int unet_mfma_probe(const uint16_t *A, const uint16_t *B, float *C, void *s) {
 
 int unet_conv3x3_fwd(const uint16_t *x, int n, int h, int w, int cin, int x_cs, int x_co, const uint16_t *wgt,
                      const float *bias, int cout, uint16_t *y, int y_cs, int y_co, int relu, void *s) {
-  if (!x || !wgt || !y || n < 1 || h < 1 || w < 1 || !ok8(cin) || x_cs % 8 || x_co % 8 || x_co + cin > x_cs ||
-      cout < 1 || y_co + cout > y_cs)
+  if (!x || !wgt || !y || n < 1 || h < 1 || w < 1 || !ok8(cin) || x_cs % 8 || x_co % 8 ||
+      !slice_ok(x_co, cin, x_cs) || !slice_ok(y_co, cout, y_cs))
     return -1;
   GemmArgs a{x, n, h, w, cin, x_cs, x_co, wgt, bias, cout, y, y_cs, y_co, relu};
   launch_igemm<0>(a, (int64_t)n * h * w, 1, (hipStream_t)s);
@@ -885,7 +889,7 @@ int unet_conv3x3_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs
 
 int unet_relu_bwd(const uint16_t *y, int n_pix, int c, int y_cs, int y_co, uint16_t *dy, int dy_cs, int dy_co,
                   void *s) {
-  if (!y || !dy || n_pix < 1 || c < 1) return -1;
+  if (!y || !dy || n_pix < 1 || !slice_ok(y_co, c, y_cs) || !slice_ok(dy_co, c, dy_cs)) return -1;
   if (c % 8 == 0 && y_cs % 8 == 0 && y_co % 8 == 0 && dy_cs % 8 == 0 && dy_co % 8 == 0)
     relu_bwd_vec<<<grid1d((int64_t)n_pix * (c / 8)), 256, 0, (hipStream_t)s>>>(y, n_pix, c / 8, y_cs, y_co, dy,
                                                                                 dy_cs, dy_co);
@@ -897,7 +901,9 @@ int unet_relu_bwd(const uint16_t *y, int n_pix, int c, int y_cs, int y_co, uint1
 
 int unet_maxpool_fwd(const uint16_t *x, int n, int h, int w, int c, int x_cs, int x_co, uint16_t *y, int y_cs,
                      int y_co, void *s) {
-  if (!x || !y || n < 1 || h < 2 || w < 2 || (h & 1) || (w & 1) || c < 1) return -1;
+  if (!x || !y || n < 1 || h < 2 || w < 2 || (h & 1) || (w & 1) || !slice_ok(x_co, c, x_cs) ||
+      !slice_ok(y_co, c, y_cs))
+    return -1;
   maxpool_fwd_kernel<<<grid1d((int64_t)n * h * w * c / 4), 256, 0, (hipStream_t)s>>>(x, n, h, w, c, x_cs, x_co, y,
                                                                                        y_cs, y_co);
   return launched();
@@ -905,7 +911,9 @@ int unet_maxpool_fwd(const uint16_t *x, int n, int h, int w, int c, int x_cs, in
 
 int unet_maxpool_bwd(const uint16_t *x, int n, int h, int w, int c, int x_cs, int x_co, const uint16_t *dy,
                      int dy_cs, int dy_co, uint16_t *dx, int dx_cs, int dx_co, int accumulate, void *s) {
-  if (!x || !dy || !dx || n < 1 || h < 2 || w < 2 || (h & 1) || (w & 1) || c < 1) return -1;
+  if (!x || !dy || !dx || n < 1 || h < 2 || w < 2 || (h & 1) || (w & 1) || !slice_ok(x_co, c, x_cs) ||
+      !slice_ok(dy_co, c, dy_cs) || !slice_ok(dx_co, c, dx_cs))
+    return -1;
   maxpool_bwd_kernel<<<grid1d((int64_t)n * h * w * c / 4), 256, 0, (hipStream_t)s>>>(
       x, n, h, w, c, x_cs, x_co, dy, dy_cs, dy_co, dx, dx_cs, dx_co, accumulate);
   return launched();
@@ -913,8 +921,8 @@ int unet_maxpool_bwd(const uint16_t *x, int n, int h, int w, int c, int x_cs, in
 
 int unet_upconv_fwd(const uint16_t *x, int n, int h, int w, int cin, int x_cs, int x_co, const uint16_t *wgt,
                     const float *bias, int cout, uint16_t *y, int y_cs, int y_co, void *s) {
-  if (!x || !wgt || !y || n < 1 || h < 1 || w < 1 || !ok8(cin) || x_cs % 8 || x_co % 8 || cout < 1 ||
-      y_co + cout > y_cs)
+  if (!x || !wgt || !y || n < 1 || h < 1 || w < 1 || !ok8(cin) || x_cs % 8 || x_co % 8 ||
+      !slice_ok(x_co, cin, x_cs) || !slice_ok(y_co, cout, y_cs))
     return -1;
   GemmArgs a{x, n, h, w, cin, x_cs, x_co, wgt, bias, cout, y, y_cs, y_co, 0};
   launch_igemm<1>(a, (int64_t)n * h * w, 4, (hipStream_t)s);
@@ -923,8 +931,8 @@ int unet_upconv_fwd(const uint16_t *x, int n, int h, int w, int cin, int x_cs, i
 
 int unet_upconv_bwd_data(const uint16_t *dy, int n, int h, int w, int cout, int dy_cs, int dy_co,
                          const uint16_t *wgt, int cin, uint16_t *wt, uint16_t *dx, int dx_cs, int dx_co, void *s) {
-  if (!dy || !wgt || !wt || !dx || n < 1 || h < 1 || w < 1 || !ok8(cout) || dy_cs % 8 || dy_co % 8 || cin < 1 ||
-      dx_co + cin > dx_cs)
+  if (!dy || !wgt || !wt || !dx || n < 1 || h < 1 || w < 1 || !ok8(cout) || dy_cs % 8 || dy_co % 8 ||
+      !slice_ok(dy_co, cout, dy_cs) || !slice_ok(dx_co, cin, dx_cs))
     return -1;
   up_rearrange<<<grid1d((int64_t)cout * 4 * cin), 256, 0, (hipStream_t)s>>>(wgt, cout, cin, wt);
   // A = dy over the 2h x 2w grid gathered at 2p + tap, output grid h x w
@@ -956,7 +964,7 @@ int unet_upconv_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs,
 
 int unet_head_fwd(const uint16_t *x, int n_pix, int c, int x_cs, const float *w, const float *b, float *sat,
                   void *s) {
-  if (!x || !w || !b || !sat || n_pix < 1 || c < 1 || c > 256 || 256 % c) return -1;
+  if (!x || !w || !b || !sat || n_pix < 1 || c < 1 || c > 256 || 256 % c || c > x_cs) return -1;
   head_fwd_kernel<<<grid1d(n_pix), 256, 0, (hipStream_t)s>>>(x, n_pix, c, x_cs, w, b, sat);
   return launched();
 }
@@ -969,7 +977,8 @@ int64_t unet_head_scratch_floats(int n_pix, int c) {
 int unet_head_loss_bwd(const uint16_t *x, int n_pix, int c, int x_cs, const float *w, const float *b,
                        const float *target, const uint8_t *mask, float scale, float *loss, uint16_t *dx,
                        float *dw, float *db, float *partial, void *s) {
-  if (!x || !w || !b || !target || !mask || !loss || !partial || n_pix < 1 || c < 1 || c > 256 || 256 % c)
+  if (!x || !w || !b || !target || !mask || !loss || !partial || n_pix < 1 || c < 1 || c > 256 || 256 % c ||
+      c > x_cs)
     return -1;
   float *g = partial, *l = partial + n_pix, *sums = partial + 2 * (int64_t)n_pix;
   const int blocks = (int)(((int64_t)n_pix + kHeadPix - 1) / kHeadPix);

@@ -305,6 +305,17 @@ def drainage_3d(n=384, r=(6.0, 14.0), porosity=0.40, seed=5, theta=60.0,
                    name=f"d3q19_{nx}x{ny}x{nz}_drainage_M10")
 
 
+def fluid_box_3d(n=384, tau=TAU_M10, collision=2) -> Problem:
+    """D3Q19 all-fluid periodic n^3 box holding two flat layers (component 1
+    in x < n/2): the upper bound of the 3D step, every node a fluid node."""
+    mask = np.zeros((n, n, n), dtype=np.uint8)
+    rho0 = np.empty((2, n, n, n))
+    rho0[0], rho0[1] = 0.027, 1.0
+    rho0[0, :, :, : n // 2], rho0[1, :, :, : n // 2] = 1.0, 0.027
+    return Problem(q=19, mask=mask, rho0=rho0, periodic=7, open_x=0, tau=tau, G=3.5,
+                   collision=collision, name=f"d3q19_{n}^3_fluid_box_M10")
+
+
 def batch_instances(k_count=64, seed0=300, nx_range=(256, 1024), collision=1):
     """Uneven batch: instance k has NX a multiple of 64 in nx_range, NY = NX/2,
     its own disc medium (radii 4-20, porosity 0.55, seed seed0 + k), a contact

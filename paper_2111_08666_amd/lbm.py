@@ -152,10 +152,10 @@ def make_params(problem, storage=STORE_F32, math=MATH_F64, strategy=AUTO, tile_r
     return p
 
 
-def workspace_bytes(problem, storage=STORE_F32) -> int:
+def workspace_bytes(problem, storage=STORE_F32, strategy=AUTO) -> int:
     keep = []
     g = make_geometry(problem, keep)
-    p = make_params(problem, storage)
+    p = make_params(problem, storage, strategy=strategy)
     return lib().lbm_workspace_bytes(C.byref(g), C.byref(p))
 
 

@@ -42,6 +42,24 @@ def test_unet_rejects_bad_arguments_before_launch():
     assert L.unet_conv3x3_fwd(None, 1, 8, 8, 16, 16, 0, fake, None, 32, fake, 32, 0, 1, None) == -1
     assert L.unet_maxpool_fwd(fake, 1, 7, 8, 8, 8, 0, fake, 8, 0, None) == -1
     assert L.unet_head_fwd(fake, 64, 24, 24, fake, fake, fake, None) == -1
+    # one channel slice outside its tensor per entry point (offset + count > channels)
+    assert L.unet_conv3x3_fwd(fake, 1, 8, 8, 16, 16, 0, fake, None, 32, fake, 32, 8, 1, None) == -1
+    assert L.unet_conv3x3_wgrad(fake, 1, 8, 8, 16, 16, 0, fake, 16, 16, 8, fake, None, fake, 0, None) == -1
+    assert L.unet_relu_bwd(fake, 64, 16, 16, 8, fake, 16, 0, None) == -1
+    assert L.unet_relu_bwd(fake, 64, 16, 16, 0, fake, 16, 8, None) == -1
+    assert L.unet_maxpool_fwd(fake, 1, 8, 8, 16, 16, 8, fake, 16, 0, None) == -1
+    assert L.unet_maxpool_fwd(fake, 1, 8, 8, 16, 16, 0, fake, 16, 8, None) == -1
+    assert L.unet_maxpool_bwd(fake, 1, 8, 8, 16, 16, 8, fake, 16, 0, fake, 16, 0, 0, None) == -1
+    assert L.unet_maxpool_bwd(fake, 1, 8, 8, 16, 16, 0, fake, 16, 8, fake, 16, 0, 0, None) == -1
+    assert L.unet_maxpool_bwd(fake, 1, 8, 8, 16, 16, 0, fake, 16, 0, fake, 16, 8, 0, None) == -1
+    assert L.unet_upconv_fwd(fake, 1, 8, 8, 16, 16, 8, fake, None, 16, fake, 16, 0, None) == -1
+    assert L.unet_upconv_fwd(fake, 1, 8, 8, 16, 16, 0, fake, None, 16, fake, 16, 8, None) == -1
+    assert L.unet_upconv_bwd_data(fake, 1, 8, 8, 16, 16, 8, fake, 16, fake, fake, 16, 0, None) == -1
+    assert L.unet_upconv_bwd_data(fake, 1, 8, 8, 16, 16, 0, fake, 16, fake, fake, 16, 8, None) == -1
+    assert L.unet_upconv_wgrad(fake, 1, 8, 8, 16, 16, 8, fake, 16, 16, 0, fake, None, fake, None) == -1
+    assert L.unet_head_fwd(fake, 64, 32, 16, fake, fake, fake, None) == -1
+    assert L.unet_head_loss_bwd(fake, 64, 32, 16, fake, fake, fake, fake, 1.0, fake, None, None, None, fake,
+                                None) == -1
     assert L.unet_wgrad_scratch_floats(2, 16, 16, 32, 64, 9) == 1 * 64 * 32 * 9 + 1 * 64  # weights + bias
 
 
@@ -61,6 +79,22 @@ def test_workspace_query_and_validation_without_device():
     bad = I.drainage_2d(nx=64, ny=32, r=(2.0, 4.0), porosity=0.8, seed=1)
     bad.tau = (0.5, 1.0)
     assert lbm.workspace_bytes(bad) == 0
+
+
+def test_compacted_layout_needs_32_bit_node_keys():
+    """The compacted layout keys fluid nodes by their 32-bit pitched index
+    x + pitch (y + ny z), pitch = nx rounded up to 64.  A narrow, tall
+    periodic grid (nx = 2, pitch 64, 2^26 rows) has few nodes but pitched
+    indices past 2^32: the compacted strategy is refused, and AUTO falls
+    back to the dense split step (whose workspace holds full dense buffers)."""
+    ny, nz = 1 << 13, 1 << 13
+    p = I.Problem(q=19, mask=np.zeros((nz, ny, 2), np.uint8), rho0=np.ones((2, 1, 1, 1)),
+                  periodic=7, open_x=0, tau=(1.0, 1.0), collision=2)
+    assert 64 * ny * nz >= 1 << 32 and 2 * ny * nz < 1 << 31
+    assert lbm.workspace_bytes(p, strategy=lbm.COMPACT) == 0
+    auto = lbm.workspace_bytes(p)
+    split = lbm.workspace_bytes(p, strategy=lbm.SPLIT)
+    assert auto == split > 2 * 2 * 19 * 64 * ny * nz * 4
 
 
 def _create(problem, ws=None, nbytes=0):

@@ -176,6 +176,40 @@ def test_checkpoint_resume_is_bitwise(lbm, storage):
     assert np.array_equal(b.density(), ref)
 
 
+def test_checkpoint_refused_on_another_layout_or_geometry(lbm):
+    """A blob is restored only onto a context with its layout and geometry:
+    a dense (split-step) checkpoint into a compacted context, a blob with a
+    corrupt buffer parity, a truncated blob and another medium are refused
+    with LBM_EINVAL before any copy, and the context keeps running."""
+    import struct
+    p = PROBLEMS["drain_srt"]
+    a = lbm.Solver(p, strategy=lbm.SPLIT)
+    a.step(5)
+    blob = a.save()
+    c = lbm.Solver(p, strategy=lbm.COMPACT)
+    with pytest.raises(lbm.LbmError) as e:
+        c.load(blob)
+    assert e.value.status == lbm.LBM_EINVAL
+    b = lbm.Solver(p, strategy=lbm.SPLIT)
+    # parity is the int32 after magic (8 bytes) and version, k, q, storage
+    bad = bytearray(blob)
+    bad[24:28] = struct.pack("<i", 7)
+    for blob_bad in (bytes(bad), blob[:-4], blob + b"\0"):
+        with pytest.raises(lbm.LbmError) as e:
+            b.load(blob_bad)
+        assert e.value.status == lbm.LBM_EINVAL
+    other = I.drainage_2d(nx=p.nx, ny=p.ny, r=(2.0, 4.0), porosity=0.7, seed=999, G=3.5, theta=45,
+                          rho_in1=1.02, minor=0.027)
+    d = lbm.Solver(other, strategy=lbm.SPLIT)
+    with pytest.raises(lbm.LbmError) as e:
+        d.load(blob)
+    assert e.value.status == lbm.LBM_EINVAL
+    b.load(blob)  # the matching blob still loads
+    b.step(3)
+    a.step(3)
+    assert np.array_equal(a.density(), b.density())
+
+
 def test_set_bc_pressure_increment(lbm):
     p = PROBLEMS["drain_srt"]
     o, s = O.OracleSim(p), lbm.Solver(p)

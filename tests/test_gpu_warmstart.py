@@ -6,7 +6,7 @@ reach that steady state in fewer steps in total, and on the instances where
 both runs settle, land within 0.01 of the cold start's saturation on most of
 them (a different metastable state counts against the surrogate).
 
-Instances: the held-out indices 2000-2031 (training used 0-1023) whose
+Instances: the held-out indices 2000-2031 (training used 0-1999) whose
 contact angle is below 90 degrees.  In that water-wet regime the cold start
 settles within the cap (about 0.8e5-2.2e5 steps); above 90 degrees the
 non-wetting phase imbibes spontaneously and neither start settles within
