@@ -92,8 +92,11 @@ typedef struct {
                              step whose collision phase runs over a per-tile
                              list of fluid nodes, their pulled populations
                              parked in LDS; nx up to about 1.8 million);
-                             LBM_COMPACT_FUSED (D2Q9: the fused tile step
-                             over the compacted layout of LBM_COMPACT).
+                             LBM_COMPACT_FUSED (the fused step over the
+                             compacted layout of LBM_COMPACT: D2Q9, the
+                             fused tile step; D3Q19 with FP32 storage, one
+                             launch that marches each x-y tile through z,
+                             pulling every population once).
                              The layout is fixed at creation: the compacted
                              strategies cannot be switched to or from the
                              others (lbm_autotune stays within the layout).

@@ -54,10 +54,36 @@ struct Tiling {
   int64_t blocks;
 };
 
-Tiling make_tiling(int q, int nx, int ny, int nz, int ty) {
+// Compute units of the device (blocks of the z-marching 3D step: one per CU).
+int device_cus() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      n = v;
+    else
+      n = 256;
+  }
+  return n;
+}
+
+Tiling make_tiling(int q, int nx, int ny, int nz, int ty, int strategy = LBM_FUSED) {
   Tiling t{};
   t.tiles_x = (nx + kTileX - 1) / kTileX;
-  if (q == 9) {
+  if (q == 19 && strategy == LBM_COMPACT_FUSED) {
+    // z-marching step: one block per CU at a time.  Choose the number of z
+    // chunks that minimises (rounds of blocks) x (planes per chunk + the 4
+    // extra density planes a chunk pulls).
+    t.tiles_y = (ny + kTileY3 - 1) / kTileY3;
+    const int64_t xy = (int64_t)t.tiles_x * t.tiles_y, cus = device_cus();
+    int64_t best = -1;
+    for (int tz = 1; tz <= std::max(1, nz / 16); ++tz) {
+      const int64_t zlen = (nz + tz - 1) / tz;
+      const int64_t cost = ((xy * tz + cus - 1) / cus) * (zlen + 4);
+      if (best < 0 || cost < best) { best = cost; t.tiles_z = tz; }
+    }
+  } else if (q == 9) {
     t.tiles_y = (ny + ty - 1) / ty;
     t.tiles_z = 1;
   } else {
@@ -194,7 +220,10 @@ bool validate(const lbm_geometry *g, const lbm_params *p, const double *rho0, st
   if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_BF16DEV) return bad(err, "unknown storage");
   if (p->math != LBM_MATH_F64 && p->math != LBM_MATH_F32) return bad(err, "unknown math precision");
   if (p->strategy < LBM_AUTO || p->strategy > LBM_COMPACT_FUSED) return bad(err, "unknown strategy");
-  if (p->strategy == LBM_COMPACT_FUSED && g->q != 9) return bad(err, "the compacted fused step is D2Q9 only");
+  if (p->strategy == LBM_COMPACT_FUSED && p->collision == LBM_MRT && g->q != 9)
+    return bad(err, "MRT is defined for D2Q9 only");
+  if (p->strategy == LBM_COMPACT_FUSED && g->q == 19 && p->storage != LBM_STORE_F32)
+    return bad(err, "the compacted fused D3Q19 step needs FP32 storage");
   if (p->strategy == LBM_FUSED_LIST && g->q != 9) return bad(err, "the listed fused step is D2Q9 only");
   if (p->strategy == LBM_FUSED_LIST && !list_fits(g->nx)) return bad(err, "nx too large for the listed fused step");
   if (p->strategy == LBM_COMPACT && p->collision == LBM_MRT && g->q != 9)
@@ -365,7 +394,8 @@ size_t batch_bytes(int32_t k, const lbm_geometry *g, const lbm_params *p, int64_
   int ob = 1;
   for (int i = 0; i < k; ++i) {
     const Layout L = make_layout(g[i], p[i]);
-    nb += make_tiling(g[i].q, g[i].nx, g[i].ny, g[i].nz, 8).blocks;
+    nb += std::max(make_tiling(g[i].q, g[i].nx, g[i].ny, g[i].nz, 8).blocks,
+                   make_tiling(g[i].q, g[i].nx, g[i].ny, g[i].nz, 8, LBM_COMPACT_FUSED).blocks);
     bytes += L.info_bytes + L.frozen_bytes + L.psi_bytes + 2 * L.buf_bytes;
     if (L.compact) bytes += L.cword_bytes + L.ckey_bytes + L.cbnd_bytes;
     InstDev tmp{};
@@ -388,7 +418,7 @@ lbm_status apply_plan(lbm_batch *b, int strategy, int ty) {
   int64_t base = 0;
   for (int i = 0; i < b->k; ++i) {
     InstDev &h = b->h[(size_t)i];
-    const Tiling t = make_tiling(b->q, h.nx, h.ny, h.nz, ty);
+    const Tiling t = make_tiling(b->q, h.nx, h.ny, h.nz, ty, strategy);
     h.tiles_x = t.tiles_x; h.tiles_y = t.tiles_y; h.tiles_z = t.tiles_z;
     h.block_base = (int32_t)base;
     for (int64_t j = 0; j < t.blocks; ++j) table.push_back(i);
@@ -826,7 +856,7 @@ lbm_status lbm_batch_kernel_info(const lbm_batch *b, char *name, size_t name_len
       *grid_blocks = b->n_blocks;
     }
   }
-  if (block_threads) *block_threads = 256;
+  if (block_threads) *block_threads = (b->strategy == LBM_COMPACT_FUSED && b->q == 19) ? 512 : 256;
   return LBM_OK;
 }
 
@@ -844,6 +874,8 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int64_t steps, char *report, size_t 
     cands.push_back({LBM_COMPACT, 12});
     if (b->q == 9)
       for (int ty : {8, 12, 16}) cands.push_back({LBM_COMPACT_FUSED, ty});
+    else if (b->collision != LBM_MRT && b->storage == LBM_STORE_F32)
+      cands.push_back({LBM_COMPACT_FUSED, 12});
   } else {
     if (b->q == 9) {
       for (int ty : {8, 12, 16}) cands.push_back({LBM_FUSED, ty});

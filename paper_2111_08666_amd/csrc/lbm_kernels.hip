@@ -1236,6 +1236,424 @@ __global__ __launch_bounds__(256) void ccollide_kernel(const InstDev *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// D3Q19 fused step on the compacted layout (FP32 storage), marching in z.
+// A block of eight waves owns a 60 x 8 tile of (x, y) (64 x 12 with a
+// two-node halo) and a chunk of z.  Wave w owns interior row 2 + w; waves
+// 0-3 also one halo row each (rows 0, 1, 10, 11).  Per plane z:
+//   phase A: form psi at the solid nodes of plane z + 1 (Eq. 17) from the
+//            densities of planes z .. z + 2, held in an LDS ring of five
+//            planes;
+//   phase B: load the row words of plane z + 6 for its rank map (compact
+//            index of each region node, or solid, or outside the domain),
+//            issue the density pulls of plane z + 3 straight into LDS
+//            landing areas (global_load_lds: no registers held in flight)
+//            and the interior pulls of plane z + 1 into registers; compute
+//            the force and collision of plane z from the registers filled
+//            one plane earlier; wait; write the rank map; store plane z;
+//            sum the densities of plane z + 3 into the ring.
+// The collision's pulls repeat the density pulls of two planes earlier and
+// are served by the L2; densities and psi never leave the chip.  Node
+// arithmetic follows the compacted split step; the ring holds the densities
+// and psi rounded to FP32.
+// ---------------------------------------------------------------------------
+constexpr int kM3Waves = 8;             // one interior row per wave
+constexpr int kM3RH = kTileY3 + 4;      // region rows
+constexpr int kM3Ring = 5;              // density planes
+constexpr int kM3Maps = 7;              // rank maps of planes z - 1 .. z + 5
+constexpr int kM3MapRows = kM3RH + 2;   // region rows -1 .. kM3RH
+constexpr int kM3MapCols = 66;          // region columns -1 .. 64
+constexpr int kM3MapPitch = 68;
+// A map entry is the node's compact index minus its row's base (the compact
+// index of the word holding the region's first column), or one of these.
+constexpr int kMapOutside = -32768, kMapSolid = -32767;
+// D3Q19 links entering the domain at the inlet (e_x = +1) and at the outlet (e_x = -1)
+constexpr int kInLinks19[5] = {1, 7, 9, 11, 13};
+constexpr int kOutLinks19[5] = {2, 8, 10, 12, 14};
+
+__device__ __forceinline__ int m3ring(int p) { return ((p % kM3Ring) + kM3Ring) % kM3Ring; }
+__device__ __forceinline__ int m3map(int p) { return ((p % kM3Maps) + kM3Maps) % kM3Maps; }
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) const void g_cvoid;
+
+template <int COLL, typename R>
+__global__ __launch_bounds__(512) void march_d3q19(const InstDev *__restrict__ insts,
+                                                   const int32_t *__restrict__ block_inst, int parity) {
+  using L = Lat<19>;
+  using V = Vec2<float>;
+  __shared__ V ring[kM3Ring][kM3RH][64];
+  __shared__ int16_t rmap[kM3Maps][kM3MapRows][kM3MapPitch];
+  __shared__ int32_t rbase[kM3Maps][kM3MapRows];
+  // landing areas [row][component * 19 + link][lane]: rows 0-7 the interior
+  // row of wave w, rows 8-11 the halo row of wave w - 8
+  __shared__ float land[kM3Waves + 4][38][64];
+
+  const int bid = xcd_block();
+  const int inst = __builtin_amdgcn_readfirstlane(block_inst ? block_inst[bid] : 0);
+  const InstDev &d = insts[inst];
+  const int lb = bid - d.block_base;
+  const int tx = lb % d.tiles_x, ty = (lb / d.tiles_x) % d.tiles_y;
+  const int zc = lb / (d.tiles_x * d.tiles_y);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  gcf *__restrict__ fin = G(d.f[parity]);
+  gf *__restrict__ fout = G(d.f[parity ^ 1]);
+  gcf *__restrict__ frz = G(d.frozen);
+  gcc *const fin_b = (gcc *)fin;
+  const int nx = d.nx, ny = d.ny, nz = d.nz, cp = d.cpitch;
+  const bool px = d.periodic & 1, py = d.periodic & 2, pz = d.periodic & 4;
+  const int zlen = (nz + d.tiles_z - 1) / d.tiles_z;
+  const int z0 = zc * zlen, z1 = min(nz, z0 + zlen);
+  const int64_t wpr = d.pitch >> 6;
+  const int64_t nt = (int64_t)ny * nz;
+  const int bc_set = d.bc_set;
+
+  // coordinate of a region index along an axis: false if outside a closed edge
+  auto wrap_ax = [](int v, int n, bool per, int &out) __attribute__((always_inline)) -> bool {
+    out = v;
+    if (v < 0 || v >= n) {
+      if (!per) return false;
+      out = wrap_index(v, n);
+    }
+    return true;
+  };
+
+  int gx;
+  const bool col_in = wrap_ax(tx * kTileX - 2 + lane, nx, px, gx);
+  const bool col_store = lane >= 2 && lane < 62 && tx * kTileX - 2 + lane < nx;
+  // inlet / outlet flags of this column
+  const uint32_t face = !d.open_x || !col_in ? 0u : (gx == 0 ? kInlet : (gx == nx - 1 ? kOutlet : 0u));
+  const bool open_face = face != 0;
+  const int rI = 2 + wave;                            // interior region row
+  const bool has_h = wave < 4;
+  const int rH = wave < 2 ? wave : kTileY3 + wave;    // halo region row: 0, 1, 10, 11
+  int gyI = 0, gyH = 0;
+  wrap_ax(ty * kTileY3 - 2 + rI, ny, py, gyI);
+  wrap_ax(ty * kTileY3 - 2 + rH, ny, py, gyH);
+  const bool storeI = col_store && ty * kTileY3 + wave < ny;
+  // column of the rank base of every map row: the region's first in-domain column
+  int xb;
+  if (!wrap_ax(tx * kTileX - 3, nx, px, xb)) xb = 0;
+
+  // ---- rank maps: two entries per thread, words loaded in one phase and
+  // the entries written in a later one
+  unsigned long long mbits[2];
+  int32_t mpre[2], mbase[2], mpos[2];  // mpos: bit position, -1 outside in x, -2 row outside
+  auto map_issue = [&](int p) __attribute__((always_inline)) {
+    // every load is issued (from row 0 for entries outside the domain), so
+    // that no register is assigned while an older load may still target it
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = threadIdx.x + 512 * k;
+      const int rr = e / kM3MapCols, cc = e - rr * kM3MapCols;
+      int xg, yg, zg;
+      const bool row_ok = e < kM3MapRows * kM3MapCols && wrap_ax(ty * kTileY3 - 3 + rr, ny, py, yg) &&
+                          wrap_ax(p, nz, pz, zg);
+      const bool col_ok = wrap_ax(tx * kTileX - 3 + cc, nx, px, xg);
+      const RowWord *row = d.cword + (row_ok ? yg + (int64_t)ny * zg : 0) * wpr;
+      mbase[k] = (int32_t)row[xb >> 6].pre;
+      const RowWord w = row[(col_ok ? xg : xb) >> 6];
+      mbits[k] = w.bits;
+      mpre[k] = (int32_t)w.pre;
+      mpos[k] = !row_ok ? -2 : (!col_ok ? -1 : (xg & 63));
+    }
+  };
+  auto map_write = [&](int p) __attribute__((always_inline)) {
+    const int m = m3map(p);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = threadIdx.x + 512 * k;
+      if (e >= kM3MapRows * kM3MapCols) continue;
+      const int rr = e / kM3MapCols, cc = e - rr * kM3MapCols;
+      int v = kMapOutside;
+      if (mpos[k] >= 0) {
+        const int b = mpos[k];
+        v = ((mbits[k] >> b) & 1ull) ? mpre[k] + (int)__popcll(mbits[k] & ((1ull << b) - 1ull)) - mbase[k]
+                                     : kMapSolid;
+      }
+      rmap[m][rr][cc] = (int16_t)v;
+      if (cc == 0) rbase[m][rr] = mbase[k];
+    }
+  };
+  // compact index at map (plane p, map row rr, map column cc): >= 0 fluid,
+  // -1 solid, -2 outside the domain
+  auto rank_at = [&](int p, int rr, int cc) __attribute__((always_inline)) -> int32_t {
+    const int m = m3map(p);
+    const int v = rmap[m][rr][cc];
+    return v <= kMapSolid ? v - kMapSolid - 1 : rbase[m][rr] + v;
+  };
+
+  // ---- pulls of the node of region row r on plane p into landing row lr
+  // (one global_load_lds per link and component); the held links of its
+  // inlet/outlet completion go to pre
+  auto pull_issue = [&](int lr, int r, int gy, int p, int32_t &c, float (&pre)[5])
+      __attribute__((always_inline)) {
+    c = rank_at(p, r + 1, lane + 1);
+    if (c < 0) return;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      int32_t sc = c;
+      int pi = i;
+      if (i != 0) {
+        // a solid source (half-way bounce-back) or a missing link across an
+        // open face (overwritten by the completion) reads this node's
+        // opposite slot
+        const int32_t sv = rank_at(p - L::ez[i], r + 1 - L::ey[i], lane + 1 - L::ex[i]);
+        if (sv >= 0) sc = sv;
+        else pi = L::opp[i];
+      }
+      const uint32_t bo = ((uint32_t)pi * (uint32_t)cp + (uint32_t)sc) * 4u;
+      __builtin_amdgcn_global_load_lds((g_cvoid *)(fin_b + bo), (lds_void *)&land[lr][i][0], 4, 0, 0);
+      __builtin_amdgcn_global_load_lds((g_cvoid *)(fin_b + (uint32_t)(19 * cp) * 4u + bo),
+                                       (lds_void *)&land[lr][19 + i][0], 4, 0, 0);
+    }
+    // component 2 at the inlet: Eq. 28 (this node's own post-collision
+    // values) or Eq. 27 (Set-2, held); component 1 at the outlet: Eq. 26
+    if (face && bc_set != 1) {
+      int zz;
+      wrap_ax(p, nz, pz, zz);
+      const int64_t t = gy + (int64_t)ny * zz;
+      if (face & kInlet) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const int i = kInLinks19[k];
+          pre[k] = bc_set == 2 ? frz[(int64_t)(19 + i) * nt + t] : ldg(fin + (int64_t)(19 + i) * cp, (uint32_t)c * 4u);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) pre[k] = frz[(int64_t)kOutLinks19[k] * nt + t];
+      }
+    }
+  };
+  // the same pulls into registers (the collision's; nothing waits for them here)
+  auto pull_regs = [&](int r, int gy, int p, int32_t &c, float (&a)[19], float (&b)[19], float (&pre)[5])
+      __attribute__((always_inline)) {
+    c = rank_at(p, r + 1, lane + 1);
+    if (c < 0) return;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      int32_t sc = c;
+      int pi = i;
+      if (i != 0) {
+        const int32_t sv = rank_at(p - L::ez[i], r + 1 - L::ey[i], lane + 1 - L::ex[i]);
+        if (sv >= 0) sc = sv;
+        else pi = L::opp[i];
+      }
+      const uint32_t bo = ((uint32_t)pi * (uint32_t)cp + (uint32_t)sc) * 4u;
+      a[i] = ldg(fin, bo);
+      b[i] = ldg(fin + (int64_t)19 * cp, bo);
+    }
+    if (face && bc_set != 1) {
+      int zz;
+      wrap_ax(p, nz, pz, zz);
+      const int64_t t = gy + (int64_t)ny * zz;
+      if (face & kInlet) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const int i = kInLinks19[k];
+          pre[k] = bc_set == 2 ? frz[(int64_t)(19 + i) * nt + t] : ldg(fin + (int64_t)(19 + i) * cp, (uint32_t)c * 4u);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) pre[k] = frz[(int64_t)kOutLinks19[k] * nt + t];
+      }
+    }
+  };
+  // inlet/outlet completion of pulled populations (links already pulled)
+  auto complete = [&](const float (&pre)[5], float (&a)[19], float (&b)[19]) __attribute__((always_inline)) {
+    if (face & kInlet) {
+      zou_he<19, double>(a, d.rho_in1, +1);  // component 1: Eqs. 22-25
+      if (bc_set == 1) {
+        zou_he<19, double>(b, d.rho_in2, +1);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) b[kInLinks19[k]] = pre[k];
+      }
+    } else if (face & kOutlet) {
+      zou_he<19, double>(b, d.rho_out2, -1);  // component 2: Eqs. 18-21
+      if (bc_set == 1) {
+        zou_he<19, double>(a, d.rho_out1, -1);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) a[kOutLinks19[k]] = pre[k];
+      }
+    }
+  };
+  // read a landed node back (after the wait) and complete it
+  auto pull_read = [&](int lr, const float (&pre)[5], float (&a)[19], float (&b)[19])
+      __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      a[i] = land[lr][i][lane];
+      b[i] = land[lr][19 + i][lane];
+    }
+    complete(pre, a, b);
+  };
+  // issue, wait, read: the prologue's pulls
+  auto pull_now = [&](int lr, int r, int gy, int p, int32_t &c, float (&a)[19], float (&b)[19])
+      __attribute__((always_inline)) {
+    float pre[5];
+    pull_issue(lr, r, gy, p, c, pre);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __builtin_amdgcn_sched_barrier(0);
+    if (c >= 0) pull_read(lr, pre, a, b);
+  };
+  auto put_rho = [&](int p, int r, int32_t c, const float (&a)[19], const float (&b)[19])
+      __attribute__((always_inline)) {
+    float r1 = 0.f, r2 = 0.f;
+    if (c >= 0) {
+      r1 = (float)sum_q<19, double>(a);
+      r2 = (float)sum_q<19, double>(b);
+    }
+    ring[m3ring(p)][r][lane] = V{r1, r2};
+  };
+  // virtual solid density (Eq. 17) in place at the solid nodes of region row
+  // r on plane p: the neighbours' map entries and densities are read first,
+  // then summed over the in-domain fluid ones in link order
+  auto ivsd = [&](int p, int r) __attribute__((always_inline)) {
+    if (r < 1 || r > kM3RH - 2 || lane < 1 || lane > 62) return;
+    if (rmap[m3map(p)][r + 1][lane + 1] != kMapSolid) return;
+    bool fl[19];
+    V q[19];
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+      fl[i] = rmap[m3map(p + L::ez[i])][r + 1 + L::ey[i]][lane + 1 + L::ex[i]] > kMapSolid;
+      q[i] = ring[m3ring(p + L::ez[i])][r + L::ey[i]][lane + L::ex[i]];
+    }
+    double s1 = 0, s2 = 0, den = 0;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+      if (fl[i]) {
+        s1 += L::w[i] * (double)q[i].x;
+        s2 += L::w[i] * (double)q[i].y;
+        den += L::w[i];
+      }
+    }
+    if (den > 0) {
+      const double inv = rcp<double>(den);
+      ring[m3ring(p)][r][lane] = V{(float)(d.chi1 * s1 * inv), (float)(d.chi2 * s2 * inv)};
+    }
+  };
+
+  // the interior row's populations of plane z (collided now) and z + 1 (in flight)
+  float a0[19], b0[19], an[19], bn[19];
+  int32_t c0 = -1, cnx = -1;
+
+  // ---- prologue: maps of z0-3 .. z0+5, densities of z0-2 .. z0+2, psi of
+  // z0-1 and z0, the populations of plane z0
+  {
+    float ta[19], tb[19];
+    int32_t tc;
+    for (int p = z0 - 3; p <= z0 + 3; ++p) {
+      map_issue(p);
+      map_write(p);
+    }
+    __syncthreads();
+    for (int p = z0 - 2; p <= z0 + 2; ++p) {
+      pull_now(wave, rI, gyI, p, tc, ta, tb);
+      put_rho(p, rI, tc, ta, tb);
+      if (p == z0) {
+        c0 = tc;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) { a0[i] = ta[i]; b0[i] = tb[i]; }
+      }
+      if (has_h) {
+        pull_now(kM3Waves + wave, rH, gyH, p, tc, ta, tb);
+        put_rho(p, rH, tc, ta, tb);
+      }
+    }
+    __syncthreads();  // the map of z0-3 is read no more
+    map_issue(z0 + 4);
+    map_write(z0 + 4);
+    ivsd(z0 - 1, rI);
+    ivsd(z0, rI);
+    if (has_h) {
+      ivsd(z0 - 1, rH);
+      ivsd(z0, rH);
+    }
+    __syncthreads();  // the map of z0-2 is read no more
+    map_issue(z0 + 5);
+    map_write(z0 + 5);
+    __syncthreads();
+  }
+
+  const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
+  for (int z = z0; z < z1; ++z) {
+    const int p = z + 3;
+    const bool need = p <= z1 + 1;  // densities are needed up to plane z1 + 1
+    // Phase A: psi at the solid nodes of plane z + 1
+    ivsd(z + 1, rI);
+    if (has_h) ivsd(z + 1, rH);
+    __syncthreads();
+    // Phase B: row words of plane z + 6, density pulls of plane p into the
+    // landing areas, the collision's pulls of plane z + 1 into registers
+    map_issue(z + 6);
+    int32_t cn = -1, hc = -1;
+    float pre[5], hpre[5], npre[5];
+    if (need) {
+      pull_issue(wave, rI, gyI, p, cn, pre);
+      if (has_h) pull_issue(kM3Waves + wave, rH, gyH, p, hc, hpre);
+    }
+    cnx = -1;
+    if (z + 1 < z1) pull_regs(rI, gyI, z + 1, cnx, an, bn, npre);
+    // force (Eq. 13 with the open-face mirror) and collision of plane z
+    // while they are in flight
+    const bool live = storeI && c0 >= 0;
+    if (live) {
+      const R rho1 = (R)sum_q<19, double>(a0), rho2 = (R)sum_q<19, double>(b0);
+      R sx1 = 0, sy1 = 0, sz1 = 0, sx2 = 0, sy2 = 0, sz2 = 0;
+#pragma unroll
+      for (int i = 1; i < 19; ++i) {
+        if (L::opp[i] < i) continue;
+        const int o = L::opp[i];
+        if (L::ex[i] != 0 && open_face) continue;
+        const V pa = ring[m3ring(z + L::ez[i])][rI + L::ey[i]][lane + L::ex[i]];
+        const V pb = ring[m3ring(z + L::ez[o])][rI + L::ey[o]][lane + L::ex[o]];
+        const R w = (R)L::w[i];
+        const R d1 = w * ((R)pa.x - (R)pb.x), d2 = w * ((R)pa.y - (R)pb.y);
+        if (L::ex[i]) { sx1 += L::ex[i] * d1; sx2 += L::ex[i] * d2; }
+        if (L::ey[i]) { sy1 += L::ey[i] * d1; sy2 += L::ey[i] * d2; }
+        if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
+      }
+      collide_node<19, COLL, R>(d, a0, b0, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb,
+                                -G_ * rho1 * sy2 + rho1 * gyb, -G_ * rho1 * sz2 + rho1 * gzb,
+                                -G_ * rho2 * sx1 + rho2 * gxb, -G_ * rho2 * sy1 + rho2 * gyb,
+                                -G_ * rho2 * sz1 + rho2 * gzb);
+    }
+    // Every load issued above has landed after this wait (the compiler does
+    // not see the landing areas as written by the pulls, so the wait and the
+    // scheduling fences are explicit); the stores are issued after it, so
+    // that it does not wait for them.
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __builtin_amdgcn_sched_barrier(0);
+    // the slot of plane z + 6 held plane z - 1, last read by the previous
+    // iteration's pulls
+    map_write(z + 6);
+    if (live) pop_store<19, 0>(fout, cp, 0, c0, a0, b0, 0.f, 0.f);
+    if (need) {
+      float ta[19], tb[19];
+      if (cn >= 0) pull_read(wave, pre, ta, tb);
+      put_rho(p, rI, cn, ta, tb);
+      if (has_h) {
+        if (hc >= 0) pull_read(kM3Waves + wave, hpre, ta, tb);
+        put_rho(p, rH, hc, ta, tb);
+      }
+    }
+    c0 = cnx;
+    if (cnx >= 0) {
+      complete(npre, an, bn);
+#pragma unroll
+      for (int i = 0; i < 19; ++i) { a0[i] = an[i]; b0[i] = bn[i]; }
+    }
+    // the densities of plane p and the rank map of plane z + 6 written in
+    // this phase are read after this barrier
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // initial state: f*_i = w_i rho0 at fluid nodes (rest equilibrium), and the
 // ghost slots of solid sources (FP32 storage)
 // ---------------------------------------------------------------------------
@@ -1427,7 +1845,9 @@ template <int COLL, int ST, typename R>
 static void launch_fused_q(int q, int ty, const InstDev *d, const int32_t *bi, int64_t nb, int parity,
                            hipStream_t s, bool compact = false) {
   const dim3 g((unsigned)nb), b(256);
-  if (q == 9 && compact) {
+  if (q == 19 && compact) {
+    if constexpr (COLL != 1 && ST == 0) march_d3q19<COLL, R><<<g, dim3(512), 0, s>>>(d, bi, parity);
+  } else if (q == 9 && compact) {
     if (ty == 8) step_d2q9<COLL, ST, R, 8, 1><<<g, b, 0, s>>>(d, bi, parity);
     else if (ty == 16) step_d2q9<COLL, ST, R, 16, 1><<<g, b, 0, s>>>(d, bi, parity);
     else step_d2q9<COLL, ST, R, 12, 1><<<g, b, 0, s>>>(d, bi, parity);
@@ -1528,6 +1948,8 @@ const char *step_kernel_name(int q, int collision, int storage, int math, int st
              st[storage], mt[math]);
   else if (strategy == 4)
     snprintf(buf, sizeof buf, "step_d2q9_list<%s,%s,%s,%d>", coll[collision], st[storage], mt[math], ty);
+  else if (strategy == 5 && q == 19)
+    snprintf(buf, sizeof buf, "march_d3q19<%s,%s,%s>", coll[collision], st[storage], mt[math]);
   else if (strategy == 5)
     snprintf(buf, sizeof buf, "step_d2q9<%s,%s,%s,%d,compact>", coll[collision], st[storage], mt[math], ty);
   else if (q == 9)

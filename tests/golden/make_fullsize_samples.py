@@ -1,7 +1,7 @@
 """Writes fullsize_samples.npz: FP64 oracle densities at seeded fluid nodes
 of the two single-instance benchmark workloads at their full sizes,
   d2q9: the 1024x512 disc-medium drainage (MRT, M = 10), after 200 steps;
-  d3q19: the 384^3 sphere-pack drainage (TRT, M = 10), after 20 steps.
+  d3q19: the 384^3 sphere-pack drainage (TRT, M = 10), after 200 steps.
 Calls only the oracle and the seeded input generators.  The 384^3 oracle
 holds about 40 GB of FP64 state and takes a few seconds per step.
 
@@ -20,7 +20,7 @@ import oracle as O                                    # noqa: E402
 from paper_2111_08666_amd import inputs as I          # noqa: E402
 
 OUT = os.path.join(HERE, "fullsize_samples.npz")
-CASES = {"d2q9": (I.large_drainage, 200), "d3q19": (I.drainage_3d, 20)}
+CASES = {"d2q9": (I.large_drainage, 200), "d3q19": (I.drainage_3d, 200)}
 SAMPLES = 2048
 
 

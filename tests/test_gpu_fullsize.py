@@ -4,7 +4,7 @@ HIP-graph replays), against FP64 oracle densities at 2048 seeded fluid nodes
 each (tests/golden/fullsize_samples.npz, written by
 tests/golden/make_fullsize_samples.py from the oracle alone):
   D2Q9 1024x512 disc-medium drainage, MRT, after 200 steps;
-  D3Q19 384^3 sphere-pack drainage, TRT, after 20 steps.
+  D3Q19 384^3 sphere-pack drainage, TRT, after 200 steps.
 Every sampled density within 1e-5 relative (FP32 storage, FP64 node
 arithmetic)."""
 import os

@@ -170,6 +170,44 @@ def test_bf16_batch_matches_single(lbm):
         assert np.array_equal(b.density(i), s.density())
 
 
+@pytest.mark.parametrize("name", sorted(P3))
+def test_d3q19_march_matches_compact_step(lbm, name):
+    """The z-marching fused step (LBM_COMPACT_FUSED) does the compacted split
+    step's node arithmetic but keeps densities and psi on chip in FP32: with
+    FP64 node arithmetic its densities stay within 1e-6 of the split step's
+    over eager steps and graph replays, ragged tiles and z chunks, and the
+    observables' counts agree exactly."""
+    p = P3[name]
+    a = lbm.Solver(p, strategy=lbm.COMPACT)
+    b = lbm.Solver(p, strategy=lbm.COMPACT_FUSED)
+    assert "march_d3q19" in b.kernel_info()[0] and b.kernel_info()[2] == 512
+    fluid = ~p.mask.astype(bool)
+    for n in (1, 36, 63):
+        a.step(n)
+        if n % 2 == 0:
+            b.step_graph(n, 1)
+        else:
+            b.step(n)
+        ra, rb = a.density().astype(np.float64), b.density().astype(np.float64)
+        err = float((np.abs(ra - rb) / np.abs(ra))[:, fluid].max())
+        print(f"[march-vs-compact] {name} t={a.t} {err:.1e}", flush=True)
+        assert err <= 1e-6, (name, n, err)
+    oa, ob = a.observables(), b.observables()
+    for k in ("n_fluid", "n_window", "n_in", "n_out"):
+        assert oa[k] == ob[k]
+
+
+@pytest.mark.parametrize("name", sorted(P3))
+def test_d3q19_march_parity_200_steps(lbm, name):
+    """The z-marching step against the FP64 oracle, both node arithmetics."""
+    p = P3[name]
+    for math in (lbm.MATH_F64, lbm.MATH_F32):
+        s = lbm.Solver(p, strategy=lbm.COMPACT_FUSED, math=math)
+        errs = _series(p, s, CHECKPOINTS)
+        print(f"[march3d] {name} math={math} errors {['%.1e' % e for e in errs]}", flush=True)
+        assert max(errs) <= (REL_TOL if math == lbm.MATH_F64 else F32_MATH_BOUND), errs
+
+
 def test_d3q19_compact_equals_split_bitwise(lbm):
     p = P3["d3_drain_trt"]
     a = lbm.Solver(p, strategy=lbm.SPLIT)
