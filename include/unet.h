@@ -64,6 +64,22 @@ int unet_conv3x3_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs
                        const uint16_t *dy, int cout, int dy_cs, int dy_co,
                        float *dw, float *db, float *partial, int accumulate, void *s);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the weight
+ * gradient of unet_conv3x3_wgrad with the same arguments except `partial`.
+ * Its split-K partial sums live in a library-held device array of
+ * 4 Mi floats (16 MiB) per GPU, held until the process ends; problems with
+ * unet_wgrad_scratch_floats(n, h, w, cin, cout, 9) above that return -2
+ * before any device work.  The array's address is looked up once per device
+ * (hipGetSymbolAddress, with that device current).  Every call on a GPU
+ * shares that GPU's array: calls that overlap on one GPU (other streams,
+ * other threads) race on it.  Nothing in it needs to start at zero.  Returns
+ * 0, -1 (invalid arguments, as unet_conv3x3_wgrad), -2 (too large) or -100
+ * (the lookup or a launch failed). */
+int unet_conv3x3_wgrad_noalloc(const uint16_t *x, int n, int h, int w, int cin, int x_cs, int x_co,
+                               const uint16_t *dy, int cout, int dy_cs, int dy_co,
+                               float *dw, float *db, int accumulate, void *s);
+
 /* dy[p][c] = 0 where y[p][c] <= 0 (ReLU backward, in place on a slice). */
 int unet_relu_bwd(const uint16_t *y, int n_pix, int c, int y_cs, int y_co,
                   uint16_t *dy, int dy_cs, int dy_co, void *s);

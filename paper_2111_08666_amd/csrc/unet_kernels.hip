@@ -8,6 +8,8 @@
 //   B fragment, lane l: B[k = 8 * (l / 32) + j][col = l % 32]
 //   C, lane l, register r: C[row = 8 * (r / 4) + 4 * (l / 32) + r % 4][col = l % 32]
 #include <hip/hip_runtime.h>
+
+#include <mutex>
 #include <stdint.h>
 
 #include "../../include/unet.h"
@@ -829,6 +831,27 @@ static bool ok8(int v) { return v > 0 && v % 8 == 0; }
 
 using namespace unet;
 
+// Split-K partial sums of the allocation-free weight gradient: a file-scope
+// device array, one copy per GPU, held until the process ends.  Host code
+// never uses its name as an address: the address comes from
+// hipGetSymbolAddress, once per device, with that device current.
+constexpr int64_t kStaticScratchFloats = (int64_t)4 << 20;  // 16 MiB
+static __device__ __align__(256) float scratch[kStaticScratchFloats];
+
+static float *scratch_ptr_current_device() {
+  static std::mutex mu;
+  static float *ptrs[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptrs[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+    ptrs[dev] = static_cast<float *>(p);
+  }
+  return ptrs[dev];
+}
+
 // A channel slice [co, co + c) of a tensor with cs channels per pixel lies
 // inside the tensor.
 static bool slice_ok(int co, int c, int cs) { return co >= 0 && c >= 1 && (int64_t)co + c <= cs; }
@@ -885,6 +908,18 @@ int unet_conv3x3_wgrad(const uint16_t *x, int n, int h, int w, int cin, int x_cs
                                                                              accumulate);
   if (db) bias_reduce<<<(cout + 63) / 64, 64, 0, (hipStream_t)s>>>(partial + wpart, kb, cout, db, accumulate);
   return launched();
+}
+
+int unet_conv3x3_wgrad_noalloc(const uint16_t *x, int n, int h, int w, int cin, int x_cs, int x_co,
+                               const uint16_t *dy, int cout, int dy_cs, int dy_co, float *dw, float *db,
+                               int accumulate, void *s) {
+  if (!x || !dy || !dw || n < 1 || h < 1 || w < 1 || !ok8(cin) || !ok8(cout) || x_cs % 8 || x_co % 8 ||
+      dy_cs % 8 || dy_co % 8 || !slice_ok(x_co, cin, x_cs) || !slice_ok(dy_co, cout, dy_cs))
+    return -1;
+  if (unet_wgrad_scratch_floats(n, h, w, cin, cout, 9) > kStaticScratchFloats) return -2;
+  float *part = scratch_ptr_current_device();
+  if (!part) return -100;
+  return unet_conv3x3_wgrad(x, n, h, w, cin, x_cs, x_co, dy, cout, dy_cs, dy_co, dw, db, part, accumulate, s);
 }
 
 int unet_relu_bwd(const uint16_t *y, int n_pix, int c, int y_cs, int y_co, uint16_t *dy, int dy_cs, int dy_co,

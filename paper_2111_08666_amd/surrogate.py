@@ -38,6 +38,7 @@ def lib():
             "unet_conv3x3_fwd": [vp, i32, i32, i32, i32, i32, i32, vp, vp, i32, vp, i32, i32, i32, vp],
             "unet_conv3x3_flip": [vp, i32, i32, vp, vp],
             "unet_conv3x3_wgrad": [vp, i32, i32, i32, i32, i32, i32, vp, i32, i32, i32, vp, vp, vp, i32, vp],
+            "unet_conv3x3_wgrad_noalloc": [vp, i32, i32, i32, i32, i32, i32, vp, i32, i32, i32, vp, vp, i32, vp],
             "unet_relu_bwd": [vp, i32, i32, i32, i32, vp, i32, i32, vp],
             "unet_maxpool_fwd": [vp, i32, i32, i32, i32, i32, i32, vp, i32, i32, vp],
             "unet_maxpool_bwd": [vp, i32, i32, i32, i32, i32, i32, vp, i32, i32, vp, i32, i32, i32, vp],
@@ -64,7 +65,7 @@ def lib():
 
 EXPORTS = [
     "unet_mfma_probe", "unet_conv3x3_fwd", "unet_conv3x3_flip", "unet_wgrad_scratch_floats",
-    "unet_conv3x3_wgrad", "unet_relu_bwd", "unet_maxpool_fwd", "unet_maxpool_bwd", "unet_upconv_fwd",
+    "unet_conv3x3_wgrad", "unet_conv3x3_wgrad_noalloc", "unet_relu_bwd", "unet_maxpool_fwd", "unet_maxpool_bwd", "unet_upconv_fwd",
     "unet_upconv_bwd_data", "unet_upconv_wgrad", "unet_head_fwd", "unet_head_scratch_floats",
     "unet_head_loss_bwd", "unet_adam", "unet_to_bf16", "unet_to_f32",
 ]

@@ -61,6 +61,13 @@ def test_unet_rejects_bad_arguments_before_launch():
     assert L.unet_head_loss_bwd(fake, 64, 32, 16, fake, fake, fake, fake, 1.0, fake, None, None, None, fake,
                                 None) == -1
     assert L.unet_wgrad_scratch_floats(2, 16, 16, 32, 64, 9) == 1 * 64 * 32 * 9 + 1 * 64  # weights + bias
+    # the allocation-free weight gradient: invalid arguments, then a problem
+    # whose split-K partials exceed its 4 Mi-float array (16 x 256 x 256
+    # pixels, 64 -> 64 channels: 256 blocks x 64 x 576 floats)
+    assert L.unet_conv3x3_wgrad_noalloc(fake, 1, 8, 8, 12, 16, 0, fake, 16, 16, 0, fake, None, 0, None) == -1
+    assert L.unet_wgrad_scratch_floats(16, 256, 256, 64, 64, 9) > 4 << 20
+    assert L.unet_conv3x3_wgrad_noalloc(fake, 16, 256, 256, 64, 64, 0, fake, 64, 64, 0, fake, fake, 0,
+                                        None) == -2
 
 
 def test_every_declared_symbol_is_exported():
