@@ -74,10 +74,12 @@ typedef struct {
   double rho_in2;         /* Set-1 only: component-2 inlet density */
   double rho_out1;        /* Set-1 only: component-1 outlet density */
   double g[3];            /* body acceleration, F^b = rho^s g (Eq. 12) */
-  int32_t collision;      /* LBM_SRT (Eq. 1), LBM_MRT (D2Q9), LBM_TRT */
+  int32_t collision;      /* LBM_SRT (Eq. 1), LBM_MRT, LBM_TRT */
   int32_t bc_set;         /* 3 = Set-3 (the paper's); 1, 2 = Set-1, Set-2 */
   int32_t half_force_shift; /* 1: u = (j + F/2)/rho (default); 0: u = j/rho */
-  int32_t mrt_sj_mode;    /* MRT momentum rate: 0 = s_nu, 1 = s_q */
+  int32_t mrt_sj_mode;    /* MRT component-momentum rate s_j: 0 = min(s_nu, s_q)
+                             (default; stable from viscosity ratio 1 to 100),
+                             1 = s_q, 2 = s_nu */
   double lambda;          /* magic (1/s_nu - 1/2)(1/s_q - 1/2); <= 0: s_q = s_nu */
   double s_e, s_eps;      /* MRT energy-mode rates; <= 0: equal to s_nu */
   int32_t storage;        /* LBM_STORE_F32 or LBM_STORE_BF16DEV: how f* is held */

@@ -72,6 +72,7 @@ def lib():
         L.ora_forcing.argtypes = [C.c_int, dp, dp, dp]
         L.ora_collide_node.argtypes = [C.POINTER(OraParams), dp, dp, dp]
         L.ora_zouhe.argtypes = [C.c_int, dp, C.c_double, C.c_int]
+        L.ora_mrt_matrix.argtypes = [C.c_int, dp]
         _lib = L
     return _lib
 
@@ -141,6 +142,12 @@ def collide_node(params: OraParams, fin, F):
     out = np.zeros(2 * q)
     lib().ora_collide_node(C.byref(params), _dp(fin), _dp(F), _dp(out))
     return out.reshape(2, q)
+
+
+def mrt_matrix(q):
+    out = np.zeros(q * q)
+    lib().ora_mrt_matrix(q, _dp(out))
+    return out.reshape(q, q)
 
 
 def zouhe(q, f, rho_bc, normal):

@@ -156,6 +156,59 @@ static void mrt_matrix(const lattice *L, double M[9][9], double Minv[9][9]) {
   }
 }
 
+/* D3Q19 moment basis of d'Humieres, Ginzburg, Krafczyk, Lallemand & Luo
+ * (2002), rows as polynomials of the link vector c (c2 = |c|^2): rho,
+ * e = 19 c2 - 30, eps = (21 c2^2 - 53 c2 + 24)/2, j and q = (5 c2 - 9) c per
+ * axis, 3 p_xx = 3 cx^2 - c2 and pi_xx = (3 c2 - 5)(3 cx^2 - c2),
+ * p_ww = cy^2 - cz^2 and pi_ww = (3 c2 - 5)(cy^2 - cz^2), p_xy, p_yz, p_xz,
+ * and the third-order m_x = (cy^2 - cz^2) cx, m_y = (cz^2 - cx^2) cy,
+ * m_z = (cx^2 - cy^2) cz.  Row order: rho, e, eps, jx, qx, jy, qy, jz, qz,
+ * 3pxx, 3pixx, pww, piww, pxy, pyz, pxz, mx, my, mz. */
+static void mrt_matrix19(const lattice *L, double M[19][19], double Minv[19][19]) {
+  for (int i = 0; i < 19; ++i) {
+    double cx = L->e[i][0], cy = L->e[i][1], cz = L->e[i][2];
+    double c2 = cx * cx + cy * cy + cz * cz;
+    M[0][i] = 1.0;
+    M[1][i] = 19.0 * c2 - 30.0;
+    M[2][i] = (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;
+    M[3][i] = cx;
+    M[4][i] = (5.0 * c2 - 9.0) * cx;
+    M[5][i] = cy;
+    M[6][i] = (5.0 * c2 - 9.0) * cy;
+    M[7][i] = cz;
+    M[8][i] = (5.0 * c2 - 9.0) * cz;
+    M[9][i] = 3.0 * cx * cx - c2;
+    M[10][i] = (3.0 * c2 - 5.0) * (3.0 * cx * cx - c2);
+    M[11][i] = cy * cy - cz * cz;
+    M[12][i] = (3.0 * c2 - 5.0) * (cy * cy - cz * cz);
+    M[13][i] = cx * cy;
+    M[14][i] = cy * cz;
+    M[15][i] = cx * cz;
+    M[16][i] = (cy * cy - cz * cz) * cx;
+    M[17][i] = (cz * cz - cx * cx) * cy;
+    M[18][i] = (cx * cx - cy * cy) * cz;
+  }
+  for (int k = 0; k < 19; ++k) {
+    double n2 = 0.0;
+    for (int i = 0; i < 19; ++i) n2 += M[k][i] * M[k][i];
+    for (int i = 0; i < 19; ++i) Minv[i][k] = M[k][i] / n2;
+  }
+}
+
+void ora_mrt_matrix(int q, double *M) {
+  lattice L;
+  if (make_lattice(q, &L)) return;
+  if (q == 9) {
+    double A[9][9], B[9][9];
+    mrt_matrix(&L, A, B);
+    for (int k = 0; k < 81; ++k) M[k] = A[k / 9][k % 9];
+  } else {
+    double A[19][19], B[19][19];
+    mrt_matrix19(&L, A, B);
+    for (int k = 0; k < 361; ++k) M[k] = A[k / 19][k % 19];
+  }
+}
+
 /* Relaxation rates at one node.  READING (Eq. 7 as printed has tau + 1/2;
  * the paper's own numbers tau = 3.5 -> nu = 1 and tau = 0.62 -> nu = 0.04
  * need nu = c_s^2 (tau - 1/2)): Eq. 6 then gives tau_s as the
@@ -171,7 +224,12 @@ static rates node_rates(const ora_params *p, double rho1, double rho2) {
   r.s_q = (p->lambda > 0.0) ? 1.0 / (0.5 + p->lambda / (r.tau_s - 0.5)) : r.s_nu;
   r.s_e = (p->s_e > 0.0) ? p->s_e : r.s_nu;
   r.s_eps = (p->s_eps > 0.0) ? p->s_eps : r.s_nu;
-  r.s_j = p->mrt_sj_mode ? r.s_q : r.s_nu;
+  /* component-momentum rate (READING: the paper names MRT but gives no
+   * rates): mode 0 the smaller of s_nu and s_q, so that neither end of the
+   * viscosity range over-relaxes the components' momenta; 1 s_q; 2 s_nu */
+  if (p->mrt_sj_mode == 1) r.s_j = r.s_q;
+  else if (p->mrt_sj_mode == 2) r.s_j = r.s_nu;
+  else r.s_j = r.s_nu < r.s_q ? r.s_nu : r.s_q;
   return r;
 }
 
@@ -208,22 +266,40 @@ static void collide(const lattice *L, const ora_params *p, const double *fin,
       for (int i = 0; i < q; ++i)
         o[i] = f[i] - (f[i] - feq[i]) / r.tau_s + (1.0 - 1.0 / (2.0 * r.tau_s)) * S[i];
     } else if (p->collision == 1) { /* MRT in moment space */
-      double M[9][9], Mi[9][9];
-      mrt_matrix(L, M, Mi);
-      double sr[9] = {1.0, r.s_e, r.s_eps, r.s_j, r.s_q, r.s_j, r.s_q, r.s_nu, r.s_nu};
-      double mstar[9];
-      for (int k = 0; k < 9; ++k) {
+      double M[19][19], Mi[19][19]; /* the leading q x q block is used */
+      double sr[19];
+      if (q == 9) {
+        double A[9][9], B[9][9];
+        mrt_matrix(L, A, B);
+        for (int k = 0; k < 9; ++k)
+          for (int i = 0; i < 9; ++i) { M[k][i] = A[k][i]; Mi[k][i] = B[k][i]; }
+        const double s9[9] = {1.0, r.s_e, r.s_eps, r.s_j, r.s_q, r.s_j, r.s_q, r.s_nu, r.s_nu};
+        for (int k = 0; k < 9; ++k) sr[k] = s9[k];
+      } else {
+        mrt_matrix19(L, M, Mi);
+        /* READING: the paper gives no rates.  The second-order moments relax
+         * at s_nu (viscosity of Eqs. 6-7), e and eps at the free energy rates,
+         * the fourth-order pi moments at s_eps and the third-order m moments
+         * at s_q, so that equal even and odd rates give TRT and equal rates
+         * give SRT. */
+        const double s19[19] = {1.0,    r.s_e,  r.s_eps, r.s_j,  r.s_q,  r.s_j,  r.s_q,
+                                r.s_j,  r.s_q,  r.s_nu,  r.s_eps, r.s_nu, r.s_eps, r.s_nu,
+                                r.s_nu, r.s_nu, r.s_q,   r.s_q,  r.s_q};
+        for (int k = 0; k < 19; ++k) sr[k] = s19[k];
+      }
+      double mstar[19];
+      for (int k = 0; k < q; ++k) {
         double m = 0.0, meq = 0.0, ms = 0.0;
-        for (int i = 0; i < 9; ++i) {
+        for (int i = 0; i < q; ++i) {
           m += M[k][i] * f[i];
           meq += M[k][i] * feq[i];
           ms += M[k][i] * S[i];
         }
         mstar[k] = m - sr[k] * (m - meq) + (1.0 - 0.5 * sr[k]) * ms;
       }
-      for (int i = 0; i < 9; ++i) {
+      for (int i = 0; i < q; ++i) {
         double v = 0.0;
-        for (int k = 0; k < 9; ++k) v += Mi[i][k] * mstar[k];
+        for (int k = 0; k < q; ++k) v += Mi[i][k] * mstar[k];
         o[i] = v;
       }
     } else { /* TRT: symmetric part at s+ = s_nu, antisymmetric at s- = s_q */
@@ -356,8 +432,8 @@ ora_sim *ora_create(const ora_params *p, const uint8_t *solid, const double *rho
   for (int c = 0; c < 2; ++c)
     if (!(p->tau[c] > 0.5) || !isfinite(p->tau[c])) { set_err(err, "tau must exceed 1/2"); return NULL; }
   if (!(fabs(p->xi) < 1.0)) { set_err(err, "|xi| must be < 1"); return NULL; }
-  if (p->collision < 0 || p->collision > 2 || (p->collision == 1 && p->q != 9)) {
-    set_err(err, "collision: 0 SRT, 1 MRT (D2Q9), 2 TRT"); return NULL;
+  if (p->collision < 0 || p->collision > 2) {
+    set_err(err, "collision: 0 SRT, 1 MRT, 2 TRT"); return NULL;
   }
   if (p->bc_set < 1 || p->bc_set > 3) { set_err(err, "bc_set must be 1, 2 or 3"); return NULL; }
 

@@ -26,9 +26,9 @@ typedef struct {
   int32_t open_x;           /* 1: pressure inlet at x = 0, outlet at x = nx-1 */
   int32_t porous_x0, porous_x1; /* saturation window [x0, x1) */
   int32_t bc_set;           /* 3: Set-3 (Sec. 2.3); 1, 2: Set-1, Set-2 */
-  int32_t collision;        /* 0 SRT (Eq. 1), 1 MRT (D2Q9 only), 2 TRT */
+  int32_t collision;        /* 0 SRT (Eq. 1), 1 MRT, 2 TRT */
   int32_t half_force_shift; /* 1: u = (j + F/2)/rho; 0: u = j/rho */
-  int32_t mrt_sj_mode;      /* 0: s_j = s_nu; 1: s_j = s_q */
+  int32_t mrt_sj_mode;      /* MRT s_j: 0 min(s_nu, s_q); 1 s_q; 2 s_nu */
   double tau[2];            /* tau^(1), tau^(2) */
   double G;                 /* G_coh = G_ads (Sec. 2.2) */
   double xi;                /* chi1 = 1 + xi, chi2 = 1 - xi */
@@ -67,6 +67,9 @@ void ora_forcing(int q, const double *u, const double *F, double *S);   /* Eq. 1
  * component), out: 2*q.  tau_s and u follow Eqs. 5-9 under the readings
  * stated in the source. */
 void ora_collide_node(const ora_params *p, const double *fin, const double *F, double *out);
+/* The MRT moment matrix (q x q, row-major): the Lallemand-Luo basis for
+ * D2Q9, the d'Humieres basis for D3Q19. */
+void ora_mrt_matrix(int q, double *M);
 /* Zou-He / on-site pressure completion of the links pointing into the domain
  * at an x-face: normal = +1 (inlet, x = 0) or -1 (outlet).  f has q entries;
  * the missing ones are overwritten. */

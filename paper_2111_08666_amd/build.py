@@ -5,7 +5,8 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = [os.path.join(HERE, "csrc", s) for s in ("lbm_kernels.hip", "lbm_api.cpp", "unet_kernels.hip")]
+SOURCES = [os.path.join(HERE, "csrc", s) for s in ("lbm_kernels.hip", "lbm_step_srt.hip", "lbm_step_mrt.hip",
+                                                    "lbm_step_trt.hip", "lbm_api.cpp", "unet_kernels.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
@@ -19,7 +20,7 @@ def kernel_source_hash() -> str:
     """Hash of the step kernels' sources: counter measurements are tied to it."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("lbm_kernels.hip", "lattice.h", "lbm_device.h"):
+    for f in ("lbm_kernels.hip", "lbm_step.h", "lattice.h", "lbm_device.h"):
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -133,6 +133,41 @@ __device__ __forceinline__ R sum_q(const float (&f)[Q]) {
   return s;
 }
 
+// D3Q19 moment basis of d'Humieres, Ginzburg, Krafczyk, Lallemand & Luo
+// (2002): entry (k, i) of the moment matrix, rows rho, e, eps, jx, qx, jy,
+// qy, jz, qz, 3pxx, 3pixx, pww, piww, pxy, pyz, pxz, mx, my, mz.  The rows are
+// mutually orthogonal, so the inverse is the transpose over the row norms.
+__host__ __device__ constexpr int mrt19(int k, int i) {
+  const int cx = Lat<19>::ex[i], cy = Lat<19>::ey[i], cz = Lat<19>::ez[i];
+  const int c2 = cx * cx + cy * cy + cz * cz;
+  switch (k) {
+    case 0: return 1;
+    case 1: return 19 * c2 - 30;
+    case 2: return (21 * c2 * c2 - 53 * c2 + 24) / 2;
+    case 3: return cx;
+    case 4: return (5 * c2 - 9) * cx;
+    case 5: return cy;
+    case 6: return (5 * c2 - 9) * cy;
+    case 7: return cz;
+    case 8: return (5 * c2 - 9) * cz;
+    case 9: return 3 * cx * cx - c2;
+    case 10: return (3 * c2 - 5) * (3 * cx * cx - c2);
+    case 11: return cy * cy - cz * cz;
+    case 12: return (3 * c2 - 5) * (cy * cy - cz * cz);
+    case 13: return cx * cy;
+    case 14: return cy * cz;
+    case 15: return cx * cz;
+    case 16: return (cy * cy - cz * cz) * cx;
+    case 17: return (cz * cz - cx * cx) * cy;
+    default: return (cx * cx - cy * cy) * cz;
+  }
+}
+__host__ __device__ constexpr int mrt19_norm(int k) {
+  int n = 0;
+  for (int i = 0; i < 19; ++i) n += mrt19(k, i) * mrt19(k, i);
+  return n;
+}
+
 // ---------------------------------------------------------------------------
 // Relaxation rates at a node.  tau_s is the density-weighted mean of the
 // component relaxation times (Eq. 6 with nu = (tau - 1/2)/3); the shear rate
@@ -152,14 +187,15 @@ __device__ __forceinline__ Rates<R> node_rates(const InstDev &d, R rho1, R rho2,
   r.s_q = d.lambda > 0 ? a * rcp<R>(R(0.5) * a + (R)d.lambda) : r.s_nu;
   r.s_e = d.s_e > 0 ? (R)d.s_e : r.s_nu;
   r.s_eps = d.s_eps > 0 ? (R)d.s_eps : r.s_nu;
-  r.s_j = d.sj_mode ? r.s_q : r.s_nu;
+  // component-momentum rate: 0 the smaller of s_nu and s_q, 1 s_q, 2 s_nu
+  r.s_j = d.sj_mode == 1 ? r.s_q : (d.sj_mode == 2 ? r.s_nu : (r.s_nu < r.s_q ? r.s_nu : r.s_q));
   return r;
 }
 
 // ---------------------------------------------------------------------------
 // Forced collision of one component at one node, in place (Eqs. 1, 2, 11).
 // u: common velocity (with the half-force shift), F: this component's force.
-// COLL: 0 SRT, 1 MRT (D2Q9 Lallemand-Luo moments), 2 TRT.  The update is
+// COLL: 0 SRT, 1 MRT (D2Q9: Lallemand-Luo moments; D3Q19: d'Humieres), 2 TRT.  The update is
 // formed as an increment f* - f so the populations' own rounding is not
 // repeated.
 // ---------------------------------------------------------------------------
@@ -208,8 +244,51 @@ __device__ __forceinline__ void collide_component(float (&fo)[Q], R rho, R ux, R
       fo[i] = (float)(fi + (dp + dm));
       fo[b] = (float)(fb + (dp - dm));
     }
+  } else if constexpr (Q == 19) {
+    // MRT in the d'Humieres moments: the second-order moments relax at s_nu,
+    // e and eps at the free energy rates, pi at s_eps, j at s_j, q and m at
+    // s_q (equal even and odd rates give TRT, equal rates give SRT).
+    R dv[Q], S[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const R eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
+      const R eF = L::ex[i] * Fx + L::ey[i] * Fy + L::ez[i] * Fz;
+      const R w = (R)L::w[i];
+      dv[i] = w * rho * (R(1) + R(3) * eu + R(4.5) * eu * eu - usq15) - (R)fo[i];
+      S[i] = w * (R(3) * (eF - uF) + R(9) * eu * eF);
+    }
+    auto rate = [&](int k) -> R {
+      switch (k) {
+        case 1: return r.s_e;
+        case 2: case 10: case 12: return r.s_eps;
+        case 3: case 5: case 7: return r.s_j;
+        case 4: case 6: case 8: case 16: case 17: case 18: return r.s_q;
+        default: return r.s_nu;
+      }
+    };
+    R dm[Q];
+#pragma unroll
+    for (int k = 1; k < Q; ++k) {
+      R a = 0, b = 0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        if (mrt19(k, i) != 0) {
+          a += R(mrt19(k, i)) * dv[i];
+          b += R(mrt19(k, i)) * S[i];
+        }
+      }
+      const R sk = rate(k);
+      dm[k] = (sk * a + (R(1) - R(0.5) * sk) * b) * (R(1) / R(mrt19_norm(k)));
+    }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      R v = 0;
+#pragma unroll
+      for (int k = 1; k < Q; ++k)
+        if (mrt19(k, i) != 0) v += R(mrt19(k, i)) * dm[k];
+      fo[i] = (float)((R)fo[i] + v);
+    }
   } else {
-    static_assert(Q == 9, "MRT is D2Q9 only");
     R f[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = (R)fo[i];

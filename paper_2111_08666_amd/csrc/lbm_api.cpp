@@ -215,19 +215,14 @@ bool validate(const lbm_geometry *g, const lbm_params *p, const double *rho0, st
   if (!(std::fabs(p->xi) < 1.0)) return bad(err, "|xi| must be < 1");
   if (!std::isfinite(p->G)) return bad(err, "G must be finite");
   if (p->collision < 0 || p->collision > 2) return bad(err, "collision must be SRT, MRT or TRT");
-  if (p->collision == LBM_MRT && g->q != 9) return bad(err, "MRT is defined for D2Q9 only");
   if (p->bc_set < 1 || p->bc_set > 3) return bad(err, "bc_set must be 1, 2 or 3");
   if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_BF16DEV) return bad(err, "unknown storage");
   if (p->math != LBM_MATH_F64 && p->math != LBM_MATH_F32) return bad(err, "unknown math precision");
   if (p->strategy < LBM_AUTO || p->strategy > LBM_COMPACT_FUSED) return bad(err, "unknown strategy");
-  if (p->strategy == LBM_COMPACT_FUSED && p->collision == LBM_MRT && g->q != 9)
-    return bad(err, "MRT is defined for D2Q9 only");
   if (p->strategy == LBM_COMPACT_FUSED && g->q == 19 && p->storage != LBM_STORE_F32)
     return bad(err, "the compacted fused D3Q19 step needs FP32 storage");
   if (p->strategy == LBM_FUSED_LIST && g->q != 9) return bad(err, "the listed fused step is D2Q9 only");
   if (p->strategy == LBM_FUSED_LIST && !list_fits(g->nx)) return bad(err, "nx too large for the listed fused step");
-  if (p->strategy == LBM_COMPACT && p->collision == LBM_MRT && g->q != 9)
-    return bad(err, "MRT is defined for D2Q9 only");
   if (compact_strategy(p->strategy) && !compact_fits(*g))
     return bad(err, "too many fluid nodes for the compacted layout (use LBM_SPLIT)");
   if (p->tile_rows != 0 && p->tile_rows != 8 && p->tile_rows != 12 && p->tile_rows != 16)
@@ -572,7 +567,6 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
   // not fit the L2), the fused step otherwise
   int strategy = resolve_strategy(g[0], p[0]);
   b->compact = compact_strategy(strategy);
-  if (strategy == LBM_SPLIT && (b->collision == LBM_MRT && b->q != 9)) strategy = LBM_FUSED;
   const lbm_status ps = apply_plan(b, strategy, p[0].tile_rows ? p[0].tile_rows : 12);
   if (ps != LBM_OK) return ps;
   *out = owner.release();
@@ -874,7 +868,7 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int64_t steps, char *report, size_t 
     cands.push_back({LBM_COMPACT, 12});
     if (b->q == 9)
       for (int ty : {8, 12, 16}) cands.push_back({LBM_COMPACT_FUSED, ty});
-    else if (b->collision != LBM_MRT && b->storage == LBM_STORE_F32)
+    else if (b->storage == LBM_STORE_F32)
       cands.push_back({LBM_COMPACT_FUSED, 12});
   } else {
     if (b->q == 9) {
@@ -886,7 +880,7 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int64_t steps, char *report, size_t 
     } else {
       cands.push_back({LBM_FUSED, 12});
     }
-    if (!(b->collision == LBM_MRT && b->q != 9)) cands.push_back({LBM_SPLIT, 12});
+    cands.push_back({LBM_SPLIT, 12});
   }
   hipEvent_t e0, e1;
   HIPCHK(b, hipEventCreate(&e0));

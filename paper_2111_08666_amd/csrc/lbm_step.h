@@ -1,0 +1,1746 @@
+// Step kernels of the two-component LBM for gfx950 (D2Q9 and D3Q19) and
+// their launchers, shared by the translation units that instantiate them for
+// one collision operator each (lbm_step_srt.hip, lbm_step_mrt.hip,
+// lbm_step_trt.hip) and by lbm_kernels.hip (set-up, observables, densities).
+#pragma once
+// State between steps: the post-collision populations f*^s_i(x), two buffers
+// in ping-pong, in a row-interleaved structure of arrays: for each (z, y) row a
+// block holding, population after population, one value per x (row pitch a
+// multiple of 64).  Accesses stay coalesced along x and the pulls of a wave
+// touch a few contiguous row blocks instead of 2Q planes far apart.
+// One step pulls f(x) = f*(x - e_i) (bounce-back from solid sources), completes
+// the inlet/outlet links, forms the densities, the solid pseudopotential,
+// the interaction force and the collision, and writes f* to the other buffer.
+// The force at x needs psi within one node, psi at a solid node needs rho
+// within one more (Eq. 17), and rho needs the pull: each block therefore
+// recomputes densities on a two-node halo around its tile in LDS.
+//
+// Populations are loaded and stored as float (or BF16 deviations); the node
+// arithmetic runs in R = double (default) or float.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "lattice.h"
+#include "lbm_device.h"
+
+namespace lbm {
+
+template <typename R> struct Vec2 { R x, y; };
+
+// global-memory views of the state (lets the compiler emit global, not flat, accesses)
+typedef __attribute__((address_space(1))) float gf;
+typedef __attribute__((address_space(1))) const float gcf;
+typedef __attribute__((address_space(1))) const uint32_t gcu32;
+typedef __attribute__((address_space(1))) uint32_t gu32;
+typedef __attribute__((address_space(1))) const uint16_t gcu16;
+
+__device__ __forceinline__ gcf *G(const float *p) { return (gcf *)p; }
+__device__ __forceinline__ gf *G(float *p) { return (gf *)p; }
+
+// Access at a wave-uniform base plus a per-lane 32-bit byte offset: the
+// compiler can then keep the base in scalar registers and address with one
+// 32-bit VGPR (global_load ... v_off, s[base]) instead of a 64-bit VGPR pair.
+typedef __attribute__((address_space(1))) const char gcc;
+typedef __attribute__((address_space(1))) char gc;
+__device__ __forceinline__ float ldg(gcf *base, uint32_t boff) { return *(gcf *)((gcc *)base + boff); }
+__device__ __forceinline__ void stg(gf *base, uint32_t boff, float v) { *(gf *)((gc *)base + boff) = v; }
+
+// ---------------------------------------------------------------------------
+// population access by storage kind; a node is addressed by its row block
+// offset `row` (y * ystride + z * zstride, in floats) and its x
+// FP32:  row block = [s][i][pitch] floats
+// BF16:  row block = [pitch] (rho1, rho2) float pairs, then [i-1][pitch]
+//        32-bit words holding both components' bf16 deviations
+//        d_i = f*_i - w_i rho (i >= 1; component 1 in the low half);
+//        f*_0 = rho - sum_i f*_i.  A pull of link i reads one float pair
+//        and one word for both components.
+// ---------------------------------------------------------------------------
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const v2f gcv2f;
+typedef __attribute__((address_space(1))) v2f gv2f;
+
+template <int Q>
+__device__ __forceinline__ float bf16_pop(gcf *__restrict__ b, int pitch, int s, int i, int64_t row, int x,
+                                          float r) {
+  gcu16 *dv = (gcu16 *)b;
+  const int64_t k = 2 * (row + (int64_t)(1 + i) * pitch + x) + s;
+  return __builtin_fmaf((float)Lat<Q>::w[i], r, bf16_to_f32(dv[k]));
+}
+
+template <int Q, int ST>
+__device__ __forceinline__ float pop_get(gcf *__restrict__ b, int pitch, int s, int i, int64_t row, int x) {
+  if constexpr (ST == 0) {
+    return b[row + (int64_t)(s * Q + i) * pitch + x];
+  } else {
+    const float r = b[row + 2 * (int64_t)x + s];
+    if (i == 0) {
+      // the rest population closes the node's mass: rho - sum of the others,
+      // reconstructed exactly as a pull elsewhere reconstructs them
+      float sum = 0.f;
+#pragma unroll
+      for (int j = 1; j < Q; ++j) sum += bf16_pop<Q>(b, pitch, s, j, row, x, r);
+      return r - sum;
+    }
+    return bf16_pop<Q>(b, pitch, s, i, row, x, r);
+  }
+}
+
+// Both components' link i of one node (the same values as two pop_get
+// calls, from one float-pair and one word load per link in BF16).
+template <int Q, int ST>
+__device__ __forceinline__ void pop_get2(gcf *__restrict__ b, int pitch, int i, int64_t row, int x, float &f0,
+                                         float &f1) {
+  if constexpr (ST == 0) {
+    f0 = pop_get<Q, 0>(b, pitch, 0, i, row, x);
+    f1 = pop_get<Q, 0>(b, pitch, 1, i, row, x);
+  } else {
+    const v2f r = *(gcv2f *)(b + row + 2 * (int64_t)x);
+    auto link = [&](int j, float &g0, float &g1) {
+      const uint32_t u = *(gcu32 *)(b + row + (int64_t)(1 + j) * pitch + x);
+      const float w = (float)Lat<Q>::w[j];
+      g0 = __builtin_fmaf(w, r.x, bf16_to_f32((uint16_t)(u & 0xffffu)));
+      g1 = __builtin_fmaf(w, r.y, bf16_to_f32((uint16_t)(u >> 16)));
+    };
+    if (i == 0) {
+      float s0 = 0.f, s1 = 0.f;
+#pragma unroll
+      for (int j = 1; j < Q; ++j) {
+        float g0, g1;
+        link(j, g0, g1);
+        s0 += g0;
+        s1 += g1;
+      }
+      f0 = r.x - s0;
+      f1 = r.y - s1;
+    } else {
+      link(i, f0, f1);
+    }
+  }
+}
+
+// Store both components' post-collision populations of one node.
+template <int Q, int ST>
+__device__ __forceinline__ void pop_store(gf *__restrict__ b, int pitch, int64_t row, int x,
+                                          const float (&f0)[Q], const float (&f1)[Q], float rho1,
+                                          float rho2) {
+  if constexpr (ST == 0) {
+    const uint32_t bo = (uint32_t)x * 4u;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      stg(b + row + (int64_t)i * pitch, bo, f0[i]);
+      stg(b + row + (int64_t)(Q + i) * pitch, bo, f1[i]);
+    }
+  } else {
+    // collision conserves each component's node mass, so rho is stored as is
+    *(gv2f *)(b + row + 2 * (int64_t)x) = v2f{rho1, rho2};
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const float w = (float)Lat<Q>::w[i];
+      const uint32_t u = (uint32_t)f32_to_bf16(f0[i] - w * rho1) | ((uint32_t)f32_to_bf16(f1[i] - w * rho2) << 16);
+      *(gu32 *)(b + row + (int64_t)(1 + i) * pitch + x) = u;
+    }
+  }
+}
+
+// Inlet/outlet completion of one pulled node (links already pulled).
+template <int Q, int ST, typename R>
+__device__ __forceinline__ void complete(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int x,
+                                         int y, int z, float (&f0)[Q], float (&f1)[Q]) {
+  const int t = y + d.ny * z;
+  const int64_t nt = (int64_t)d.ny * d.nz;
+  const int64_t row = y * d.ystride + z * d.zstride;
+  gcf *frz = G(d.frozen);
+  complete_boundary<Q, R>(
+      d, info, f0, f1, [&](int s, int i) { return pop_get<Q, ST>(fin, d.pitch, s, i, row, x); },
+      [&](int s, int i) { return frz[(int64_t)(s * Q + i) * nt + t]; });
+}
+
+// ---------------------------------------------------------------------------
+// Streaming.  f_i(x) = f*_i(x - e_i), or f*_opp(i)(x) where x - e_i is solid.
+// FP32 storage keeps the bounce-back values in ghost slots: when fluid node x
+// stores its post-collision state, it also writes f*_opp(i)(x) into link i's
+// slot of each solid source node x - e_i.  A slot (i, s) of a solid node s has
+// exactly one writer (x = s + e_i), so every pull is the uniform
+// f_i(x) = buf[i][x - e_i].  BF16 storage reads the node's own opposite slot.
+// Sources wrap periodically; a wrapped source across an open face is a
+// missing link whose value the inlet/outlet completion overwrites.
+// ---------------------------------------------------------------------------
+
+// Source row offsets (in floats) for a node row (y, z): src[ey+1][ez+1] is
+// the row of (y - ey, z - ez) with periodic wrap.  Uniform across a wave when
+// y and z are.
+// A value the caller knows to be equal across the wave, marked as such so
+// that addresses built from it stay in scalar registers.
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// UNI: the caller guarantees (y, z) is the same for every active lane.
+template <int Q, bool UNI = false>
+__device__ __forceinline__ void source_rows(const InstDev &d, int y, int z, int64_t (&src)[3][3]) {
+  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
+  const int ys[3] = {yp, y, ym}, zs[3] = {zp, z, zm};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      const int64_t v = ys[a] * d.ystride + zs[b] * d.zstride;
+      src[a][b] = UNI ? uniform64(v) : v;
+    }
+}
+
+// Source x for e_x = -1, 0, +1 (periodic wrap).
+__device__ __forceinline__ void source_x(const InstDev &d, int x, int (&xs)[3]) {
+  xs[0] = x == d.nx - 1 ? 0 : x + 1;
+  xs[1] = x;
+  xs[2] = x == 0 ? d.nx - 1 : x - 1;
+}
+
+// Pull both components at (x, row src[1][1]) given its source rows.
+template <int Q, int ST>
+__device__ __forceinline__ void pull_row(const InstDev &d, gcf *__restrict__ fin, uint32_t info,
+                                         const int64_t (&src)[3][3], const int (&xs)[3], float (&f0)[Q],
+                                         float (&f1)[Q]) {
+  using L = Lat<Q>;
+  const int pitch = __builtin_amdgcn_readfirstlane(d.pitch);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int64_t row = src[L::ey[i] + 1][L::ez[i] + 1];
+    const int sx = xs[L::ex[i] + 1];
+    if constexpr (ST == 0) {
+      gcf *b = fin + row + (int64_t)i * pitch;
+      const uint32_t bo = (uint32_t)sx * 4u;
+      f0[i] = ldg(b, bo);
+      f1[i] = ldg(b + (int64_t)Q * pitch, bo);
+    } else {
+      const bool bb = (info >> i) & 1u;
+      const int64_t r = bb ? src[1][1] : row;
+      const int x = bb ? xs[1] : sx;
+      const int pi = bb ? L::opp[i] : i;
+      pop_get2<Q, 1>(fin, pitch, pi, r, x, f0[i], f1[i]);
+    }
+  }
+}
+
+// Ghost slots (FP32 storage): link i of each solid source x - e_i receives f*_opp(i)(x).
+template <int Q, int ST>
+__device__ __forceinline__ void store_ghosts(const InstDev &d, gf *__restrict__ fout, uint32_t info,
+                                             const int64_t (&src)[3][3], const int (&xs)[3],
+                                             const float (&f0)[Q], const float (&f1)[Q]) {
+  if constexpr (ST == 0) {
+    using L = Lat<Q>;
+    if (!(info & kLinkMask)) return;
+    const int pitch = d.pitch;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if (info & (1u << i)) {
+        gf *b = fout + src[L::ey[i] + 1][L::ez[i] + 1] + (int64_t)i * pitch;
+        const uint32_t bo = (uint32_t)xs[L::ex[i] + 1] * 4u;
+        stg(b, bo, f0[L::opp[i]]);
+        stg(b + (int64_t)Q * pitch, bo, f1[L::opp[i]]);
+      }
+    }
+  }
+}
+
+// Pull + completion for one fluid node at in-domain (x, y, z) (per-lane rows).
+template <int Q, int ST, typename R>
+__device__ __forceinline__ void gather(const InstDev &d, gcf *__restrict__ fin, uint32_t info,
+                                       int x, int y, int z, float (&f0)[Q], float (&f1)[Q]) {
+  int64_t src[3][3];
+  int xs[3];
+  source_rows<Q>(d, y, z, src);
+  source_x(d, x, xs);
+  pull_row<Q, ST>(d, fin, info, src, xs, f0, f1);
+  if (info & (kInlet | kOutlet)) complete<Q, ST, R>(d, fin, info, x, y, z, f0, f1);
+}
+
+// Periodic image of a tile-region coordinate.  A tile's halo (and the
+// unused tail of the last tile) can lie more than one period away when the
+// periodic extent is smaller than the tile, so this is a true modulo.
+__device__ __forceinline__ int wrap_index(int v, int n) {
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; renumber them so each XCD
+// works on a contiguous range of tiles and neighbouring tiles share its L2.
+__device__ __forceinline__ int xcd_block() {
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int q8 = nb >> 3, r8 = nb & 7, xcd = b & 7;
+  return xcd * q8 + min(xcd, r8) + (b >> 3);
+}
+
+// Compact index of fluid node (x, row), row = y + ny * z.  For a solid
+// position it is the index of the next fluid node (at most nf).
+__device__ __forceinline__ int64_t crank(const InstDev &d, int x, int64_t row) {
+  const RowWord w = d.cword[row * (d.pitch >> 6) + (x >> 6)];
+  const unsigned long long below = (1ull << (x & 63)) - 1ull;
+  return w.pre + __popcll(w.bits & below);
+}
+
+// Pull of D2Q9 fluid node (x, y) in the compacted layout (f*[s][i][c] over
+// fluid nodes); c receives the node's compact index.
+// The rank of column x in each source row gives every fluid source's index
+// (x - 1: rank - 1; x + 1: rank + the column's fluid bit); bounce-back reads
+// the node's own opposite slot; wrapped x sources are ranked directly.
+template <int ST>
+__device__ __forceinline__ void cpull9(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int x, int y,
+                                       const int (&xs)[3], int32_t &c, float (&f0)[9], float (&f1)[9]) {
+  using L = Lat<9>;
+  const int cp = d.cpitch, ny = d.ny;
+  const int ys[3] = {y == ny - 1 ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};  // y - e_y, by e_y + 1
+  const int64_t wpr = d.pitch >> 6;
+  const unsigned long long below = (1ull << (x & 63)) - 1ull;
+  int32_t rk[3];
+  int fl[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const RowWord w = d.cword[ys[a] * wpr + (x >> 6)];
+    rk[a] = (int32_t)(w.pre + __popcll(w.bits & below));
+    fl[a] = (int)((w.bits >> (x & 63)) & 1ull);
+  }
+  c = rk[1];
+  const bool x_edge = x == 0 || x == d.nx - 1;
+  const int32_t last = (int32_t)(d.nf - 1);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    int32_t sc = c;
+    int pi = i;
+    if (i != 0) {
+      if ((info >> i) & 1u) {
+        pi = L::opp[i];
+      } else {
+        const int a = L::ey[i] + 1;
+        if (L::ex[i] == 0) {
+          sc = rk[a];
+        } else if (!x_edge) {
+          sc = L::ex[i] > 0 ? rk[a] - 1 : rk[a] + fl[a];
+        } else {
+          // wrapped source: periodic x, or a missing link at an open face
+          // (an arbitrary node, overwritten by the completion below)
+          const int32_t r = (int32_t)crank(d, xs[L::ex[i] + 1], ys[a]);
+          sc = r < last ? r : last;
+        }
+      }
+    }
+    if constexpr (ST == 0) {
+      const uint32_t bo = ((uint32_t)pi * (uint32_t)cp + (uint32_t)sc) * 4u;
+      f0[i] = ldg(fin, bo);
+      f1[i] = ldg(fin + (int64_t)9 * cp, bo);
+    } else {
+      pop_get2<9, ST>(fin, cp, pi, 0, (int)sc, f0[i], f1[i]);
+    }
+  }
+}
+
+// Inlet/outlet completion of a D2Q9 node pulled by cpull9 (compact index c).
+template <int ST, typename R>
+__device__ __forceinline__ void ccomplete9(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int y,
+                                           int32_t c, float (&f0)[9], float (&f1)[9]) {
+  gcf *frz = G(d.frozen);
+  const int cp = d.cpitch, ny = d.ny;
+  complete_boundary<9, R>(
+      d, info, f0, f1, [&](int s, int i) { return pop_get<9, ST>(fin, cp, s, i, 0, (int)c); },
+      [&](int s, int i) { return frz[(int64_t)(s * 9 + i) * ny + y]; });
+}
+
+// ---------------------------------------------------------------------------
+// D2Q9 fused step.  Block = 4 waves over a region of 64 columns x (TY + 4)
+// rows: 60 x TY interior nodes plus a 2-node halo.  Wave w owns interior rows
+// 2 + w + 4k (k < TY/4) and one halo row; a row is wave-uniform, so every pull
+// is one load from a scalar row base plus the lane's x.
+// Phase 1: pull + complete + densities for all region nodes -> LDS.
+// Phase 2: virtual solid density (Eq. 17) in place at solid region nodes.
+// Phase 3: force (Eq. 13 with the open-face mirror) and collision for the
+//          interior nodes, whose pulled populations stayed in registers.
+// ---------------------------------------------------------------------------
+// Occupancy: TY = 8 fits 128 registers (four waves per SIMD) with every
+// pulled row in registers.  TY = 12 parks the last interior row of each wave
+// in LDS between the phases, which fits it in 128 registers and 35 KB of LDS
+// (four blocks per CU) instead of three waves per SIMD.
+template <int TY> struct FusedShape {
+  static constexpr int kParked = TY == 12 ? 1 : 0;  // interior rows per wave kept in LDS
+  static constexpr int kWaves = TY == 16 ? 1 : 4;
+};
+
+// CL = 1: the same step over the compacted layout (fluid nodes only stored,
+// pulls by rank, bounce-back from the node's own slots, no ghost slots).
+template <int COLL, int ST, typename R, int TY, int CL = 0>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FusedShape<TY>::kWaves))) void step_d2q9(
+    const InstDev *__restrict__ insts, const int32_t *__restrict__ block_inst, int parity) {
+  using L = Lat<9>;
+  using V = Vec2<R>;
+  constexpr int KR = TY / 4;        // interior rows per wave
+  constexpr int kRH = TY + 4;       // region rows
+  constexpr int KP = FusedShape<TY>::kParked;
+  __shared__ V psi[kRH][64];
+  __shared__ float park[KP > 0 ? KP * 4 : 1][18][64];  // [row slot * 4 + wave][component * 9 + link][lane]
+
+  const int bid = xcd_block();
+  const int inst = __builtin_amdgcn_readfirstlane(block_inst ? block_inst[bid] : 0);
+  const InstDev &d = insts[inst];
+  const int lb = bid - d.block_base;
+  const int tx = lb % d.tiles_x, ty = lb / d.tiles_x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  gcf *__restrict__ fin = G(d.f[parity]);
+  gf *__restrict__ fout = G(d.f[parity ^ 1]);
+  gcu32 *__restrict__ infop = (gcu32 *)d.info;
+  const int nx = d.nx, ny = d.ny;
+  const bool px = d.periodic & 1, py = d.periodic & 2;
+
+  // region column of this lane
+  int gx = tx * kTileX - 2 + lane;
+  const bool col_store = lane >= 2 && lane < 62 && gx < nx;
+  bool col_in = true;
+  if (gx < 0 || gx >= nx) {
+    if (px) gx = wrap_index(gx, nx);
+    else col_in = false;
+  }
+  const int gxa = col_in ? gx : (gx < 0 ? 0 : nx - 1);
+  int xs[3];
+  source_x(d, gxa, xs);
+
+  // rows owned (wave-uniform): k < KR interior (2 + wave + 4k), k = KR halo
+  int rows[KR + 1], gy[KR + 1];
+  bool row_in[KR + 1];
+#pragma unroll
+  for (int k = 0; k <= KR; ++k) {
+    rows[k] = k < KR ? 2 + wave + 4 * k : (wave < 2 ? wave : TY + wave);
+    int y = ty * TY - 2 + rows[k];
+    bool in = true;
+    if (y < 0 || y >= ny) {
+      if (py) y = wrap_index(y, ny);
+      else in = false;
+    }
+    gy[k] = in ? y : 0;
+    row_in[k] = in;
+  }
+  uint32_t info[KR + 1];
+#pragma unroll
+  for (int k = 0; k <= KR; ++k)
+    info[k] = (row_in[k] && col_in) ? infop[gx + (int64_t)d.pitch * gy[k]] : kSolid;
+
+  // Phase 1: issue every pull of this thread, then complete and sum.  Solid
+  // and out-of-domain lanes read valid addresses in the same rows and discard
+  // them (the BF16 layout pulls only for fluid lanes, to bound the loads in
+  // flight).
+  float f0[KR][9], f1[KR][9], h0[9], h1[9];
+  int64_t srow[KR + 1][3][3];
+  int32_t cidx[KR + 1];  // compact indices (CL)
+  if constexpr (CL) {
+#pragma unroll
+    for (int k = 0; k <= KR; ++k) {
+      float(&a)[9] = k < KR ? f0[k < KR ? k : 0] : h0;
+      float(&b)[9] = k < KR ? f1[k < KR ? k : 0] : h1;
+      cidx[k] = 0;
+      if (!(info[k] & kSolid)) cpull9<ST>(d, fin, info[k], gx, gy[k], xs, cidx[k], a, b);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k <= KR; ++k) source_rows<9, true>(d, gy[k], 0, srow[k]);
+#pragma unroll
+    for (int k = 0; k < KR; ++k)
+      if (ST == 0 || !(info[k] & kSolid)) pull_row<9, ST>(d, fin, info[k], srow[k], xs, f0[k], f1[k]);
+    if (ST == 0 || !(info[KR] & kSolid)) pull_row<9, ST>(d, fin, info[KR], srow[KR], xs, h0, h1);
+  }
+#pragma unroll
+  for (int k = 0; k <= KR; ++k) {
+    R rho1 = 0, rho2 = 0;
+    if (!(info[k] & kSolid)) {
+      float(&a)[9] = k < KR ? f0[k < KR ? k : 0] : h0;
+      float(&b)[9] = k < KR ? f1[k < KR ? k : 0] : h1;
+      if (info[k] & (kInlet | kOutlet)) {
+        if constexpr (CL) ccomplete9<ST, R>(d, fin, info[k], gy[k], cidx[k], a, b);
+        else complete<9, ST, R>(d, fin, info[k], gx, gy[k], 0, a, b);
+      }
+      rho1 = sum_q<9, R>(a);
+      rho2 = sum_q<9, R>(b);
+    }
+    psi[rows[k]][lane] = V{rho1, rho2};
+    if (k >= KR - KP && k < KR) {
+      float(&pk)[18][64] = park[(k - (KR - KP)) * 4 + wave];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        pk[i][lane] = f0[k < KR ? k : 0][i];
+        pk[9 + i][lane] = f1[k < KR ? k : 0][i];
+      }
+    }
+  }
+  __syncthreads();
+
+  // Phase 2: psi at solid nodes = chi^s * weighted mean of fluid-neighbour rho^s
+#pragma unroll
+  for (int k = 0; k <= KR; ++k) {
+    const int r = rows[k];
+    if (!row_in[k] || !col_in || !(info[k] & kSolid) || r < 1 || r > kRH - 2 || lane < 1 || lane > 62)
+      continue;
+    const uint32_t nb = info[k];
+    if (!(nb & kLinkMask)) continue;
+    R s1 = 0, s2 = 0, den = 0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      if (nb & (1u << i)) {
+        const V p = psi[r + L::ey[i]][lane + L::ex[i]];
+        const R w = (R)L::w[i];
+        s1 += w * p.x;
+        s2 += w * p.y;
+        den += w;
+      }
+    }
+    const R inv = rcp<R>(den);
+    psi[r][lane] = V{(R)d.chi1 * s1 * inv, (R)d.chi2 * s2 * inv};
+  }
+  __syncthreads();
+
+  // Phase 3: force + collision for interior rows
+  const R w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+#pragma unroll
+  for (int k = 0; k < KR; ++k) {
+    const int r = rows[k];
+    const int gy_raw = ty * TY - 2 + r;
+    if (!row_in[k] || !col_store || gy_raw >= ny || (info[k] & kSolid)) continue;
+    const uint32_t inf = info[k];
+    const V c = psi[r][lane];
+    const R rho1 = c.x, rho2 = c.y;
+    // sum_i w_i psi(x + e_i) e_i by opposite pairs
+    R sx1, sy1, sx2, sy2;  // sums of component 1's / 2's psi
+    {
+      const V p2 = psi[r + 1][lane], p4 = psi[r - 1][lane];
+      if (inf & (kInlet | kOutlet)) {
+        // mirrored neighbours cancel every pair with an x component
+        sx1 = 0;
+        sx2 = 0;
+        sy1 = w1 * (p2.x - p4.x);
+        sy2 = w1 * (p2.y - p4.y);
+      } else {
+        const V p1 = psi[r][lane + 1], p3 = psi[r][lane - 1];
+        const V p5 = psi[r + 1][lane + 1], p7 = psi[r - 1][lane - 1];
+        const V p6 = psi[r + 1][lane - 1], p8 = psi[r - 1][lane + 1];
+        const R a57 = p5.x - p7.x, a68 = p6.x - p8.x;
+        const R b57 = p5.y - p7.y, b68 = p6.y - p8.y;
+        sx1 = w1 * (p1.x - p3.x) + w5 * (a57 - a68);
+        sy1 = w1 * (p2.x - p4.x) + w5 * (a57 + a68);
+        sx2 = w1 * (p1.y - p3.y) + w5 * (b57 - b68);
+        sy2 = w1 * (p2.y - p4.y) + w5 * (b57 + b68);
+      }
+    }
+    const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy;
+    const R F1x = -G_ * rho1 * sx2 + rho1 * gxb, F1y = -G_ * rho1 * sy2 + rho1 * gyb;
+    const R F2x = -G_ * rho2 * sx1 + rho2 * gxb, F2y = -G_ * rho2 * sy1 + rho2 * gyb;
+    if (k >= KR - KP) {
+      const float(&pk)[18][64] = park[(k - (KR - KP)) * 4 + wave];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        f0[k][i] = pk[i][lane];
+        f1[k][i] = pk[9 + i][lane];
+      }
+    }
+    collide_node<9, COLL, R>(d, f0[k], f1[k], rho1, rho2, F1x, F1y, R(0), F2x, F2y, R(0));
+    if constexpr (CL) {
+      pop_store<9, ST>(fout, d.cpitch, 0, cidx[k], f0[k], f1[k], (float)rho1, (float)rho2);
+    } else {
+      pop_store<9, ST>(fout, d.pitch, uniform64(gy_raw * d.ystride), gx, f0[k], f1[k], (float)rho1, (float)rho2);
+      store_ghosts<9, ST>(d, fout, inf, srow[k], xs, f0[k], f1[k]);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// D2Q9 fused step with a listed collision phase.  Phases 1 and 2 as in the
+// fused step; in phase 1 every interior fluid node also parks its pulled
+// (and completed) populations and its info word in LDS, dense by interior
+// position.  Phase 3 runs over a per-tile list of the fluid interior nodes
+// (row-major, built from ballots and a fixed-order prefix in LDS), one list
+// entry per thread, so no lane spends the collision on a solid node.  The
+// arithmetic is the fused step's, value for value.
+// LDS: populations 72 B per interior node (34.6 KB at TY = 8) + densities.
+// ---------------------------------------------------------------------------
+template <int COLL, int ST, typename R, int TY>
+__global__ __launch_bounds__(256) void step_d2q9_list(const InstDev *__restrict__ insts,
+                                                      const int32_t *__restrict__ block_inst, int parity) {
+  using L = Lat<9>;
+  using V = Vec2<R>;
+  constexpr int KR = TY / 4;
+  constexpr int kRH = TY + 4;
+  constexpr int kN = TY * kTileX;   // interior nodes of a tile
+  __shared__ V psi[kRH][64];
+  __shared__ float pops[18][kN];    // [component * 9 + link][interior position]
+  __shared__ uint32_t pinfo[kN];
+  __shared__ uint16_t list[kN];     // interior positions of the fluid nodes, row-major
+  __shared__ int cnt[TY];
+
+  const int bid = xcd_block();
+  const int inst = __builtin_amdgcn_readfirstlane(block_inst ? block_inst[bid] : 0);
+  const InstDev &d = insts[inst];
+  const int lb = bid - d.block_base;
+  const int tx = lb % d.tiles_x, ty = lb / d.tiles_x;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  gcf *__restrict__ fin = G(d.f[parity]);
+  gf *__restrict__ fout = G(d.f[parity ^ 1]);
+  gcu32 *__restrict__ infop = (gcu32 *)d.info;
+  const int nx = d.nx, ny = d.ny;
+  const bool px = d.periodic & 1, py = d.periodic & 2;
+
+  int gx = tx * kTileX - 2 + lane;
+  const bool col_store = lane >= 2 && lane < 62 && gx < nx;
+  bool col_in = true;
+  if (gx < 0 || gx >= nx) {
+    if (px) gx = wrap_index(gx, nx);
+    else col_in = false;
+  }
+  const int gxa = col_in ? gx : (gx < 0 ? 0 : nx - 1);
+  int xs[3];
+  source_x(d, gxa, xs);
+
+  int rows[KR + 1], gy[KR + 1];
+  bool row_in[KR + 1];
+#pragma unroll
+  for (int k = 0; k <= KR; ++k) {
+    rows[k] = k < KR ? 2 + wave + 4 * k : (wave < 2 ? wave : TY + wave);
+    int y = ty * TY - 2 + rows[k];
+    bool in = true;
+    if (y < 0 || y >= ny) {
+      if (py) y = wrap_index(y, ny);
+      else in = false;
+    }
+    gy[k] = in ? y : 0;
+    row_in[k] = in;
+  }
+  uint32_t info[KR + 1];
+#pragma unroll
+  for (int k = 0; k <= KR; ++k)
+    info[k] = (row_in[k] && col_in) ? infop[gx + (int64_t)d.pitch * gy[k]] : kSolid;
+
+  // Phase 1: pull every row of this thread, then complete, sum, and park the
+  // interior fluid nodes' populations
+  {
+    float f0[KR + 1][9], f1[KR + 1][9];
+    int64_t srow[KR + 1][3][3];
+#pragma unroll
+    for (int k = 0; k <= KR; ++k) source_rows<9, true>(d, gy[k], 0, srow[k]);
+#pragma unroll
+    for (int k = 0; k <= KR; ++k)
+      if (ST == 0 || !(info[k] & kSolid)) pull_row<9, ST>(d, fin, info[k], srow[k], xs, f0[k], f1[k]);
+#pragma unroll
+    for (int k = 0; k <= KR; ++k) {
+      R rho1 = 0, rho2 = 0;
+      if (!(info[k] & kSolid)) {
+        if (info[k] & (kInlet | kOutlet)) complete<9, ST, R>(d, fin, info[k], gx, gy[k], 0, f0[k], f1[k]);
+        rho1 = sum_q<9, R>(f0[k]);
+        rho2 = sum_q<9, R>(f1[k]);
+      }
+      psi[rows[k]][lane] = V{rho1, rho2};
+      if (k < KR) {
+        const bool fluid = row_in[k] && col_store && ty * TY - 2 + rows[k] < ny && !(info[k] & kSolid);
+        if (fluid) {
+          const int pos = (rows[k] - 2) * kTileX + lane - 2;
+#pragma unroll
+          for (int i = 0; i < 9; ++i) {
+            pops[i][pos] = f0[k][i];
+            pops[9 + i][pos] = f1[k][i];
+          }
+          pinfo[pos] = info[k];
+        }
+        const unsigned long long m = __ballot(fluid);
+        if (lane == 0) cnt[rows[k] - 2] = __popcll(m);
+      }
+    }
+  }
+  __syncthreads();
+
+  // Phase 2: virtual solid density; the list of fluid interior nodes
+#pragma unroll
+  for (int k = 0; k <= KR; ++k) {
+    const int r = rows[k];
+    const uint32_t nb = info[k];
+    if (k < KR) {
+      const bool fluid = row_in[k] && col_store && ty * TY - 2 + r < ny && !(nb & kSolid);
+      const unsigned long long m = __ballot(fluid);
+      int base = 0;
+      for (int q = 0; q < r - 2; ++q) base += cnt[q];
+      if (fluid) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (uint16_t)((r - 2) * kTileX + lane - 2);
+    }
+    if (!row_in[k] || !col_in || !(nb & kSolid) || r < 1 || r > kRH - 2 || lane < 1 || lane > 62) continue;
+    if (!(nb & kLinkMask)) continue;
+    R s1 = 0, s2 = 0, den = 0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      if (nb & (1u << i)) {
+        const V p = psi[r + L::ey[i]][lane + L::ex[i]];
+        const R w = (R)L::w[i];
+        s1 += w * p.x;
+        s2 += w * p.y;
+        den += w;
+      }
+    }
+    const R inv = rcp<R>(den);
+    psi[r][lane] = V{(R)d.chi1 * s1 * inv, (R)d.chi2 * s2 * inv};
+  }
+  int total = 0;
+#pragma unroll
+  for (int q = 0; q < TY; ++q) total += cnt[q];
+  __syncthreads();
+
+  // Phase 3: force + collision over the list.  Stores address the tile's
+  // first interior row (wave-uniform) plus a 32-bit byte offset; the host
+  // keeps TY row blocks within 2^31 bytes for this strategy.
+  const R w1 = R(1.0 / 9.0), w5 = R(1.0 / 36.0);
+  gf *const tile_out = fout + uniform64((int64_t)ty * TY * d.ystride);
+  const int pitch = __builtin_amdgcn_readfirstlane(d.pitch);
+  const uint32_t ystride = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)d.ystride);
+  for (int t = threadIdx.x; t < total; t += 256) {
+    const int pos = list[t];
+    const int ri = pos / kTileX, ci = pos - ri * kTileX;
+    const int r = ri + 2, ln = ci + 2;
+    const int x = tx * kTileX + ci, y = ty * TY + ri;
+    const uint32_t inf = pinfo[pos];
+    float f0[9], f1[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      f0[i] = pops[i][pos];
+      f1[i] = pops[9 + i][pos];
+    }
+    const V c = psi[r][ln];
+    const R rho1 = c.x, rho2 = c.y;
+    R sx1, sy1, sx2, sy2;
+    {
+      const V p2 = psi[r + 1][ln], p4 = psi[r - 1][ln];
+      if (inf & (kInlet | kOutlet)) {
+        sx1 = 0;
+        sx2 = 0;
+        sy1 = w1 * (p2.x - p4.x);
+        sy2 = w1 * (p2.y - p4.y);
+      } else {
+        const V p1 = psi[r][ln + 1], p3 = psi[r][ln - 1];
+        const V p5 = psi[r + 1][ln + 1], p7 = psi[r - 1][ln - 1];
+        const V p6 = psi[r + 1][ln - 1], p8 = psi[r - 1][ln + 1];
+        const R a57 = p5.x - p7.x, a68 = p6.x - p8.x;
+        const R b57 = p5.y - p7.y, b68 = p6.y - p8.y;
+        sx1 = w1 * (p1.x - p3.x) + w5 * (a57 - a68);
+        sy1 = w1 * (p2.x - p4.x) + w5 * (a57 + a68);
+        sx2 = w1 * (p1.y - p3.y) + w5 * (b57 - b68);
+        sy2 = w1 * (p2.y - p4.y) + w5 * (b57 + b68);
+      }
+    }
+    const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy;
+    const R F1x = -G_ * rho1 * sx2 + rho1 * gxb, F1y = -G_ * rho1 * sy2 + rho1 * gyb;
+    const R F2x = -G_ * rho2 * sx1 + rho2 * gxb, F2y = -G_ * rho2 * sy1 + rho2 * gyb;
+    collide_node<9, COLL, R>(d, f0, f1, rho1, rho2, F1x, F1y, R(0), F2x, F2y, R(0));
+    if constexpr (ST == 0) {
+      const uint32_t bo = ((uint32_t)ri * ystride + (uint32_t)x) * 4u;
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        stg(tile_out + (int64_t)i * pitch, bo, f0[i]);
+        stg(tile_out + (int64_t)(9 + i) * pitch, bo, f1[i]);
+      }
+    } else {
+      pop_store<9, ST>(fout, d.pitch, y * d.ystride, x, f0, f1, (float)rho1, (float)rho2);
+    }
+    if (inf & kLinkMask) {
+      int64_t src[3][3];
+      int xsl[3];
+      source_rows<9>(d, y, 0, src);
+      source_x(d, x, xsl);
+      store_ghosts<9, ST>(d, fout, inf, src, xsl, f0, f1);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// D3Q19 fused step.  A block owns a 60 x kTileY3 column of (x, y) and marches
+// through a chunk of z.  Per plane it keeps densities of the 64 x (kTileY3+4)
+// region in an LDS ring of five planes (z-2 .. z+2): at plane z it forms rho of
+// plane z+2, psi at the solid nodes of plane z+1, and collides plane z.  The
+// interior populations of plane z are pulled again for the collision (they
+// were fetched two planes earlier and come from cache), which keeps the
+// register footprint small.  Wave w owns interior rows 2+w and 6+w and one
+// halo row; rows and planes are wave-uniform.
+// ---------------------------------------------------------------------------
+constexpr int kRH3 = kTileY3 + 4;
+constexpr int kRing = 5;
+
+__device__ __forceinline__ int ring(int z) { return ((z % kRing) + kRing) % kRing; }
+
+template <int COLL, int ST, typename R>
+__global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ insts,
+                                                   const int32_t *__restrict__ block_inst, int parity) {
+  using L = Lat<19>;
+  using V = Vec2<R>;
+  __shared__ V psi[kRing][kRH3][64];
+
+  const int bid = xcd_block();
+  const int inst = __builtin_amdgcn_readfirstlane(block_inst ? block_inst[bid] : 0);
+  const InstDev &d = insts[inst];
+  const int lb = bid - d.block_base;
+  const int tx = lb % d.tiles_x, ty = (lb / d.tiles_x) % d.tiles_y;
+  const int zc = lb / (d.tiles_x * d.tiles_y);  // z chunk
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  gcf *__restrict__ fin = G(d.f[parity]);
+  gf *__restrict__ fout = G(d.f[parity ^ 1]);
+  gcu32 *__restrict__ infop = (gcu32 *)d.info;
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const bool px = d.periodic & 1, py = d.periodic & 2, pz = d.periodic & 4;
+  const int zlen = (nz + d.tiles_z - 1) / d.tiles_z;
+  const int z0 = zc * zlen, z1 = min(nz, z0 + zlen);
+  const int64_t islab = (int64_t)d.pitch * ny;
+
+  int gx = tx * kTileX - 2 + lane;
+  const bool col_store = lane >= 2 && lane < 62 && gx < nx;
+  bool col_in = true;
+  if (gx < 0 || gx >= nx) {
+    if (px) gx = wrap_index(gx, nx);
+    else col_in = false;
+  }
+  const int gxa = col_in ? gx : (gx < 0 ? 0 : nx - 1);
+  int xs[3];
+  source_x(d, gxa, xs);
+  // rows of this wave (uniform): interior rows 2+w, 6+w (k = 0, 1) and a halo row (k = 2)
+  int rows[3], gy[3], gy_raw[3];
+  bool row_in[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    rows[k] = k < 2 ? 2 + wave + 4 * k : (wave < 2 ? wave : kTileY3 + wave);
+    int y = ty * kTileY3 - 2 + rows[k];
+    gy_raw[k] = y;
+    bool in = true;
+    if (y < 0 || y >= ny) {
+      if (py) y = wrap_index(y, ny);
+      else in = false;
+    }
+    gy[k] = in ? y : 0;
+    row_in[k] = in;
+  }
+
+  // plane index with periodic wrap; false if outside a closed z edge
+  auto wrap_z = [&](int zp, int &zz) __attribute__((always_inline)) -> bool {
+    zz = zp;
+    if (zz < 0 || zz >= nz) {
+      if (pz) { zz = wrap_index(zz, nz); return true; }
+      zz = 0;
+      return false;
+    }
+    return true;
+  };
+
+  // densities of the region rows of plane zp -> LDS ring
+  auto load_plane = [&](int zp) __attribute__((always_inline)) {
+    const int slot = ring(zp);
+    int zz;
+    const bool zin = wrap_z(zp, zz);
+    uint32_t inf[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+      inf[k] = (row_in[k] && col_in && zin) ? infop[gx + (int64_t)d.pitch * gy[k] + islab * zz] : kSolid;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      R rho1 = 0, rho2 = 0;
+      if (!(inf[k] & kSolid)) {
+        int64_t src[3][3];
+        source_rows<19, true>(d, gy[k], zz, src);
+        float a[19], b[19];
+        pull_row<19, ST>(d, fin, inf[k], src, xs, a, b);
+        if (inf[k] & (kInlet | kOutlet)) complete<19, ST, R>(d, fin, inf[k], gx, gy[k], zz, a, b);
+        rho1 = sum_q<19, R>(a);
+        rho2 = sum_q<19, R>(b);
+      }
+      psi[slot][rows[k]][lane] = V{rho1, rho2};
+    }
+  };
+
+  // virtual solid density (Eq. 17) at the solid nodes of plane zp, in place;
+  // reads rho at planes zp-1 .. zp+1
+  auto solid_psi = [&](int zp) __attribute__((always_inline)) {
+    const int slot = ring(zp);
+    int zz;
+    if (!wrap_z(zp, zz)) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const int r = rows[k];
+      if (!row_in[k] || !col_in || r < 1 || r > kRH3 - 2 || lane < 1 || lane > 62) continue;
+      const uint32_t nb = infop[gx + (int64_t)d.pitch * gy[k] + islab * zz];
+      if (!(nb & kSolid) || !(nb & kLinkMask)) continue;
+      R s1 = 0, s2 = 0, den = 0;
+#pragma unroll
+      for (int i = 1; i < 19; ++i) {
+        if (nb & (1u << i)) {
+          const V p = psi[ring(zp + L::ez[i])][r + L::ey[i]][lane + L::ex[i]];
+          const R w = (R)L::w[i];
+          s1 += w * p.x;
+          s2 += w * p.y;
+          den += w;
+        }
+      }
+      const R inv = rcp<R>(den);
+      psi[slot][r][lane] = V{(R)d.chi1 * s1 * inv, (R)d.chi2 * s2 * inv};
+    }
+  };
+
+  // force (Eq. 13 with the open-face mirror) + collision + store, plane z
+  auto collide_plane = [&](int z) __attribute__((always_inline)) {
+#pragma unroll 1
+    for (int k = 0; k < 2; ++k) {
+      if (!col_store || !row_in[k] || gy_raw[k] >= ny) continue;
+      const int ri = rows[k];
+      const uint32_t inf = infop[gx + (int64_t)d.pitch * gy[k] + islab * z];
+      if (inf & kSolid) continue;
+      int64_t src[3][3];
+      source_rows<19, true>(d, gy[k], z, src);
+      float a[19], b[19];
+      pull_row<19, ST>(d, fin, inf, src, xs, a, b);
+      if (inf & (kInlet | kOutlet)) complete<19, ST, R>(d, fin, inf, gx, gy[k], z, a, b);
+      const V c = psi[ring(z)][ri][lane];
+      const R rho1 = c.x, rho2 = c.y;
+      R sx1 = 0, sy1 = 0, sz1 = 0, sx2 = 0, sy2 = 0, sz2 = 0;
+      const bool open_face = (inf & (kInlet | kOutlet)) != 0;
+#pragma unroll
+      for (int i = 1; i < 19; ++i) {
+        if (L::opp[i] < i) continue;
+        const int o = L::opp[i];
+        if (open_face && L::ex[i] != 0) continue;  // mirrored pair cancels
+        const V pa = psi[ring(z + L::ez[i])][ri + L::ey[i]][lane + L::ex[i]];
+        const V pb = psi[ring(z + L::ez[o])][ri + L::ey[o]][lane + L::ex[o]];
+        const R w = (R)L::w[i];
+        const R d1 = w * (pa.x - pb.x), d2 = w * (pa.y - pb.y);
+        if (L::ex[i]) { sx1 += L::ex[i] * d1; sx2 += L::ex[i] * d2; }
+        if (L::ey[i]) { sy1 += L::ey[i] * d1; sy2 += L::ey[i] * d2; }
+        if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
+      }
+      const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
+      collide_node<19, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb,
+                                -G_ * rho1 * sy2 + rho1 * gyb, -G_ * rho1 * sz2 + rho1 * gzb,
+                                -G_ * rho2 * sx1 + rho2 * gxb, -G_ * rho2 * sy1 + rho2 * gyb,
+                                -G_ * rho2 * sz1 + rho2 * gzb);
+      pop_store<19, ST>(fout, d.pitch, uniform64(gy_raw[k] * d.ystride + z * d.zstride), gx, a, b, (float)rho1,
+                        (float)rho2);
+      store_ghosts<19, ST>(d, fout, inf, src, xs, a, b);
+    }
+  };
+
+  // prologue: densities of planes z0-2 .. z0+1, psi of planes z0-1 and z0
+  for (int zp = z0 - 2; zp <= z0 + 1; ++zp) load_plane(zp);
+  __syncthreads();
+  solid_psi(z0 - 1);
+  solid_psi(z0);
+  __syncthreads();
+  for (int z = z0; z < z1; ++z) {
+    load_plane(z + 2);
+    __syncthreads();
+    solid_psi(z + 1);  // needs rho at z .. z+2
+    __syncthreads();
+    collide_plane(z);
+    // ring slot of z-2 is rewritten at z+3: every read of it is behind this barrier
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Split step (three launches) for grids whose per-block working set does not
+// fit the L2: the halo recompute of the fused kernels would then refetch
+// populations from memory.  Each wave owns 64 consecutive x of one (y, z)
+// row (wave-uniform rows), one thread per node.
+//   rho_kernel:     pull + complete -> rho^s(x) into the psi array (double2)
+//   psi_kernel:     virtual solid density (Eq. 17) at solid nodes, in place
+//   collide_kernel: force from psi (Eq. 13 with the open-face mirror), pull
+//                   again, collide, store
+// psi array layout: index x + pitch * (y + ny * z), like the node info.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool wave_row(const InstDev &d, int &x, int &y, int &z) {
+  const int segs = (d.nx + 63) >> 6;
+  const int64_t W = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t row = W / segs;
+  const int seg = (int)(W - row * segs);
+  y = (int)(row % d.ny);
+  z = (int)(row / d.ny);
+  x = seg * 64 + (int)(threadIdx.x & 63);
+  return z < d.nz && x < d.nx;
+}
+
+typedef __attribute__((address_space(1))) double gd;
+typedef __attribute__((address_space(1))) const double gcd;
+
+// psi entries are (rho1, rho2) pairs of doubles
+__device__ __forceinline__ Vec2<double> psi_ld(gcd *p, int64_t j) {
+  return Vec2<double>{p[2 * j], p[2 * j + 1]};
+}
+__device__ __forceinline__ void psi_st(gd *p, int64_t j, double a, double b) {
+  p[2 * j] = a;
+  p[2 * j + 1] = b;
+}
+
+template <int Q, int ST>
+__global__ __launch_bounds__(256) void rho_kernel(const InstDev *__restrict__ insts, int parity) {
+  const InstDev &d = insts[0];
+  int x, y, z;
+  if (!wave_row(d, x, y, z)) return;
+  const int64_t pi = x + (int64_t)d.pitch * (y + (int64_t)d.ny * z);
+  const uint32_t info = ((gcu32 *)d.info)[pi];
+  if (info & kSolid) return;
+  gcf *__restrict__ fin = G(d.f[parity]);
+  int64_t src[3][3];
+  int xs[3];
+  source_rows<Q, true>(d, y, z, src);  // one row per wave
+  source_x(d, x, xs);
+  float a[Q], b[Q];
+  pull_row<Q, ST>(d, fin, info, src, xs, a, b);
+  if (info & (kInlet | kOutlet)) complete<Q, ST, double>(d, fin, info, x, y, z, a, b);
+  psi_st((gd *)d.psi, pi, sum_q<Q, double>(a), sum_q<Q, double>(b));
+}
+
+// Virtual solid density (Eq. 17) of solid node (x, y, z), dense index pi,
+// whose fluid neighbours are flagged in nb.
+template <int Q>
+__device__ __forceinline__ void ivsd_node(const InstDev &d, int x, int y, int z, int64_t pi, uint32_t nb) {
+  using L = Lat<Q>;
+  gd *__restrict__ psi = (gd *)d.psi;
+  int xs[3];
+  source_x(d, x, xs);  // xs[1 - e_x]: x + e_x with wrap
+  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
+  const int yy[3] = {ym, y, yp}, zz[3] = {zm, z, zp};  // index by e + 1
+  double s1 = 0, s2 = 0, den = 0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (nb & (1u << i)) {
+      const int64_t j = xs[1 - L::ex[i]] + (int64_t)d.pitch * (yy[L::ey[i] + 1] + (int64_t)d.ny * zz[L::ez[i] + 1]);
+      const Vec2<double> p = psi_ld(psi, j);
+      s1 += L::w[i] * p.x;
+      s2 += L::w[i] * p.y;
+      den += L::w[i];
+    }
+  }
+  const double inv = rcp<double>(den);
+  psi_st(psi, pi, d.chi1 * s1 * inv, d.chi2 * s2 * inv);
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void psi_kernel(const InstDev *__restrict__ insts) {
+  const InstDev &d = insts[0];
+  int x, y, z;
+  if (!wave_row(d, x, y, z)) return;
+  const int64_t pi = x + (int64_t)d.pitch * (y + (int64_t)d.ny * z);
+  const uint32_t nb = ((gcu32 *)d.info)[pi];
+  if (!(nb & kSolid) || !(nb & kLinkMask)) return;
+  ivsd_node<Q>(d, x, y, z, pi, nb);
+}
+
+// Densities at node pi and the pair sums sum_i w_i psi(x + e_i) e_i of the
+// interaction force (Eq. 13); at an open face the mirrored pairs with an x
+// component cancel.
+template <int Q, typename R>
+__device__ __forceinline__ void psi_force_sums(const InstDev &d, int x, int y, int z, int64_t pi,
+                                               uint32_t info, R &rho1, R &rho2, R &sx1, R &sy1, R &sz1,
+                                               R &sx2, R &sy2, R &sz2) {
+  using L = Lat<Q>;
+  gcd *__restrict__ psi = (gcd *)d.psi;
+  int xs[3];
+  source_x(d, x, xs);
+  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
+  const int yy[3] = {ym, y, yp}, zz[3] = {zm, z, zp};
+  const Vec2<double> c = psi_ld(psi, pi);
+  rho1 = (R)c.x;
+  rho2 = (R)c.y;
+  const bool open_face = (info & (kInlet | kOutlet)) != 0;
+  sx1 = 0; sy1 = 0; sz1 = 0; sx2 = 0; sy2 = 0; sz2 = 0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (L::opp[i] < i) continue;
+    const int o = L::opp[i];
+    if (L::ex[i] != 0 && open_face) continue;
+    const int64_t ja = xs[1 - L::ex[i]] + (int64_t)d.pitch * (yy[L::ey[i] + 1] + (int64_t)d.ny * zz[L::ez[i] + 1]);
+    const int64_t jb = xs[1 - L::ex[o]] + (int64_t)d.pitch * (yy[L::ey[o] + 1] + (int64_t)d.ny * zz[L::ez[o] + 1]);
+    const Vec2<double> pa = psi_ld(psi, ja), pb = psi_ld(psi, jb);
+    const R w = (R)L::w[i];
+    const R d1 = w * ((R)pa.x - (R)pb.x), d2 = w * ((R)pa.y - (R)pb.y);
+    if (L::ex[i]) { sx1 += L::ex[i] * d1; sx2 += L::ex[i] * d2; }
+    if (L::ey[i]) { sy1 += L::ey[i] * d1; sy2 += L::ey[i] * d2; }
+    if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
+  }
+}
+
+template <int Q, int COLL, int ST, typename R>
+__global__ __launch_bounds__(256) void collide_kernel(const InstDev *__restrict__ insts, int parity) {
+  const InstDev &d = insts[0];
+  int x, y, z;
+  if (!wave_row(d, x, y, z)) return;
+  const int64_t pi = x + (int64_t)d.pitch * (y + (int64_t)d.ny * z);
+  const uint32_t info = ((gcu32 *)d.info)[pi];
+  if (info & kSolid) return;
+  gcf *__restrict__ fin = G(d.f[parity]);
+  gf *__restrict__ fout = G(d.f[parity ^ 1]);
+  int xs[3];
+  source_x(d, x, xs);
+  R rho1, rho2, sx1, sy1, sz1, sx2, sy2, sz2;
+  psi_force_sums<Q, R>(d, x, y, z, pi, info, rho1, rho2, sx1, sy1, sz1, sx2, sy2, sz2);
+  int64_t src[3][3];
+  source_rows<Q, true>(d, y, z, src);  // one row per wave
+  float a[Q], b[Q];
+  pull_row<Q, ST>(d, fin, info, src, xs, a, b);
+  if (info & (kInlet | kOutlet)) complete<Q, ST, R>(d, fin, info, x, y, z, a, b);
+  const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
+  collide_node<Q, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb, -G_ * rho1 * sy2 + rho1 * gyb,
+                           -G_ * rho1 * sz2 + rho1 * gzb, -G_ * rho2 * sx1 + rho2 * gxb,
+                           -G_ * rho2 * sy1 + rho2 * gyb, -G_ * rho2 * sz1 + rho2 * gzb);
+  pop_store<Q, ST>(fout, d.pitch, uniform64(y * d.ystride + z * d.zstride), x, a, b, (float)rho1, (float)rho2);
+  store_ghosts<Q, ST>(d, fout, info, src, xs, a, b);
+}
+
+// ---------------------------------------------------------------------------
+// Compacted fluid-node step.  Thread per fluid node (nothing is spent on solid
+// nodes, whose populations are not stored).  The state is f*[s][i][c] over
+// the compact index c; a pull from a fluid source reads the source's compact
+// index (popcount rank in its row), a pull across a solid link reads the
+// node's own f*_opp(i) (half-way bounce-back without ghost slots).  Densities
+// and the virtual solid density go through the dense psi array as in the
+// split step, and the force and collision are the split step's arithmetic.
+// ---------------------------------------------------------------------------
+
+// Does some link of the lattice pull from row offset (dy, dz)?
+template <int Q>
+__device__ __forceinline__ constexpr bool row_used(int dy, int dz) {
+  for (int i = 1; i < Q; ++i)
+    if (Lat<Q>::ey[i] == dy && Lat<Q>::ez[i] == dz) return true;
+  return false;
+}
+
+__device__ __forceinline__ void ckey_xyz(const InstDev &d, uint32_t key, int &x, int &y, int &z) {
+  const uint32_t r = key / (uint32_t)d.pitch;
+  x = (int)(key - r * (uint32_t)d.pitch);
+  y = (int)(r % (uint32_t)d.ny);
+  z = (int)(r / (uint32_t)d.ny);
+}
+
+// Pull + inlet/outlet completion of fluid node c at (x, y, z).
+template <int Q, int ST, typename R>
+__device__ __forceinline__ void cgather(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int x, int y,
+                                        int z, int64_t c, float (&f0)[Q], float (&f1)[Q]) {
+  using L = Lat<Q>;
+  const int cp = d.cpitch;
+  int xs[3];
+  source_x(d, x, xs);  // indexed by e_x + 1: x - e_x with wrap
+  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
+  const int ys[3] = {yp, y, ym}, zs[3] = {zp, z, zm};  // indexed by e + 1: y - e_y, z - e_z
+  const int64_t last = d.nf - 1;
+  // Rank rk and fluid bit fl at column x of every source row (one row word
+  // each; the node's own row is rk = c, fl = 1).  A fluid source at x - 1 has
+  // rank rk - 1, one at x + 1 rank rk + fl; wrapped x sources are looked up.
+  int64_t rk[3][3];
+  int fl[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      rk[a][b] = c;
+      fl[a][b] = 1;
+      if ((a == 1 && b == 1) || !row_used<Q>(a - 1, b - 1)) continue;
+      const int64_t row = ys[a] + (int64_t)d.ny * zs[b];
+      const RowWord w = d.cword[row * (d.pitch >> 6) + (x >> 6)];
+      rk[a][b] = w.pre + __popcll(w.bits & ((1ull << (x & 63)) - 1ull));
+      fl[a][b] = (int)((w.bits >> (x & 63)) & 1ull);
+    }
+  const bool x_edge = x == 0 || x == d.nx - 1;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    int64_t sc = c;
+    int pi = i;
+    if (i != 0) {
+      if ((info >> i) & 1u) {
+        pi = L::opp[i];
+      } else {
+        const int a = L::ey[i] + 1, b = L::ez[i] + 1;
+        if (L::ex[i] == 0) {
+          sc = rk[a][b];
+        } else if (!x_edge) {
+          sc = L::ex[i] > 0 ? rk[a][b] - 1 : rk[a][b] + fl[a][b];
+        } else {
+          // wrapped source: periodic x, or a missing link at an open face
+          // (an arbitrary node, overwritten by the completion below)
+          sc = crank(d, xs[L::ex[i] + 1], ys[a] + (int64_t)d.ny * zs[b]);
+          sc = sc < last ? sc : last;
+        }
+      }
+    }
+    if constexpr (ST == 0) {
+      // component planes from a wave-uniform base, 32-bit byte offsets (the
+      // host keeps Q * cpitch * 4 below 2^32)
+      const uint32_t bo = ((uint32_t)pi * (uint32_t)cp + (uint32_t)sc) * 4u;
+      f0[i] = ldg(fin, bo);
+      f1[i] = ldg(fin + (int64_t)Q * cp, bo);
+    } else {
+      pop_get2<Q, ST>(fin, cp, pi, 0, (int)sc, f0[i], f1[i]);
+    }
+  }
+  if (info & (kInlet | kOutlet)) {
+    const int t = y + d.ny * z;
+    const int64_t nt = (int64_t)d.ny * d.nz;
+    gcf *frz = G(d.frozen);
+    complete_boundary<Q, R>(
+        d, info, f0, f1, [&](int s, int i) { return pop_get<Q, ST>(fin, cp, s, i, 0, (int)c); },
+        [&](int s, int i) { return frz[(int64_t)(s * Q + i) * nt + t]; });
+  }
+}
+
+template <int Q, int ST>
+__global__ __launch_bounds__(256) void crho_kernel(const InstDev *__restrict__ insts, int parity) {
+  const InstDev &d = insts[0];
+  const int64_t c = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (c >= d.nf) return;
+  const uint32_t key = d.ckey[c];
+  int x, y, z;
+  ckey_xyz(d, key, x, y, z);
+  const uint32_t info = ((gcu32 *)d.info)[key];
+  float a[Q], b[Q];
+  cgather<Q, ST, double>(d, G(d.f[parity]), info, x, y, z, c, a, b);
+  psi_st((gd *)d.psi, key, sum_q<Q, double>(a), sum_q<Q, double>(b));
+}
+
+template <int Q>
+__global__ __launch_bounds__(256) void cpsi_kernel(const InstDev *__restrict__ insts) {
+  const InstDev &d = insts[0];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d.nbnd) return;
+  const uint32_t key = d.cbnd[j];
+  int x, y, z;
+  ckey_xyz(d, key, x, y, z);
+  ivsd_node<Q>(d, x, y, z, key, ((gcu32 *)d.info)[key]);
+}
+
+template <int Q, int COLL, int ST, typename R>
+__global__ __launch_bounds__(256) void ccollide_kernel(const InstDev *__restrict__ insts, int parity) {
+  const InstDev &d = insts[0];
+  const int64_t c = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (c >= d.nf) return;
+  const uint32_t key = d.ckey[c];
+  int x, y, z;
+  ckey_xyz(d, key, x, y, z);
+  const uint32_t info = ((gcu32 *)d.info)[key];
+  R rho1, rho2, sx1, sy1, sz1, sx2, sy2, sz2;
+  psi_force_sums<Q, R>(d, x, y, z, key, info, rho1, rho2, sx1, sy1, sz1, sx2, sy2, sz2);
+  // keep the psi loads and the pulls apart: both in flight at once would
+  // double the live registers and halve the waves per SIMD
+  __builtin_amdgcn_sched_barrier(0);
+  float a[Q], b[Q];
+  cgather<Q, ST, R>(d, G(d.f[parity]), info, x, y, z, c, a, b);
+  const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
+  collide_node<Q, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb, -G_ * rho1 * sy2 + rho1 * gyb,
+                           -G_ * rho1 * sz2 + rho1 * gzb, -G_ * rho2 * sx1 + rho2 * gxb,
+                           -G_ * rho2 * sy1 + rho2 * gyb, -G_ * rho2 * sz1 + rho2 * gzb);
+  pop_store<Q, ST>(G(d.f[parity ^ 1]), d.cpitch, 0, (int)c, a, b, (float)rho1, (float)rho2);
+}
+
+// ---------------------------------------------------------------------------
+// D3Q19 fused step on the compacted layout (FP32 storage), marching in z.
+// A block of eight waves owns a 60 x 8 tile of (x, y) (64 x 12 with a
+// two-node halo) and a chunk of z.  Wave w owns interior row 2 + w; waves
+// 0-3 also one halo row each (rows 0, 1, 10, 11).  Per plane z:
+//   phase A: form psi at the solid nodes of plane z + 1 (Eq. 17) from the
+//            densities of planes z .. z + 2, held in an LDS ring of five
+//            planes;
+//   phase B: load the row words of plane z + 6 for its rank map (compact
+//            index of each region node, or solid, or outside the domain),
+//            issue the density pulls of plane z + 3 straight into LDS
+//            landing areas (global_load_lds: no registers held in flight)
+//            and the interior pulls of plane z + 1 into registers; compute
+//            the force and collision of plane z from the registers filled
+//            one plane earlier; wait; write the rank map; store plane z;
+//            sum the densities of plane z + 3 into the ring.
+// The collision's pulls repeat the density pulls of two planes earlier and
+// are served by the L2; densities and psi never leave the chip.  Node
+// arithmetic follows the compacted split step; the ring holds the densities
+// and psi rounded to FP32.
+// ---------------------------------------------------------------------------
+constexpr int kM3Waves = 8;             // one interior row per wave
+constexpr int kM3RH = kTileY3 + 4;      // region rows
+constexpr int kM3Ring = 5;              // density planes
+constexpr int kM3Maps = 7;              // rank maps of planes z - 1 .. z + 5
+constexpr int kM3MapRows = kM3RH + 2;   // region rows -1 .. kM3RH
+constexpr int kM3MapCols = 66;          // region columns -1 .. 64
+constexpr int kM3MapPitch = 68;
+// A map entry is the node's compact index minus its row's base (the compact
+// index of the word holding the region's first column), or one of these.
+constexpr int kMapOutside = -32768, kMapSolid = -32767;
+// D3Q19 links entering the domain at the inlet (e_x = +1) and at the outlet (e_x = -1)
+constexpr int kInLinks19[5] = {1, 7, 9, 11, 13};
+constexpr int kOutLinks19[5] = {2, 8, 10, 12, 14};
+
+__device__ __forceinline__ int m3ring(int p) { return ((p % kM3Ring) + kM3Ring) % kM3Ring; }
+__device__ __forceinline__ int m3map(int p) { return ((p % kM3Maps) + kM3Maps) % kM3Maps; }
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) const void g_cvoid;
+
+template <int COLL, typename R>
+__global__ __launch_bounds__(512) void march_d3q19(const InstDev *__restrict__ insts,
+                                                   const int32_t *__restrict__ block_inst, int parity) {
+  using L = Lat<19>;
+  using V = Vec2<float>;
+  __shared__ V ring[kM3Ring][kM3RH][64];
+  __shared__ int16_t rmap[kM3Maps][kM3MapRows][kM3MapPitch];
+  __shared__ int32_t rbase[kM3Maps][kM3MapRows];
+  // landing areas [row][component * 19 + link][lane]: rows 0-7 the interior
+  // row of wave w, rows 8-11 the halo row of wave w - 8
+  __shared__ float land[kM3Waves + 4][38][64];
+
+  const int bid = xcd_block();
+  const int inst = __builtin_amdgcn_readfirstlane(block_inst ? block_inst[bid] : 0);
+  const InstDev &d = insts[inst];
+  const int lb = bid - d.block_base;
+  const int tx = lb % d.tiles_x, ty = (lb / d.tiles_x) % d.tiles_y;
+  const int zc = lb / (d.tiles_x * d.tiles_y);
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  gcf *__restrict__ fin = G(d.f[parity]);
+  gf *__restrict__ fout = G(d.f[parity ^ 1]);
+  gcf *__restrict__ frz = G(d.frozen);
+  gcc *const fin_b = (gcc *)fin;
+  const int nx = d.nx, ny = d.ny, nz = d.nz, cp = d.cpitch;
+  const bool px = d.periodic & 1, py = d.periodic & 2, pz = d.periodic & 4;
+  const int zlen = (nz + d.tiles_z - 1) / d.tiles_z;
+  const int z0 = zc * zlen, z1 = min(nz, z0 + zlen);
+  const int64_t wpr = d.pitch >> 6;
+  const int64_t nt = (int64_t)ny * nz;
+  const int bc_set = d.bc_set;
+
+  // coordinate of a region index along an axis: false if outside a closed edge
+  auto wrap_ax = [](int v, int n, bool per, int &out) __attribute__((always_inline)) -> bool {
+    out = v;
+    if (v < 0 || v >= n) {
+      if (!per) return false;
+      out = wrap_index(v, n);
+    }
+    return true;
+  };
+
+  int gx;
+  const bool col_in = wrap_ax(tx * kTileX - 2 + lane, nx, px, gx);
+  const bool col_store = lane >= 2 && lane < 62 && tx * kTileX - 2 + lane < nx;
+  // inlet / outlet flags of this column
+  const uint32_t face = !d.open_x || !col_in ? 0u : (gx == 0 ? kInlet : (gx == nx - 1 ? kOutlet : 0u));
+  const bool open_face = face != 0;
+  const int rI = 2 + wave;                            // interior region row
+  const bool has_h = wave < 4;
+  const int rH = wave < 2 ? wave : kTileY3 + wave;    // halo region row: 0, 1, 10, 11
+  int gyI = 0, gyH = 0;
+  wrap_ax(ty * kTileY3 - 2 + rI, ny, py, gyI);
+  wrap_ax(ty * kTileY3 - 2 + rH, ny, py, gyH);
+  const bool storeI = col_store && ty * kTileY3 + wave < ny;
+  // column of the rank base of every map row: the region's first in-domain column
+  int xb;
+  if (!wrap_ax(tx * kTileX - 3, nx, px, xb)) xb = 0;
+
+  // ---- rank maps: two entries per thread, words loaded in one phase and
+  // the entries written in a later one
+  unsigned long long mbits[2];
+  int32_t mpre[2], mbase[2], mpos[2];  // mpos: bit position, -1 outside in x, -2 row outside
+  auto map_issue = [&](int p) __attribute__((always_inline)) {
+    // every load is issued (from row 0 for entries outside the domain), so
+    // that no register is assigned while an older load may still target it
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = threadIdx.x + 512 * k;
+      const int rr = e / kM3MapCols, cc = e - rr * kM3MapCols;
+      int xg, yg, zg;
+      const bool row_ok = e < kM3MapRows * kM3MapCols && wrap_ax(ty * kTileY3 - 3 + rr, ny, py, yg) &&
+                          wrap_ax(p, nz, pz, zg);
+      const bool col_ok = wrap_ax(tx * kTileX - 3 + cc, nx, px, xg);
+      const RowWord *row = d.cword + (row_ok ? yg + (int64_t)ny * zg : 0) * wpr;
+      mbase[k] = (int32_t)row[xb >> 6].pre;
+      const RowWord w = row[(col_ok ? xg : xb) >> 6];
+      mbits[k] = w.bits;
+      mpre[k] = (int32_t)w.pre;
+      mpos[k] = !row_ok ? -2 : (!col_ok ? -1 : (xg & 63));
+    }
+  };
+  auto map_write = [&](int p) __attribute__((always_inline)) {
+    const int m = m3map(p);
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int e = threadIdx.x + 512 * k;
+      if (e >= kM3MapRows * kM3MapCols) continue;
+      const int rr = e / kM3MapCols, cc = e - rr * kM3MapCols;
+      int v = kMapOutside;
+      if (mpos[k] >= 0) {
+        const int b = mpos[k];
+        v = ((mbits[k] >> b) & 1ull) ? mpre[k] + (int)__popcll(mbits[k] & ((1ull << b) - 1ull)) - mbase[k]
+                                     : kMapSolid;
+      }
+      rmap[m][rr][cc] = (int16_t)v;
+      if (cc == 0) rbase[m][rr] = mbase[k];
+    }
+  };
+  // compact index at map (plane p, map row rr, map column cc): >= 0 fluid,
+  // -1 solid, -2 outside the domain
+  auto rank_at = [&](int p, int rr, int cc) __attribute__((always_inline)) -> int32_t {
+    const int m = m3map(p);
+    const int v = rmap[m][rr][cc];
+    return v <= kMapSolid ? v - kMapSolid - 1 : rbase[m][rr] + v;
+  };
+
+  // ---- pulls of the node of region row r on plane p into landing row lr
+  // (one global_load_lds per link and component); the held links of its
+  // inlet/outlet completion go to pre
+  auto pull_issue = [&](int lr, int r, int gy, int p, int32_t &c, float (&pre)[5])
+      __attribute__((always_inline)) {
+    c = rank_at(p, r + 1, lane + 1);
+    if (c < 0) return;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      int32_t sc = c;
+      int pi = i;
+      if (i != 0) {
+        // a solid source (half-way bounce-back) or a missing link across an
+        // open face (overwritten by the completion) reads this node's
+        // opposite slot
+        const int32_t sv = rank_at(p - L::ez[i], r + 1 - L::ey[i], lane + 1 - L::ex[i]);
+        if (sv >= 0) sc = sv;
+        else pi = L::opp[i];
+      }
+      const uint32_t bo = ((uint32_t)pi * (uint32_t)cp + (uint32_t)sc) * 4u;
+      __builtin_amdgcn_global_load_lds((g_cvoid *)(fin_b + bo), (lds_void *)&land[lr][i][0], 4, 0, 0);
+      __builtin_amdgcn_global_load_lds((g_cvoid *)(fin_b + (uint32_t)(19 * cp) * 4u + bo),
+                                       (lds_void *)&land[lr][19 + i][0], 4, 0, 0);
+    }
+    // component 2 at the inlet: Eq. 28 (this node's own post-collision
+    // values) or Eq. 27 (Set-2, held); component 1 at the outlet: Eq. 26
+    if (face && bc_set != 1) {
+      int zz;
+      wrap_ax(p, nz, pz, zz);
+      const int64_t t = gy + (int64_t)ny * zz;
+      if (face & kInlet) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const int i = kInLinks19[k];
+          pre[k] = bc_set == 2 ? frz[(int64_t)(19 + i) * nt + t] : ldg(fin + (int64_t)(19 + i) * cp, (uint32_t)c * 4u);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) pre[k] = frz[(int64_t)kOutLinks19[k] * nt + t];
+      }
+    }
+  };
+  // the same pulls into registers (the collision's; nothing waits for them here)
+  auto pull_regs = [&](int r, int gy, int p, int32_t &c, float (&a)[19], float (&b)[19], float (&pre)[5])
+      __attribute__((always_inline)) {
+    c = rank_at(p, r + 1, lane + 1);
+    if (c < 0) return;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      int32_t sc = c;
+      int pi = i;
+      if (i != 0) {
+        const int32_t sv = rank_at(p - L::ez[i], r + 1 - L::ey[i], lane + 1 - L::ex[i]);
+        if (sv >= 0) sc = sv;
+        else pi = L::opp[i];
+      }
+      const uint32_t bo = ((uint32_t)pi * (uint32_t)cp + (uint32_t)sc) * 4u;
+      a[i] = ldg(fin, bo);
+      b[i] = ldg(fin + (int64_t)19 * cp, bo);
+    }
+    if (face && bc_set != 1) {
+      int zz;
+      wrap_ax(p, nz, pz, zz);
+      const int64_t t = gy + (int64_t)ny * zz;
+      if (face & kInlet) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) {
+          const int i = kInLinks19[k];
+          pre[k] = bc_set == 2 ? frz[(int64_t)(19 + i) * nt + t] : ldg(fin + (int64_t)(19 + i) * cp, (uint32_t)c * 4u);
+        }
+      } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) pre[k] = frz[(int64_t)kOutLinks19[k] * nt + t];
+      }
+    }
+  };
+  // inlet/outlet completion of pulled populations (links already pulled)
+  auto complete = [&](const float (&pre)[5], float (&a)[19], float (&b)[19]) __attribute__((always_inline)) {
+    if (face & kInlet) {
+      zou_he<19, double>(a, d.rho_in1, +1);  // component 1: Eqs. 22-25
+      if (bc_set == 1) {
+        zou_he<19, double>(b, d.rho_in2, +1);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) b[kInLinks19[k]] = pre[k];
+      }
+    } else if (face & kOutlet) {
+      zou_he<19, double>(b, d.rho_out2, -1);  // component 2: Eqs. 18-21
+      if (bc_set == 1) {
+        zou_he<19, double>(a, d.rho_out1, -1);
+      } else {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) a[kOutLinks19[k]] = pre[k];
+      }
+    }
+  };
+  // read a landed node back (after the wait) and complete it
+  auto pull_read = [&](int lr, const float (&pre)[5], float (&a)[19], float (&b)[19])
+      __attribute__((always_inline)) {
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      a[i] = land[lr][i][lane];
+      b[i] = land[lr][19 + i][lane];
+    }
+    complete(pre, a, b);
+  };
+  // issue, wait, read: the prologue's pulls
+  auto pull_now = [&](int lr, int r, int gy, int p, int32_t &c, float (&a)[19], float (&b)[19])
+      __attribute__((always_inline)) {
+    float pre[5];
+    pull_issue(lr, r, gy, p, c, pre);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __builtin_amdgcn_sched_barrier(0);
+    if (c >= 0) pull_read(lr, pre, a, b);
+  };
+  auto put_rho = [&](int p, int r, int32_t c, const float (&a)[19], const float (&b)[19])
+      __attribute__((always_inline)) {
+    float r1 = 0.f, r2 = 0.f;
+    if (c >= 0) {
+      r1 = (float)sum_q<19, double>(a);
+      r2 = (float)sum_q<19, double>(b);
+    }
+    ring[m3ring(p)][r][lane] = V{r1, r2};
+  };
+  // virtual solid density (Eq. 17) in place at the solid nodes of region row
+  // r on plane p: the neighbours' map entries and densities are read first,
+  // then summed over the in-domain fluid ones in link order
+  auto ivsd = [&](int p, int r) __attribute__((always_inline)) {
+    if (r < 1 || r > kM3RH - 2 || lane < 1 || lane > 62) return;
+    if (rmap[m3map(p)][r + 1][lane + 1] != kMapSolid) return;
+    bool fl[19];
+    V q[19];
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+      fl[i] = rmap[m3map(p + L::ez[i])][r + 1 + L::ey[i]][lane + 1 + L::ex[i]] > kMapSolid;
+      q[i] = ring[m3ring(p + L::ez[i])][r + L::ey[i]][lane + L::ex[i]];
+    }
+    double s1 = 0, s2 = 0, den = 0;
+#pragma unroll
+    for (int i = 1; i < 19; ++i) {
+      if (fl[i]) {
+        s1 += L::w[i] * (double)q[i].x;
+        s2 += L::w[i] * (double)q[i].y;
+        den += L::w[i];
+      }
+    }
+    if (den > 0) {
+      const double inv = rcp<double>(den);
+      ring[m3ring(p)][r][lane] = V{(float)(d.chi1 * s1 * inv), (float)(d.chi2 * s2 * inv)};
+    }
+  };
+
+  // the interior row's populations of plane z (collided now) and z + 1 (in flight)
+  float a0[19], b0[19], an[19], bn[19];
+  int32_t c0 = -1, cnx = -1;
+
+  // ---- prologue: maps of z0-3 .. z0+5, densities of z0-2 .. z0+2, psi of
+  // z0-1 and z0, the populations of plane z0
+  {
+    float ta[19], tb[19];
+    int32_t tc;
+    for (int p = z0 - 3; p <= z0 + 3; ++p) {
+      map_issue(p);
+      map_write(p);
+    }
+    __syncthreads();
+    for (int p = z0 - 2; p <= z0 + 2; ++p) {
+      pull_now(wave, rI, gyI, p, tc, ta, tb);
+      put_rho(p, rI, tc, ta, tb);
+      if (p == z0) {
+        c0 = tc;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) { a0[i] = ta[i]; b0[i] = tb[i]; }
+      }
+      if (has_h) {
+        pull_now(kM3Waves + wave, rH, gyH, p, tc, ta, tb);
+        put_rho(p, rH, tc, ta, tb);
+      }
+    }
+    __syncthreads();  // the map of z0-3 is read no more
+    map_issue(z0 + 4);
+    map_write(z0 + 4);
+    ivsd(z0 - 1, rI);
+    ivsd(z0, rI);
+    if (has_h) {
+      ivsd(z0 - 1, rH);
+      ivsd(z0, rH);
+    }
+    __syncthreads();  // the map of z0-2 is read no more
+    map_issue(z0 + 5);
+    map_write(z0 + 5);
+    __syncthreads();
+  }
+
+  const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
+  for (int z = z0; z < z1; ++z) {
+    const int p = z + 3;
+    const bool need = p <= z1 + 1;  // densities are needed up to plane z1 + 1
+    // Phase A: psi at the solid nodes of plane z + 1
+    ivsd(z + 1, rI);
+    if (has_h) ivsd(z + 1, rH);
+    __syncthreads();
+    // Phase B: row words of plane z + 6, density pulls of plane p into the
+    // landing areas, the collision's pulls of plane z + 1 into registers
+    map_issue(z + 6);
+    int32_t cn = -1, hc = -1;
+    float pre[5], hpre[5], npre[5];
+    if (need) {
+      pull_issue(wave, rI, gyI, p, cn, pre);
+      if (has_h) pull_issue(kM3Waves + wave, rH, gyH, p, hc, hpre);
+    }
+    cnx = -1;
+    if (z + 1 < z1) pull_regs(rI, gyI, z + 1, cnx, an, bn, npre);
+    // force (Eq. 13 with the open-face mirror) and collision of plane z
+    // while they are in flight
+    const bool live = storeI && c0 >= 0;
+    if (live) {
+      const R rho1 = (R)sum_q<19, double>(a0), rho2 = (R)sum_q<19, double>(b0);
+      R sx1 = 0, sy1 = 0, sz1 = 0, sx2 = 0, sy2 = 0, sz2 = 0;
+#pragma unroll
+      for (int i = 1; i < 19; ++i) {
+        if (L::opp[i] < i) continue;
+        const int o = L::opp[i];
+        if (L::ex[i] != 0 && open_face) continue;
+        const V pa = ring[m3ring(z + L::ez[i])][rI + L::ey[i]][lane + L::ex[i]];
+        const V pb = ring[m3ring(z + L::ez[o])][rI + L::ey[o]][lane + L::ex[o]];
+        const R w = (R)L::w[i];
+        const R d1 = w * ((R)pa.x - (R)pb.x), d2 = w * ((R)pa.y - (R)pb.y);
+        if (L::ex[i]) { sx1 += L::ex[i] * d1; sx2 += L::ex[i] * d2; }
+        if (L::ey[i]) { sy1 += L::ey[i] * d1; sy2 += L::ey[i] * d2; }
+        if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
+      }
+      collide_node<19, COLL, R>(d, a0, b0, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb,
+                                -G_ * rho1 * sy2 + rho1 * gyb, -G_ * rho1 * sz2 + rho1 * gzb,
+                                -G_ * rho2 * sx1 + rho2 * gxb, -G_ * rho2 * sy1 + rho2 * gyb,
+                                -G_ * rho2 * sz1 + rho2 * gzb);
+    }
+    // Every load issued above has landed after this wait (the compiler does
+    // not see the landing areas as written by the pulls, so the wait and the
+    // scheduling fences are explicit); the stores are issued after it, so
+    // that it does not wait for them.
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __builtin_amdgcn_sched_barrier(0);
+    // the slot of plane z + 6 held plane z - 1, last read by the previous
+    // iteration's pulls
+    map_write(z + 6);
+    if (live) pop_store<19, 0>(fout, cp, 0, c0, a0, b0, 0.f, 0.f);
+    if (need) {
+      float ta[19], tb[19];
+      if (cn >= 0) pull_read(wave, pre, ta, tb);
+      put_rho(p, rI, cn, ta, tb);
+      if (has_h) {
+        if (hc >= 0) pull_read(kM3Waves + wave, hpre, ta, tb);
+        put_rho(p, rH, hc, ta, tb);
+      }
+    }
+    c0 = cnx;
+    if (cnx >= 0) {
+      complete(npre, an, bn);
+#pragma unroll
+      for (int i = 0; i < 19; ++i) { a0[i] = an[i]; b0[i] = bn[i]; }
+    }
+    // the densities of plane p and the rank map of plane z + 6 written in
+    // this phase are read after this barrier
+    __syncthreads();
+  }
+}
+
+template <int COLL, int ST, typename R>
+static void launch_fused_q(int q, int ty, const InstDev *d, const int32_t *bi, int64_t nb, int parity,
+                           hipStream_t s, bool compact = false) {
+  const dim3 g((unsigned)nb), b(256);
+  if (q == 19 && compact) {
+    if constexpr (ST == 0) march_d3q19<COLL, R><<<g, dim3(512), 0, s>>>(d, bi, parity);
+  } else if (q == 9 && compact) {
+    if (ty == 8) step_d2q9<COLL, ST, R, 8, 1><<<g, b, 0, s>>>(d, bi, parity);
+    else if (ty == 16) step_d2q9<COLL, ST, R, 16, 1><<<g, b, 0, s>>>(d, bi, parity);
+    else step_d2q9<COLL, ST, R, 12, 1><<<g, b, 0, s>>>(d, bi, parity);
+  } else if (q == 9) {
+    if (ty == 8) step_d2q9<COLL, ST, R, 8><<<g, b, 0, s>>>(d, bi, parity);
+    else if (ty == 16) step_d2q9<COLL, ST, R, 16><<<g, b, 0, s>>>(d, bi, parity);
+    else step_d2q9<COLL, ST, R, 12><<<g, b, 0, s>>>(d, bi, parity);
+  } else {
+    step_d3q19<COLL, ST, R><<<g, b, 0, s>>>(d, bi, parity);
+  }
+}
+
+template <int COLL, int ST, typename R>
+static void launch_fused_list_q(int q, int ty, const InstDev *d, const int32_t *bi, int64_t nb, int parity,
+                                hipStream_t s) {
+  const dim3 g((unsigned)nb), b(256);
+  if (q != 9) return;
+  if (ty == 8) step_d2q9_list<COLL, ST, R, 8><<<g, b, 0, s>>>(d, bi, parity);
+  else if (ty == 16) step_d2q9_list<COLL, ST, R, 16><<<g, b, 0, s>>>(d, bi, parity);
+  else step_d2q9_list<COLL, ST, R, 12><<<g, b, 0, s>>>(d, bi, parity);
+}
+
+template <int COLL, int ST, typename R>
+static void launch_split_q(int q, const InstDev *d, const InstDev &h, int parity, hipStream_t s) {
+  const int64_t waves = (int64_t)((h.nx + 63) / 64) * h.ny * h.nz;
+  const dim3 g((unsigned)((waves + 3) / 4)), b(256);
+  if (q == 9) {
+    rho_kernel<9, ST><<<g, b, 0, s>>>(d, parity);
+    psi_kernel<9><<<g, b, 0, s>>>(d);
+    collide_kernel<9, COLL, ST, R><<<g, b, 0, s>>>(d, parity);
+  } else {
+    rho_kernel<19, ST><<<g, b, 0, s>>>(d, parity);
+    psi_kernel<19><<<g, b, 0, s>>>(d);
+    collide_kernel<19, COLL, ST, R><<<g, b, 0, s>>>(d, parity);
+  }
+}
+
+template <int COLL, int ST, typename R>
+static void launch_compact_q(int q, const InstDev *d, const InstDev &h, int parity, hipStream_t s) {
+  if (h.nf == 0) return;  // no fluid: nothing moves
+  const dim3 g((unsigned)((h.nf + 255) / 256)), gb((unsigned)((h.nbnd + 255) / 256)), b(256);
+  if (q == 9) {
+    crho_kernel<9, ST><<<g, b, 0, s>>>(d, parity);
+    if (h.nbnd) cpsi_kernel<9><<<gb, b, 0, s>>>(d);
+    ccollide_kernel<9, COLL, ST, R><<<g, b, 0, s>>>(d, parity);
+  } else {
+    crho_kernel<19, ST><<<g, b, 0, s>>>(d, parity);
+    if (h.nbnd) cpsi_kernel<19><<<gb, b, 0, s>>>(d);
+    ccollide_kernel<19, COLL, ST, R><<<g, b, 0, s>>>(d, parity);
+  }
+}
+
+// One step of every instance of a batch, for one collision operator: the
+// storage, node arithmetic and strategy decide the kernels (see StepLaunch).
+template <int COLL, int ST, typename R>
+static void launch_st(const StepLaunch &L, hipStream_t s) {
+  if (L.strategy == 2) {
+    for (int i = 0; i < L.k; ++i) launch_split_q<COLL, ST, R>(L.q, L.d_insts + i, L.h[i], L.parity, s);
+  } else if (L.strategy == 3) {
+    for (int i = 0; i < L.k; ++i) launch_compact_q<COLL, ST, R>(L.q, L.d_insts + i, L.h[i], L.parity, s);
+  } else if (L.strategy == 4) {
+    launch_fused_list_q<COLL, ST, R>(L.q, L.ty, L.d_insts, L.block_inst, L.n_blocks, L.parity, s);
+  } else if (L.strategy == 5) {
+    launch_fused_q<COLL, ST, R>(L.q, L.ty, L.d_insts, L.block_inst, L.n_blocks, L.parity, s, true);
+  } else {
+    launch_fused_q<COLL, ST, R>(L.q, L.ty, L.d_insts, L.block_inst, L.n_blocks, L.parity, s);
+  }
+}
+
+template <int COLL>
+hipError_t launch_step_coll(const StepLaunch &L, hipStream_t s) {
+  if (L.math == 0) {
+    if (L.storage == 0) launch_st<COLL, 0, double>(L, s);
+    else launch_st<COLL, 1, double>(L, s);
+  } else {
+    if (L.storage == 0) launch_st<COLL, 0, float>(L, s);
+    else launch_st<COLL, 1, float>(L, s);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace lbm

@@ -1,0 +1,7 @@
+// Step kernels instantiated for the MRT collision (one translation
+// unit per operator, so that they compile in parallel).
+#include "lbm_step.h"
+
+namespace lbm {
+hipError_t launch_step_mrt(const StepLaunch &L, hipStream_t s) { return launch_step_coll<1>(L, s); }
+}  // namespace lbm

@@ -357,6 +357,8 @@ def surrogate_instance(k: int, seed0: int = 40000, n: int = 256, collision: int 
     p = Problem(q=9, mask=mask, rho0=rho0, periodic=0, open_x=1, porous_x0=8, porous_x1=n - 8,
                 tau=TAU_M10, G=3.5, xi=xi_of_theta(theta), rho_in1=1.0 + 3 * dp, rho_out2=1.0,
                 collision=collision, name=f"surrogate{k}_{n}x{n}")
+    # the trained network's fields were generated with s_j = s_nu
+    p.mrt_sj_mode = 2
     p.theta = theta
     p.dp = dp
     return p

@@ -10,8 +10,9 @@ paper's water) and the invading component at M times that.  All cells of
 one collision operator run as one batch; a cell counts as stable when no
 density became non-finite or negative within the run, and its final
 window saturation is reported.  D2Q9 SRT, MRT (Lallemand-Luo moments,
-s_e = s_eps = 1, s_q from Lambda = 3/16) and TRT (Lambda = 3/16).  Prints
-one progress line per operator and one JSON line.
+s_e = s_eps = 1, s_q from Lambda = 3/16, component-momentum rate
+s_j = min(s_nu, s_q)) and TRT (Lambda = 3/16).  Prints one progress line per
+operator and one JSON line.
 
 --tune-mrt adds a sweep of the MRT operator's free rates at high viscosity
 ratio (G = 3.5): the energy rates s_e = s_eps and the magic parameter

@@ -36,6 +36,9 @@ def problems3d():
     out["d3_drain_srt"] = I.Problem(q=19, mask=m, rho0=r0, periodic=0, open_x=1, porous_x0=8,
                                     porous_x1=32, tau=(1.0, 0.8), G=3.5, xi=I.xi_of_theta(45),
                                     rho_in1=1.02, collision=0)
+    out["d3_drain_mrt"] = I.Problem(q=19, mask=m, rho0=r0, periodic=0, open_x=1, porous_x0=8,
+                                    porous_x1=32, tau=I.TAU_M10, G=3.5, xi=I.xi_of_theta(60),
+                                    rho_in1=1.015, collision=1)
     # fully periodic droplet with z chunks (nz = 72 -> several chunks)
     n = (24, 20, 72)
     mask = np.zeros(n[::-1], np.uint8)

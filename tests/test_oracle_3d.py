@@ -192,5 +192,12 @@ def test_channel_flow_exact_for_trt_at_magic_lambda_3d(wall_axis, tau):
     assert _channel3d_error(wall_axis, 2, tau, steps=25000) < 1e-7
 
 
+@pytest.mark.parametrize("tau", [1.7, 1.0])
+def test_channel_flow_exact_for_mrt_at_magic_lambda_3d(tau):
+    """The D3Q19 MRT (d'Humieres moments, default component-momentum rate)
+    gives the exact parabola between z walls at the magic parameter."""
+    assert _channel3d_error("z", 1, tau, steps=25000) < 1e-7
+
+
 def test_channel_flow_exact_for_srt_at_magic_tau_3d():
     assert _channel3d_error("z", 0, 0.5 + np.sqrt(3) / 4, steps=30000) < 1e-9

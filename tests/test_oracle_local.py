@@ -97,7 +97,7 @@ def _random_node(q, rng, minority=False):
     return fin, F
 
 
-COLLISIONS = [(9, 0), (9, 1), (9, 2), (19, 0), (19, 2)]
+COLLISIONS = [(9, 0), (9, 1), (9, 2), (19, 0), (19, 1), (19, 2)]
 
 
 @pytest.mark.parametrize("q,coll", COLLISIONS)
@@ -160,7 +160,7 @@ def test_srt_matches_closed_form():
         assert np.abs(out[c] - exp).max() < 1e-15
 
 
-@pytest.mark.parametrize("q", [9])
+@pytest.mark.parametrize("q", [9, 19])
 def test_mrt_with_equal_rates_is_srt(q):
     rng = np.random.default_rng(4)
     Pm = _params(q, 1, s_e=-1.0, s_eps=-1.0, lam=-1.0, mrt_sj_mode=0)
@@ -170,15 +170,36 @@ def test_mrt_with_equal_rates_is_srt(q):
         assert np.abs(O.collide_node(Pm, fin, F) - O.collide_node(Ps, fin, F)).max() < 1e-14
 
 
-def test_mrt_with_trt_rates_is_trt():
+@pytest.mark.parametrize("q", [9, 19])
+def test_mrt_with_trt_rates_is_trt(q):
     """MRT with even-moment rates s_nu and odd-moment rates s- (s_j = s_q)
     collapses to the two-relaxation-time operator."""
     rng = np.random.default_rng(5)
-    Pm = _params(9, 1, s_e=-1.0, s_eps=-1.0, lam=3 / 16, mrt_sj_mode=1)
-    Pt = _params(9, 2, lam=3 / 16)
+    Pm = _params(q, 1, s_e=-1.0, s_eps=-1.0, lam=3 / 16, mrt_sj_mode=1)
+    Pt = _params(q, 2, lam=3 / 16)
     for _ in range(10):
-        fin, F = _random_node(9, rng)
+        fin, F = _random_node(q, rng)
         assert np.abs(O.collide_node(Pm, fin, F) - O.collide_node(Pt, fin, F)).max() < 1e-14
+
+
+def test_d3q19_mrt_basis_is_the_textbook_moments():
+    """The D3Q19 moment matrix: its rows are mutually orthogonal; the
+    conserved rows are the density and momentum; the energy row weighted by
+    w gives 19 c_s^2 - 30 = -23... of the equilibrium (checked through
+    sum_i w_i M_ki = <M_k> of the rest state): only rho, e and eps have a
+    nonzero rest-state mean, with e = -11 and eps = 3 (per unit density)."""
+    M = O.mrt_matrix(19)
+    e, w, _ = O.lattice(19)
+    G = M @ M.T
+    assert np.abs(G - np.diag(np.diag(G))).max() == 0.0
+    assert np.array_equal(M[0], np.ones(19))
+    assert np.array_equal(M[3], e[:, 0]) and np.array_equal(M[5], e[:, 1]) and np.array_equal(M[7], e[:, 2])
+    mean = M @ w
+    assert abs(mean[0] - 1) < 1e-15 and abs(mean[1] + 11) < 1e-14 and abs(mean[2] - 3) < 1e-14
+    assert np.abs(mean[3:]).max() < 1e-15
+    # second-order rows: the shear moments are the traceless products of c
+    c2 = (e ** 2).sum(axis=1)
+    assert np.array_equal(M[9], 3 * e[:, 0] ** 2 - c2) and np.array_equal(M[13], e[:, 0] * e[:, 1])
 
 
 @pytest.mark.parametrize("q", [9, 19])
@@ -257,15 +278,15 @@ def test_viscosity_reading_matches_printed_pairs(paper):
 
 
 def test_mrt_momentum_rate_moves_components_not_the_total():
-    """The MRT component-momentum rate s_j (s_nu, or s_q with mrt_sj_mode = 1)
+    """The MRT component-momentum rate s_j (mrt_sj_mode 2: s_nu; 1: s_q)
     leaves the total momentum change at F but changes how the two
     components share it: each component's momentum relaxes towards
-    rho^s u at rate s_j."""
+    rho^s u at rate s_j.  Mode 0 takes the smaller of the two."""
     rng = np.random.default_rng(9)
     e, _, _ = O.lattice(9)
     e = e.astype(float)
     outs = []
-    for sj in (0, 1):
+    for sj in (2, 1, 0):
         P = _params(9, 1)
         P.mrt_sj_mode = sj
         fin, F = _random_node(9, np.random.default_rng(9))
@@ -273,5 +294,11 @@ def test_mrt_momentum_rate_moves_components_not_the_total():
         j0, j1 = fin @ e, out @ e
         assert np.abs(j1.sum(axis=0) - (j0.sum(axis=0) + F.sum(axis=0))).max() < 1e-15
         outs.append(j1)
-    # the per-component momenta differ between the two rates
+    # the per-component momenta differ between the two rates, and mode 0 is
+    # the one with the smaller rate
     assert np.abs(outs[0] - outs[1]).max() > 1e-6
+    fin, _ = _random_node(9, np.random.default_rng(9))
+    r1, r2 = fin[0].sum(), fin[1].sum()
+    tau_s = (0.8 * r1 + 1.7 * r2) / (r1 + r2)
+    s_nu, s_q = 1 / tau_s, (tau_s - 0.5) / ((tau_s - 0.5) / 2 + 3 / 16)
+    assert np.array_equal(outs[2], outs[1] if s_q < s_nu else outs[0])
