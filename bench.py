@@ -111,11 +111,12 @@ def time_steps(torch, solver, steps, warmup, chunk, eager):
     return time.perf_counter() - t0, e0.elapsed_time(e1)
 
 
-def side_line(torch, lbm, name, args, dev, steps, warmup, chunk):
-    """A shorter measurement of another workload (same protocol)."""
+def side_line(torch, lbm, name, args, dev, steps, warmup, chunk, math=None):
+    """A shorter measurement of another workload, or of the same one with the
+    other node arithmetic (same protocol)."""
     problem = workload(name)
     batch = isinstance(problem, list)
-    solver = make_solver(lbm, problem, args, dev)
+    solver = make_solver(lbm, problem, args, dev, math=math)
     try:
         if not args.no_autotune and args.strategy == 0:
             solver.autotune(10)
@@ -131,7 +132,8 @@ def side_line(torch, lbm, name, args, dev, steps, warmup, chunk):
                "ms_per_step": round(wall * 1e3 / steps, 5), "value": round(n_nodes * steps / wall / 1e6, 1),
                "unit": "MLUPS", "kernel": kname,
                "roofline_frac": round(alg / (step_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-               "alg_bytes_per_step": alg, "traffic": traffic_for(kname, name)}
+               "alg_bytes_per_step": alg, "traffic": traffic_for(kname, name),
+               "math": "f32" if (args.math if math is None else math) == 0 else "f64"}
         if name == "d2q9_1024x512":
             out["note"] = ("both population buffers (75 MB) stay in the 256 MB last-level cache: "
                            "the fraction is of on-chip bandwidth, not of HBM")
@@ -148,7 +150,7 @@ def main():
     ap.add_argument("--workload", default="d3q19_384")
     ap.add_argument("--chunk", type=int, default=20, help="steps per captured graph (even)")
     ap.add_argument("--storage", type=int, default=0, help="0 FP32, 1 BF16 deviations")
-    ap.add_argument("--math", type=int, default=0, help="node arithmetic: 0 FP64, 1 FP32")
+    ap.add_argument("--math", type=int, default=0, help="node arithmetic: 0 FP32 (default), 1 FP64")
     ap.add_argument("--strategy", type=int, default=0,
                     help="0 auto (autotuned), 1 fused, 2 split, 3 compact, 4 fused with listed collision, "
                          "5 compacted fused (D2Q9)")
@@ -226,7 +228,7 @@ def main():
         "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": ("f64" if args.math == 0 else "f32") + " node arithmetic, "
+        "dtype": ("f32" if args.math == 0 else "f64") + " node arithmetic, "
                  + ("f32" if args.storage == 0 else "bf16-deviation") + " storage",
         "data": "synthetic (seeded sphere/disc media; the paper's geometry is not available)",
         "config": {"workload": (f"batch of {len(problems)} D2Q9 drainage instances "
@@ -249,6 +251,11 @@ def main():
                 continue
             print(f"[bench] side workload {name}", file=sys.stderr, flush=True)
             side[name] = side_line(torch, lbm, name, args, dev, steps, max(10, steps // 10), chunk)
+        other = 1 - args.math
+        print(f"[bench] side: {args.workload} with {'FP64' if other else 'FP32'} node arithmetic",
+              file=sys.stderr, flush=True)
+        side[f"{args.workload}_{'f64' if other else 'f32'}_arithmetic"] = side_line(
+            torch, lbm, args.workload, args, dev, min(args.steps, 200), 20, chunk, math=other)
         out["side"] = side
     if not args.no_cpu_baseline:
         if not batch and q == 19 and problem.nx > 64:

@@ -48,7 +48,7 @@ typedef enum {
 
 enum { LBM_SRT = 0, LBM_MRT = 1, LBM_TRT = 2 };            /* lbm_params.collision */
 enum { LBM_STORE_F32 = 0, LBM_STORE_BF16DEV = 1 };          /* lbm_params.storage */
-enum { LBM_MATH_F64 = 0, LBM_MATH_F32 = 1 };                /* lbm_params.math */
+enum { LBM_MATH_F32 = 0, LBM_MATH_F64 = 1 };                /* lbm_params.math */
 enum { LBM_AUTO = 0, LBM_FUSED = 1, LBM_SPLIT = 2, LBM_COMPACT = 3,
        LBM_FUSED_LIST = 4, LBM_COMPACT_FUSED = 5 };         /* lbm_params.strategy */
 
@@ -83,7 +83,10 @@ typedef struct {
   double lambda;          /* magic (1/s_nu - 1/2)(1/s_q - 1/2); <= 0: s_q = s_nu */
   double s_e, s_eps;      /* MRT energy-mode rates; <= 0: equal to s_nu */
   int32_t storage;        /* LBM_STORE_F32 or LBM_STORE_BF16DEV: how f* is held */
-  int32_t math;           /* node arithmetic: LBM_MATH_F64 (default) or LBM_MATH_F32 */
+  int32_t math;           /* node arithmetic: LBM_MATH_F32 (default: the
+                             collision works on departures from w_i rho with
+                             FP64 density sums, and stays within 1e-5 of
+                             FP64 over 200 steps) or LBM_MATH_F64 */
   int32_t strategy;       /* LBM_AUTO, LBM_FUSED (one launch per step, halo
                              densities recomputed per block), LBM_SPLIT
                              (density, solid-density and collide launches) or

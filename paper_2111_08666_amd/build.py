@@ -12,6 +12,9 @@ FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     # keep FP32 arithmetic off the packed-math path
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # fuse a*b + c only inside one source expression: kernels that share the
+    # node arithmetic then round alike, whatever else surrounds it
+    "-ffp-contract=on",
     "-Wno-unused-command-line-argument",
 ]
 

@@ -35,8 +35,8 @@ template <> struct Lat<19> {
 };
 
 // ---------------------------------------------------------------------------
-// Node arithmetic runs in the type R (double by default, float optional);
-// populations are held and stored as float.
+// Node arithmetic runs in the type R (float by default, double optional);
+// populations are held and stored as float, density sums run in double.
 // ---------------------------------------------------------------------------
 
 // Zou-He pressure completion at an x face (Eqs. 18-25): given the density
@@ -107,8 +107,8 @@ __device__ __forceinline__ void complete_boundary(const InstDev &d, uint32_t inf
   }
 }
 
-// Reciprocal: hardware estimate refined by two Newton steps in double (to
-// full precision), one in float.
+// Reciprocal: hardware estimate refined by two Newton steps (to full
+// precision in double, correctly rounded in nearly every case in float).
 template <typename R> __device__ __forceinline__ R rcp(R x);
 template <> __device__ __forceinline__ double rcp<double>(double x) {
   double r = __builtin_amdgcn_rcp(x);
@@ -119,18 +119,21 @@ template <> __device__ __forceinline__ double rcp<double>(double x) {
 }
 template <> __device__ __forceinline__ float rcp<float>(float x) {
   float r = __builtin_amdgcn_rcpf(x);
-  const float e = __builtin_fmaf(-x, r, 1.f);
+  float e = __builtin_fmaf(-x, r, 1.f);
+  r = __builtin_fmaf(r, e, r);
+  e = __builtin_fmaf(-x, r, 1.f);
   return __builtin_fmaf(r, e, r);
 }
 
-// Sum of the populations, pairing opposite links first.
+// Sum of the populations, pairing opposite links first; accumulated in FP64
+// whatever the node arithmetic (the density is then rounded once).
 template <int Q, typename R>
 __device__ __forceinline__ R sum_q(const float (&f)[Q]) {
-  R s = (R)f[0];
+  double s = (double)f[0];
 #pragma unroll
   for (int i = 1; i < Q; ++i)
-    if (Lat<Q>::opp[i] > i) s += (R)f[i] + (R)f[Lat<Q>::opp[i]];
-  return s;
+    if (Lat<Q>::opp[i] > i) s += (double)f[i] + (double)f[Lat<Q>::opp[i]];
+  return (R)s;
 }
 
 // D3Q19 moment basis of d'Humieres, Ginzburg, Krafczyk, Lallemand & Luo
@@ -192,12 +195,34 @@ __device__ __forceinline__ Rates<R> node_rates(const InstDev &d, R rho1, R rho2,
   return r;
 }
 
+// Fused multiply-add in the node arithmetic's type (one rounding).
+template <typename R> __device__ __forceinline__ R fmar(R a, R b, R c);
+template <> __device__ __forceinline__ double fmar<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
+template <> __device__ __forceinline__ float fmar<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+
+// Departure of population i from the equilibrium (Eq. 2) and its source
+// term (Eq. 11) at velocity u with force F:
+//   feq_i - f_i = (w_i rho - f_i) + w_i rho (3 e.u + 4.5 (e.u)^2 - 1.5 u.u),
+// the first term formed in one rounding (fused multiply-add), so that a
+// population near its rest equilibrium loses nothing to cancellation.
+template <int Q, typename R>
+__device__ __forceinline__ void departure(int i, float f, R rho, R ux, R uy, R uz, R Fx, R Fy, R Fz, R usq15,
+                                          R uF, R &dv, R &S) {
+  using L = Lat<Q>;
+  const R eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
+  const R eF = L::ex[i] * Fx + L::ey[i] * Fy + L::ez[i] * Fz;
+  const R w = (R)L::w[i];
+  dv = fmar<R>(w, rho, -(R)f) + w * rho * (R(3) * eu + R(4.5) * eu * eu - usq15);
+  S = w * (R(3) * (eF - uF) + R(9) * eu * eF);
+}
+
 // ---------------------------------------------------------------------------
 // Forced collision of one component at one node, in place (Eqs. 1, 2, 11).
 // u: common velocity (with the half-force shift), F: this component's force.
-// COLL: 0 SRT, 1 MRT (D2Q9: Lallemand-Luo moments; D3Q19: d'Humieres), 2 TRT.  The update is
-// formed as an increment f* - f so the populations' own rounding is not
-// repeated.
+// COLL: 0 SRT, 1 MRT (D2Q9: Lallemand-Luo moments; D3Q19: d'Humieres), 2 TRT.
+// Each moving population changes by an increment built from its departure
+// from equilibrium; the rest population takes minus their sum, so the node
+// keeps its mass to the rounding of the stores.
 // ---------------------------------------------------------------------------
 template <int Q, int COLL, typename R>
 __device__ __forceinline__ void collide_component(float (&fo)[Q], R rho, R ux, R uy, R uz, R Fx,
@@ -205,44 +230,39 @@ __device__ __forceinline__ void collide_component(float (&fo)[Q], R rho, R ux, R
   using L = Lat<Q>;
   const R usq15 = R(1.5) * (ux * ux + uy * uy + uz * uz);
   const R uF = ux * Fx + uy * Fy + uz * Fz;
+  R moved = 0;  // sum of the moving populations' changes
   if constexpr (COLL == 0) {
     const R om = r.s_nu, fac = R(1) - R(0.5) * om;
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const R fi = (R)fo[i];
-      const R eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
-      const R eF = L::ex[i] * Fx + L::ey[i] * Fy + L::ez[i] * Fz;
-      const R w = (R)L::w[i];
-      const R feq = w * rho * (R(1) + R(3) * eu + R(4.5) * eu * eu - usq15);
-      const R S = w * (R(3) * (eF - uF) + R(9) * eu * eF);
-      fo[i] = (float)(fi + (om * (feq - fi) + fac * S));
+    for (int i = 1; i < Q; ++i) {
+      R dv, S;
+      departure<Q, R>(i, fo[i], rho, ux, uy, uz, Fx, Fy, Fz, usq15, uF, dv, S);
+      const R df = om * dv + fac * S;
+      fo[i] = (float)((R)fo[i] + df);
+      moved += df;
     }
   } else if constexpr (COLL == 2) {
     const R sp = r.s_nu, sm = r.s_q;
     const R fp = R(1) - R(0.5) * sp, fm = R(1) - R(0.5) * sm;
-    {  // rest population: symmetric part only
-      const R f0 = (R)fo[0];
-      const R w = (R)L::w[0];
-      fo[0] = (float)(f0 + (sp * (w * rho * (R(1) - usq15) - f0) - fp * w * R(3) * uF));
-    }
     // opposite pairs (i, b): the pair's symmetric and antisymmetric parts
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const int b = L::opp[i];
       if (b < i) continue;
-      const R fi = (R)fo[i], fb = (R)fo[b];
+      // e_b = -e_i: the pair shares e.u and e.F up to sign, so the
+      // departures' halves come from one evaluation of each
       const R eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
       const R eF = L::ex[i] * Fx + L::ey[i] * Fy + L::ez[i] * Fz;
-      const R w = (R)L::w[i];
-      const R eq_p = w * rho * (R(1) + R(4.5) * eu * eu - usq15);
-      const R eq_m = w * rho * R(3) * eu;
-      const R S_p = w * (R(9) * eu * eF - R(3) * uF);
-      const R S_m = w * R(3) * eF;
-      const R f_p = R(0.5) * (fi + fb), f_m = R(0.5) * (fi - fb);
-      const R dp = sp * (eq_p - f_p) + fp * S_p;  // change of the symmetric part
-      const R dm = sm * (eq_m - f_m) + fm * S_m;  // change of the antisymmetric part
-      fo[i] = (float)(fi + (dp + dm));
-      fo[b] = (float)(fb + (dp - dm));
+      const R w = (R)L::w[i], wr = w * rho;
+      const R ai = fmar<R>(w, rho, -(R)fo[i]), ab = fmar<R>(w, rho, -(R)fo[b]);
+      const R dv_p = R(0.5) * (ai + ab) + wr * (R(4.5) * eu * eu - usq15);  // (dv_i + dv_b) / 2
+      const R dv_m = R(0.5) * (ai - ab) + wr * R(3) * eu;                    // (dv_i - dv_b) / 2
+      const R S_p = w * (R(9) * eu * eF - R(3) * uF), S_m = w * R(3) * eF;
+      const R dp = sp * dv_p + fp * S_p;  // change of the symmetric part
+      const R dm = sm * dv_m + fm * S_m;  // change of the antisymmetric part
+      fo[i] = (float)((R)fo[i] + (dp + dm));
+      fo[b] = (float)((R)fo[b] + (dp - dm));
+      moved += R(2) * dp;
     }
   } else if constexpr (Q == 19) {
     // MRT in the d'Humieres moments: the second-order moments relax at s_nu,
@@ -250,13 +270,7 @@ __device__ __forceinline__ void collide_component(float (&fo)[Q], R rho, R ux, R
     // s_q (equal even and odd rates give TRT, equal rates give SRT).
     R dv[Q], S[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const R eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
-      const R eF = L::ex[i] * Fx + L::ey[i] * Fy + L::ez[i] * Fz;
-      const R w = (R)L::w[i];
-      dv[i] = w * rho * (R(1) + R(3) * eu + R(4.5) * eu * eu - usq15) - (R)fo[i];
-      S[i] = w * (R(3) * (eF - uF) + R(9) * eu * eF);
-    }
+    for (int i = 0; i < Q; ++i) departure<Q, R>(i, fo[i], rho, ux, uy, uz, Fx, Fy, Fz, usq15, uF, dv[i], S[i]);
     auto rate = [&](int k) -> R {
       switch (k) {
         case 1: return r.s_e;
@@ -281,62 +295,64 @@ __device__ __forceinline__ void collide_component(float (&fo)[Q], R rho, R ux, R
       dm[k] = (sk * a + (R(1) - R(0.5) * sk) * b) * (R(1) / R(mrt19_norm(k)));
     }
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
+    for (int i = 1; i < Q; ++i) {
       R v = 0;
 #pragma unroll
       for (int k = 1; k < Q; ++k)
         if (mrt19(k, i) != 0) v += R(mrt19(k, i)) * dm[k];
       fo[i] = (float)((R)fo[i] + v);
+      moved += v;
     }
   } else {
-    R f[Q];
+    // D2Q9 MRT: moments (Lallemand-Luo rows e, eps, jx, qx, jy, qy, pxx,
+    // pxy) of the departures from equilibrium and of the source
+    R d[Q], S[Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = (R)fo[i];
-    // non-conserved moments (Lallemand-Luo rows e, eps, jx, qx, jy, qy, pxx, pxy)
-    const R a = f[1] + f[2] + f[3] + f[4];
-    const R dg = f[5] + f[6] + f[7] + f[8];
-    const R m_e = R(-4) * f[0] - a + R(2) * dg;
-    const R m_eps = R(4) * f[0] - R(2) * a + dg;
-    const R d13 = f[1] - f[3], d24 = f[2] - f[4];
-    const R p5 = f[5] - f[7], p6 = f[6] - f[8];
-    const R m_jx = d13 + p5 - p6;
-    const R m_qx = R(-2) * d13 + p5 - p6;
-    const R m_jy = d24 + p5 + p6;
-    const R m_qy = R(-2) * d24 + p5 + p6;
-    const R m_pxx = (f[1] + f[3]) - (f[2] + f[4]);
-    const R m_pxy = (f[5] + f[7]) - (f[6] + f[8]);
-    const R u2 = ux * ux + uy * uy;
-    // equilibrium moments of Eq. 2 and moments of the source of Eq. 11
-    const R e_eq = rho * (R(-2) + R(3) * u2), eps_eq = rho * (R(1) - R(3) * u2);
-    const R jx_eq = rho * ux, jy_eq = rho * uy;
-    const R pxx_eq = rho * (ux * ux - uy * uy), pxy_eq = rho * ux * uy;
-    const R S_e = R(6) * uF, S_eps = R(-6) * uF;
-    const R S_pxx = R(2) * (ux * Fx - uy * Fy), S_pxy = ux * Fy + uy * Fx;
-    const R dm_e = r.s_e * (e_eq - m_e) + (R(1) - R(0.5) * r.s_e) * S_e;
-    const R dm_eps = r.s_eps * (eps_eq - m_eps) + (R(1) - R(0.5) * r.s_eps) * S_eps;
-    const R dm_jx = r.s_j * (jx_eq - m_jx) + (R(1) - R(0.5) * r.s_j) * Fx;
-    const R dm_jy = r.s_j * (jy_eq - m_jy) + (R(1) - R(0.5) * r.s_j) * Fy;
-    const R dm_qx = r.s_q * (-jx_eq - m_qx) - (R(1) - R(0.5) * r.s_q) * Fx;
-    const R dm_qy = r.s_q * (-jy_eq - m_qy) - (R(1) - R(0.5) * r.s_q) * Fy;
-    const R dm_pxx = r.s_nu * (pxx_eq - m_pxx) + (R(1) - R(0.5) * r.s_nu) * S_pxx;
-    const R dm_pxy = r.s_nu * (pxy_eq - m_pxy) + (R(1) - R(0.5) * r.s_nu) * S_pxy;
+    for (int i = 0; i < Q; ++i) departure<Q, R>(i, fo[i], rho, ux, uy, uz, Fx, Fy, Fz, usq15, uF, d[i], S[i]);
+    auto mom = [](const R(&f)[Q], R(&m)[8]) {
+      const R a = f[1] + f[2] + f[3] + f[4];
+      const R dg = f[5] + f[6] + f[7] + f[8];
+      const R d13 = f[1] - f[3], d24 = f[2] - f[4];
+      const R p5 = f[5] - f[7], p6 = f[6] - f[8];
+      m[0] = R(-4) * f[0] - a + R(2) * dg;      // e
+      m[1] = R(4) * f[0] - R(2) * a + dg;       // eps
+      m[2] = d13 + p5 - p6;                     // jx
+      m[3] = R(-2) * d13 + p5 - p6;             // qx
+      m[4] = d24 + p5 + p6;                     // jy
+      m[5] = R(-2) * d24 + p5 + p6;             // qy
+      m[6] = (f[1] + f[3]) - (f[2] + f[4]);     // pxx
+      m[7] = (f[5] + f[7]) - (f[6] + f[8]);     // pxy
+    };
+    R md[8], ms[8];
+    mom(d, md);
+    mom(S, ms);
+    const R sr[8] = {r.s_e, r.s_eps, r.s_j, r.s_q, r.s_j, r.s_q, r.s_nu, r.s_nu};
+    R dmv[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) dmv[k] = sr[k] * md[k] + (R(1) - R(0.5) * sr[k]) * ms[k];
     // f += M^-1 dm, M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
-    const R ce = dm_e * R(1.0 / 36.0), cp = dm_eps * R(1.0 / 36.0);
-    const R jx = dm_jx * R(1.0 / 6.0), qx = dm_qx * R(1.0 / 12.0);
-    const R jy = dm_jy * R(1.0 / 6.0), qy = dm_qy * R(1.0 / 12.0);
-    const R pxx = dm_pxx * R(0.25), pxy = dm_pxy * R(0.25);
+    const R ce = dmv[0] * R(1.0 / 36.0), cp = dmv[1] * R(1.0 / 36.0);
+    const R jx = dmv[2] * R(1.0 / 6.0), qx = dmv[3] * R(1.0 / 12.0);
+    const R jy = dmv[4] * R(1.0 / 6.0), qy = dmv[5] * R(1.0 / 12.0);
+    const R pxx = dmv[6] * R(0.25), pxy = dmv[7] * R(0.25);
     const R ax = -ce - R(2) * cp;
     const R dd = R(2) * ce + cp;
-    fo[0] = (float)(f[0] + (R(-4) * ce + R(4) * cp));
-    fo[1] = (float)(f[1] + (ax + jx - R(2) * qx + pxx));
-    fo[2] = (float)(f[2] + (ax + jy - R(2) * qy - pxx));
-    fo[3] = (float)(f[3] + (ax - jx + R(2) * qx + pxx));
-    fo[4] = (float)(f[4] + (ax - jy + R(2) * qy - pxx));
-    fo[5] = (float)(f[5] + (dd + jx + qx + jy + qy + pxy));
-    fo[6] = (float)(f[6] + (dd - jx - qx + jy + qy - pxy));
-    fo[7] = (float)(f[7] + (dd - jx - qx - jy - qy + pxy));
-    fo[8] = (float)(f[8] + (dd + jx + qx - jy - qy - pxy));
+    const R df[Q] = {0,
+                     ax + jx - R(2) * qx + pxx,
+                     ax + jy - R(2) * qy - pxx,
+                     ax - jx + R(2) * qx + pxx,
+                     ax - jy + R(2) * qy - pxx,
+                     dd + jx + qx + jy + qy + pxy,
+                     dd - jx - qx + jy + qy - pxy,
+                     dd - jx - qx - jy - qy + pxy,
+                     dd + jx + qx - jy - qy - pxy};
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      fo[i] = (float)((R)fo[i] + df[i]);
+      moved += df[i];
+    }
   }
+  fo[0] = (float)((R)fo[0] - moved);
 }
 
 // Mixture velocity, rates and the collision of both components at a node.

@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/lbm.h"
+
 namespace lbm {
 
 // Per-node info word.  For a fluid node, bit i (i < Q) says that the pull

@@ -209,7 +209,7 @@ const char *step_kernel_name(int q, int collision, int storage, int math, int st
   static const char *lat[2] = {"d2q9", "d3q19"};
   static const char *coll[3] = {"SRT", "MRT", "TRT"};
   static const char *st[2] = {"f32", "bf16dev"};
-  static const char *mt[2] = {"double", "float"};
+  static const char *mt[2] = {"float", "double"};  // indexed by LBM_MATH_F32, LBM_MATH_F64
   static thread_local char buf[128];
   if (strategy == 2)
     snprintf(buf, sizeof buf, "collide_kernel<%d,%s,%s,%s> (+rho_kernel, psi_kernel)", q, coll[collision],

@@ -1733,11 +1733,11 @@ static void launch_st(const StepLaunch &L, hipStream_t s) {
 
 template <int COLL>
 hipError_t launch_step_coll(const StepLaunch &L, hipStream_t s) {
-  if (L.math == 0) {
-    if (L.storage == 0) launch_st<COLL, 0, double>(L, s);
+  if (L.math == LBM_MATH_F64) {
+    if (L.storage == LBM_STORE_F32) launch_st<COLL, 0, double>(L, s);
     else launch_st<COLL, 1, double>(L, s);
   } else {
-    if (L.storage == 0) launch_st<COLL, 0, float>(L, s);
+    if (L.storage == LBM_STORE_F32) launch_st<COLL, 0, float>(L, s);
     else launch_st<COLL, 1, float>(L, s);
   }
   return hipGetLastError();

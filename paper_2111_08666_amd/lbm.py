@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "liblbm.so")
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EUNSTABLE, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 SRT, MRT, TRT = 0, 1, 2
 STORE_F32, STORE_BF16DEV = 0, 1
-MATH_F64, MATH_F32 = 0, 1
+MATH_F32, MATH_F64 = 0, 1
 AUTO, FUSED, SPLIT, COMPACT, FUSED_LIST, COMPACT_FUSED = 0, 1, 2, 3, 4, 5
 
 EXPORTS = [
@@ -134,7 +134,7 @@ def make_geometry(problem, keep: list) -> Geometry:
     return g
 
 
-def make_params(problem, storage=STORE_F32, math=MATH_F64, strategy=AUTO, tile_rows=0) -> Params:
+def make_params(problem, storage=STORE_F32, math=MATH_F32, strategy=AUTO, tile_rows=0) -> Params:
     p = Params()
     p.tau[0], p.tau[1] = problem.tau
     p.G, p.xi = problem.G, problem.xi
@@ -176,7 +176,7 @@ class Solver:
     """One instance on one GPU.  torch allocates the workspace; every kernel
     runs on `stream` (default: a new non-default torch stream)."""
 
-    def __init__(self, problem, storage=STORE_F32, device="cuda:0", stream=None, math=MATH_F64,
+    def __init__(self, problem, storage=STORE_F32, device="cuda:0", stream=None, math=MATH_F32,
                  strategy=AUTO, tile_rows=0):
         import torch
         self.problem = problem
@@ -280,7 +280,7 @@ class Solver:
 class BatchSolver:
     """Many instances advanced by one launch per step (flat block table)."""
 
-    def __init__(self, problems, storage=STORE_F32, device="cuda:0", stream=None, math=MATH_F64,
+    def __init__(self, problems, storage=STORE_F32, device="cuda:0", stream=None, math=MATH_F32,
                  strategy=AUTO, tile_rows=0):
         import torch
         self.problems = list(problems)

@@ -6,8 +6,8 @@ autotuner has picked the variant -- the configuration bench.py times.
 Per-instance error against the FP64 oracle after 200 steps at 1024 seeded
 fluid nodes per instance (tests/golden/batch64_step200_samples.npz, written
 by tests/golden/make_batch64_samples.py from the oracle alone):
-  FP32 storage: every sampled density within 1e-5 relative, with FP64 and
-  with FP32 node arithmetic;
+  FP32 storage: every sampled density within 1e-5 relative, with FP32 (the
+  default) and with FP64 node arithmetic;
   BF16-deviation storage: within 2e-2 (measured values printed).
 """
 import os
@@ -54,7 +54,9 @@ def _advance_like_bench(b, steps=200):
     return rep
 
 
-@pytest.mark.parametrize("storage,math,bound", [(0, 0, 1e-5), (1, 0, 2e-2), (0, 1, 1e-5)])
+# storage 0 FP32, 1 BF16 deviations; math 0 FP32 node arithmetic (the
+# default), 1 FP64
+@pytest.mark.parametrize("storage,math,bound", [(0, 0, 1e-5), (0, 1, 1e-5), (1, 0, 2e-2)])
 def test_batch64_per_instance_error_vs_oracle(lbm, problems, ref, storage, math, bound):
     assert int(ref["steps"]) == 200
     b = lbm.BatchSolver(problems, storage=storage, math=math)

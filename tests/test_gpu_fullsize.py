@@ -5,8 +5,8 @@ each (tests/golden/fullsize_samples.npz, written by
 tests/golden/make_fullsize_samples.py from the oracle alone):
   D2Q9 1024x512 disc-medium drainage, MRT, after 200 steps;
   D3Q19 384^3 sphere-pack drainage, TRT, after 200 steps.
-Every sampled density within 1e-5 relative (FP32 storage, FP64 node
-arithmetic)."""
+Every sampled density within 1e-5 relative (FP32 storage, FP32 and FP64
+node arithmetic)."""
 import os
 
 import numpy as np
@@ -36,12 +36,12 @@ def ref():
         return {k: z[k] for k in z.files}
 
 
+# lbm_params.math: 0 FP32 node arithmetic (the default), 1 FP64
 @pytest.mark.parametrize("name,make,math", [("d2q9", I.large_drainage, 0), ("d2q9", I.large_drainage, 1),
-                                            ("d3q19", I.drainage_3d, 0)])
+                                            ("d3q19", I.drainage_3d, 0), ("d3q19", I.drainage_3d, 1)])
 def test_full_size_workload_matches_oracle_samples(lbm, ref, name, make, math):
-    """math = 1: FP32 node arithmetic on the MRT drainage, held to the same
-    1e-5 bar (FP32 arithmetic misses it on some SRT/TRT parity cases, so it
-    is not the default)."""
+    """Both node arithmetics on the full-size MRT drainage (D2Q9) and TRT
+    sphere-pack drainage (D3Q19), held to the same 1e-5 bar."""
     if f"{name}_rho" not in ref:
         pytest.skip(f"no {name} samples in the fixture")
     steps = int(ref[f"{name}_steps"])

@@ -47,13 +47,15 @@ def _rel_err(g, o, mask):
 STRATEGIES = {"fused": 1, "split": 2, "compact": 3, "fused_list": 4, "compact_fused": 5}
 
 
+@pytest.mark.parametrize("math", ["f32", "f64"])
 @pytest.mark.parametrize("strategy", sorted(STRATEGIES))
 @pytest.mark.parametrize("name", sorted(PROBLEMS))
-def test_density_parity_200_steps(lbm, name, strategy):
+def test_density_parity_200_steps(lbm, name, strategy, math):
+    """Both node arithmetics (FP32, the default, and FP64) on every layout."""
     p = PROBLEMS[name]
-    print(f"[parity] {name} {p.mask.shape} q={p.q} coll={p.collision} {strategy}", flush=True)
+    print(f"[parity] {name} {p.mask.shape} q={p.q} coll={p.collision} {strategy} {math}", flush=True)
     ref = _oracle_series(p, CHECKPOINTS)
-    s = lbm.Solver(p, strategy=STRATEGIES[strategy])
+    s = lbm.Solver(p, strategy=STRATEGIES[strategy], math=lbm.MATH_F64 if math == "f64" else lbm.MATH_F32)
     t = 0
     worst = 0.0
     for c in CHECKPOINTS:
@@ -62,7 +64,7 @@ def test_density_parity_200_steps(lbm, name, strategy):
         err = _rel_err(s.density(), ref[c], p.mask)
         worst = max(worst, err)
         assert err <= REL_TOL, (name, c, err)
-    print(f"[parity] {name} {strategy}: worst relative density error {worst:.2e}", flush=True)
+    print(f"[parity] {name} {strategy} {math}: worst relative density error {worst:.2e}", flush=True)
 
 
 @pytest.mark.parametrize("strategy", [1, 4, 5])
