@@ -99,9 +99,12 @@ typedef struct {
                              parked in LDS; nx up to about 1.8 million);
                              LBM_COMPACT_FUSED (the fused step over the
                              compacted layout of LBM_COMPACT: D2Q9, the
-                             fused tile step; D3Q19 with FP32 storage, one
-                             launch that marches each x-y tile through z,
-                             pulling every population once).
+                             fused tile step; D3Q19 with FP32 storage, a
+                             tile march that pulls every population once and
+                             sums the next step's densities on chip, which
+                             the context then carries between steps, plus a
+                             pull for the tiles' edge nodes and the solid
+                             densities of Eq. 17: three launches).
                              The layout is fixed at creation: the compacted
                              strategies cannot be switched to or from the
                              others (lbm_autotune stays within the layout).

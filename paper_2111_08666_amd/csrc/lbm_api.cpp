@@ -45,7 +45,7 @@ struct Layout {
   bool compact;
   int64_t nf, nsolid;
   int32_t cpitch;
-  size_t cword_bytes, ckey_bytes, cbnd_bytes;
+  size_t cword_bytes, ckey_bytes, cbnd_bytes, cedge_bytes;
 };
 
 // Fused-kernel tiling of one instance for a tile height (D2Q9) / fixed 3D tile.
@@ -54,7 +54,7 @@ struct Tiling {
   int64_t blocks;
 };
 
-// Compute units of the device (blocks of the z-marching 3D step: one per CU).
+// Compute units of the device (for the z-chunking of the compacted 3D fused step).
 int device_cus() {
   static int n = 0;
   if (!n) {
@@ -72,15 +72,17 @@ Tiling make_tiling(int q, int nx, int ny, int nz, int ty, int strategy = LBM_FUS
   Tiling t{};
   t.tiles_x = (nx + kTileX - 1) / kTileX;
   if (q == 19 && strategy == LBM_COMPACT_FUSED) {
-    // z-marching step: one block per CU at a time.  Choose the number of z
-    // chunks that minimises (rounds of blocks) x (planes per chunk + the 4
-    // extra density planes a chunk pulls).
-    t.tiles_y = (ny + kTileY3 - 1) / kTileY3;
-    const int64_t xy = (int64_t)t.tiles_x * t.tiles_y, cus = device_cus();
+    // compacted 3D fused step: tiles of one row word by kFwdRows rows, three
+    // blocks resident per CU (LDS).  Choose the number of z chunks that
+    // minimises (rounds of blocks) x (planes per chunk + 2): a chunk's two
+    // end planes leave their densities to the edge pull.
+    t.tiles_x = (nx + 63) / 64;
+    t.tiles_y = (ny + kFwdRows - 1) / kFwdRows;
+    const int64_t xy = (int64_t)t.tiles_x * t.tiles_y, slots = 3 * (int64_t)device_cus();
     int64_t best = -1;
-    for (int tz = 1; tz <= std::max(1, nz / 16); ++tz) {
+    for (int tz = 1; tz <= std::max(1, nz / 8); ++tz) {
       const int64_t zlen = (nz + tz - 1) / tz;
-      const int64_t cost = ((xy * tz + cus - 1) / cus) * (zlen + 4);
+      const int64_t cost = ((xy * tz + slots - 1) / slots) * (zlen + 2);
       if (best < 0 || cost < best) { best = cost; t.tiles_z = tz; }
     }
   } else if (q == 9) {
@@ -150,12 +152,17 @@ Layout make_layout(const lbm_geometry &g, const lbm_params &p) {
     L.cword_bytes = align_up((size_t)g.ny * g.nz * (L.pitch / 64) * sizeof(RowWord));
     L.ckey_bytes = align_up((size_t)std::max<int64_t>(nf, 1) * sizeof(uint32_t));
     L.cbnd_bytes = align_up((size_t)std::max<int64_t>(L.nsolid, 1) * sizeof(uint32_t));
+    L.cedge_bytes = g.q == 19 ? L.ckey_bytes : 0;
   }
   return L;
 }
 
 // Compact index tables of one instance (see RowWord): row words, compact ->
-// dense node index, and the solid nodes with a fluid neighbour.
+// dense node index, and the solid nodes with a fluid neighbour.  Fluid nodes
+// are numbered row by row in x order, so the fluid nodes of a row word are
+// consecutive.  (A tile-ordered numbering, each kFwdRows x 64 tile plane one
+// contiguous run, was measured for D3Q19 at 384^3: the fused 3D step gained
+// 22 %, the compacted split step lost 4 %, and the split step stays faster.)
 void build_compact(const lbm_geometry &g, const Layout &L, const std::vector<uint32_t> &info,
                    std::vector<RowWord> &words, std::vector<uint32_t> &key, std::vector<uint32_t> &bnd) {
   const int W = L.pitch / 64;
@@ -337,6 +344,10 @@ struct lbm_batch {
   hipGraph_t graph = nullptr;
   int64_t graph_n = 0;
   int graph_parity = 0;
+  // compacted 3D fused step: compact -> dense node keys per instance (host
+  // copy, for the edge lists) and whether the carried psi matches the state
+  std::vector<std::vector<uint32_t>> ckey_host;
+  bool psi_valid = false;
 };
 
 struct lbm_ctx {
@@ -392,7 +403,7 @@ size_t batch_bytes(int32_t k, const lbm_geometry *g, const lbm_params *p, int64_
     nb += std::max(make_tiling(g[i].q, g[i].nx, g[i].ny, g[i].nz, 8).blocks,
                    make_tiling(g[i].q, g[i].nx, g[i].ny, g[i].nz, 8, LBM_COMPACT_FUSED).blocks);
     bytes += L.info_bytes + L.frozen_bytes + L.psi_bytes + 2 * L.buf_bytes;
-    if (L.compact) bytes += L.cword_bytes + L.ckey_bytes + L.cbnd_bytes;
+    if (L.compact) bytes += L.cword_bytes + L.ckey_bytes + L.cbnd_bytes + L.cedge_bytes;
     InstDev tmp{};
     tmp.nx = g[i].nx; tmp.ny = g[i].ny; tmp.nz = g[i].nz;
     ob = std::max(ob, obs_blocks(tmp));
@@ -420,6 +431,31 @@ lbm_status apply_plan(lbm_batch *b, int strategy, int ty) {
     base += t.blocks;
   }
   if (base > b->table_cap) return fail(b, LBM_EINVAL, "block table capacity exceeded");
+  // compacted 3D fused step: the fluid nodes whose next-step densities the
+  // tile march does not complete (outer ring of each tile, end planes of
+  // each z chunk), in compact order
+  for (int i = 0; i < b->k; ++i) {
+    InstDev &h = b->h[(size_t)i];
+    h.nedge = 0;
+    if (!(b->q == 19 && strategy == LBM_COMPACT_FUSED)) continue;
+    std::vector<uint32_t> edge;
+    const std::vector<uint32_t> &key = b->ckey_host[(size_t)i];
+    const int zlen = (h.nz + h.tiles_z - 1) / h.tiles_z;
+    for (size_t c = 0; c < key.size(); ++c) {
+      const uint32_t r = key[c] / (uint32_t)h.pitch;
+      const int x = (int)(key[c] - r * (uint32_t)h.pitch), y = (int)(r % (uint32_t)h.ny), z = (int)(r / (uint32_t)h.ny);
+      const int x0 = x / 64 * 64, y0 = y / kFwdRows * kFwdRows, z0 = z / zlen * zlen;
+      const int W = std::min(64, h.nx - x0), H = std::min(kFwdRows, h.ny - y0), z1 = std::min(h.nz, z0 + zlen);
+      const bool inner = x - x0 >= 1 && x - x0 <= W - 2 && y - y0 >= 1 && y - y0 <= H - 2 && z > z0 && z < z1 - 1;
+      if (!inner) edge.push_back((uint32_t)c);
+    }
+    h.nedge = (int64_t)edge.size();
+    if (!edge.empty())
+      HIPCHK(b, hipMemcpyAsync((void *)h.cedge, edge.data(), sizeof(uint32_t) * edge.size(), hipMemcpyHostToDevice,
+                               b->stream));
+    HIPCHK(b, hipStreamSynchronize(b->stream));  // the host list dies here
+  }
+  b->psi_valid = false;
   b->strategy = strategy;
   b->ty = ty;
   b->n_blocks = base;
@@ -525,6 +561,7 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
       h.cword = reinterpret_cast<const RowWord *>(take(L.cword_bytes));
       h.ckey = reinterpret_cast<const uint32_t *>(take(L.ckey_bytes));
       h.cbnd = reinterpret_cast<const uint32_t *>(take(L.cbnd_bytes));
+      if (L.cedge_bytes) h.cedge = reinterpret_cast<const uint32_t *>(take(L.cedge_bytes));
       build_compact(g[i], L, info, cw, ck, cb);
       h.nf = (int64_t)ck.size();
       h.nbnd = (int64_t)cb.size();
@@ -539,6 +576,7 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
     }
     b->h.push_back(h);
     b->lay.push_back(L);
+    b->ckey_host.push_back(g[i].q == 19 ? ck : std::vector<uint32_t>());
     b->geom_hash.push_back(geometry_hash(g[i]));
     // held (frozen) links: rest equilibria of the initial densities
     const int64_t N = L.n_nodes;
@@ -573,10 +611,26 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
   return LBM_OK;
 }
 
+// The compacted 3D fused step carries the next step's psi; rebuild it from
+// the current state when set-up, a load, new boundary densities, a change
+// of step variant or a density read-out staged through it left it stale.
+bool carries_psi(const lbm_batch *b) { return b->q == 19 && b->strategy == LBM_COMPACT_FUSED; }
+
+lbm_status ensure_psi(lbm_batch *b) {
+  if (!carries_psi(b) || b->psi_valid) return LBM_OK;
+  for (int i = 0; i < b->k; ++i) HIPCHK(b, launch_fwd_rebuild(b->d_insts + i, b->h[i], b->parity, b->stream));
+  b->psi_valid = true;
+  return LBM_OK;
+}
+
 lbm_status batch_step(lbm_batch *b, int64_t n) {
   if (!b) return fail(nullptr, LBM_EINVAL, "NULL handle");
   if (n < 0) return fail(b, LBM_EINVAL, "n must be >= 0");
   if (b->unstable) return fail(b, LBM_EUNSTABLE, "state is unstable (non-finite density)");
+  if (n > 0) {
+    const lbm_status st = ensure_psi(b);
+    if (st != LBM_OK) return st;
+  }
   for (int64_t s = 0; s < n; ++s) {
     HIPCHK(b, launch_step(step_launch(b, b->parity), b->stream));
     b->parity ^= 1;
@@ -590,6 +644,10 @@ lbm_status batch_step_graph(lbm_batch *b, int64_t n, int64_t reps) {
   if (n <= 0 || (n & 1) || reps < 0) return fail(b, LBM_EINVAL, "n must be even and > 0, reps >= 0");
   if (!b->stream) return fail(b, LBM_ESTATE, "graph capture needs a non-default stream");
   if (b->unstable) return fail(b, LBM_EUNSTABLE, "state is unstable (non-finite density)");
+  if (reps > 0) {
+    const lbm_status st = ensure_psi(b);
+    if (st != LBM_OK) return st;
+  }
   if (!b->gexec || b->graph_n != n || b->graph_parity != b->parity) {
     if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
     if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
@@ -671,6 +729,7 @@ lbm_status batch_density(lbm_batch *b, int32_t i, float *dst, int32_t dst_is_dev
   // compacted population buffers may hold fewer than 2N floats), and every
   // step rewrites it before reading it
   float *stage = reinterpret_cast<float *>(h.psi);
+  b->psi_valid = false;
   HIPCHK(b, launch_density(b->d_insts + i, h, b->parity, stage, b->stream));
   HIPCHK(b, hipMemcpyAsync(dst, stage, sizeof(float) * 2 * (size_t)N, hipMemcpyDeviceToHost, b->stream));
   HIPCHK(b, hipStreamSynchronize(b->stream));
@@ -678,9 +737,9 @@ lbm_status batch_density(lbm_batch *b, int32_t i, float *dst, int32_t dst_is_dev
 }
 
 // Checkpoint blob: header, the boundary densities, the held (Eq. 26/27)
-// links, then the current population buffer.  The header records the layout
-// and the geometry, and lbm_load restores a blob only onto a context with
-// the same ones.
+// links, the current population buffer, and (compacted 3D fused step) the
+// carried psi.  The header records the layout and the geometry, and lbm_load
+// restores a blob only onto a context with the same ones.
 struct CkptHeader {
   char magic[8];
   int32_t version, k, q, storage;
@@ -690,10 +749,14 @@ struct CkptHeader {
   int64_t step;
   uint64_t buf_bytes, frozen_bytes, geom_hash;
   double rho_in1, rho_out2;
+  uint64_t psi_bytes;  // 0, or the carried psi array (dense float pairs)
 };
-constexpr int32_t kCkptVersion = 2;
+constexpr int32_t kCkptVersion = 3;
 
-size_t ckpt_bytes(const Layout &L) { return sizeof(CkptHeader) + L.frozen_bytes + L.buf_bytes; }
+size_t carried_psi_bytes(const InstDev &h) { return (size_t)h.pitch * h.ny * h.nz * 2 * sizeof(float); }
+size_t ckpt_bytes(const Layout &L, size_t psi_bytes) {
+  return sizeof(CkptHeader) + L.frozen_bytes + L.buf_bytes + psi_bytes;
+}
 
 }  // namespace
 
@@ -728,6 +791,7 @@ lbm_status lbm_set_bc(lbm_ctx *ctx, double rho_in1, double rho_out2) {
     return fail(b, LBM_EINVAL, "boundary densities must be finite and > 0");
   b->h[0].rho_in1 = rho_in1;
   b->h[0].rho_out2 = rho_out2;
+  b->psi_valid = false;  // the carried inlet/outlet densities follow the old values
   HIPCHK(b, hipMemcpyAsync(b->d_insts, &b->h[0], sizeof(InstDev), hipMemcpyHostToDevice, b->stream));
   HIPCHK(b, hipStreamSynchronize(b->stream));
   return LBM_OK;
@@ -757,9 +821,14 @@ lbm_status lbm_save(lbm_ctx *ctx, void *host_blob, size_t *bytes) {
   if (!ctx || !bytes) return fail(nullptr, LBM_EINVAL, "NULL argument");
   lbm_batch *b = ctx->b;
   const Layout &L = b->lay[0];
-  const size_t need = ckpt_bytes(L);
+  const size_t pb = carries_psi(b) ? carried_psi_bytes(b->h[0]) : 0;
+  const size_t need = ckpt_bytes(L, pb);
   if (!host_blob) { *bytes = need; return LBM_OK; }
   if (*bytes < need) return fail(b, LBM_EINVAL, "checkpoint buffer too small");
+  if (pb) {
+    const lbm_status st = ensure_psi(b);
+    if (st != LBM_OK) return st;
+  }
   const InstDev &h = b->h[0];
   CkptHeader hd{};
   std::memcpy(hd.magic, "LBMCKPT", 8);
@@ -769,11 +838,16 @@ lbm_status lbm_save(lbm_ctx *ctx, void *host_blob, size_t *bytes) {
   hd.step = b->step;
   hd.buf_bytes = L.buf_bytes; hd.frozen_bytes = L.frozen_bytes; hd.geom_hash = b->geom_hash[0];
   hd.rho_in1 = h.rho_in1; hd.rho_out2 = h.rho_out2;
+  hd.psi_bytes = pb;
   char *p = reinterpret_cast<char *>(host_blob);
   std::memcpy(p, &hd, sizeof(hd));
   HIPCHK(b, hipMemcpyAsync(p + sizeof(hd), h.frozen, L.frozen_bytes, hipMemcpyDeviceToHost, b->stream));
   HIPCHK(b, hipMemcpyAsync(p + sizeof(hd) + L.frozen_bytes, h.f[b->parity], L.buf_bytes, hipMemcpyDeviceToHost,
                            b->stream));
+  if (pb)
+    HIPCHK(b, hipMemcpyAsync(p + sizeof(hd) + L.frozen_bytes + L.buf_bytes,
+                             reinterpret_cast<const char *>(h.psi) + (size_t)b->parity * pb, pb,
+                             hipMemcpyDeviceToHost, b->stream));
   HIPCHK(b, hipStreamSynchronize(b->stream));
   *bytes = need;
   return LBM_OK;
@@ -783,10 +857,12 @@ lbm_status lbm_load(lbm_ctx *ctx, const void *host_blob, size_t bytes) {
   if (!ctx || !host_blob) return fail(nullptr, LBM_EINVAL, "NULL argument");
   lbm_batch *b = ctx->b;
   const Layout &L = b->lay[0];
-  const size_t need = ckpt_bytes(L);
   if (bytes < sizeof(CkptHeader)) return fail(b, LBM_EINVAL, "checkpoint too small");
   CkptHeader hd;
   std::memcpy(&hd, host_blob, sizeof(hd));
+  if (hd.psi_bytes != 0 && hd.psi_bytes != carried_psi_bytes(b->h[0]))
+    return fail(b, LBM_EINVAL, "corrupt checkpoint (carried psi size)");
+  const size_t need = ckpt_bytes(L, (size_t)hd.psi_bytes);
   const InstDev &cur = b->h[0];
   if (std::memcmp(hd.magic, "LBMCKPT", 8) || hd.version != kCkptVersion || hd.k != 1)
     return fail(b, LBM_EINVAL, "not a checkpoint of this library version");
@@ -806,6 +882,13 @@ lbm_status lbm_load(lbm_ctx *ctx, const void *host_blob, size_t bytes) {
                            b->stream));
   HIPCHK(b, hipMemcpyAsync(b->h[0].f[b->parity], p + sizeof(hd) + L.frozen_bytes, L.buf_bytes,
                            hipMemcpyHostToDevice, b->stream));
+  // a carried psi is restored only for the step that carries it; otherwise
+  // it is rebuilt from the state before the next step
+  b->psi_valid = hd.psi_bytes != 0 && carries_psi(b);
+  if (b->psi_valid)
+    HIPCHK(b, hipMemcpyAsync(reinterpret_cast<char *>(b->h[0].psi) + (size_t)b->parity * hd.psi_bytes,
+                             p + sizeof(hd) + L.frozen_bytes + L.buf_bytes, hd.psi_bytes, hipMemcpyHostToDevice,
+                             b->stream));
   HIPCHK(b, hipMemcpyAsync(b->d_insts, &b->h[0], sizeof(InstDev), hipMemcpyHostToDevice, b->stream));
   HIPCHK(b, hipStreamSynchronize(b->stream));
   b->unstable = false;
@@ -850,7 +933,7 @@ lbm_status lbm_batch_kernel_info(const lbm_batch *b, char *name, size_t name_len
       *grid_blocks = b->n_blocks;
     }
   }
-  if (block_threads) *block_threads = (b->strategy == LBM_COMPACT_FUSED && b->q == 19) ? 512 : 256;
+  if (block_threads) *block_threads = 256;
   return LBM_OK;
 }
 

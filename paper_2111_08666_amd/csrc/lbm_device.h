@@ -22,6 +22,9 @@ constexpr uint32_t kLinkMask = (1u << 19) - 1u;
 constexpr int kTileX = 60;
 // 3D step tile: the same 64-lane rows, TY3 interior rows in y, marching in z.
 constexpr int kTileY3 = 8;
+// Compacted 3D fused step: a tile is one row word (64 columns) by kFwdRows
+// rows, marching a chunk of z.
+constexpr int kFwdRows = 8;
 
 // Compacted layout: the fluid nodes of each (y, z) row, in x order, get
 // consecutive compact indices c.  A 64-node word of a row is described by its
@@ -52,7 +55,9 @@ struct InstDev {
   const RowWord *cword;   // [ny * nz][pitch / 64]
   const uint32_t *ckey;   // [nf]: dense node index x + pitch * (y + ny * z) of compact node c
   const uint32_t *cbnd;   // [nbnd]: dense index of each solid node with a fluid neighbour
-  int64_t nf, nbnd;
+  const uint32_t *cedge;  // [nedge]: compact indices of the fluid nodes whose next-step
+                          // densities the compacted 3D fused step leaves to a pull
+  int64_t nf, nbnd, nedge;
   int32_t cpitch, compact;
 };
 
@@ -77,6 +82,10 @@ hipError_t launch_observables(const InstDev *d_inst, const InstDev &h_inst, int 
                               double *partials, int n_blocks, double *result, hipStream_t s);
 hipError_t launch_density(const InstDev *d_inst, const InstDev &h_inst, int parity,
                           float *dst, hipStream_t s);
+// The compacted 3D fused step carries the next step's psi between steps;
+// this recomputes it from buffer `parity` (after set-up, a checkpoint load,
+// a change of boundary densities or of step variant).
+hipError_t launch_fwd_rebuild(const InstDev *d_inst, const InstDev &h_inst, int parity, hipStream_t s);
 const char *step_kernel_name(int q, int collision, int storage, int math, int strategy, int ty);
 int obs_blocks(const InstDev &h_inst);
 

@@ -220,7 +220,8 @@ const char *step_kernel_name(int q, int collision, int storage, int math, int st
   else if (strategy == 4)
     snprintf(buf, sizeof buf, "step_d2q9_list<%s,%s,%s,%d>", coll[collision], st[storage], mt[math], ty);
   else if (strategy == 5 && q == 19)
-    snprintf(buf, sizeof buf, "march_d3q19<%s,%s,%s>", coll[collision], st[storage], mt[math]);
+    snprintf(buf, sizeof buf, "fwd_step_d3q19<%s,%s,%s> (+fwd_rho_kernel, fwd_ivsd_kernel)", coll[collision],
+             st[storage], mt[math]);
   else if (strategy == 5)
     snprintf(buf, sizeof buf, "step_d2q9<%s,%s,%s,%d,compact>", coll[collision], st[storage], mt[math], ty);
   else if (q == 9)
@@ -228,6 +229,13 @@ const char *step_kernel_name(int q, int collision, int storage, int math, int st
   else
     snprintf(buf, sizeof buf, "step_d3q19<%s,%s,%s>", coll[collision], st[storage], mt[math]);
   return buf;
+}
+
+hipError_t launch_fwd_rebuild(const InstDev *d_inst, const InstDev &h, int parity, hipStream_t s) {
+  if (h.q != 19 || h.nf == 0) return hipSuccess;
+  fwd_rho_kernel<19><<<dim3((unsigned)((h.nf + 255) / 256)), dim3(256), 0, s>>>(d_inst, nullptr, h.nf, parity);
+  if (h.nbnd) fwd_ivsd_kernel<19><<<dim3((unsigned)((h.nbnd + 255) / 256)), dim3(256), 0, s>>>(d_inst, parity);
+  return hipGetLastError();
 }
 
 hipError_t launch_observables(const InstDev *d_inst, const InstDev &h, int parity, double *partials,

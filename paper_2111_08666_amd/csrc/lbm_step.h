@@ -1050,6 +1050,8 @@ __device__ __forceinline__ void psi_force_sums(const InstDev &d, int x, int y, i
   rho2 = (R)c.y;
   const bool open_face = (info & (kInlet | kOutlet)) != 0;
   sx1 = 0; sy1 = 0; sz1 = 0; sx2 = 0; sy2 = 0; sz2 = 0;
+  // (loading all eighteen FP64 pairs at once, without the branch, was
+  // measured slower: 156 registers, three waves per SIMD instead of four)
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     if (L::opp[i] < i) continue;
@@ -1132,7 +1134,8 @@ __device__ __forceinline__ void cgather(const InstDev &d, gcf *__restrict__ fin,
   const int64_t last = d.nf - 1;
   // Rank rk and fluid bit fl at column x of every source row (one row word
   // each; the node's own row is rk = c, fl = 1).  A fluid source at x - 1 has
-  // rank rk - 1, one at x + 1 rank rk + fl; wrapped x sources are looked up.
+  // rank rk - 1, one at x + 1 rank rk + fl (a row's fluid nodes are numbered
+  // consecutively); sources across the x edge are looked up.
   int64_t rk[3][3];
   int fl[3][3];
 #pragma unroll
@@ -1147,28 +1150,30 @@ __device__ __forceinline__ void cgather(const InstDev &d, gcf *__restrict__ fin,
       rk[a][b] = w.pre + __popcll(w.bits & ((1ull << (x & 63)) - 1ull));
       fl[a][b] = (int)((w.bits >> (x & 63)) & 1ull);
     }
-  const bool x_edge = x == 0 || x == d.nx - 1;
+  int64_t scs[Q];
+  scs[0] = c;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    int64_t sc = c;
-    int pi = i;
-    if (i != 0) {
-      if ((info >> i) & 1u) {
-        pi = L::opp[i];
-      } else {
-        const int a = L::ey[i] + 1, b = L::ez[i] + 1;
-        if (L::ex[i] == 0) {
-          sc = rk[a][b];
-        } else if (!x_edge) {
-          sc = L::ex[i] > 0 ? rk[a][b] - 1 : rk[a][b] + fl[a][b];
-        } else {
-          // wrapped source: periodic x, or a missing link at an open face
-          // (an arbitrary node, overwritten by the completion below)
-          sc = crank(d, xs[L::ex[i] + 1], ys[a] + (int64_t)d.ny * zs[b]);
-          sc = sc < last ? sc : last;
-        }
+  for (int i = 1; i < Q; ++i) {
+    const int a = L::ey[i] + 1, b = L::ez[i] + 1;
+    scs[i] = L::ex[i] == 0 ? rk[a][b] : (L::ex[i] > 0 ? rk[a][b] - 1 : rk[a][b] + fl[a][b]);
+  }
+  const bool cross_lo = x == 0, cross_hi = x == d.nx - 1;
+  if (cross_lo || cross_hi) {
+    // the periodic image across the x edge, or a missing link at an open
+    // face (an arbitrary node, overwritten by the completion below)
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if ((L::ex[i] > 0 && cross_lo) || (L::ex[i] < 0 && cross_hi)) {
+        const int64_t k = crank(d, xs[L::ex[i] + 1], ys[L::ey[i] + 1] + (int64_t)d.ny * zs[L::ez[i] + 1]);
+        scs[i] = k < last ? k : last;
       }
     }
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const bool bb = i != 0 && ((info >> i) & 1u);  // half-way bounce-back: own opposite slot
+    const int pi = bb ? L::opp[i] : i;
+    const int64_t sc = bb ? c : scs[i];
     if constexpr (ST == 0) {
       // component planes from a wave-uniform base, 32-bit byte offsets (the
       // host keeps Q * cpitch * 4 below 2^32)
@@ -1238,57 +1243,103 @@ __global__ __launch_bounds__(256) void ccollide_kernel(const InstDev *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// D3Q19 fused step on the compacted layout (FP32 storage), marching in z.
-// A block of eight waves owns a 60 x 8 tile of (x, y) (64 x 12 with a
-// two-node halo) and a chunk of z.  Wave w owns interior row 2 + w; waves
-// 0-3 also one halo row each (rows 0, 1, 10, 11).  Per plane z:
-//   phase A: form psi at the solid nodes of plane z + 1 (Eq. 17) from the
-//            densities of planes z .. z + 2, held in an LDS ring of five
-//            planes;
-//   phase B: load the row words of plane z + 6 for its rank map (compact
-//            index of each region node, or solid, or outside the domain),
-//            issue the density pulls of plane z + 3 straight into LDS
-//            landing areas (global_load_lds: no registers held in flight)
-//            and the interior pulls of plane z + 1 into registers; compute
-//            the force and collision of plane z from the registers filled
-//            one plane earlier; wait; write the rank map; store plane z;
-//            sum the densities of plane z + 3 into the ring.
-// The collision's pulls repeat the density pulls of two planes earlier and
-// are served by the L2; densities and psi never leave the chip.  Node
-// arithmetic follows the compacted split step; the ring holds the densities
-// and psi rounded to FP32.
+// D3Q19 fused step over the compacted layout with FP32 storage
+// (LBM_COMPACT_FUSED for q = 19): every population is pulled once per step.
+//
+// Besides f*, the state between steps holds the pseudopotential the coming
+// step needs (Eq. 13 with Eq. 15), as (psi1, psi2) float pairs on the dense
+// grid: rho^s(x, t+1) = sum_i f^s_i(x, t+1) at fluid nodes and the virtual
+// solid density of Eq. 17 at solid nodes next to fluid.  Two such arrays fill
+// the psi buffer and alternate with the population buffers.  A step is three
+// launches:
+//   fwd_step_d3q19   a block owns a tile of one row word (64 columns) by
+//                    kFwdRows rows and marches a chunk of z.  Per plane it
+//                    lists the tile's fluid nodes; one thread per list entry
+//                    pulls the node's populations, forms its densities,
+//                    reads the neighbours' psi from the carried array,
+//                    collides, stores f* and stages it in LDS.  Each tile
+//                    position then adds up what its fluid sources in the
+//                    tile stream into it (bounce-back and rest links come
+//                    from the node itself), so rho(t+1) is complete, and
+//                    written, at every node whose 18 sources lie in the tile
+//                    and chunk: all but the tile's outer ring and the
+//                    chunk's end planes.
+//   fwd_rho_kernel   those edge nodes pull their t+1 populations from the new
+//                    f* and sum them, as the compacted density kernel does
+//                    (every fluid node when the carried array is rebuilt).
+//   fwd_ivsd_kernel  Eq. 17 at the solid nodes next to fluid.
+// The node arithmetic is the compacted split step's; psi is carried in FP32.
 // ---------------------------------------------------------------------------
-constexpr int kM3Waves = 8;             // one interior row per wave
-constexpr int kM3RH = kTileY3 + 4;      // region rows
-constexpr int kM3Ring = 5;              // density planes
-constexpr int kM3Maps = 7;              // rank maps of planes z - 1 .. z + 5
-constexpr int kM3MapRows = kM3RH + 2;   // region rows -1 .. kM3RH
-constexpr int kM3MapCols = 66;          // region columns -1 .. 64
-constexpr int kM3MapPitch = 68;
-// A map entry is the node's compact index minus its row's base (the compact
-// index of the word holding the region's first column), or one of these.
-constexpr int kMapOutside = -32768, kMapSolid = -32767;
-// D3Q19 links entering the domain at the inlet (e_x = +1) and at the outlet (e_x = -1)
-constexpr int kInLinks19[5] = {1, 7, 9, 11, 13};
-constexpr int kOutLinks19[5] = {2, 8, 10, 12, 14};
+constexpr int kFwdThreads = 256;             // list entries collided per round
+constexpr int kFwdPos = 64 * kFwdRows;       // tile positions per plane
 
-__device__ __forceinline__ int m3ring(int p) { return ((p % kM3Ring) + kM3Ring) % kM3Ring; }
-__device__ __forceinline__ int m3map(int p) { return ((p % kM3Maps) + kM3Maps) % kM3Maps; }
+// Carried psi array p (0 or 1): index x + pitch * (y + ny * z).
+__device__ __forceinline__ gv2f *psi32(const InstDev &d, int p) {
+  return (gv2f *)d.psi + (int64_t)p * d.pitch * d.ny * d.nz;
+}
 
-typedef __attribute__((address_space(3))) void lds_void;
-typedef __attribute__((address_space(1))) const void g_cvoid;
+__device__ __forceinline__ int wrap3(int p) { return ((p % 3) + 3) % 3; }
+
+// Pair sums sum_i w_i psi(x + e_i) e_i of Eq. 13 from a carried psi array
+// (D3Q19); at an open face the mirrored pairs with an x component cancel.
+template <typename R>
+__device__ __forceinline__ void psi32_force_sums(const InstDev &d, gcv2f *__restrict__ psi, int x, int y, int z,
+                                                 bool open_face, R &sx1, R &sy1, R &sz1, R &sx2, R &sy2,
+                                                 R &sz2) {
+  using L = Lat<19>;
+  int xs[3];
+  source_x(d, x, xs);  // xs[1 - e_x]: x + e_x with wrap
+  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
+  const uint32_t pitch = (uint32_t)d.pitch, ny = (uint32_t)d.ny;
+  const uint32_t yy[3] = {(uint32_t)ym, (uint32_t)y, (uint32_t)yp}, zz[3] = {(uint32_t)zm, (uint32_t)z, (uint32_t)zp};
+  sx1 = 0; sy1 = 0; sz1 = 0; sx2 = 0; sy2 = 0; sz2 = 0;
+  // every neighbour is loaded (no branch between the loads, so they are all
+  // in flight at once); an open face drops the mirrored x pairs afterwards
+  v2f pv[19];
+#pragma unroll
+  for (int i = 1; i < 19; ++i)
+    pv[i] = psi[(uint32_t)xs[1 - L::ex[i]] + pitch * (yy[L::ey[i] + 1] + ny * zz[L::ez[i] + 1])];
+#pragma unroll
+  for (int i = 1; i < 19; ++i) {
+    if (L::opp[i] < i) continue;
+    const int o = L::opp[i];
+    const v2f pa = pv[i], pb = pv[o];
+    const R w = (R)L::w[i];
+    R d1 = w * ((R)pa.x - (R)pb.x), d2 = w * ((R)pa.y - (R)pb.y);
+    if (L::ex[i] != 0) {
+      d1 = open_face ? R(0) : d1;
+      d2 = open_face ? R(0) : d2;
+    }
+    if (L::ex[i]) { sx1 += L::ex[i] * d1; sx2 += L::ex[i] * d2; }
+    if (L::ey[i]) { sy1 += L::ey[i] * d1; sy2 += L::ey[i] * d2; }
+    if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
+  }
+}
+
+// Block barrier for LDS traffic only: waits for the wave's own LDS (and
+// scalar) operations, not for its global loads and stores, which no other
+// thread of the launch reads.  (__syncthreads would also drain every
+// outstanding global store at each plane's barriers.)
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 template <int COLL, typename R>
-__global__ __launch_bounds__(512) void march_d3q19(const InstDev *__restrict__ insts,
-                                                   const int32_t *__restrict__ block_inst, int parity) {
+__global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3))) void fwd_step_d3q19(
+    const InstDev *__restrict__ insts, const int32_t *__restrict__ block_inst, int parity) {
   using L = Lat<19>;
-  using V = Vec2<float>;
-  __shared__ V ring[kM3Ring][kM3RH][64];
-  __shared__ int16_t rmap[kM3Maps][kM3MapRows][kM3MapPitch];
-  __shared__ int32_t rbase[kM3Maps][kM3MapRows];
-  // landing areas [row][component * 19 + link][lane]: rows 0-7 the interior
-  // row of wave w, rows 8-11 the halo row of wave w - 8
-  __shared__ float land[kM3Waves + 4][38][64];
+  constexpr int Q = 19;
+  constexpr int RW = kFwdRows + 2;  // staged rows: y0 - 1 .. y0 + kFwdRows
+  constexpr int RC = 66;            // rank columns: x0 - 1 .. x0 + 64
+  // compact index of the node at each staged (plane mod 3, row, column)
+  // when it is fluid
+  __shared__ int32_t rtab[3][RW][RC];
+  __shared__ unsigned long long fbits[3][kFwdRows];  // fluid bits of the tile rows
+  __shared__ uint16_t lst[2][kFwdPos];               // (row << 6) | column, by plane parity
+  __shared__ int nls[2];
+  // one component's post-collision links of the round's nodes by tile
+  // position; link 0 holds the node's own share of its next density (rest
+  // link and bounced links); positions without a node of the round hold 0
+  __shared__ float stage[Q][kFwdPos];
 
   const int bid = xcd_block();
   const int inst = __builtin_amdgcn_readfirstlane(block_inst ? block_inst[bid] : 0);
@@ -1296,372 +1347,300 @@ __global__ __launch_bounds__(512) void march_d3q19(const InstDev *__restrict__ i
   const int lb = bid - d.block_base;
   const int tx = lb % d.tiles_x, ty = (lb / d.tiles_x) % d.tiles_y;
   const int zc = lb / (d.tiles_x * d.tiles_y);
-  const int lane = threadIdx.x & 63;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int nx = d.nx, ny = d.ny, nz = d.nz;
+  const int zlen = (nz + d.tiles_z - 1) / d.tiles_z;
+  const int z0 = zc * zlen, z1 = min(nz, z0 + zlen);
+  if (z0 >= z1) return;  // the whole block
+  const int x0 = tx * 64, y0 = ty * kFwdRows;
+  const int W = min(64, nx - x0), H = min(kFwdRows, ny - y0);
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t wpr = d.pitch >> 6;
+  const uint32_t cp = (uint32_t)d.cpitch, pitch = (uint32_t)d.pitch;
+  const bool py = d.periodic & 2, pz = d.periodic & 4;
+  const bool open_x = d.open_x != 0;
   gcf *__restrict__ fin = G(d.f[parity]);
   gf *__restrict__ fout = G(d.f[parity ^ 1]);
   gcf *__restrict__ frz = G(d.frozen);
-  gcc *const fin_b = (gcc *)fin;
-  const int nx = d.nx, ny = d.ny, nz = d.nz, cp = d.cpitch;
-  const bool px = d.periodic & 1, py = d.periodic & 2, pz = d.periodic & 4;
-  const int zlen = (nz + d.tiles_z - 1) / d.tiles_z;
-  const int z0 = zc * zlen, z1 = min(nz, z0 + zlen);
-  const int64_t wpr = d.pitch >> 6;
-  const int64_t nt = (int64_t)ny * nz;
-  const int bc_set = d.bc_set;
-
-  // coordinate of a region index along an axis: false if outside a closed edge
-  auto wrap_ax = [](int v, int n, bool per, int &out) __attribute__((always_inline)) -> bool {
-    out = v;
-    if (v < 0 || v >= n) {
-      if (!per) return false;
-      out = wrap_index(v, n);
-    }
-    return true;
-  };
-
-  int gx;
-  const bool col_in = wrap_ax(tx * kTileX - 2 + lane, nx, px, gx);
-  const bool col_store = lane >= 2 && lane < 62 && tx * kTileX - 2 + lane < nx;
-  // inlet / outlet flags of this column
-  const uint32_t face = !d.open_x || !col_in ? 0u : (gx == 0 ? kInlet : (gx == nx - 1 ? kOutlet : 0u));
-  const bool open_face = face != 0;
-  const int rI = 2 + wave;                            // interior region row
-  const bool has_h = wave < 4;
-  const int rH = wave < 2 ? wave : kTileY3 + wave;    // halo region row: 0, 1, 10, 11
-  int gyI = 0, gyH = 0;
-  wrap_ax(ty * kTileY3 - 2 + rI, ny, py, gyI);
-  wrap_ax(ty * kTileY3 - 2 + rH, ny, py, gyH);
-  const bool storeI = col_store && ty * kTileY3 + wave < ny;
-  // column of the rank base of every map row: the region's first in-domain column
-  int xb;
-  if (!wrap_ax(tx * kTileX - 3, nx, px, xb)) xb = 0;
-
-  // ---- rank maps: two entries per thread, words loaded in one phase and
-  // the entries written in a later one
-  unsigned long long mbits[2];
-  int32_t mpre[2], mbase[2], mpos[2];  // mpos: bit position, -1 outside in x, -2 row outside
-  auto map_issue = [&](int p) __attribute__((always_inline)) {
-    // every load is issued (from row 0 for entries outside the domain), so
-    // that no register is assigned while an older load may still target it
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int e = threadIdx.x + 512 * k;
-      const int rr = e / kM3MapCols, cc = e - rr * kM3MapCols;
-      int xg, yg, zg;
-      const bool row_ok = e < kM3MapRows * kM3MapCols && wrap_ax(ty * kTileY3 - 3 + rr, ny, py, yg) &&
-                          wrap_ax(p, nz, pz, zg);
-      const bool col_ok = wrap_ax(tx * kTileX - 3 + cc, nx, px, xg);
-      const RowWord *row = d.cword + (row_ok ? yg + (int64_t)ny * zg : 0) * wpr;
-      mbase[k] = (int32_t)row[xb >> 6].pre;
-      const RowWord w = row[(col_ok ? xg : xb) >> 6];
-      mbits[k] = w.bits;
-      mpre[k] = (int32_t)w.pre;
-      mpos[k] = !row_ok ? -2 : (!col_ok ? -1 : (xg & 63));
-    }
-  };
-  auto map_write = [&](int p) __attribute__((always_inline)) {
-    const int m = m3map(p);
-#pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int e = threadIdx.x + 512 * k;
-      if (e >= kM3MapRows * kM3MapCols) continue;
-      const int rr = e / kM3MapCols, cc = e - rr * kM3MapCols;
-      int v = kMapOutside;
-      if (mpos[k] >= 0) {
-        const int b = mpos[k];
-        v = ((mbits[k] >> b) & 1ull) ? mpre[k] + (int)__popcll(mbits[k] & ((1ull << b) - 1ull)) - mbase[k]
-                                     : kMapSolid;
-      }
-      rmap[m][rr][cc] = (int16_t)v;
-      if (cc == 0) rbase[m][rr] = mbase[k];
-    }
-  };
-  // compact index at map (plane p, map row rr, map column cc): >= 0 fluid,
-  // -1 solid, -2 outside the domain
-  auto rank_at = [&](int p, int rr, int cc) __attribute__((always_inline)) -> int32_t {
-    const int m = m3map(p);
-    const int v = rmap[m][rr][cc];
-    return v <= kMapSolid ? v - kMapSolid - 1 : rbase[m][rr] + v;
-  };
-
-  // ---- pulls of the node of region row r on plane p into landing row lr
-  // (one global_load_lds per link and component); the held links of its
-  // inlet/outlet completion go to pre
-  auto pull_issue = [&](int lr, int r, int gy, int p, int32_t &c, float (&pre)[5])
-      __attribute__((always_inline)) {
-    c = rank_at(p, r + 1, lane + 1);
-    if (c < 0) return;
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      int32_t sc = c;
-      int pi = i;
-      if (i != 0) {
-        // a solid source (half-way bounce-back) or a missing link across an
-        // open face (overwritten by the completion) reads this node's
-        // opposite slot
-        const int32_t sv = rank_at(p - L::ez[i], r + 1 - L::ey[i], lane + 1 - L::ex[i]);
-        if (sv >= 0) sc = sv;
-        else pi = L::opp[i];
-      }
-      const uint32_t bo = ((uint32_t)pi * (uint32_t)cp + (uint32_t)sc) * 4u;
-      __builtin_amdgcn_global_load_lds((g_cvoid *)(fin_b + bo), (lds_void *)&land[lr][i][0], 4, 0, 0);
-      __builtin_amdgcn_global_load_lds((g_cvoid *)(fin_b + (uint32_t)(19 * cp) * 4u + bo),
-                                       (lds_void *)&land[lr][19 + i][0], 4, 0, 0);
-    }
-    // component 2 at the inlet: Eq. 28 (this node's own post-collision
-    // values) or Eq. 27 (Set-2, held); component 1 at the outlet: Eq. 26
-    if (face && bc_set != 1) {
-      int zz;
-      wrap_ax(p, nz, pz, zz);
-      const int64_t t = gy + (int64_t)ny * zz;
-      if (face & kInlet) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-          const int i = kInLinks19[k];
-          pre[k] = bc_set == 2 ? frz[(int64_t)(19 + i) * nt + t] : ldg(fin + (int64_t)(19 + i) * cp, (uint32_t)c * 4u);
-        }
-      } else {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) pre[k] = frz[(int64_t)kOutLinks19[k] * nt + t];
-      }
-    }
-  };
-  // the same pulls into registers (the collision's; nothing waits for them here)
-  auto pull_regs = [&](int r, int gy, int p, int32_t &c, float (&a)[19], float (&b)[19], float (&pre)[5])
-      __attribute__((always_inline)) {
-    c = rank_at(p, r + 1, lane + 1);
-    if (c < 0) return;
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      int32_t sc = c;
-      int pi = i;
-      if (i != 0) {
-        const int32_t sv = rank_at(p - L::ez[i], r + 1 - L::ey[i], lane + 1 - L::ex[i]);
-        if (sv >= 0) sc = sv;
-        else pi = L::opp[i];
-      }
-      const uint32_t bo = ((uint32_t)pi * (uint32_t)cp + (uint32_t)sc) * 4u;
-      a[i] = ldg(fin, bo);
-      b[i] = ldg(fin + (int64_t)19 * cp, bo);
-    }
-    if (face && bc_set != 1) {
-      int zz;
-      wrap_ax(p, nz, pz, zz);
-      const int64_t t = gy + (int64_t)ny * zz;
-      if (face & kInlet) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) {
-          const int i = kInLinks19[k];
-          pre[k] = bc_set == 2 ? frz[(int64_t)(19 + i) * nt + t] : ldg(fin + (int64_t)(19 + i) * cp, (uint32_t)c * 4u);
-        }
-      } else {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) pre[k] = frz[(int64_t)kOutLinks19[k] * nt + t];
-      }
-    }
-  };
-  // inlet/outlet completion of pulled populations (links already pulled)
-  auto complete = [&](const float (&pre)[5], float (&a)[19], float (&b)[19]) __attribute__((always_inline)) {
-    if (face & kInlet) {
-      zou_he<19, double>(a, d.rho_in1, +1);  // component 1: Eqs. 22-25
-      if (bc_set == 1) {
-        zou_he<19, double>(b, d.rho_in2, +1);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) b[kInLinks19[k]] = pre[k];
-      }
-    } else if (face & kOutlet) {
-      zou_he<19, double>(b, d.rho_out2, -1);  // component 2: Eqs. 18-21
-      if (bc_set == 1) {
-        zou_he<19, double>(a, d.rho_out1, -1);
-      } else {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) a[kOutLinks19[k]] = pre[k];
-      }
-    }
-  };
-  // read a landed node back (after the wait) and complete it
-  auto pull_read = [&](int lr, const float (&pre)[5], float (&a)[19], float (&b)[19])
-      __attribute__((always_inline)) {
-#pragma unroll
-    for (int i = 0; i < 19; ++i) {
-      a[i] = land[lr][i][lane];
-      b[i] = land[lr][19 + i][lane];
-    }
-    complete(pre, a, b);
-  };
-  // issue, wait, read: the prologue's pulls
-  auto pull_now = [&](int lr, int r, int gy, int p, int32_t &c, float (&a)[19], float (&b)[19])
-      __attribute__((always_inline)) {
-    float pre[5];
-    pull_issue(lr, r, gy, p, c, pre);
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-    __builtin_amdgcn_sched_barrier(0);
-    if (c >= 0) pull_read(lr, pre, a, b);
-  };
-  auto put_rho = [&](int p, int r, int32_t c, const float (&a)[19], const float (&b)[19])
-      __attribute__((always_inline)) {
-    float r1 = 0.f, r2 = 0.f;
-    if (c >= 0) {
-      r1 = (float)sum_q<19, double>(a);
-      r2 = (float)sum_q<19, double>(b);
-    }
-    ring[m3ring(p)][r][lane] = V{r1, r2};
-  };
-  // virtual solid density (Eq. 17) in place at the solid nodes of region row
-  // r on plane p: the neighbours' map entries and densities are read first,
-  // then summed over the in-domain fluid ones in link order
-  auto ivsd = [&](int p, int r) __attribute__((always_inline)) {
-    if (r < 1 || r > kM3RH - 2 || lane < 1 || lane > 62) return;
-    if (rmap[m3map(p)][r + 1][lane + 1] != kMapSolid) return;
-    bool fl[19];
-    V q[19];
-#pragma unroll
-    for (int i = 1; i < 19; ++i) {
-      fl[i] = rmap[m3map(p + L::ez[i])][r + 1 + L::ey[i]][lane + 1 + L::ex[i]] > kMapSolid;
-      q[i] = ring[m3ring(p + L::ez[i])][r + L::ey[i]][lane + L::ex[i]];
-    }
-    double s1 = 0, s2 = 0, den = 0;
-#pragma unroll
-    for (int i = 1; i < 19; ++i) {
-      if (fl[i]) {
-        s1 += L::w[i] * (double)q[i].x;
-        s2 += L::w[i] * (double)q[i].y;
-        den += L::w[i];
-      }
-    }
-    if (den > 0) {
-      const double inv = rcp<double>(den);
-      ring[m3ring(p)][r][lane] = V{(float)(d.chi1 * s1 * inv), (float)(d.chi2 * s2 * inv)};
-    }
-  };
-
-  // the interior row's populations of plane z (collided now) and z + 1 (in flight)
-  float a0[19], b0[19], an[19], bn[19];
-  int32_t c0 = -1, cnx = -1;
-
-  // ---- prologue: maps of z0-3 .. z0+5, densities of z0-2 .. z0+2, psi of
-  // z0-1 and z0, the populations of plane z0
-  {
-    float ta[19], tb[19];
-    int32_t tc;
-    for (int p = z0 - 3; p <= z0 + 3; ++p) {
-      map_issue(p);
-      map_write(p);
-    }
-    __syncthreads();
-    for (int p = z0 - 2; p <= z0 + 2; ++p) {
-      pull_now(wave, rI, gyI, p, tc, ta, tb);
-      put_rho(p, rI, tc, ta, tb);
-      if (p == z0) {
-        c0 = tc;
-#pragma unroll
-        for (int i = 0; i < 19; ++i) { a0[i] = ta[i]; b0[i] = tb[i]; }
-      }
-      if (has_h) {
-        pull_now(kM3Waves + wave, rH, gyH, p, tc, ta, tb);
-        put_rho(p, rH, tc, ta, tb);
-      }
-    }
-    __syncthreads();  // the map of z0-3 is read no more
-    map_issue(z0 + 4);
-    map_write(z0 + 4);
-    ivsd(z0 - 1, rI);
-    ivsd(z0, rI);
-    if (has_h) {
-      ivsd(z0 - 1, rH);
-      ivsd(z0, rH);
-    }
-    __syncthreads();  // the map of z0-2 is read no more
-    map_issue(z0 + 5);
-    map_write(z0 + 5);
-    __syncthreads();
-  }
-
+  gcv2f *__restrict__ psi_in = psi32(d, parity);
+  gv2f *__restrict__ psi_out = psi32(d, parity ^ 1);
   const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
+
+  // staged row words of plane p (rows y0 - 1 .. y0 + kFwdRows; rows outside
+  // a closed y or z edge hold no fluid), read with scalar loads, which wait
+  // on no vector load or store of the wave; the tile rows' fluid bits too
+  // (with the words left and right of the tile's, for the first and last column)
+  __shared__ RowWord wst[RW][3];
+  auto stage_words = [&](int p) __attribute__((always_inline)) {
+    for (int k = wave; k < RW; k += kFwdThreads / 64) {
+      int yy = y0 - 1 + k, zz = p;
+      bool in = true;
+      if (yy < 0 || yy >= ny) { if (py) yy = wrap_index(yy, ny); else in = false; }
+      if (zz < 0 || zz >= nz) { if (pz) zz = wrap_index(zz, nz); else in = false; }
+      RowWord w[3];
+#pragma unroll
+      for (int h = 0; h < 3; ++h) {
+        w[h] = RowWord{0ull, 0ll};
+        const int t = tx - 1 + h;
+        if (in && t >= 0 && t < wpr) {
+          const int64_t wi = ((int64_t)yy + (int64_t)ny * zz) * wpr + t;
+          typedef __attribute__((address_space(4))) const RowWord kRowWord;
+          const kRowWord *cw = (const kRowWord *)d.cword + uniform64(wi);
+          w[h].bits = cw->bits;
+          w[h].pre = cw->pre;
+        }
+      }
+      if (lane == 0) { wst[k][0] = w[0]; wst[k][1] = w[1]; wst[k][2] = w[2]; }
+      if (lane == 0 && k >= 1 && k <= kFwdRows) fbits[wrap3(p)][k - 1] = k - 1 < H ? w[1].bits : 0ull;
+    }
+  };
+  // rank table of plane p and its fluid list (after put_words(p) and a barrier)
+  auto build_plane = [&](int p) __attribute__((always_inline)) {
+    const int s = wrap3(p);
+    for (int e = tid; e < RW * RC; e += kFwdThreads) {
+      const int k = e / RC, c = e - k * RC;
+      int32_t v;
+      if (c == 0) {  // x0 - 1: the last column of the word on the left
+        const RowWord w = wst[k][0];
+        v = (int32_t)(w.pre + __popcll(w.bits & ((1ull << 63) - 1ull)));
+      } else if (c == RC - 1) {  // x0 + 64: the first column of the word on the right
+        v = (int32_t)wst[k][2].pre;
+      } else {
+        const RowWord w = wst[k][1];
+        v = (int32_t)(w.pre + __popcll(w.bits & ((1ull << (c - 1)) - 1ull)));
+      }
+      rtab[s][k][c] = v;
+    }
+    // wave w lists rows w and w + 4
+#pragma unroll
+    for (int j = 0; j < kFwdRows / 4; ++j) {
+      const int r = wave + 4 * j;
+      int pre = 0;
+#pragma unroll
+      for (int rr = 0; rr < kFwdRows; ++rr)
+        if (rr < r && rr < H) pre += __popcll(wst[rr + 1][1].bits);
+      const unsigned long long bits = r < H ? wst[r + 1][1].bits : 0ull;
+      if ((bits >> lane) & 1ull) lst[p & 1][pre + __popcll(bits & ((1ull << lane) - 1ull))] = (uint16_t)((r << 6) | lane);
+    }
+    if (tid == 0) {
+      int total = 0;
+#pragma unroll
+      for (int rr = 0; rr < kFwdRows; ++rr)
+        if (rr < H) total += __popcll(wst[rr + 1][1].bits);
+      nls[p & 1] = total;
+    }
+  };
+
+  stage_words(z0 - 1);
+  lds_barrier();
+  build_plane(z0 - 1);
+  lds_barrier();
+  stage_words(z0);
+  lds_barrier();
+  build_plane(z0);
+  // next-step density sums of this thread's positions (rows wave and
+  // wave + 4, column lane) on planes z - 1, z, z + 1
+  float acc[2][3][2];
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) acc[j][k][0] = acc[j][k][1] = 0.f;
+
   for (int z = z0; z < z1; ++z) {
-    const int p = z + 3;
-    const bool need = p <= z1 + 1;  // densities are needed up to plane z1 + 1
-    // Phase A: psi at the solid nodes of plane z + 1
-    ivsd(z + 1, rI);
-    if (has_h) ivsd(z + 1, rH);
-    __syncthreads();
-    // Phase B: row words of plane z + 6, density pulls of plane p into the
-    // landing areas, the collision's pulls of plane z + 1 into registers
-    map_issue(z + 6);
-    int32_t cn = -1, hc = -1;
-    float pre[5], hpre[5], npre[5];
-    if (need) {
-      pull_issue(wave, rI, gyI, p, cn, pre);
-      if (has_h) pull_issue(kM3Waves + wave, rH, gyH, p, hc, hpre);
-    }
-    cnx = -1;
-    if (z + 1 < z1) pull_regs(rI, gyI, z + 1, cnx, an, bn, npre);
-    // force (Eq. 13 with the open-face mirror) and collision of plane z
-    // while they are in flight
-    const bool live = storeI && c0 >= 0;
-    if (live) {
-      const R rho1 = (R)sum_q<19, double>(a0), rho2 = (R)sum_q<19, double>(b0);
-      R sx1 = 0, sy1 = 0, sz1 = 0, sx2 = 0, sy2 = 0, sz2 = 0;
+    lds_barrier();  // the previous plane's rank tables are read
+    stage_words(z + 1);
+    lds_barrier();
+    build_plane(z + 1);
+    lds_barrier();
+    const int n = nls[z & 1];
+    const int sz = wrap3(z);
+    for (int base = 0; base < n; base += kFwdThreads) {
+      // positions without a node of this round stream nothing
 #pragma unroll
-      for (int i = 1; i < 19; ++i) {
-        if (L::opp[i] < i) continue;
-        const int o = L::opp[i];
-        if (L::ex[i] != 0 && open_face) continue;
-        const V pa = ring[m3ring(z + L::ez[i])][rI + L::ey[i]][lane + L::ex[i]];
-        const V pb = ring[m3ring(z + L::ez[o])][rI + L::ey[o]][lane + L::ex[o]];
-        const R w = (R)L::w[i];
-        const R d1 = w * ((R)pa.x - (R)pb.x), d2 = w * ((R)pa.y - (R)pb.y);
-        if (L::ex[i]) { sx1 += L::ex[i] * d1; sx2 += L::ex[i] * d2; }
-        if (L::ey[i]) { sy1 += L::ey[i] * d1; sy2 += L::ey[i] * d2; }
-        if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
-      }
-      collide_node<19, COLL, R>(d, a0, b0, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb,
-                                -G_ * rho1 * sy2 + rho1 * gyb, -G_ * rho1 * sz2 + rho1 * gzb,
-                                -G_ * rho2 * sx1 + rho2 * gxb, -G_ * rho2 * sy1 + rho2 * gyb,
-                                -G_ * rho2 * sz1 + rho2 * gzb);
-    }
-    // Every load issued above has landed after this wait (the compiler does
-    // not see the landing areas as written by the pulls, so the wait and the
-    // scheduling fences are explicit); the stores are issued after it, so
-    // that it does not wait for them.
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
-    __builtin_amdgcn_sched_barrier(0);
-    // the slot of plane z + 6 held plane z - 1, last read by the previous
-    // iteration's pulls
-    map_write(z + 6);
-    if (live) pop_store<19, 0>(fout, cp, 0, c0, a0, b0, 0.f, 0.f);
-    if (need) {
-      float ta[19], tb[19];
-      if (cn >= 0) pull_read(wave, pre, ta, tb);
-      put_rho(p, rI, cn, ta, tb);
-      if (has_h) {
-        if (hc >= 0) pull_read(kM3Waves + wave, hpre, ta, tb);
-        put_rho(p, rH, hc, ta, tb);
-      }
-    }
-    c0 = cnx;
-    if (cnx >= 0) {
-      complete(npre, an, bn);
+      for (int i = 0; i < Q; ++i)
+        for (int e = tid; e < kFwdPos; e += kFwdThreads) stage[i][e] = 0.f;
+      const int e = base + tid;
+      const bool act = e < n;
+      int pos = 0;
+      float a[Q], b[Q];
+      if (act) {
+        const int ent = lst[z & 1][e];
+        const int r = ent >> 6, l = ent & 63;
+        pos = ent;
+        const int x = x0 + l, y = y0 + r;
+        const uint32_t key = (uint32_t)x + pitch * ((uint32_t)y + (uint32_t)ny * (uint32_t)z);
+        const bool face = open_x && (x == 0 || x == nx - 1);
+        R sx1, sy1, sz1, sx2, sy2, sz2;
+        psi32_force_sums<R>(d, psi_in, x, y, z, face, sx1, sy1, sz1, sx2, sy2, sz2);
+        const uint32_t info = ((gcu32 *)d.info)[key];
+        // keep the psi loads and the pulls apart (register pressure)
+        __builtin_amdgcn_sched_barrier(0);
+        // compact index of every link's source from the rank tables (all read
+        // before any pull is issued)
+        const int sp[3] = {wrap3(z + 1), sz, wrap3(z - 1)};  // plane of z - e_z, by e_z + 1
+        uint32_t sc[Q];
+        sc[0] = (uint32_t)rtab[sz][r + 1][l + 1];
 #pragma unroll
-      for (int i = 0; i < 19; ++i) { a0[i] = an[i]; b0[i] = bn[i]; }
+        for (int i = 1; i < Q; ++i) sc[i] = (uint32_t)rtab[sp[L::ez[i] + 1]][r - L::ey[i] + 1][l - L::ex[i] + 1];
+        if (x == 0 || x == nx - 1) {
+          // sources across the x edge: the periodic image, or a missing link at
+          // an open face (any node; the completion below overwrites it)
+#pragma unroll
+          for (int i = 1; i < Q; ++i) {
+            if ((L::ex[i] > 0 && x == 0) || (L::ex[i] < 0 && x == nx - 1)) {
+              const int ys = wrap_index(y - L::ey[i], ny), zs = wrap_index(z - L::ez[i], nz);
+              const int64_t k = crank(d, L::ex[i] > 0 ? nx - 1 : 0, ys + (int64_t)ny * zs);
+              sc[i] = (uint32_t)(k < d.nf - 1 ? k : d.nf - 1);
+            }
+          }
+        }
+        const uint32_t c = sc[0];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          // half-way bounce-back: the node's own opposite slot
+          const bool bb = i != 0 && ((info >> i) & 1u);
+          const uint32_t pi = bb ? (uint32_t)L::opp[i] : (uint32_t)i;
+          const uint32_t bo = (pi * cp + (bb ? c : sc[i])) * 4u;
+          a[i] = ldg(fin, bo);
+          b[i] = ldg(fin + (int64_t)Q * cp, bo);
+        }
+        if (face) {
+          const int t = y + ny * z;
+          const int64_t nt = (int64_t)ny * nz;
+          complete_boundary<Q, R>(
+              d, info, a, b, [&](int s_, int i) { return fin[(int64_t)(s_ * Q + i) * cp + c]; },
+              [&](int s_, int i) { return frz[(int64_t)(s_ * Q + i) * nt + t]; });
+        }
+        const R rho1 = sum_q<Q, R>(a), rho2 = sum_q<Q, R>(b);
+        collide_node<Q, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb, -G_ * rho1 * sy2 + rho1 * gyb,
+                                 -G_ * rho1 * sz2 + rho1 * gzb, -G_ * rho2 * sx1 + rho2 * gxb,
+                                 -G_ * rho2 * sy1 + rho2 * gyb, -G_ * rho2 * sz1 + rho2 * gzb);
+        const uint32_t so = c * 4u;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          stg(fout + (int64_t)i * cp, so, a[i]);
+          stg(fout + (int64_t)(Q + i) * cp, so, b[i]);
+        }
+        // the node's own share of its next density: rest link and the links
+        // that bounce back into it
+        float s1 = a[0], s2 = b[0];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          const bool bb = (info >> i) & 1u;
+          s1 += bb ? a[L::opp[i]] : 0.f;
+          s2 += bb ? b[L::opp[i]] : 0.f;
+        }
+        a[0] = s1;
+        b[0] = s2;
+      }
+      // one component at a time: stage by position, then every inner tile
+      // position of planes z - 1, z, z + 1 adds what streams into it
+#pragma unroll
+      for (int comp = 0; comp < 2; ++comp) {
+        lds_barrier();
+        if (act) {
+#pragma unroll
+          for (int i = 0; i < Q; ++i) stage[i][pos] = comp ? b[i] : a[i];
+        }
+        lds_barrier();
+#pragma unroll
+        for (int j = 0; j < kFwdRows / 4; ++j) {
+          const int r = wave + 4 * j;
+          if (r < 1 || r > H - 2 || lane < 1 || lane > W - 2) continue;
+          const int tp = (r << 6) | lane;
+          float t0 = 0.f, t1 = stage[0][tp], t2 = 0.f;
+#pragma unroll
+          for (int i = 1; i < Q; ++i) {
+            const float v = stage[i][tp - L::ex[i] - 64 * L::ey[i]];
+            if (L::ez[i] < 0) t0 += v;
+            else if (L::ez[i] == 0) t1 += v;
+            else t2 += v;
+          }
+          acc[j][0][comp] += t0;
+          acc[j][1][comp] += t1;
+          acc[j][2][comp] += t2;
+        }
+      }
+      lds_barrier();
     }
-    // the densities of plane p and the rank map of plane z + 6 written in
-    // this phase are read after this barrier
-    __syncthreads();
+    // plane z - 1 has received all its links: its inner fluid nodes' densities
+    const int pd = z - 1;
+    if (pd > z0 && pd < z1 - 1) {
+#pragma unroll
+      for (int j = 0; j < kFwdRows / 4; ++j) {
+        const int r = wave + 4 * j;
+        if (r < 1 || r > H - 2 || lane < 1 || lane > W - 2 || !((fbits[wrap3(pd)][r] >> lane) & 1ull)) continue;
+        const uint32_t key = (uint32_t)(x0 + lane) + pitch * ((uint32_t)(y0 + r) + (uint32_t)ny * (uint32_t)pd);
+        psi_out[key] = v2f{acc[j][0][0], acc[j][0][1]};
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      acc[j][0][0] = acc[j][1][0]; acc[j][0][1] = acc[j][1][1];
+      acc[j][1][0] = acc[j][2][0]; acc[j][1][1] = acc[j][2][1];
+      acc[j][2][0] = 0.f; acc[j][2][1] = 0.f;
+    }
   }
+}
+
+// Densities of the coming step at the fluid nodes `list` names (every fluid
+// node when list is NULL): pull from buffer `parity` with the inlet/outlet
+// completion, sum, and store in carried psi array `parity`.
+template <int Q>
+__global__ __launch_bounds__(256) void fwd_rho_kernel(const InstDev *__restrict__ insts,
+                                                      const uint32_t *__restrict__ list, int64_t n, int parity) {
+  const InstDev &d = insts[0];
+  const int64_t j = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const int64_t c = list ? (int64_t)list[j] : j;
+  const uint32_t key = d.ckey[c];
+  int x, y, z;
+  ckey_xyz(d, key, x, y, z);
+  const uint32_t info = ((gcu32 *)d.info)[key];
+  float a[Q], b[Q];
+  cgather<Q, 0, double>(d, G(d.f[parity]), info, x, y, z, c, a, b);
+  psi32(d, parity)[key] = v2f{(float)sum_q<Q, double>(a), (float)sum_q<Q, double>(b)};
+}
+
+// Virtual solid density (Eq. 17) at the solid nodes next to fluid, from the
+// densities in carried psi array `parity`.
+template <int Q>
+__global__ __launch_bounds__(256) void fwd_ivsd_kernel(const InstDev *__restrict__ insts, int parity) {
+  using L = Lat<Q>;
+  const InstDev &d = insts[0];
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= d.nbnd) return;
+  const uint32_t key = d.cbnd[j];
+  int x, y, z;
+  ckey_xyz(d, key, x, y, z);
+  const uint32_t nb = ((gcu32 *)d.info)[key];
+  gv2f *__restrict__ psi = psi32(d, parity);
+  int xs[3];
+  source_x(d, x, xs);  // xs[1 - e_x]: x + e_x with wrap
+  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
+  const int yy[3] = {ym, y, yp}, zz[3] = {zm, z, zp};
+  double s1 = 0, s2 = 0, den = 0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (nb & (1u << i)) {
+      const uint32_t k = (uint32_t)xs[1 - L::ex[i]] +
+                         (uint32_t)d.pitch * ((uint32_t)yy[L::ey[i] + 1] + (uint32_t)d.ny * (uint32_t)zz[L::ez[i] + 1]);
+      const v2f p = psi[k];
+      s1 += L::w[i] * (double)p.x;
+      s2 += L::w[i] * (double)p.y;
+      den += L::w[i];
+    }
+  }
+  const double inv = rcp<double>(den);
+  psi[key] = v2f{(float)(d.chi1 * s1 * inv), (float)(d.chi2 * s2 * inv)};
 }
 
 template <int COLL, int ST, typename R>
 static void launch_fused_q(int q, int ty, const InstDev *d, const int32_t *bi, int64_t nb, int parity,
                            hipStream_t s, bool compact = false) {
   const dim3 g((unsigned)nb), b(256);
-  if (q == 19 && compact) {
-    if constexpr (ST == 0) march_d3q19<COLL, R><<<g, dim3(512), 0, s>>>(d, bi, parity);
-  } else if (q == 9 && compact) {
+  if (q == 9 && compact) {
     if (ty == 8) step_d2q9<COLL, ST, R, 8, 1><<<g, b, 0, s>>>(d, bi, parity);
     else if (ty == 16) step_d2q9<COLL, ST, R, 16, 1><<<g, b, 0, s>>>(d, bi, parity);
     else step_d2q9<COLL, ST, R, 12, 1><<<g, b, 0, s>>>(d, bi, parity);
@@ -1671,6 +1650,23 @@ static void launch_fused_q(int q, int ty, const InstDev *d, const int32_t *bi, i
     else step_d2q9<COLL, ST, R, 12><<<g, b, 0, s>>>(d, bi, parity);
   } else {
     step_d3q19<COLL, ST, R><<<g, b, 0, s>>>(d, bi, parity);
+  }
+}
+
+// Compacted 3D fused step of every instance (one launch over the block
+// table), then per instance the pulled densities of its edge nodes and the
+// virtual solid densities, into the carried psi of the next step.
+template <int COLL, typename R>
+static void launch_fwd_q(const StepLaunch &L, hipStream_t s) {
+  fwd_step_d3q19<COLL, R><<<dim3((unsigned)L.n_blocks), dim3(kFwdThreads), 0, s>>>(L.d_insts, L.block_inst,
+                                                                                  L.parity);
+  for (int i = 0; i < L.k; ++i) {
+    const InstDev &h = L.h[i];
+    if (h.nedge)
+      fwd_rho_kernel<19><<<dim3((unsigned)((h.nedge + 255) / 256)), dim3(256), 0, s>>>(L.d_insts + i, h.cedge,
+                                                                                      h.nedge, L.parity ^ 1);
+    if (h.nbnd)
+      fwd_ivsd_kernel<19><<<dim3((unsigned)((h.nbnd + 255) / 256)), dim3(256), 0, s>>>(L.d_insts + i, L.parity ^ 1);
   }
 }
 
@@ -1724,6 +1720,8 @@ static void launch_st(const StepLaunch &L, hipStream_t s) {
     for (int i = 0; i < L.k; ++i) launch_compact_q<COLL, ST, R>(L.q, L.d_insts + i, L.h[i], L.parity, s);
   } else if (L.strategy == 4) {
     launch_fused_list_q<COLL, ST, R>(L.q, L.ty, L.d_insts, L.block_inst, L.n_blocks, L.parity, s);
+  } else if (L.strategy == 5 && L.q == 19) {
+    if constexpr (ST == 0) launch_fwd_q<COLL, R>(L, s);
   } else if (L.strategy == 5) {
     launch_fused_q<COLL, ST, R>(L.q, L.ty, L.d_insts, L.block_inst, L.n_blocks, L.parity, s, true);
   } else {

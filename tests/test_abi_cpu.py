@@ -138,9 +138,9 @@ def test_small_or_misaligned_workspace_rejected():
     assert st == lbm.LBM_ENOMEM and "aligned" in err
 
 
-def test_d3q19_mrt_is_accepted_and_the_march_needs_fp32_storage():
+def test_d3q19_mrt_is_accepted_and_the_fused_step_needs_fp32_storage():
     """D3Q19 MRT (d'Humieres moments) passes validation on every layout; the
-    z-marching compacted fused step refuses BF16 storage."""
+    compacted 3D fused step refuses BF16 storage."""
     m = I.sphere_medium(24, 12, 12, 2.0, 3.0, 0.8, seed=1)
     p = I.Problem(q=19, mask=m, rho0=I.reservoir_front(m, 8), collision=1)
     for strat in (lbm.AUTO, lbm.SPLIT, lbm.COMPACT, lbm.COMPACT_FUSED):

@@ -188,16 +188,17 @@ def test_bf16_batch_matches_single(lbm):
 
 
 @pytest.mark.parametrize("name", sorted(P3))
-def test_d3q19_march_matches_compact_step(lbm, name):
-    """The z-marching fused step (LBM_COMPACT_FUSED) does the compacted split
-    step's node arithmetic but keeps densities and psi on chip in FP32: with
-    FP64 node arithmetic its densities stay within 1e-6 of the split step's
-    over eager steps and graph replays, ragged tiles and z chunks, and the
+def test_d3q19_fused_matches_compact_step(lbm, name):
+    """The compacted 3D fused step (LBM_COMPACT_FUSED: tile march with the
+    next step's densities summed on chip and carried between steps) does the
+    compacted split step's node arithmetic but carries psi in FP32: with FP64
+    node arithmetic its densities stay within 1e-6 of the split step's over
+    eager steps and graph replays, ragged tiles and z chunks, and the
     observables' counts agree exactly."""
     p = P3[name]
     a = lbm.Solver(p, strategy=lbm.COMPACT, math=lbm.MATH_F64)
     b = lbm.Solver(p, strategy=lbm.COMPACT_FUSED, math=lbm.MATH_F64)
-    assert "march_d3q19" in b.kernel_info()[0] and b.kernel_info()[2] == 512
+    assert "fwd_step_d3q19" in b.kernel_info()[0] and b.kernel_info()[2] == 256
     fluid = ~p.mask.astype(bool)
     for n in (1, 36, 63):
         a.step(n)
@@ -207,7 +208,7 @@ def test_d3q19_march_matches_compact_step(lbm, name):
             b.step(n)
         ra, rb = a.density().astype(np.float64), b.density().astype(np.float64)
         err = float((np.abs(ra - rb) / np.abs(ra))[:, fluid].max())
-        print(f"[march-vs-compact] {name} t={a.t} {err:.1e}", flush=True)
+        print(f"[fused3d-vs-compact] {name} t={a.t} {err:.1e}", flush=True)
         assert err <= 1e-6, (name, n, err)
     oa, ob = a.observables(), b.observables()
     for k in ("n_fluid", "n_window", "n_in", "n_out"):
@@ -215,14 +216,39 @@ def test_d3q19_march_matches_compact_step(lbm, name):
 
 
 @pytest.mark.parametrize("name", sorted(P3))
-def test_d3q19_march_parity_200_steps(lbm, name):
-    """The z-marching step against the FP64 oracle, both node arithmetics."""
+def test_d3q19_fused_parity_200_steps(lbm, name):
+    """The compacted 3D fused step against the FP64 oracle, both node arithmetics."""
     p = P3[name]
     for math in (lbm.MATH_F64, lbm.MATH_F32):
         s = lbm.Solver(p, strategy=lbm.COMPACT_FUSED, math=math)
         errs = _series(p, s, CHECKPOINTS)
-        print(f"[march3d] {name} math={math} errors {['%.1e' % e for e in errs]}", flush=True)
+        print(f"[fused3d] {name} math={math} errors {['%.1e' % e for e in errs]}", flush=True)
         assert max(errs) <= (REL_TOL if math == lbm.MATH_F64 else F32_MATH_BOUND), errs
+
+
+def test_d3q19_fused_carried_psi_follows_the_state(lbm):
+    """The carried psi is rebuilt whenever the state changes outside a step:
+    a pressure increment between graph replays, a host density read-out
+    (staged through the psi buffer) and a checkpoint restored into a fresh
+    context all continue exactly like an uninterrupted context that took the
+    same increments, and a checkpoint resumes bit for bit."""
+    p = P3["d3_drain_trt"]
+    a = lbm.Solver(p, strategy=lbm.COMPACT_FUSED)
+    b = lbm.Solver(p, strategy=lbm.COMPACT)
+    for s in (a, b):
+        s.step_graph(10, 2)
+        s.set_bc(1.02, 1.0)
+        s.step_graph(10, 1)
+    fluid = ~p.mask.astype(bool)
+    ra, rb = a.density().astype(np.float64), b.density().astype(np.float64)
+    assert float((np.abs(ra - rb) / np.abs(ra))[:, fluid].max()) <= 1e-6
+    blob = a.save()
+    a.step(17)
+    ref = a.density()
+    c = lbm.Solver(p, strategy=lbm.COMPACT_FUSED)
+    c.load(blob)
+    c.step(17)
+    assert np.array_equal(c.density(), ref)
 
 
 def test_d3q19_compact_equals_split_bitwise(lbm):
