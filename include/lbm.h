@@ -185,6 +185,20 @@ lbm_status lbm_observables(lbm_ctx *ctx, lbm_obs *out);
  * device pointer (stream-ordered); 0: host pointer (synchronises). */
 lbm_status lbm_get_density(lbm_ctx *ctx, float *dst, int32_t dst_is_device);
 
+/* Warm start from a saturation field (a learned surrogate's prediction of
+ * the steady state, Sec. 4.2 drainage): replace the state by the rest
+ * equilibria w_i rho of densities set node by node, (rho1, rho2) =
+ * (rho_major, rho_minor) where sat > threshold (component 1, the invading
+ * non-wetting fluid, fills the node) and (rho_minor, rho_major) elsewhere,
+ * at every fluid node.  sat: nx*ny*nz floats, x fastest, values at solid
+ * nodes ignored; a device pointer (sat_is_device = 1, stream-ordered) or a
+ * host pointer (0: copied through the workspace; synchronises).  The held
+ * boundary links of Eqs. 26-27 keep their values and the step counter
+ * restarts at 0.  The densities must be finite and >= 0 with a positive
+ * sum (LBM_EINVAL). */
+lbm_status lbm_init_from_saturation(lbm_ctx *ctx, const float *sat, int32_t sat_is_device, double threshold,
+                                    double rho_major, double rho_minor);
+
 /* Checkpoint: all state needed to continue bit-identically.  With
  * host_blob = NULL, *bytes receives the size.  Both synchronise. */
 lbm_status lbm_save(lbm_ctx *ctx, void *host_blob, size_t *bytes);

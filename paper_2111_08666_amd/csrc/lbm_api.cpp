@@ -895,6 +895,31 @@ lbm_status lbm_load(lbm_ctx *ctx, const void *host_blob, size_t bytes) {
   return LBM_OK;
 }
 
+lbm_status lbm_init_from_saturation(lbm_ctx *ctx, const float *sat, int32_t sat_is_device, double threshold,
+                                    double rho_major, double rho_minor) {
+  if (!ctx || !sat) return fail(nullptr, LBM_EINVAL, "NULL argument");
+  lbm_batch *b = ctx->b;
+  if (!std::isfinite(threshold) || !std::isfinite(rho_major) || !std::isfinite(rho_minor) || rho_major < 0 ||
+      rho_minor < 0 || !(rho_major + rho_minor > 0))
+    return fail(b, LBM_EINVAL, "densities must be finite and >= 0 with a positive sum");
+  const InstDev &h = b->h[0];
+  const float *src = sat;
+  if (!sat_is_device) {
+    // stage in the psi buffer (16 bytes per node); the carried psi is rebuilt
+    float *stage = reinterpret_cast<float *>(h.psi);
+    HIPCHK(b, hipMemcpyAsync(stage, sat, sizeof(float) * (size_t)h.nx * h.ny * h.nz, hipMemcpyHostToDevice,
+                             b->stream));
+    src = stage;
+  }
+  HIPCHK(b, launch_init_sat(b->d_insts, h, src, (float)threshold, (float)rho_major, (float)rho_minor, b->parity,
+                            b->stream));
+  if (!sat_is_device) HIPCHK(b, hipStreamSynchronize(b->stream));
+  b->psi_valid = false;
+  b->unstable = false;
+  b->step = 0;
+  return LBM_OK;
+}
+
 int64_t lbm_get_step(const lbm_ctx *ctx) { return ctx ? ctx->b->step : -1; }
 
 lbm_status lbm_destroy(lbm_ctx *ctx) {

@@ -67,6 +67,10 @@ constexpr int kObsFields = 12;  // mass0 mass1 nfluid nwin swcount sumrw sumr pi
 // Launchers (defined in the .hip sources).
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, const float *rho0_dev,
                        int parity, hipStream_t s);
+// Rest equilibria of densities set from a saturation field (device, one
+// float per node): (major, minor) where sat > thr, (minor, major) elsewhere.
+hipError_t launch_init_sat(const InstDev *d_inst, const InstDev &h_inst, const float *sat_dev, float thr,
+                           float major, float minor, int parity, hipStream_t s);
 // One step of every instance of a batch.  strategy 1: fused kernel (one
 // launch over a flat block table); 2: split step (three launches per instance);
 // 3: compacted fluid-node step (three launches per instance, compact layout).

@@ -9,10 +9,14 @@ namespace lbm {
 
 // ---------------------------------------------------------------------------
 // initial state: f*_i = w_i rho0 at fluid nodes (rest equilibrium), and the
-// ghost slots of solid sources (FP32 storage)
+// ghost slots of solid sources (FP32 storage).  With a saturation field
+// (sat != NULL) the densities are (major, minor) where sat > thr and
+// (minor, major) elsewhere instead of rho0.
 // ---------------------------------------------------------------------------
 template <int Q, int ST>
-__global__ void init_kernel(const InstDev *__restrict__ insts, const float *__restrict__ rho0, int parity) {
+__global__ void init_kernel(const InstDev *__restrict__ insts, const float *__restrict__ rho0, int parity,
+                            const float *__restrict__ sat = nullptr, float thr = 0.f, float major = 0.f,
+                            float minor = 0.f) {
   const InstDev &d = insts[0];
   const int64_t n_nodes = (int64_t)d.nx * d.ny * d.nz;
   gf *b = G(d.f[parity]);
@@ -23,7 +27,8 @@ __global__ void init_kernel(const InstDev *__restrict__ insts, const float *__re
     const int y = yz % d.ny, z = yz / d.ny;
     const uint32_t info = d.info[x + (int64_t)d.pitch * yz];
     if (info & kSolid) continue;
-    const float r1 = rho0[n], r2 = rho0[n_nodes + n];
+    const bool nw = sat && sat[n] > thr;
+    const float r1 = sat ? (nw ? major : minor) : rho0[n], r2 = sat ? (nw ? minor : major) : rho0[n_nodes + n];
     float a[Q], c[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -191,6 +196,19 @@ hipError_t launch_init(const InstDev *d_inst, const InstDev &h, const float *rho
   } else {
     if (h.storage == 0) init_kernel<19, 0><<<g, 256, 0, s>>>(d_inst, rho0, parity);
     else init_kernel<19, 1><<<g, 256, 0, s>>>(d_inst, rho0, parity);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_init_sat(const InstDev *d_inst, const InstDev &h, const float *sat, float thr, float major,
+                           float minor, int parity, hipStream_t s) {
+  const int g = grid_for((int64_t)h.nx * h.ny * h.nz);
+  if (h.q == 9) {
+    if (h.storage == 0) init_kernel<9, 0><<<g, 256, 0, s>>>(d_inst, nullptr, parity, sat, thr, major, minor);
+    else init_kernel<9, 1><<<g, 256, 0, s>>>(d_inst, nullptr, parity, sat, thr, major, minor);
+  } else {
+    if (h.storage == 0) init_kernel<19, 0><<<g, 256, 0, s>>>(d_inst, nullptr, parity, sat, thr, major, minor);
+    else init_kernel<19, 1><<<g, 256, 0, s>>>(d_inst, nullptr, parity, sat, thr, major, minor);
   }
   return hipGetLastError();
 }

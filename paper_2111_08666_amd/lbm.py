@@ -22,7 +22,7 @@ AUTO, FUSED, SPLIT, COMPACT, FUSED_LIST, COMPACT_FUSED = 0, 1, 2, 3, 4, 5
 
 EXPORTS = [
     "lbm_workspace_bytes", "lbm_create", "lbm_set_bc", "lbm_step", "lbm_step_graph",
-    "lbm_observables", "lbm_get_density", "lbm_save", "lbm_load", "lbm_get_step",
+    "lbm_observables", "lbm_get_density", "lbm_init_from_saturation", "lbm_save", "lbm_load", "lbm_get_step",
     "lbm_destroy", "lbm_last_error", "lbm_kernel_info", "lbm_autotune", "lbm_batch_workspace_bytes",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_step_graph", "lbm_batch_observables",
     "lbm_batch_get_density", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_kernel_info",
@@ -93,6 +93,7 @@ def lib():
         L.lbm_get_density.argtypes = [vp, vp, i32]
         L.lbm_save.argtypes = [vp, vp, C.POINTER(sz)]
         L.lbm_load.argtypes = [vp, vp, sz]
+        L.lbm_init_from_saturation.argtypes = [vp, vp, i32, C.c_double, C.c_double, C.c_double]
         L.lbm_get_step.restype = i64
         L.lbm_get_step.argtypes = [vp]
         L.lbm_destroy.argtypes = [vp]
@@ -245,6 +246,31 @@ class Solver:
         out = np.empty((2,) + self.shape, dtype=np.float32)
         self._chk(lib().lbm_get_density(self._h, out.ctypes.data, 0))
         return out
+
+    def init_from_saturation(self, sat, threshold=0.5, rho_major=None, rho_minor=None):
+        """Warm start (lbm_init_from_saturation) from a saturation field of
+        the grid's shape: a torch tensor on the solver's device or a host
+        array.  The densities default to the problem's major and minor
+        phase densities (largest component-2 and smallest component-1 initial
+        density over the fluid)."""
+        fluid = self.problem.mask == 0
+        rho0 = np.asarray(self.problem.rho0)
+        major = float(rho0[1][fluid].max()) if rho_major is None else float(rho_major)
+        minor = float(rho0[0][fluid].min()) if rho_minor is None else float(rho_minor)
+        if hasattr(sat, "data_ptr"):
+            import torch
+            t = sat.to(device=self.device, dtype=torch.float32).contiguous()
+            if tuple(t.shape) != tuple(self.shape):
+                raise ValueError(f"saturation shape {tuple(t.shape)} != grid {self.shape}")
+            # the library reads it on its own stream
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            self._chk(lib().lbm_init_from_saturation(self._h, t.data_ptr(), 1, float(threshold), major, minor))
+            t.record_stream(self.stream)
+        else:
+            a = np.ascontiguousarray(sat, dtype=np.float32)
+            if a.shape != tuple(self.shape):
+                raise ValueError(f"saturation shape {a.shape} != grid {self.shape}")
+            self._chk(lib().lbm_init_from_saturation(self._h, a.ctypes.data, 0, float(threshold), major, minor))
 
     def density_device(self, out=None):
         import torch

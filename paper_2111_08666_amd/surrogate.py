@@ -423,6 +423,21 @@ def warm_start_density(problem, sat: np.ndarray, threshold: float = 0.5) -> np.n
     return rho
 
 
+def full_saturation(problem, sat: np.ndarray) -> np.ndarray:
+    """A saturation field over the whole grid for the solver's warm start
+    (lbm_init_from_saturation): the prediction inside the porous window, the
+    cold start's phases (1 where component 1 is the majority) outside it, 0
+    at solid nodes.  With the threshold 0.5 it sets the same densities as
+    warm_start_density."""
+    rho = np.asarray(problem.rho0)
+    out = (rho[0] > rho[1]).astype(np.float32)
+    win = np.zeros(problem.mask.shape, dtype=bool)
+    win[:, problem.porous_x0:problem.porous_x1] = True
+    out[win] = np.asarray(sat, dtype=np.float32)[win]
+    out[problem.mask != 0] = 0.0
+    return out
+
+
 def predict(net: "UNet", problems, batch: int = 8) -> np.ndarray:
     """Saturation predictions (k, h, w) for problems with attributes theta, dp."""
     import torch

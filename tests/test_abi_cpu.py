@@ -79,6 +79,15 @@ def test_every_declared_symbol_is_exported():
     assert sorted(lbm.EXPORTS) == names
 
 
+def test_init_from_saturation_refuses_null_arguments():
+    """The warm-start entry point checks its handle and field before any
+    device work."""
+    L = lbm.lib()
+    assert L.lbm_init_from_saturation(None, None, 1, 0.5, 1.0, 0.027) == lbm.LBM_EINVAL
+    fake = C.c_void_p(4096)
+    assert L.lbm_init_from_saturation(None, fake, 1, 0.5, 1.0, 0.027) == lbm.LBM_EINVAL
+
+
 def test_workspace_query_and_validation_without_device():
     p = I.drainage_2d(nx=64, ny=32, r=(2.0, 4.0), porosity=0.8, seed=1)
     assert lbm.workspace_bytes(p) > 2 * 2 * 9 * 64 * 32 * 4
