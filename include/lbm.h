@@ -114,6 +114,12 @@ typedef struct {
                              256 MB last-level cache, else compacted fused
                              (every instance must then be LBM_AUTO). */
   int32_t tile_rows;      /* fused D2Q9 tile height: 8, 12 or 16 (0 = 12) */
+  int32_t eq26_mode;      /* reading of Eqs. 26-27 (the outlet links of component 1
+                             in Set-2 and Set-3, the inlet links of component 2 in
+                             Set-2), which the paper says maintain themselves
+                             through collision and streaming: 0 (default) they
+                             keep their initial values; 1 they take the node's
+                             own post-collision values, the rule of Eq. 28 */
 } lbm_params;
 
 /* Observables at the current time (Eq. 14 pressure, Sec. 4.2 saturation).

@@ -436,6 +436,7 @@ ora_sim *ora_create(const ora_params *p, const uint8_t *solid, const double *rho
     set_err(err, "collision: 0 SRT, 1 MRT, 2 TRT"); return NULL;
   }
   if (p->bc_set < 1 || p->bc_set > 3) { set_err(err, "bc_set must be 1, 2 or 3"); return NULL; }
+  if (p->eq26_mode != 0 && p->eq26_mode != 1) { set_err(err, "eq26_mode must be 0 or 1"); return NULL; }
 
   ora_sim *s = (ora_sim *)calloc(1, sizeof(ora_sim));
   s->p = *p;
@@ -563,10 +564,14 @@ static void stream_complete(ora_sim *s) {
           if (zou) {
             zouhe(L, f, rho_bc, normal);
           } else if (side == 1 || set == 2) {
-            /* Eq. 26 (outlet, comp 1) and Eq. 27 (inlet, comp 2, Set-2): frozen */
+            /* Eq. 26 (outlet, comp 1) and Eq. 27 (inlet, comp 2, Set-2).
+             * READING 0 (default): the links "maintain themselves" through
+             * collision and streaming, so they never change from their
+             * initial values.  READING 1: they keep the node's own
+             * post-collision values, the rule Eq. 28 writes out. */
             int fc = side == 1 ? 0 : 1;
             for (int i = 0; i < q; ++i)
-              if (L->e[i][0] == normal) f[i] = FRZ(s, fc, i, t);
+              if (L->e[i][0] == normal) f[i] = s->p.eq26_mode ? FS(s, c, i, n) : FRZ(s, fc, i, t);
           } else {
             /* Eq. 28 (Set-3, inlet, comp 2): keep this node's post-collision value */
             for (int i = 0; i < q; ++i)

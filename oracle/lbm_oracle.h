@@ -37,6 +37,10 @@ typedef struct {
   double g[3];              /* body acceleration: F^b = rho^s g */
   double lambda;            /* magic parameter (1/s+ - 1/2)(1/s- - 1/2); <= 0: s- = s+ */
   double s_e, s_eps;        /* MRT energy-mode rates; <= 0: equal to s_nu */
+  int32_t eq26_mode;        /* reading of Eqs. 26-27: 0 the links hold their initial
+                               values; 1 they take the node's own post-collision
+                               values (the rule Eq. 28 states for Set-3's inlet) */
+  int32_t pad_;
 } ora_params;
 
 typedef struct {

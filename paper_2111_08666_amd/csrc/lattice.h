@@ -76,7 +76,8 @@ __device__ __forceinline__ void zou_he(float (&f)[Q], R rho_b, int dir) {
 
 // Inlet / outlet completion of one node for both components (Sec. 2.3).
 // own(c, i) returns this node's post-collision value (Eq. 28),
-// frozen(c, i) the held initial value (Eq. 26, Eq. 27).
+// frozen(c, i) the held initial value (Eq. 26, Eq. 27; with eq26_mode 1
+// those links take own(c, i) as well).
 template <int Q, typename R, class OwnF, class FrozenF>
 __device__ __forceinline__ void complete_boundary(const InstDev &d, uint32_t info, float (&f0)[Q],
                                                   float (&f1)[Q], OwnF own, FrozenF frozen) {
@@ -88,7 +89,7 @@ __device__ __forceinline__ void complete_boundary(const InstDev &d, uint32_t inf
     } else if (d.bc_set == 2) {
 #pragma unroll
       for (int i = 0; i < Q; ++i)
-        if (L::ex[i] > 0) f1[i] = frozen(1, i);  // Eq. 27
+        if (L::ex[i] > 0) f1[i] = d.eq26_mode ? own(1, i) : frozen(1, i);  // Eq. 27
     } else {
 #pragma unroll
       for (int i = 0; i < Q; ++i)
@@ -102,7 +103,7 @@ __device__ __forceinline__ void complete_boundary(const InstDev &d, uint32_t inf
     } else {
 #pragma unroll
       for (int i = 0; i < Q; ++i)
-        if (L::ex[i] < 0) f0[i] = frozen(0, i);  // Eq. 26
+        if (L::ex[i] < 0) f0[i] = d.eq26_mode ? own(0, i) : frozen(0, i);  // Eq. 26
     }
   }
 }

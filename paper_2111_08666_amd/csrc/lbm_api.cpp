@@ -223,6 +223,7 @@ bool validate(const lbm_geometry *g, const lbm_params *p, const double *rho0, st
   if (!std::isfinite(p->G)) return bad(err, "G must be finite");
   if (p->collision < 0 || p->collision > 2) return bad(err, "collision must be SRT, MRT or TRT");
   if (p->bc_set < 1 || p->bc_set > 3) return bad(err, "bc_set must be 1, 2 or 3");
+  if (p->eq26_mode != 0 && p->eq26_mode != 1) return bad(err, "eq26_mode must be 0 or 1");
   if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_BF16DEV) return bad(err, "unknown storage");
   if (p->math != LBM_MATH_F64 && p->math != LBM_MATH_F32) return bad(err, "unknown math precision");
   if (p->strategy < LBM_AUTO || p->strategy > LBM_COMPACT_FUSED) return bad(err, "unknown strategy");
@@ -542,6 +543,7 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
     h.bc_set = p[i].bc_set; h.collision = p[i].collision;
     h.half_shift = p[i].half_force_shift; h.sj_mode = p[i].mrt_sj_mode;
     h.storage = p[i].storage; h.q = g[i].q;
+    h.eq26_mode = p[i].eq26_mode;
     h.tau1 = p[i].tau[0]; h.tau2 = p[i].tau[1];
     h.G = p[i].G;
     h.chi1 = 1.0 + p[i].xi; h.chi2 = 1.0 - p[i].xi;

@@ -45,6 +45,7 @@ struct InstDev {
   int32_t nx, ny, nz, pitch;  // pitch = padded row length (a multiple of 64)
   int32_t periodic, open_x, bc_set, collision;
   int32_t half_shift, sj_mode, storage, q;
+  int32_t eq26_mode, pad_;
   int32_t tiles_x, tiles_y, tiles_z, block_base;
   double tau1, tau2, G, chi1, chi2, gx, gy, gz;
   double rho_in1, rho_out2, rho_in2, rho_out1;

@@ -235,6 +235,7 @@ class Problem:
     lam: float = 3.0 / 16.0
     s_e: float = 1.0
     s_eps: float = 1.0
+    eq26_mode: int = 0          # Eqs. 26-27: 0 held initial values, 1 own post-collision values
     name: str = ""
 
     @property

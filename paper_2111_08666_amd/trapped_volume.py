@@ -1,14 +1,17 @@
-"""Trapped-volume study (paper Sec. 4.1): the three inlet/outlet treatments
-side by side in one batch on the U-shaped obstacle (inputs.u_trap), with the
-mass of component 2 inside the U's cup recorded over time.
+"""Trapped-volume study (paper Sec. 4.1): the inlet/outlet treatments side by
+side in one batch on the U-shaped obstacle (inputs.u_trap), with the mass of
+component 2 inside the U's cup recorded over time.
 
     python -m paper_2111_08666_amd.trapped_volume --steps 300000 --every 5000 --out trapped.json
 
 Set-1 fixes both components' densities at both faces, Set-2 lets the other
-component's missing links keep their values, Set-3 is the paper's treatment
-(Eq. 26 at the outlet, Eq. 28 at the inlet).  The paper reports that the
-water trapped in the cup shrinks markedly under Set-1 and Set-2 and survives
-under Set-3.  Prints one progress line per record interval.
+component's missing links keep their values (Eqs. 26-27), Set-3 is the
+paper's treatment (Eq. 26 at the outlet, Eq. 28 at the inlet).  Eqs. 26-27
+are run under both readings of "maintain themselves": held at their initial
+values (eq26 0) and the node's own post-collision values (eq26 1).  The paper
+reports that the water trapped in the cup shrinks markedly under Set-1 and
+Set-2 and survives under Set-3.  --geom overrides the U's dimensions (JSON).
+Prints one progress line per record interval.
 """
 from __future__ import annotations
 
@@ -28,18 +31,32 @@ from paper_2111_08666_amd import inputs as I   # noqa: E402
 from paper_2111_08666_amd import lbm           # noqa: E402
 
 
-def run(steps=300000, every=5000, collision=0, log=print):
-    sets = (1, 2, 3)
-    probs = [I.u_trap(bc_set=s, collision=collision) for s in sets]
-    cup = I.u_trap_cup(**I.U_TRAP)
+VARIANTS = ((1, 0), (2, 0), (2, 1), (3, 0), (3, 1))  # (boundary set, eq26_mode)
+
+
+def variant_name(bc_set, eq26):
+    return f"set{bc_set}" + ("_post" if eq26 else "")
+
+
+def run(steps=300000, every=5000, collision=0, variants=VARIANTS, geom=None, log=print):
+    geom = dict(geom or {})
+    names = [variant_name(s, e) for s, e in variants]
+    probs = []
+    for s, e in variants:
+        p = I.u_trap(bc_set=s, collision=collision, **geom)
+        p.eq26_mode = e
+        probs.append(p)
+    g = dict(I.U_TRAP)
+    g.update(geom)
+    cup = I.u_trap_cup(**g)
     b = lbm.BatchSolver(probs)
-    rec = {s: {"t": [], "cup_mass2": [], "cup_mass1": [], "mass1": [], "mass2": [], "s_w": []} for s in sets}
+    rec = {n: {"t": [], "cup_mass2": [], "cup_mass1": [], "mass1": [], "mass2": [], "s_w": []} for n in names}
 
     def record(t):
         obs = b.observables(allow_unstable=True)
-        for i, s in enumerate(sets):
+        for i, n in enumerate(names):
             rho = b.density(i).astype(np.float64)
-            r = rec[s]
+            r = rec[n]
             r["t"].append(t)
             r["cup_mass2"].append(float(rho[1][cup].sum()))
             r["cup_mass1"].append(float(rho[0][cup].sum()))
@@ -54,12 +71,12 @@ def run(steps=300000, every=5000, collision=0, log=print):
         b.step_graph(every, 1)
         t += every
         record(t)
-        log("[trapped] t=%d cup water (set1 set2 set3): %s (%.0fs)" % (
-            t, " ".join("%.4f" % (rec[s]["cup_mass2"][-1] / rec[s]["cup_mass2"][0]) for s in sets),
-            time.time() - t0))
+        log("[trapped] t=%d cup water (%s): %s; S_w %s (%.0fs)" % (
+            t, " ".join(names), " ".join("%.4f" % (rec[n]["cup_mass2"][-1] / rec[n]["cup_mass2"][0]) for n in names),
+            " ".join("%.3f" % rec[n]["s_w"][-1] for n in names), time.time() - t0))
     b.close()
-    return {"steps": steps, "every": every, "collision": collision, "geometry": I.U_TRAP,
-            "cup_nodes": int(cup.sum()), "sets": {str(s): rec[s] for s in sets}}
+    return {"steps": steps, "every": every, "collision": collision, "geometry": g,
+            "cup_nodes": int(cup.sum()), "variants": {n: rec[n] for n in names}}
 
 
 def main():
@@ -67,13 +84,16 @@ def main():
     ap.add_argument("--steps", type=int, default=300000)
     ap.add_argument("--every", type=int, default=5000)
     ap.add_argument("--collision", type=int, default=0)
+    ap.add_argument("--geom", default="", help="JSON overrides of the U's dimensions")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
-    res = run(a.steps, a.every, a.collision, log=lambda m: print(m, flush=True))
-    summary = {s: {"cup_water_final_over_initial": r["cup_mass2"][-1] / r["cup_mass2"][0],
-                   "cup_water_min_over_initial": min(r["cup_mass2"]) / r["cup_mass2"][0]}
-               for s, r in res["sets"].items()}
-    print(json.dumps({"summary": summary}), flush=True)
+    res = run(a.steps, a.every, a.collision, geom=json.loads(a.geom) if a.geom else None,
+              log=lambda m: print(m, flush=True))
+    summary = {n: {"cup_water_final_over_initial": r["cup_mass2"][-1] / r["cup_mass2"][0],
+                   "cup_water_min_over_initial": min(r["cup_mass2"]) / r["cup_mass2"][0],
+                   "s_w_final": r["s_w"][-1]}
+               for n, r in res["variants"].items()}
+    print(json.dumps({"geometry": res["geometry"], "summary": summary}), flush=True)
     if a.out:
         with open(a.out, "w") as f:
             json.dump(res, f)

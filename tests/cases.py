@@ -27,6 +27,12 @@ def problems():
         p.bc_set = s
         p.rho_in2, p.rho_out1 = 0.027, 0.027
         out[f"set{s}"] = p
+    # the post-collision reading of Eqs. 26-27, Set-2 and Set-3
+    for s in (2, 3):
+        p = I.drainage_2d(nx=70, ny=26, r=(2.0, 4.0), porosity=0.75, seed=30 + s, G=3.5, theta=50,
+                          rho_in1=1.02, minor=0.027)
+        p.bc_set, p.eq26_mode = s, 1
+        out[f"set{s}_eq26_post"] = p
     # periodic droplet (Laplace case), both axes periodic
     n = 64
     out["droplet_periodic"] = I.Problem(

@@ -192,6 +192,58 @@ def test_set3_inlet_and_outlet_rules():
     assert np.abs(r[0][:, 1:-1]).max() == 0.0
 
 
+def test_eq26_post_collision_reading():
+    """The post-collision reading of Eqs. 26-27 (eq26_mode 1): component 1's
+    outlet links (and in Set-2 component 2's inlet links) take the node's own
+    post-collision values, like Eq. 28.  With component 1's f* zero except the
+    outlet's own (3, 6, 7) links, its outlet density is exactly their sum; the
+    held initial values no longer enter."""
+    for bc_set in (2, 3):
+        p = I.drainage_2d(nx=40, ny=20, r=(2.0, 3.0), porosity=0.8, seed=4, G=3.5, theta=45,
+                          rho_in1=1.03, rho_out2=0.99)
+        p.bc_set, p.eq26_mode = bc_set, 1
+        s = O.OracleSim(p)
+        s.step(7)
+        fluid = ~p.mask.astype(bool)
+        yi = np.where(fluid[:, 0])[0]
+        yo = np.where(fluid[:, -1])[0]
+        fs = s.fstar()
+        z = np.zeros_like(fs)
+        z[1] = fs[1]
+        for i in (3, 6, 7):
+            z[0, i, yo, -1] = 0.1 * i
+        s.set_fstar(z)
+        r = s.density()
+        # (rows next to a wall also receive bounced-back links, so skip them)
+        assert np.abs(r[0, yo[1:-1], -1] - 1.6).max() < 1e-14
+        if bc_set == 2:
+            # Eq. 27 at the inlet under the same reading: component 2's (1, 5, 8)
+            z = np.zeros_like(fs)
+            z[0] = fs[0]
+            for i in (1, 5, 8):
+                z[1, i, yi, 0] = 0.1 * i
+            s.set_fstar(z)
+            assert np.abs(s.density()[1, yi[1:-1], 0] - 1.4).max() < 1e-14
+
+
+@pytest.mark.parametrize("bc_set", [2, 3])
+def test_open_box_mass_identity_eq26_post(bc_set):
+    """The exact per-step mass balance of the open box under the
+    post-collision reading of Eqs. 26-27."""
+    p = I.drainage_2d(nx=48, ny=24, r=(2.0, 4.0), porosity=0.75, seed=3, G=3.5, theta=45,
+                      rho_in1=1.02)
+    p.bc_set, p.eq26_mode = bc_set, 1
+    s = O.OracleSim(p)
+    prev = s.observables()
+    for _ in range(40):
+        s.step(1)
+        o = s.observables()
+        for c in range(2):
+            d = o["mass"][c] - prev["mass"][c]
+            assert abs(d - (o["flux_in"][c] - o["flux_out"][c])) < 1e-12 * o["mass"][c]
+        prev = o
+
+
 def test_periodic_translation_is_bitwise():
     rng = np.random.default_rng(1)
     nx, ny = 24, 20
