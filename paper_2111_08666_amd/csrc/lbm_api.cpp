@@ -139,7 +139,7 @@ Layout make_layout(const lbm_geometry &g, const lbm_params &p) {
   L.buf_bytes = align_up((size_t)L.zstride * g.nz * sizeof(float));
   L.info_bytes = align_up((size_t)L.pitch * g.ny * g.nz * sizeof(uint32_t));
   L.frozen_bytes = align_up((size_t)2 * g.q * g.ny * g.nz * sizeof(float));
-  L.psi_bytes = align_up((size_t)L.pitch * g.ny * g.nz * 2 * sizeof(double));
+  L.psi_bytes = align_up((size_t)L.pitch * g.ny * g.nz * 2 * 2 * sizeof(float));  // two pair arrays
   L.compact = compact_strategy(resolve_strategy(g, p));
   if (L.compact) {  // validate() keeps q * cpitch * 4 bytes below 2^32
     int64_t nf = 0;
@@ -533,7 +533,7 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
     InstDev h{};
     h.info = reinterpret_cast<const uint32_t *>(take(L.info_bytes));
     h.frozen = reinterpret_cast<const float *>(take(L.frozen_bytes));
-    h.psi = reinterpret_cast<double *>(take(L.psi_bytes));
+    h.psi = reinterpret_cast<float *>(take(L.psi_bytes));
     h.f[0] = reinterpret_cast<float *>(take(L.buf_bytes));
     h.f[1] = reinterpret_cast<float *>(take(L.buf_bytes));
     h.ystride = L.ystride;
@@ -600,7 +600,7 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
     for (int64_t n = 0; n < 2 * N; ++n) r0[(size_t)n] = (float)rho0[i][n];
     HIPCHK(b, hipMemcpyAsync(h.psi, r0.data(), sizeof(float) * r0.size(), hipMemcpyHostToDevice, b->stream));
     HIPCHK(b, hipMemcpyAsync(b->d_insts + i, &b->h.back(), sizeof(InstDev), hipMemcpyHostToDevice, b->stream));
-    HIPCHK(b, launch_init(b->d_insts + i, h, reinterpret_cast<const float *>(h.psi), 0, b->stream));
+    HIPCHK(b, launch_init(b->d_insts + i, h, h.psi, 0, b->stream));
     HIPCHK(b, hipStreamSynchronize(b->stream));  // host staging vectors die here
   }
   // default plan: the split step for D3Q19 (its per-block working set does
@@ -730,7 +730,7 @@ lbm_status batch_density(lbm_batch *b, int32_t i, float *dst, int32_t dst_is_dev
   // stage in the psi array: 16 bytes per node, so always large enough (the
   // compacted population buffers may hold fewer than 2N floats), and every
   // step rewrites it before reading it
-  float *stage = reinterpret_cast<float *>(h.psi);
+  float *stage = h.psi;
   b->psi_valid = false;
   HIPCHK(b, launch_density(b->d_insts + i, h, b->parity, stage, b->stream));
   HIPCHK(b, hipMemcpyAsync(dst, stage, sizeof(float) * 2 * (size_t)N, hipMemcpyDeviceToHost, b->stream));
@@ -908,7 +908,7 @@ lbm_status lbm_init_from_saturation(lbm_ctx *ctx, const float *sat, int32_t sat_
   const float *src = sat;
   if (!sat_is_device) {
     // stage in the psi buffer (16 bytes per node); the carried psi is rebuilt
-    float *stage = reinterpret_cast<float *>(h.psi);
+    float *stage = h.psi;
     HIPCHK(b, hipMemcpyAsync(stage, sat, sizeof(float) * (size_t)h.nx * h.ny * h.nz, hipMemcpyHostToDevice,
                              b->stream));
     src = stage;

@@ -40,7 +40,7 @@ struct InstDev {
   float *f[2];            // ping-pong post-collision state (layout by storage)
   const uint32_t *info;   // node info words, index x + pitch * (y + ny * z)
   const float *frozen;    // [2][Q][ny*nz]: component-1 outlet / component-2 inlet links
-  double *psi;            // split step: [nz][ny][pitch] x (rho1, rho2) / virtual solid density
+  float *psi;             // two arrays of [nz][ny][pitch] (psi1, psi2) float pairs
   int64_t ystride, zstride;  // f buffers: row blocks of (y, z) at y * ystride + z * zstride
   int32_t nx, ny, nz, pitch;  // pitch = padded row length (a multiple of 64)
   int32_t periodic, open_x, bc_set, collision;

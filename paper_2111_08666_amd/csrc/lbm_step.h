@@ -942,15 +942,76 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
 }
 
 // ---------------------------------------------------------------------------
+// The pseudopotential between the launches of a step: (psi1, psi2) FP32
+// pairs in the psi buffer.  Array 0 is dense, index x + pitch * (y + ny * z)
+// like the node info: the densities at fluid nodes (split step) and the
+// virtual solid density of Eq. 17 at solid nodes next to fluid.  Array 1
+// holds, for the compacted split step, the fluid densities by compact index
+// (the compacted 3D fused step uses both arrays as its carried psi, one per
+// buffer parity).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ gv2f *psi32(const InstDev &d, int p) {
+  return (gv2f *)d.psi + (int64_t)p * d.pitch * d.ny * d.nz;
+}
+
+__device__ __forceinline__ int wrap3(int p) { return ((p % 3) + 3) % 3; }
+
+// Pair sums sum_i w_i psi(x + e_i) e_i of Eq. 13 from the eighteen (or
+// eight) neighbour values pv[i] = psi(x + e_i); at an open face the mirrored
+// pairs with an x component cancel.
+template <int Q, typename R>
+__device__ __forceinline__ void force_sums(const v2f (&pv)[Q], bool open_face, R &sx1, R &sy1, R &sz1, R &sx2,
+                                           R &sy2, R &sz2) {
+  using L = Lat<Q>;
+  sx1 = 0; sy1 = 0; sz1 = 0; sx2 = 0; sy2 = 0; sz2 = 0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (L::opp[i] < i) continue;
+    const int o = L::opp[i];
+    const v2f pa = pv[i], pb = pv[o];
+    const R w = (R)L::w[i];
+    R d1 = w * ((R)pa.x - (R)pb.x), d2 = w * ((R)pa.y - (R)pb.y);
+    if (L::ex[i] != 0) {
+      d1 = open_face ? R(0) : d1;
+      d2 = open_face ? R(0) : d2;
+    }
+    if (L::ex[i]) { sx1 += L::ex[i] * d1; sx2 += L::ex[i] * d2; }
+    if (L::ey[i]) { sy1 += L::ey[i] * d1; sy2 += L::ey[i] * d2; }
+    if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
+  }
+}
+
+// The same sums from a dense psi array: every neighbour is loaded (no branch
+// between the loads, so they are all in flight at once); an open face drops
+// the mirrored x pairs afterwards.
+template <int Q, typename R>
+__device__ __forceinline__ void psi32_force_sums(const InstDev &d, gcv2f *__restrict__ psi, int x, int y, int z,
+                                                 bool open_face, R &sx1, R &sy1, R &sz1, R &sx2, R &sy2,
+                                                 R &sz2) {
+  using L = Lat<Q>;
+  int xs[3];
+  source_x(d, x, xs);  // xs[1 - e_x]: x + e_x with wrap
+  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
+  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
+  const uint32_t pitch = (uint32_t)d.pitch, ny = (uint32_t)d.ny;
+  const uint32_t yy[3] = {(uint32_t)ym, (uint32_t)y, (uint32_t)yp}, zz[3] = {(uint32_t)zm, (uint32_t)z, (uint32_t)zp};
+  v2f pv[Q];
+  pv[0] = v2f{0.f, 0.f};
+#pragma unroll
+  for (int i = 1; i < Q; ++i)
+    pv[i] = psi[(uint32_t)xs[1 - L::ex[i]] + pitch * (yy[L::ey[i] + 1] + ny * zz[L::ez[i] + 1])];
+  force_sums<Q, R>(pv, open_face, sx1, sy1, sz1, sx2, sy2, sz2);
+}
+
+// ---------------------------------------------------------------------------
 // Split step (three launches) for grids whose per-block working set does not
 // fit the L2: the halo recompute of the fused kernels would then refetch
 // populations from memory.  Each wave owns 64 consecutive x of one (y, z)
 // row (wave-uniform rows), one thread per node.
-//   rho_kernel:     pull + complete -> rho^s(x) into the psi array (double2)
+//   rho_kernel:     pull + complete -> rho^s(x) into dense psi array 0 (FP32)
 //   psi_kernel:     virtual solid density (Eq. 17) at solid nodes, in place
 //   collide_kernel: force from psi (Eq. 13 with the open-face mirror), pull
-//                   again, collide, store
-// psi array layout: index x + pitch * (y + ny * z), like the node info.
+//                   again, densities from the pull, collide, store
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool wave_row(const InstDev &d, int &x, int &y, int &z) {
   const int segs = (d.nx + 63) >> 6;
@@ -961,18 +1022,6 @@ __device__ __forceinline__ bool wave_row(const InstDev &d, int &x, int &y, int &
   z = (int)(row / d.ny);
   x = seg * 64 + (int)(threadIdx.x & 63);
   return z < d.nz && x < d.nx;
-}
-
-typedef __attribute__((address_space(1))) double gd;
-typedef __attribute__((address_space(1))) const double gcd;
-
-// psi entries are (rho1, rho2) pairs of doubles
-__device__ __forceinline__ Vec2<double> psi_ld(gcd *p, int64_t j) {
-  return Vec2<double>{p[2 * j], p[2 * j + 1]};
-}
-__device__ __forceinline__ void psi_st(gd *p, int64_t j, double a, double b) {
-  p[2 * j] = a;
-  p[2 * j + 1] = b;
 }
 
 template <int Q, int ST>
@@ -991,15 +1040,16 @@ __global__ __launch_bounds__(256) void rho_kernel(const InstDev *__restrict__ in
   float a[Q], b[Q];
   pull_row<Q, ST>(d, fin, info, src, xs, a, b);
   if (info & (kInlet | kOutlet)) complete<Q, ST, double>(d, fin, info, x, y, z, a, b);
-  psi_st((gd *)d.psi, pi, sum_q<Q, double>(a), sum_q<Q, double>(b));
+  psi32(d, 0)[pi] = v2f{(float)sum_q<Q, double>(a), (float)sum_q<Q, double>(b)};
 }
 
 // Virtual solid density (Eq. 17) of solid node (x, y, z), dense index pi,
-// whose fluid neighbours are flagged in nb.
-template <int Q>
-__device__ __forceinline__ void ivsd_node(const InstDev &d, int x, int y, int z, int64_t pi, uint32_t nb) {
+// whose fluid neighbours are flagged in nb; fluid density of neighbour
+// x + e_i from dens(i, dense index), summed in FP64.
+template <int Q, class DensF>
+__device__ __forceinline__ void ivsd_node(const InstDev &d, int x, int y, int z, int64_t pi, uint32_t nb,
+                                          DensF dens) {
   using L = Lat<Q>;
-  gd *__restrict__ psi = (gd *)d.psi;
   int xs[3];
   source_x(d, x, xs);  // xs[1 - e_x]: x + e_x with wrap
   const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
@@ -1009,15 +1059,14 @@ __device__ __forceinline__ void ivsd_node(const InstDev &d, int x, int y, int z,
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     if (nb & (1u << i)) {
-      const int64_t j = xs[1 - L::ex[i]] + (int64_t)d.pitch * (yy[L::ey[i] + 1] + (int64_t)d.ny * zz[L::ez[i] + 1]);
-      const Vec2<double> p = psi_ld(psi, j);
-      s1 += L::w[i] * p.x;
-      s2 += L::w[i] * p.y;
+      const v2f p = dens(xs[1 - L::ex[i]], yy[L::ey[i] + 1], zz[L::ez[i] + 1]);
+      s1 += L::w[i] * (double)p.x;
+      s2 += L::w[i] * (double)p.y;
       den += L::w[i];
     }
   }
   const double inv = rcp<double>(den);
-  psi_st(psi, pi, d.chi1 * s1 * inv, d.chi2 * s2 * inv);
+  psi32(d, 0)[pi] = v2f{(float)(d.chi1 * s1 * inv), (float)(d.chi2 * s2 * inv)};
 }
 
 template <int Q>
@@ -1028,44 +1077,10 @@ __global__ __launch_bounds__(256) void psi_kernel(const InstDev *__restrict__ in
   const int64_t pi = x + (int64_t)d.pitch * (y + (int64_t)d.ny * z);
   const uint32_t nb = ((gcu32 *)d.info)[pi];
   if (!(nb & kSolid) || !(nb & kLinkMask)) return;
-  ivsd_node<Q>(d, x, y, z, pi, nb);
-}
-
-// Densities at node pi and the pair sums sum_i w_i psi(x + e_i) e_i of the
-// interaction force (Eq. 13); at an open face the mirrored pairs with an x
-// component cancel.
-template <int Q, typename R>
-__device__ __forceinline__ void psi_force_sums(const InstDev &d, int x, int y, int z, int64_t pi,
-                                               uint32_t info, R &rho1, R &rho2, R &sx1, R &sy1, R &sz1,
-                                               R &sx2, R &sy2, R &sz2) {
-  using L = Lat<Q>;
-  gcd *__restrict__ psi = (gcd *)d.psi;
-  int xs[3];
-  source_x(d, x, xs);
-  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
-  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
-  const int yy[3] = {ym, y, yp}, zz[3] = {zm, z, zp};
-  const Vec2<double> c = psi_ld(psi, pi);
-  rho1 = (R)c.x;
-  rho2 = (R)c.y;
-  const bool open_face = (info & (kInlet | kOutlet)) != 0;
-  sx1 = 0; sy1 = 0; sz1 = 0; sx2 = 0; sy2 = 0; sz2 = 0;
-  // (loading all eighteen FP64 pairs at once, without the branch, was
-  // measured slower: 156 registers, three waves per SIMD instead of four)
-#pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    if (L::opp[i] < i) continue;
-    const int o = L::opp[i];
-    if (L::ex[i] != 0 && open_face) continue;
-    const int64_t ja = xs[1 - L::ex[i]] + (int64_t)d.pitch * (yy[L::ey[i] + 1] + (int64_t)d.ny * zz[L::ez[i] + 1]);
-    const int64_t jb = xs[1 - L::ex[o]] + (int64_t)d.pitch * (yy[L::ey[o] + 1] + (int64_t)d.ny * zz[L::ez[o] + 1]);
-    const Vec2<double> pa = psi_ld(psi, ja), pb = psi_ld(psi, jb);
-    const R w = (R)L::w[i];
-    const R d1 = w * ((R)pa.x - (R)pb.x), d2 = w * ((R)pa.y - (R)pb.y);
-    if (L::ex[i]) { sx1 += L::ex[i] * d1; sx2 += L::ex[i] * d2; }
-    if (L::ey[i]) { sy1 += L::ey[i] * d1; sy2 += L::ey[i] * d2; }
-    if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
-  }
+  gcv2f *__restrict__ psi = psi32(d, 0);
+  ivsd_node<Q>(d, x, y, z, pi, nb, [&](int xn, int yn, int zn) {
+    return psi[xn + (int64_t)d.pitch * (yn + (int64_t)d.ny * zn)];
+  });
 }
 
 template <int Q, int COLL, int ST, typename R>
@@ -1080,13 +1095,16 @@ __global__ __launch_bounds__(256) void collide_kernel(const InstDev *__restrict_
   gf *__restrict__ fout = G(d.f[parity ^ 1]);
   int xs[3];
   source_x(d, x, xs);
-  R rho1, rho2, sx1, sy1, sz1, sx2, sy2, sz2;
-  psi_force_sums<Q, R>(d, x, y, z, pi, info, rho1, rho2, sx1, sy1, sz1, sx2, sy2, sz2);
+  R sx1, sy1, sz1, sx2, sy2, sz2;
+  psi32_force_sums<Q, R>(d, psi32(d, 0), x, y, z, (info & (kInlet | kOutlet)) != 0, sx1, sy1, sz1, sx2, sy2, sz2);
+  // keep the psi loads and the pulls apart (register pressure)
+  __builtin_amdgcn_sched_barrier(0);
   int64_t src[3][3];
   source_rows<Q, true>(d, y, z, src);  // one row per wave
   float a[Q], b[Q];
   pull_row<Q, ST>(d, fin, info, src, xs, a, b);
   if (info & (kInlet | kOutlet)) complete<Q, ST, R>(d, fin, info, x, y, z, a, b);
+  const R rho1 = sum_q<Q, R>(a), rho2 = sum_q<Q, R>(b);
   const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
   collide_node<Q, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb, -G_ * rho1 * sy2 + rho1 * gyb,
                            -G_ * rho1 * sz2 + rho1 * gzb, -G_ * rho2 * sx1 + rho2 * gxb,
@@ -1101,8 +1119,8 @@ __global__ __launch_bounds__(256) void collide_kernel(const InstDev *__restrict_
 // the compact index c; a pull from a fluid source reads the source's compact
 // index (popcount rank in its row), a pull across a solid link reads the
 // node's own f*_opp(i) (half-way bounce-back without ghost slots).  Densities
-// and the virtual solid density go through the dense psi array as in the
-// split step, and the force and collision are the split step's arithmetic.
+// and the virtual solid density go through dense psi array 0 as in the split
+// step, and the force and collision are the split step's arithmetic.
 // ---------------------------------------------------------------------------
 
 // Does some link of the lattice pull from row offset (dy, dz)?
@@ -1205,7 +1223,7 @@ __global__ __launch_bounds__(256) void crho_kernel(const InstDev *__restrict__ i
   const uint32_t info = ((gcu32 *)d.info)[key];
   float a[Q], b[Q];
   cgather<Q, ST, double>(d, G(d.f[parity]), info, x, y, z, c, a, b);
-  psi_st((gd *)d.psi, key, sum_q<Q, double>(a), sum_q<Q, double>(b));
+  psi32(d, 0)[key] = v2f{(float)sum_q<Q, double>(a), (float)sum_q<Q, double>(b)};
 }
 
 template <int Q>
@@ -1216,7 +1234,10 @@ __global__ __launch_bounds__(256) void cpsi_kernel(const InstDev *__restrict__ i
   const uint32_t key = d.cbnd[j];
   int x, y, z;
   ckey_xyz(d, key, x, y, z);
-  ivsd_node<Q>(d, x, y, z, key, ((gcu32 *)d.info)[key]);
+  gcv2f *__restrict__ psi = psi32(d, 0);
+  ivsd_node<Q>(d, x, y, z, key, ((gcu32 *)d.info)[key], [&](int xn, int yn, int zn) {
+    return psi[xn + (int64_t)d.pitch * (yn + (int64_t)d.ny * zn)];
+  });
 }
 
 template <int Q, int COLL, int ST, typename R>
@@ -1228,13 +1249,14 @@ __global__ __launch_bounds__(256) void ccollide_kernel(const InstDev *__restrict
   int x, y, z;
   ckey_xyz(d, key, x, y, z);
   const uint32_t info = ((gcu32 *)d.info)[key];
-  R rho1, rho2, sx1, sy1, sz1, sx2, sy2, sz2;
-  psi_force_sums<Q, R>(d, x, y, z, key, info, rho1, rho2, sx1, sy1, sz1, sx2, sy2, sz2);
+  R sx1, sy1, sz1, sx2, sy2, sz2;
+  psi32_force_sums<Q, R>(d, psi32(d, 0), x, y, z, (info & (kInlet | kOutlet)) != 0, sx1, sy1, sz1, sx2, sy2, sz2);
   // keep the psi loads and the pulls apart: both in flight at once would
   // double the live registers and halve the waves per SIMD
   __builtin_amdgcn_sched_barrier(0);
   float a[Q], b[Q];
   cgather<Q, ST, R>(d, G(d.f[parity]), info, x, y, z, c, a, b);
+  const R rho1 = sum_q<Q, R>(a), rho2 = sum_q<Q, R>(b);
   const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
   collide_node<Q, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb, -G_ * rho1 * sy2 + rho1 * gyb,
                            -G_ * rho1 * sz2 + rho1 * gzb, -G_ * rho2 * sx1 + rho2 * gxb,
@@ -1272,50 +1294,6 @@ __global__ __launch_bounds__(256) void ccollide_kernel(const InstDev *__restrict
 // ---------------------------------------------------------------------------
 constexpr int kFwdThreads = 256;             // list entries collided per round
 constexpr int kFwdPos = 64 * kFwdRows;       // tile positions per plane
-
-// Carried psi array p (0 or 1): index x + pitch * (y + ny * z).
-__device__ __forceinline__ gv2f *psi32(const InstDev &d, int p) {
-  return (gv2f *)d.psi + (int64_t)p * d.pitch * d.ny * d.nz;
-}
-
-__device__ __forceinline__ int wrap3(int p) { return ((p % 3) + 3) % 3; }
-
-// Pair sums sum_i w_i psi(x + e_i) e_i of Eq. 13 from a carried psi array
-// (D3Q19); at an open face the mirrored pairs with an x component cancel.
-template <typename R>
-__device__ __forceinline__ void psi32_force_sums(const InstDev &d, gcv2f *__restrict__ psi, int x, int y, int z,
-                                                 bool open_face, R &sx1, R &sy1, R &sz1, R &sx2, R &sy2,
-                                                 R &sz2) {
-  using L = Lat<19>;
-  int xs[3];
-  source_x(d, x, xs);  // xs[1 - e_x]: x + e_x with wrap
-  const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
-  const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
-  const uint32_t pitch = (uint32_t)d.pitch, ny = (uint32_t)d.ny;
-  const uint32_t yy[3] = {(uint32_t)ym, (uint32_t)y, (uint32_t)yp}, zz[3] = {(uint32_t)zm, (uint32_t)z, (uint32_t)zp};
-  sx1 = 0; sy1 = 0; sz1 = 0; sx2 = 0; sy2 = 0; sz2 = 0;
-  // every neighbour is loaded (no branch between the loads, so they are all
-  // in flight at once); an open face drops the mirrored x pairs afterwards
-  v2f pv[19];
-#pragma unroll
-  for (int i = 1; i < 19; ++i)
-    pv[i] = psi[(uint32_t)xs[1 - L::ex[i]] + pitch * (yy[L::ey[i] + 1] + ny * zz[L::ez[i] + 1])];
-#pragma unroll
-  for (int i = 1; i < 19; ++i) {
-    if (L::opp[i] < i) continue;
-    const int o = L::opp[i];
-    const v2f pa = pv[i], pb = pv[o];
-    const R w = (R)L::w[i];
-    R d1 = w * ((R)pa.x - (R)pb.x), d2 = w * ((R)pa.y - (R)pb.y);
-    if (L::ex[i] != 0) {
-      d1 = open_face ? R(0) : d1;
-      d2 = open_face ? R(0) : d2;
-    }
-    if (L::ex[i]) { sx1 += L::ex[i] * d1; sx2 += L::ex[i] * d2; }
-    if (L::ey[i]) { sy1 += L::ey[i] * d1; sy2 += L::ey[i] * d2; }
-    if (L::ez[i]) { sz1 += L::ez[i] * d1; sz2 += L::ez[i] * d2; }
-  }
-}
 
 // Block barrier for LDS traffic only: waits for the wave's own LDS (and
 // scalar) operations, not for its global loads and stores, which no other
@@ -1471,7 +1449,7 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3))
         const uint32_t key = (uint32_t)x + pitch * ((uint32_t)y + (uint32_t)ny * (uint32_t)z);
         const bool face = open_x && (x == 0 || x == nx - 1);
         R sx1, sy1, sz1, sx2, sy2, sz2;
-        psi32_force_sums<R>(d, psi_in, x, y, z, face, sx1, sy1, sz1, sx2, sy2, sz2);
+        psi32_force_sums<Q, R>(d, psi_in, x, y, z, face, sx1, sy1, sz1, sx2, sy2, sz2);
         const uint32_t info = ((gcu32 *)d.info)[key];
         // keep the psi loads and the pulls apart (register pressure)
         __builtin_amdgcn_sched_barrier(0);
