@@ -113,7 +113,10 @@ typedef struct {
                              instances of the context or batch fit in the
                              256 MB last-level cache, else compacted fused
                              (every instance must then be LBM_AUTO). */
-  int32_t tile_rows;      /* fused D2Q9 tile height: 8, 12 or 16 (0 = 12) */
+  int32_t tile_rows;      /* fused D2Q9 tile height: 8, 12 or 16 (0 = 12);
+                             for the compacted layouts in 3D, the rows per
+                             band of the fluid-node numbering (bands of rows,
+                             z-slice by z-slice; 0 = sized from the grid) */
   int32_t eq26_mode;      /* reading of Eqs. 26-27 (the outlet links of component 1
                              in Set-2 and Set-3, the inlet links of component 2 in
                              Set-2), which the paper says maintain themselves

@@ -20,10 +20,12 @@ FLAGS = [
 
 
 def kernel_source_hash() -> str:
-    """Hash of the step kernels' sources: counter measurements are tied to it."""
+    """Hash of the step kernels' sources and of the host code that lays out
+    their data (the node numbering sets the memory traffic): counter
+    measurements are tied to it."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("lbm_kernels.hip", "lbm_step.h", "lattice.h", "lbm_device.h"):
+    for f in ("lbm_kernels.hip", "lbm_step.h", "lattice.h", "lbm_device.h", "lbm_api.cpp"):
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
