@@ -275,10 +275,24 @@ __device__ __forceinline__ int xcd_block() {
   return xcd * q8 + min(xcd, r8) + (b >> 3);
 }
 
+// The compacted layout's tables are read through global-address loads: a
+// flat load would also count against the scalar-load counter, so that every
+// wait for an instance field (scalar loads) would wait for it as well.
+// Only the low word of a row word's prefix is loaded (compact indices stay
+// below 2^32): a 16-byte load whose last register the code never reads would
+// make the compiler wait for the load before reusing that register.
+typedef unsigned int u32x3 __attribute__((ext_vector_type(3)));
+typedef __attribute__((address_space(1))) const u32x3 gcu32x3;
+__device__ __forceinline__ RowWord row_word(const InstDev &d, int64_t i) {
+  const u32x3 v = *(gcu32x3 *)((gcu32 *)d.cword + 4 * i);
+  return RowWord{(unsigned long long)v.x | ((unsigned long long)v.y << 32), (long long)v.z};
+}
+__device__ __forceinline__ uint32_t gld32(const uint32_t *p, int64_t i) { return ((gcu32 *)p)[i]; }
+
 // Compact index of fluid node (x, row), row = y + ny * z.  For a solid
 // position it is the index of the next fluid node (at most nf).
 __device__ __forceinline__ int64_t crank(const InstDev &d, int x, int64_t row) {
-  const RowWord w = d.cword[row * (d.pitch >> 6) + (x >> 6)];
+  const RowWord w = row_word(d, row * (d.pitch >> 6) + (x >> 6));
   const unsigned long long below = (1ull << (x & 63)) - 1ull;
   return w.pre + __popcll(w.bits & below);
 }
@@ -300,7 +314,7 @@ __device__ __forceinline__ void cpull9(const InstDev &d, gcf *__restrict__ fin, 
   int fl[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const RowWord w = d.cword[ys[a] * wpr + (x >> 6)];
+    const RowWord w = row_word(d, ys[a] * wpr + (x >> 6));
     rk[a] = (int32_t)(w.pre + __popcll(w.bits & below));
     fl[a] = (int)((w.bits >> (x & 63)) & 1ull);
   }
@@ -981,13 +995,12 @@ __device__ __forceinline__ void force_sums(const v2f (&pv)[Q], bool open_face, R
   }
 }
 
-// The same sums from a dense psi array: every neighbour is loaded (no branch
-// between the loads, so they are all in flight at once); an open face drops
-// the mirrored x pairs afterwards.
-template <int Q, typename R>
-__device__ __forceinline__ void psi32_force_sums(const InstDev &d, gcv2f *__restrict__ psi, int x, int y, int z,
-                                                 bool open_face, R &sx1, R &sy1, R &sz1, R &sx2, R &sy2,
-                                                 R &sz2) {
+// The neighbour values pv[i] = psi(x + e_i) from a dense psi array: every
+// neighbour is loaded, with no branch between the loads, so they are all in
+// flight at once (an open face drops the mirrored x pairs afterwards).
+template <int Q>
+__device__ __forceinline__ void psi32_neighbours(const InstDev &d, gcv2f *__restrict__ psi, int x, int y, int z,
+                                                 v2f (&pv)[Q]) {
   using L = Lat<Q>;
   int xs[3];
   source_x(d, x, xs);  // xs[1 - e_x]: x + e_x with wrap
@@ -995,11 +1008,19 @@ __device__ __forceinline__ void psi32_force_sums(const InstDev &d, gcv2f *__rest
   const int zm = z == 0 ? d.nz - 1 : z - 1, zp = z == d.nz - 1 ? 0 : z + 1;
   const uint32_t pitch = (uint32_t)d.pitch, ny = (uint32_t)d.ny;
   const uint32_t yy[3] = {(uint32_t)ym, (uint32_t)y, (uint32_t)yp}, zz[3] = {(uint32_t)zm, (uint32_t)z, (uint32_t)zp};
-  v2f pv[Q];
   pv[0] = v2f{0.f, 0.f};
 #pragma unroll
   for (int i = 1; i < Q; ++i)
     pv[i] = psi[(uint32_t)xs[1 - L::ex[i]] + pitch * (yy[L::ey[i] + 1] + ny * zz[L::ez[i] + 1])];
+}
+
+// Pair sums of Eq. 13 from a dense psi array.
+template <int Q, typename R>
+__device__ __forceinline__ void psi32_force_sums(const InstDev &d, gcv2f *__restrict__ psi, int x, int y, int z,
+                                                 bool open_face, R &sx1, R &sy1, R &sz1, R &sx2, R &sy2,
+                                                 R &sz2) {
+  v2f pv[Q];
+  psi32_neighbours<Q>(d, psi, x, y, z, pv);
   force_sums<Q, R>(pv, open_face, sx1, sy1, sz1, sx2, sy2, sz2);
 }
 
@@ -1138,12 +1159,14 @@ __device__ __forceinline__ void ckey_xyz(const InstDev &d, uint32_t key, int &x,
   z = (int)(r / (uint32_t)d.ny);
 }
 
-// Pull + inlet/outlet completion of fluid node c at (x, y, z).
-template <int Q, int ST, typename R>
-__device__ __forceinline__ void cgather(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int x, int y,
-                                        int z, int64_t c, float (&f0)[Q], float (&f1)[Q]) {
+// Compact index scs[i] of the pull source x - e_i of every link of fluid node
+// c at (x, y, z) (scs[0] = c).  A link whose source is solid gets a value
+// that is never used (bounce-back reads the node's own slot); a link across
+// an open face gets the periodic image's, overwritten by the completion.
+// The host keeps compact indices below 2^32.
+template <int Q>
+__device__ __forceinline__ void csources(const InstDev &d, int x, int y, int z, int64_t c, uint32_t (&scs)[Q]) {
   using L = Lat<Q>;
-  const int cp = d.cpitch;
   int xs[3];
   source_x(d, x, xs);  // indexed by e_x + 1: x - e_x with wrap
   const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;
@@ -1154,22 +1177,20 @@ __device__ __forceinline__ void cgather(const InstDev &d, gcf *__restrict__ fin,
   // each; the node's own row is rk = c, fl = 1).  A fluid source at x - 1 has
   // rank rk - 1, one at x + 1 rank rk + fl (a row's fluid nodes are numbered
   // consecutively); sources across the x edge are looked up.
-  int64_t rk[3][3];
-  int fl[3][3];
+  uint32_t rk[3][3], fl[3][3];
 #pragma unroll
   for (int a = 0; a < 3; ++a)
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      rk[a][b] = c;
+      rk[a][b] = (uint32_t)c;
       fl[a][b] = 1;
       if ((a == 1 && b == 1) || !row_used<Q>(a - 1, b - 1)) continue;
       const int64_t row = ys[a] + (int64_t)d.ny * zs[b];
-      const RowWord w = d.cword[row * (d.pitch >> 6) + (x >> 6)];
-      rk[a][b] = w.pre + __popcll(w.bits & ((1ull << (x & 63)) - 1ull));
-      fl[a][b] = (int)((w.bits >> (x & 63)) & 1ull);
+      const RowWord w = row_word(d, row * (d.pitch >> 6) + (x >> 6));
+      rk[a][b] = (uint32_t)(w.pre + __popcll(w.bits & ((1ull << (x & 63)) - 1ull)));
+      fl[a][b] = (uint32_t)((w.bits >> (x & 63)) & 1ull);
     }
-  int64_t scs[Q];
-  scs[0] = c;
+  scs[0] = (uint32_t)c;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     const int a = L::ey[i] + 1, b = L::ez[i] + 1;
@@ -1177,25 +1198,32 @@ __device__ __forceinline__ void cgather(const InstDev &d, gcf *__restrict__ fin,
   }
   const bool cross_lo = x == 0, cross_hi = x == d.nx - 1;
   if (cross_lo || cross_hi) {
-    // the periodic image across the x edge, or a missing link at an open
-    // face (an arbitrary node, overwritten by the completion below)
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       if ((L::ex[i] > 0 && cross_lo) || (L::ex[i] < 0 && cross_hi)) {
         const int64_t k = crank(d, xs[L::ex[i] + 1], ys[L::ey[i] + 1] + (int64_t)d.ny * zs[L::ez[i] + 1]);
-        scs[i] = k < last ? k : last;
+        scs[i] = (uint32_t)(k < last ? k : last);
       }
     }
   }
+}
+
+// Pull of fluid node c from the sources scs (bounce-back across solid links)
+// + inlet/outlet completion.
+template <int Q, int ST, typename R>
+__device__ __forceinline__ void cpull(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int y, int z,
+                                      int64_t c, const uint32_t (&scs)[Q], float (&f0)[Q], float (&f1)[Q]) {
+  using L = Lat<Q>;
+  const int cp = d.cpitch;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const bool bb = i != 0 && ((info >> i) & 1u);  // half-way bounce-back: own opposite slot
     const int pi = bb ? L::opp[i] : i;
-    const int64_t sc = bb ? c : scs[i];
+    const uint32_t sc = bb ? (uint32_t)c : scs[i];
     if constexpr (ST == 0) {
       // component planes from a wave-uniform base, 32-bit byte offsets (the
       // host keeps Q * cpitch * 4 below 2^32)
-      const uint32_t bo = ((uint32_t)pi * (uint32_t)cp + (uint32_t)sc) * 4u;
+      const uint32_t bo = ((uint32_t)pi * (uint32_t)cp + sc) * 4u;
       f0[i] = ldg(fin, bo);
       f1[i] = ldg(fin + (int64_t)Q * cp, bo);
     } else {
@@ -1212,12 +1240,21 @@ __device__ __forceinline__ void cgather(const InstDev &d, gcf *__restrict__ fin,
   }
 }
 
+// Pull + inlet/outlet completion of fluid node c at (x, y, z).
+template <int Q, int ST, typename R>
+__device__ __forceinline__ void cgather(const InstDev &d, gcf *__restrict__ fin, uint32_t info, int x, int y,
+                                        int z, int64_t c, float (&f0)[Q], float (&f1)[Q]) {
+  uint32_t scs[Q];
+  csources<Q>(d, x, y, z, c, scs);
+  cpull<Q, ST, R>(d, fin, info, y, z, c, scs, f0, f1);
+}
+
 template <int Q, int ST>
 __global__ __launch_bounds__(256) void crho_kernel(const InstDev *__restrict__ insts, int parity) {
   const InstDev &d = insts[0];
   const int64_t c = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
   if (c >= d.nf) return;
-  const uint32_t key = d.ckey[c];
+  const uint32_t key = gld32(d.ckey, c);
   int x, y, z;
   ckey_xyz(d, key, x, y, z);
   const uint32_t info = ((gcu32 *)d.info)[key];
@@ -1231,7 +1268,7 @@ __global__ __launch_bounds__(256) void cpsi_kernel(const InstDev *__restrict__ i
   const InstDev &d = insts[0];
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= d.nbnd) return;
-  const uint32_t key = d.cbnd[j];
+  const uint32_t key = gld32(d.cbnd, j);
   int x, y, z;
   ckey_xyz(d, key, x, y, z);
   gcv2f *__restrict__ psi = psi32(d, 0);
@@ -1245,17 +1282,23 @@ __global__ __launch_bounds__(256) void ccollide_kernel(const InstDev *__restrict
   const InstDev &d = insts[0];
   const int64_t c = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
   if (c >= d.nf) return;
-  const uint32_t key = d.ckey[c];
+  const uint32_t key = gld32(d.ckey, c);
   int x, y, z;
   ckey_xyz(d, key, x, y, z);
   const uint32_t info = ((gcu32 *)d.info)[key];
+  // the neighbours' psi and the source ranks' row words depend only on the
+  // node's position: both are in flight in one round trip
+  v2f pv[Q];
+  psi32_neighbours<Q>(d, psi32(d, 0), x, y, z, pv);
+  uint32_t scs[Q];
+  csources<Q>(d, x, y, z, c, scs);
   R sx1, sy1, sz1, sx2, sy2, sz2;
-  psi32_force_sums<Q, R>(d, psi32(d, 0), x, y, z, (info & (kInlet | kOutlet)) != 0, sx1, sy1, sz1, sx2, sy2, sz2);
+  force_sums<Q, R>(pv, (info & (kInlet | kOutlet)) != 0, sx1, sy1, sz1, sx2, sy2, sz2);
   // keep the psi loads and the pulls apart: both in flight at once would
   // double the live registers and halve the waves per SIMD
   __builtin_amdgcn_sched_barrier(0);
   float a[Q], b[Q];
-  cgather<Q, ST, R>(d, G(d.f[parity]), info, x, y, z, c, a, b);
+  cpull<Q, ST, R>(d, G(d.f[parity]), info, y, z, c, scs, a, b);
   const R rho1 = sum_q<Q, R>(a), rho2 = sum_q<Q, R>(b);
   const R G_ = (R)d.G, gxb = (R)d.gx, gyb = (R)d.gy, gzb = (R)d.gz;
   collide_node<Q, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb, -G_ * rho1 * sy2 + rho1 * gyb,
@@ -1570,8 +1613,8 @@ __global__ __launch_bounds__(256) void fwd_rho_kernel(const InstDev *__restrict_
   const InstDev &d = insts[0];
   const int64_t j = (int64_t)xcd_block() * blockDim.x + threadIdx.x;
   if (j >= n) return;
-  const int64_t c = list ? (int64_t)list[j] : j;
-  const uint32_t key = d.ckey[c];
+  const int64_t c = list ? (int64_t)gld32(list, j) : j;
+  const uint32_t key = gld32(d.ckey, c);
   int x, y, z;
   ckey_xyz(d, key, x, y, z);
   const uint32_t info = ((gcu32 *)d.info)[key];
@@ -1588,7 +1631,7 @@ __global__ __launch_bounds__(256) void fwd_ivsd_kernel(const InstDev *__restrict
   const InstDev &d = insts[0];
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= d.nbnd) return;
-  const uint32_t key = d.cbnd[j];
+  const uint32_t key = gld32(d.cbnd, j);
   int x, y, z;
   ckey_xyz(d, key, x, y, z);
   const uint32_t nb = ((gcu32 *)d.info)[key];
