@@ -373,25 +373,31 @@ __device__ __forceinline__ void ccomplete9(const InstDev &d, gcf *__restrict__ f
 // Phase 3: force (Eq. 13 with the open-face mirror) and collision for the
 //          interior nodes, whose pulled populations stayed in registers.
 // ---------------------------------------------------------------------------
-// Occupancy: TY = 8 fits 128 registers (four waves per SIMD) with every
-// pulled row in registers.  TY = 12 parks the last interior row of each wave
-// in LDS between the phases, which fits it in 128 registers and 35 KB of LDS
-// (four blocks per CU) instead of three waves per SIMD.
-template <int TY> struct FusedShape {
-  static constexpr int kParked = TY == 12 ? 1 : 0;  // interior rows per wave kept in LDS
-  static constexpr int kWaves = TY == 16 ? 1 : 4;
+// Occupancy: the step is bound by the latency of its memory chain, so
+// resident waves count (the 64-instance batch at TY = 12 takes 15 % longer
+// with three blocks per CU than with four, 49 % with two).  TY = 12 parks
+// the last interior row of each wave in LDS between the phases, which fits
+// it in 128 registers and 26 KB of LDS (four waves per SIMD).  With FP32
+// node arithmetic and FP32 storage TY = 8 parks its last row as well and
+// fits 80 registers: six waves per SIMD (measured 5 % faster on the batch
+// and 7 % on a 1024 x 512 instance than four waves with every row in
+// registers); otherwise it keeps every pulled row in registers at four waves.
+template <int TY, typename R, int ST> struct FusedShape {
+  static constexpr bool kF32 = sizeof(R) == 4 && ST == 0;
+  static constexpr int kParked = (TY == 12 || (TY == 8 && kF32)) ? 1 : 0;  // interior rows per wave kept in LDS
+  static constexpr int kWaves = TY == 16 ? 1 : ((TY == 8 && kF32) ? 6 : 4);
 };
 
 // CL = 1: the same step over the compacted layout (fluid nodes only stored,
 // pulls by rank, bounce-back from the node's own slots, no ghost slots).
 template <int COLL, int ST, typename R, int TY, int CL = 0>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FusedShape<TY>::kWaves))) void step_d2q9(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FusedShape<TY, R, ST>::kWaves))) void step_d2q9(
     const InstDev *__restrict__ insts, const int32_t *__restrict__ block_inst, int parity) {
   using L = Lat<9>;
   using V = Vec2<R>;
   constexpr int KR = TY / 4;        // interior rows per wave
   constexpr int kRH = TY + 4;       // region rows
-  constexpr int KP = FusedShape<TY>::kParked;
+  constexpr int KP = FusedShape<TY, R, ST>::kParked;
   __shared__ V psi[kRH][64];
   __shared__ float park[KP > 0 ? KP * 4 : 1][18][64];  // [row slot * 4 + wave][component * 9 + link][lane]
 
