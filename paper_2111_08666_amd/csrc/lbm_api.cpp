@@ -779,7 +779,7 @@ struct CkptHeader {
   double rho_in1, rho_out2;
   uint64_t psi_bytes;  // 0, or the carried psi array (dense float pairs)
 };
-constexpr int32_t kCkptVersion = 4;
+constexpr int32_t kCkptVersion = 5;
 
 size_t carried_psi_bytes(const InstDev &h) { return (size_t)h.pitch * h.ny * h.nz * 2 * sizeof(float); }
 size_t ckpt_bytes(const Layout &L, size_t psi_bytes) {

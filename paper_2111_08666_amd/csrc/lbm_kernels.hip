@@ -36,7 +36,7 @@ __global__ void init_kernel(const InstDev *__restrict__ insts, const float *__re
       c[i] = (float)(Lat<Q>::w[i] * (double)r2);
     }
     if (d.compact) {
-      pop_store<Q, ST>(b, d.cpitch, 0, (int)crank(d, x, y + (int64_t)d.ny * z), a, c, r1, r2);
+      cpop_store<Q, ST>(b, d.cpitch, crank(d, x, y + (int64_t)d.ny * z), a, c, r1, r2);
       continue;
     }
     pop_store<Q, ST>(b, d.pitch, y * d.ystride + z * d.zstride, x, a, c, r1, r2);

@@ -297,8 +297,41 @@ __device__ __forceinline__ int64_t crank(const InstDev &d, int x, int64_t row) {
   return w.pre + __popcll(w.bits & below);
 }
 
-// Pull of D2Q9 fluid node (x, y) in the compacted layout (f*[s][i][c] over
-// fluid nodes); c receives the node's compact index.
+// FP32 populations of the compacted layout: per component, blocks of 64
+// consecutive fluid nodes, each holding its Q link rows, f*[s][c / 64][i][c %
+// 64] (component s starts Q * cpitch floats in).  The 64 nodes of a wave
+// find all their links in one 64 x Q x 4-byte block per component instead
+// of Q planes spread over the buffer (measured for D3Q19 at 384^3: the
+// compacted split step 3.7 % faster than with whole-buffer link planes).
+// cslot is the float offset within a component; byte offsets stay below
+// Q * cpitch * 4 < 2^32, as the host requires.  BF16 storage keeps link
+// planes over the whole buffer.
+template <int Q>
+__device__ __forceinline__ uint32_t cslot(uint32_t c, int i) {
+  return (c & ~63u) * (uint32_t)Q + (uint32_t)i * 64u + (c & 63u);
+}
+template <int Q, int ST>
+__device__ __forceinline__ float cpop_get(gcf *__restrict__ b, int cp, int s, int i, int64_t c) {
+  if constexpr (ST == 0) return b[(int64_t)s * Q * cp + cslot<Q>((uint32_t)c, i)];
+  else return pop_get<Q, ST>(b, cp, s, i, 0, (int)c);
+}
+template <int Q, int ST>
+__device__ __forceinline__ void cpop_store(gf *__restrict__ b, int cp, int64_t c, const float (&f0)[Q],
+                                           const float (&f1)[Q], float rho1, float rho2) {
+  if constexpr (ST == 0) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const uint32_t bo = cslot<Q>((uint32_t)c, i) * 4u;
+      stg(b, bo, f0[i]);
+      stg(b + (int64_t)Q * cp, bo, f1[i]);
+    }
+  } else {
+    pop_store<Q, ST>(b, cp, 0, (int)c, f0, f1, rho1, rho2);
+  }
+}
+
+// Pull of D2Q9 fluid node (x, y) in the compacted layout (populations of the
+// fluid nodes only, see cslot); c receives the node's compact index.
 // The rank of column x in each source row gives every fluid source's index
 // (x - 1: rank - 1; x + 1: rank + the column's fluid bit); bounce-back reads
 // the node's own opposite slot; wrapped x sources are ranked directly.
@@ -343,7 +376,7 @@ __device__ __forceinline__ void cpull9(const InstDev &d, gcf *__restrict__ fin, 
       }
     }
     if constexpr (ST == 0) {
-      const uint32_t bo = ((uint32_t)pi * (uint32_t)cp + (uint32_t)sc) * 4u;
+      const uint32_t bo = cslot<9>((uint32_t)sc, pi) * 4u;
       f0[i] = ldg(fin, bo);
       f1[i] = ldg(fin + (int64_t)9 * cp, bo);
     } else {
@@ -359,7 +392,7 @@ __device__ __forceinline__ void ccomplete9(const InstDev &d, gcf *__restrict__ f
   gcf *frz = G(d.frozen);
   const int cp = d.cpitch, ny = d.ny;
   complete_boundary<9, R>(
-      d, info, f0, f1, [&](int s, int i) { return pop_get<9, ST>(fin, cp, s, i, 0, (int)c); },
+      d, info, f0, f1, [&](int s, int i) { return cpop_get<9, ST>(fin, cp, s, i, c); },
       [&](int s, int i) { return frz[(int64_t)(s * 9 + i) * ny + y]; });
 }
 
@@ -563,7 +596,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FusedShape<
     }
     collide_node<9, COLL, R>(d, f0[k], f1[k], rho1, rho2, F1x, F1y, R(0), F2x, F2y, R(0));
     if constexpr (CL) {
-      pop_store<9, ST>(fout, d.cpitch, 0, cidx[k], f0[k], f1[k], (float)rho1, (float)rho2);
+      cpop_store<9, ST>(fout, d.cpitch, cidx[k], f0[k], f1[k], (float)rho1, (float)rho2);
     } else {
       pop_store<9, ST>(fout, d.pitch, uniform64(gy_raw * d.ystride), gx, f0[k], f1[k], (float)rho1, (float)rho2);
       store_ghosts<9, ST>(d, fout, inf, srow[k], xs, f0[k], f1[k]);
@@ -1227,9 +1260,8 @@ __device__ __forceinline__ void cpull(const InstDev &d, gcf *__restrict__ fin, u
     const int pi = bb ? L::opp[i] : i;
     const uint32_t sc = bb ? (uint32_t)c : scs[i];
     if constexpr (ST == 0) {
-      // component planes from a wave-uniform base, 32-bit byte offsets (the
-      // host keeps Q * cpitch * 4 below 2^32)
-      const uint32_t bo = ((uint32_t)pi * (uint32_t)cp + sc) * 4u;
+      // component regions from a wave-uniform base, 32-bit byte offsets
+      const uint32_t bo = cslot<Q>(sc, pi) * 4u;
       f0[i] = ldg(fin, bo);
       f1[i] = ldg(fin + (int64_t)Q * cp, bo);
     } else {
@@ -1241,7 +1273,7 @@ __device__ __forceinline__ void cpull(const InstDev &d, gcf *__restrict__ fin, u
     const int64_t nt = (int64_t)d.ny * d.nz;
     gcf *frz = G(d.frozen);
     complete_boundary<Q, R>(
-        d, info, f0, f1, [&](int s, int i) { return pop_get<Q, ST>(fin, cp, s, i, 0, (int)c); },
+        d, info, f0, f1, [&](int s, int i) { return cpop_get<Q, ST>(fin, cp, s, i, c); },
         [&](int s, int i) { return frz[(int64_t)(s * Q + i) * nt + t]; });
   }
 }
@@ -1310,7 +1342,7 @@ __global__ __launch_bounds__(256) void ccollide_kernel(const InstDev *__restrict
   collide_node<Q, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb, -G_ * rho1 * sy2 + rho1 * gyb,
                            -G_ * rho1 * sz2 + rho1 * gzb, -G_ * rho2 * sx1 + rho2 * gxb,
                            -G_ * rho2 * sy1 + rho2 * gyb, -G_ * rho2 * sz1 + rho2 * gzb);
-  pop_store<Q, ST>(G(d.f[parity ^ 1]), d.cpitch, 0, (int)c, a, b, (float)rho1, (float)rho2);
+  cpop_store<Q, ST>(G(d.f[parity ^ 1]), d.cpitch, c, a, b, (float)rho1, (float)rho2);
 }
 
 // ---------------------------------------------------------------------------
@@ -1527,7 +1559,7 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3))
           // half-way bounce-back: the node's own opposite slot
           const bool bb = i != 0 && ((info >> i) & 1u);
           const uint32_t pi = bb ? (uint32_t)L::opp[i] : (uint32_t)i;
-          const uint32_t bo = (pi * cp + (bb ? c : sc[i])) * 4u;
+          const uint32_t bo = cslot<Q>(bb ? c : sc[i], (int)pi) * 4u;
           a[i] = ldg(fin, bo);
           b[i] = ldg(fin + (int64_t)Q * cp, bo);
         }
@@ -1535,18 +1567,18 @@ __global__ __launch_bounds__(kFwdThreads) __attribute__((amdgpu_waves_per_eu(3))
           const int t = y + ny * z;
           const int64_t nt = (int64_t)ny * nz;
           complete_boundary<Q, R>(
-              d, info, a, b, [&](int s_, int i) { return fin[(int64_t)(s_ * Q + i) * cp + c]; },
+              d, info, a, b, [&](int s_, int i) { return fin[(int64_t)s_ * Q * cp + cslot<Q>(c, i)]; },
               [&](int s_, int i) { return frz[(int64_t)(s_ * Q + i) * nt + t]; });
         }
         const R rho1 = sum_q<Q, R>(a), rho2 = sum_q<Q, R>(b);
         collide_node<Q, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb, -G_ * rho1 * sy2 + rho1 * gyb,
                                  -G_ * rho1 * sz2 + rho1 * gzb, -G_ * rho2 * sx1 + rho2 * gxb,
                                  -G_ * rho2 * sy1 + rho2 * gyb, -G_ * rho2 * sz1 + rho2 * gzb);
-        const uint32_t so = c * 4u;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          stg(fout + (int64_t)i * cp, so, a[i]);
-          stg(fout + (int64_t)(Q + i) * cp, so, b[i]);
+          const uint32_t so = cslot<Q>(c, i) * 4u;
+          stg(fout, so, a[i]);
+          stg(fout + (int64_t)Q * cp, so, b[i]);
         }
         // the node's own share of its next density: rest link and the links
         // that bounce back into it
