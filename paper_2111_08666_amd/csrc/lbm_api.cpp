@@ -45,7 +45,7 @@ struct Layout {
   bool compact;
   int64_t nf, nsolid;
   int32_t cpitch;
-  size_t cword_bytes, ckey_bytes, cbnd_bytes, cedge_bytes;
+  size_t cword_bytes, ckey_bytes, cbnd_bytes, cedge_bytes;  // cinfo: ckey_bytes
 };
 
 // Fused-kernel tiling of one instance for a tile height (D2Q9) / fixed 3D tile.
@@ -430,7 +430,7 @@ size_t batch_bytes(int32_t k, const lbm_geometry *g, const lbm_params *p, int64_
     nb += std::max(make_tiling(g[i].q, g[i].nx, g[i].ny, g[i].nz, 8).blocks,
                    make_tiling(g[i].q, g[i].nx, g[i].ny, g[i].nz, 8, LBM_COMPACT_FUSED).blocks);
     bytes += L.info_bytes + L.frozen_bytes + L.psi_bytes + 2 * L.buf_bytes;
-    if (L.compact) bytes += L.cword_bytes + L.ckey_bytes + L.cbnd_bytes + L.cedge_bytes;
+    if (L.compact) bytes += L.cword_bytes + 2 * L.ckey_bytes + L.cbnd_bytes + L.cedge_bytes;
     InstDev tmp{};
     tmp.nx = g[i].nx; tmp.ny = g[i].ny; tmp.nz = g[i].nz;
     ob = std::max(ob, obs_blocks(tmp));
@@ -588,6 +588,7 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
       h.cpitch = L.cpitch;
       h.cword = reinterpret_cast<const RowWord *>(take(L.cword_bytes));
       h.ckey = reinterpret_cast<const uint32_t *>(take(L.ckey_bytes));
+      h.cinfo = reinterpret_cast<const uint32_t *>(take(L.ckey_bytes));
       h.cbnd = reinterpret_cast<const uint32_t *>(take(L.cbnd_bytes));
       if (L.cedge_bytes) h.cedge = reinterpret_cast<const uint32_t *>(take(L.cedge_bytes));
       build_compact(g[i], L, info, cw, ck, cb, p[i].tile_rows);
@@ -595,9 +596,15 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
       h.nbnd = (int64_t)cb.size();
       HIPCHK(b, hipMemcpyAsync((void *)h.cword, cw.data(), sizeof(RowWord) * cw.size(), hipMemcpyHostToDevice,
                                b->stream));
-      if (!ck.empty())
+      if (!ck.empty()) {
         HIPCHK(b, hipMemcpyAsync((void *)h.ckey, ck.data(), sizeof(uint32_t) * ck.size(), hipMemcpyHostToDevice,
                                  b->stream));
+        std::vector<uint32_t> ci(ck.size());
+        for (size_t c = 0; c < ck.size(); ++c) ci[c] = info[ck[c]];
+        HIPCHK(b, hipMemcpyAsync((void *)h.cinfo, ci.data(), sizeof(uint32_t) * ci.size(), hipMemcpyHostToDevice,
+                                 b->stream));
+        HIPCHK(b, hipStreamSynchronize(b->stream));  // ci is freed at the end of this block
+      }
       if (!cb.empty())
         HIPCHK(b, hipMemcpyAsync((void *)h.cbnd, cb.data(), sizeof(uint32_t) * cb.size(), hipMemcpyHostToDevice,
                                  b->stream));

@@ -50,11 +50,12 @@ struct InstDev {
   double tau1, tau2, G, chi1, chi2, gx, gy, gz;
   double rho_in1, rho_out2, rho_in2, rho_out1;
   double lambda, s_e, s_eps;
-  // compacted layout (compact != 0): the dense row block's planes over the
-  // compact index c (cpitch entries each): FP32 f[s][i][c]; BF16 (rho1, rho2)
-  // pairs, then deviation words
+  // compacted layout (compact != 0), over the compact index c (cpitch
+  // entries per link): FP32 f[s][c / 64][i][c % 64]; BF16 the dense row
+  // block's planes, (rho1, rho2) pairs, then deviation words
   const RowWord *cword;   // [ny * nz][pitch / 64]
   const uint32_t *ckey;   // [nf]: dense node index x + pitch * (y + ny * z) of compact node c
+  const uint32_t *cinfo;  // [nf]: node info word of compact node c
   const uint32_t *cbnd;   // [nbnd]: dense index of each solid node with a fluid neighbour
   const uint32_t *cedge;  // [nedge]: compact indices of the fluid nodes whose next-step
                           // densities the compacted 3D fused step leaves to a pull

@@ -1295,7 +1295,7 @@ __global__ __launch_bounds__(256) void crho_kernel(const InstDev *__restrict__ i
   const uint32_t key = gld32(d.ckey, c);
   int x, y, z;
   ckey_xyz(d, key, x, y, z);
-  const uint32_t info = ((gcu32 *)d.info)[key];
+  const uint32_t info = gld32(d.cinfo, c);
   float a[Q], b[Q];
   cgather<Q, ST, double>(d, G(d.f[parity]), info, x, y, z, c, a, b);
   psi32(d, 0)[key] = v2f{(float)sum_q<Q, double>(a), (float)sum_q<Q, double>(b)};
@@ -1323,7 +1323,7 @@ __global__ __launch_bounds__(256) void ccollide_kernel(const InstDev *__restrict
   const uint32_t key = gld32(d.ckey, c);
   int x, y, z;
   ckey_xyz(d, key, x, y, z);
-  const uint32_t info = ((gcu32 *)d.info)[key];
+  const uint32_t info = gld32(d.cinfo, c);
   // the neighbours' psi and the source ranks' row words depend only on the
   // node's position: both are in flight in one round trip
   v2f pv[Q];
@@ -1655,7 +1655,7 @@ __global__ __launch_bounds__(256) void fwd_rho_kernel(const InstDev *__restrict_
   const uint32_t key = gld32(d.ckey, c);
   int x, y, z;
   ckey_xyz(d, key, x, y, z);
-  const uint32_t info = ((gcu32 *)d.info)[key];
+  const uint32_t info = gld32(d.cinfo, c);
   float a[Q], b[Q];
   cgather<Q, 0, double>(d, G(d.f[parity]), info, x, y, z, c, a, b);
   psi32(d, parity)[key] = v2f{(float)sum_q<Q, double>(a), (float)sum_q<Q, double>(b)};
