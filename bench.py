@@ -99,16 +99,20 @@ def time_steps(torch, solver, steps, warmup, chunk, eager):
         if n - full * chunk:
             solver.step(n - full * chunk)
 
-    run(warmup)
-    torch.cuda.synchronize()
+    from paper_2111_08666_amd.roctx import rng
+    with rng(f"warmup {warmup} steps"):
+        run(warmup)
+        torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    e0.record(solver.stream)
-    run(steps)
-    e1.record(solver.stream)
-    torch.cuda.synchronize()
-    return time.perf_counter() - t0, e0.elapsed_time(e1)
+    with rng(f"timed {steps} steps"):
+        t0 = time.perf_counter()
+        e0.record(solver.stream)
+        run(steps)
+        e1.record(solver.stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+    return wall, e0.elapsed_time(e1)
 
 
 def side_line(torch, lbm, name, args, dev, steps, warmup, chunk, math=None):
@@ -171,6 +175,7 @@ def main():
 
     import torch
     from paper_2111_08666_amd import lbm
+    from paper_2111_08666_amd.roctx import rng
 
     dev = torch.device("cuda:0")
     chunk = max(2, args.chunk - args.chunk % 2)
@@ -191,9 +196,11 @@ def main():
         n_nodes, n_fluid, q = problem.n_nodes, problem.n_fluid, problem.q
     tune = None
     if not args.no_autotune and args.strategy == 0:
-        tune = solver.autotune(10)
+        with rng("autotune"):
+            tune = solver.autotune(10)
         print("[bench] autotune:\n" + tune, file=sys.stderr, flush=True)
-    wall, ev_ms = time_steps(torch, solver, args.steps, args.warmup, chunk, args.eager)
+    with rng(f"workload {args.workload}"):
+        wall, ev_ms = time_steps(torch, solver, args.steps, args.warmup, chunk, args.eager)
     ms_per_step = wall * 1e3 / args.steps
     print(f"[bench] timed {args.steps} steps: {ms_per_step:.4f} ms/step", file=sys.stderr, flush=True)
 
@@ -250,7 +257,8 @@ def main():
             if name == args.workload:
                 continue
             print(f"[bench] side workload {name}", file=sys.stderr, flush=True)
-            side[name] = side_line(torch, lbm, name, args, dev, steps, max(10, steps // 10), chunk)
+            with rng(f"side workload {name}"):
+                side[name] = side_line(torch, lbm, name, args, dev, steps, max(10, steps // 10), chunk)
         other = 1 - args.math
         print(f"[bench] side: {args.workload} with {'FP64' if other else 'FP32'} node arithmetic",
               file=sys.stderr, flush=True)
@@ -266,12 +274,14 @@ def main():
             cpu_problem = sorted(problems, key=lambda p: p.n_nodes)[len(problems) // 2]
         else:
             sample, cpu_problem = "the same workload", problem
-        out["cpu_baseline"] = cpu_baseline(cpu_problem, sample)
+        with rng("cpu baseline (oracle)"):
+            out["cpu_baseline"] = cpu_baseline(cpu_problem, sample)
     if not args.no_warm_start:
         # after the timed region: held-out instances run to steady state from
         # the cold start and from the trained network's prediction
         from paper_2111_08666_amd import bench_warmstart
-        w = bench_warmstart.measure(log=lambda m: print(m, file=sys.stderr, flush=True))
+        with rng("time to steady state"):
+            w = bench_warmstart.measure(log=lambda m: print(m, file=sys.stderr, flush=True))
         out["time_to_steady"] = bench_warmstart.summary(w)
     print(json.dumps(out), flush=True)
 

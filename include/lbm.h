@@ -208,6 +208,18 @@ lbm_status lbm_get_density(lbm_ctx *ctx, float *dst, int32_t dst_is_device);
 lbm_status lbm_init_from_saturation(lbm_ctx *ctx, const float *sat, int32_t sat_is_device, double threshold,
                                     double rho_major, double rho_minor);
 
+/* Debug aid for tests of failure handling (it computes nothing of the
+ * paper): overwrite one stored value of fluid node (x, y, z) in the current
+ * state, the post-collision populations the next step streams.  FP32
+ * storage: population f*_i of component s (0 or 1), i in [0, q).  BF16-
+ * deviation storage: the node's FP32 density word of component s, from
+ * which every population of that node and component is rebuilt (i is
+ * checked but not used).  A NaN makes the next observables report
+ * LBM_EUNSTABLE without any device fault.  LBM_EINVAL for a NULL handle, a
+ * node outside the grid or solid, or s or i out of range.  Synchronises
+ * the stream. */
+lbm_status lbm_debug_poke(lbm_ctx *ctx, int32_t x, int32_t y, int32_t z, int32_t s, int32_t i, float value);
+
 /* Checkpoint: all state needed to continue bit-identically.  With
  * host_blob = NULL, *bytes receives the size.  Both synchronise. */
 lbm_status lbm_save(lbm_ctx *ctx, void *host_blob, size_t *bytes);

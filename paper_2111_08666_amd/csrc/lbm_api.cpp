@@ -930,6 +930,23 @@ lbm_status lbm_load(lbm_ctx *ctx, const void *host_blob, size_t bytes) {
   return LBM_OK;
 }
 
+lbm_status lbm_debug_poke(lbm_ctx *ctx, int32_t x, int32_t y, int32_t z, int32_t s, int32_t i, float value) {
+  if (!ctx) return fail(nullptr, LBM_EINVAL, "NULL handle");
+  lbm_batch *b = ctx->b;
+  const InstDev &h = b->h[0];
+  if (x < 0 || x >= h.nx || y < 0 || y >= h.ny || z < 0 || z >= h.nz)
+    return fail(b, LBM_EINVAL, "node outside the grid");
+  if (s < 0 || s > 1 || i < 0 || i >= h.q) return fail(b, LBM_EINVAL, "component must be 0 or 1, link in [0, q)");
+  int32_t *status = reinterpret_cast<int32_t *>(b->result);
+  HIPCHK(b, launch_poke(b->d_insts, h, b->parity, x, y, z, s, i, value, status, b->stream));
+  int32_t st = -1;
+  HIPCHK(b, hipMemcpyAsync(&st, status, sizeof st, hipMemcpyDeviceToHost, b->stream));
+  HIPCHK(b, hipStreamSynchronize(b->stream));
+  if (st != 0) return fail(b, LBM_EINVAL, "node is solid");
+  b->psi_valid = false;  // the carried psi followed the old value
+  return LBM_OK;
+}
+
 lbm_status lbm_init_from_saturation(lbm_ctx *ctx, const float *sat, int32_t sat_is_device, double threshold,
                                     double rho_major, double rho_minor) {
   if (!ctx || !sat) return fail(nullptr, LBM_EINVAL, "NULL argument");

@@ -69,6 +69,8 @@ constexpr int kObsFields = 12;  // mass0 mass1 nfluid nwin swcount sumrw sumr pi
 // Launchers (defined in the .hip sources).
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, const float *rho0_dev,
                        int parity, hipStream_t s);
+hipError_t launch_poke(const InstDev *d_inst, const InstDev &h, int parity, int x, int y, int z, int s, int i,
+                       float v, int32_t *status, hipStream_t st);
 // Rest equilibria of densities set from a saturation field (device, one
 // float per node): (major, minor) where sat > thr, (minor, major) elsewhere.
 hipError_t launch_init_sat(const InstDev *d_inst, const InstDev &h_inst, const float *sat_dev, float thr,

@@ -213,6 +213,43 @@ hipError_t launch_init_sat(const InstDev *d_inst, const InstDev &h, const float 
   return hipGetLastError();
 }
 
+// One thread: overwrite one stored value of fluid node (x, y, z) in buffer
+// `parity` (population s, i with FP32 storage; the density word of component
+// s with BF16-deviation storage).  status: 0 written, 1 a solid node.
+template <int Q, int ST>
+__global__ void poke_kernel(const InstDev *__restrict__ insts, int parity, int x, int y, int z, int s, int i,
+                            float v, int32_t *__restrict__ status) {
+  const InstDev &d = insts[0];
+  const int64_t row = y + (int64_t)d.ny * z;
+  if (d.info[x + (int64_t)d.pitch * row] & kSolid) {
+    *status = 1;
+    return;
+  }
+  float *b = d.f[parity];
+  if (d.compact) {
+    const int64_t c = crank(d, x, row);
+    if constexpr (ST == 0) b[(int64_t)s * Q * d.cpitch + cslot<Q>((uint32_t)c, i)] = v;
+    else b[2 * c + s] = v;
+  } else {
+    const int64_t rb = y * d.ystride + z * d.zstride;
+    if constexpr (ST == 0) b[rb + (int64_t)(s * Q + i) * d.pitch + x] = v;
+    else b[rb + 2 * (int64_t)x + s] = v;
+  }
+  *status = 0;
+}
+
+hipError_t launch_poke(const InstDev *d_inst, const InstDev &h, int parity, int x, int y, int z, int s, int i,
+                       float v, int32_t *status, hipStream_t st) {
+  if (h.q == 9) {
+    if (h.storage == 0) poke_kernel<9, 0><<<1, 1, 0, st>>>(d_inst, parity, x, y, z, s, i, v, status);
+    else poke_kernel<9, 1><<<1, 1, 0, st>>>(d_inst, parity, x, y, z, s, i, v, status);
+  } else {
+    if (h.storage == 0) poke_kernel<19, 0><<<1, 1, 0, st>>>(d_inst, parity, x, y, z, s, i, v, status);
+    else poke_kernel<19, 1><<<1, 1, 0, st>>>(d_inst, parity, x, y, z, s, i, v, status);
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_step_srt(const StepLaunch &L, hipStream_t s);
 hipError_t launch_step_mrt(const StepLaunch &L, hipStream_t s);
 hipError_t launch_step_trt(const StepLaunch &L, hipStream_t s);

@@ -22,7 +22,8 @@ AUTO, FUSED, SPLIT, COMPACT, FUSED_LIST, COMPACT_FUSED = 0, 1, 2, 3, 4, 5
 
 EXPORTS = [
     "lbm_workspace_bytes", "lbm_create", "lbm_set_bc", "lbm_step", "lbm_step_graph",
-    "lbm_observables", "lbm_get_density", "lbm_init_from_saturation", "lbm_save", "lbm_load", "lbm_get_step",
+    "lbm_observables", "lbm_get_density", "lbm_init_from_saturation", "lbm_debug_poke", "lbm_save", "lbm_load",
+    "lbm_get_step",
     "lbm_destroy", "lbm_last_error", "lbm_kernel_info", "lbm_autotune", "lbm_batch_workspace_bytes",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_step_graph", "lbm_batch_observables",
     "lbm_batch_get_density", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_kernel_info",
@@ -94,6 +95,7 @@ def lib():
         L.lbm_save.argtypes = [vp, vp, C.POINTER(sz)]
         L.lbm_load.argtypes = [vp, vp, sz]
         L.lbm_init_from_saturation.argtypes = [vp, vp, i32, C.c_double, C.c_double, C.c_double]
+        L.lbm_debug_poke.argtypes = [vp, i32, i32, i32, i32, i32, C.c_float]
         L.lbm_get_step.restype = i64
         L.lbm_get_step.argtypes = [vp]
         L.lbm_destroy.argtypes = [vp]
@@ -272,6 +274,12 @@ class Solver:
             if a.shape != tuple(self.shape):
                 raise ValueError(f"saturation shape {a.shape} != grid {self.shape}")
             self._chk(lib().lbm_init_from_saturation(self._h, a.ctypes.data, 0, float(threshold), major, minor))
+
+    def debug_poke(self, x, y, z, s, i, value):
+        """Overwrite one stored value of fluid node (x, y, z) (lbm_debug_poke):
+        population i of component s with FP32 storage, the component's density
+        word with BF16-deviation storage."""
+        self._chk(lib().lbm_debug_poke(self._h, int(x), int(y), int(z), int(s), int(i), float(value)))
 
     def density_device(self, out=None):
         import torch

@@ -88,6 +88,13 @@ def test_init_from_saturation_refuses_null_arguments():
     assert L.lbm_init_from_saturation(None, fake, 1, 0.5, 1.0, 0.027) == lbm.LBM_EINVAL
 
 
+def test_debug_poke_refuses_a_null_handle():
+    """The failure-injection entry point checks its handle before any device
+    work."""
+    L = lbm.lib()
+    assert L.lbm_debug_poke(None, 0, 0, 0, 0, 0, float("nan")) == lbm.LBM_EINVAL
+
+
 def test_workspace_query_and_validation_without_device():
     p = I.drainage_2d(nx=64, ny=32, r=(2.0, 4.0), porosity=0.8, seed=1)
     assert lbm.workspace_bytes(p) > 2 * 2 * 9 * 64 * 32 * 4
