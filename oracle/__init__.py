@@ -27,7 +27,7 @@ class OraParams(C.Structure):
         ("rho_in2", C.c_double), ("rho_out1", C.c_double),
         ("g", C.c_double * 3), ("lam", C.c_double),
         ("s_e", C.c_double), ("s_eps", C.c_double),
-        ("eq26_mode", C.c_int32), ("pad_", C.c_int32),
+        ("eq26_mode", C.c_int32), ("ivsd_frozen", C.c_int32),
     ]
 
 
@@ -93,14 +93,14 @@ def make_params(problem=None, **kw) -> OraParams:
                  mrt_sj_mode=p.mrt_sj_mode, tau=p.tau, G=p.G, xi=p.xi,
                  rho_in1=p.rho_in1, rho_out2=p.rho_out2, rho_in2=p.rho_in2,
                  rho_out1=p.rho_out1, g=p.g, lam=p.lam, s_e=p.s_e, s_eps=p.s_eps,
-                 eq26_mode=p.eq26_mode)
+                 eq26_mode=p.eq26_mode, ivsd_frozen=p.ivsd_frozen)
     d.update(kw)
     P = OraParams()
     defaults = dict(q=9, nx=1, ny=1, nz=1, periodic=0, open_x=0, porous_x0=0, porous_x1=0,
                     bc_set=3, collision=0, half_force_shift=1, mrt_sj_mode=0,
                     tau=(1.0, 1.0), G=0.0, xi=0.0, rho_in1=1.0, rho_out2=1.0,
                     rho_in2=0.0, rho_out1=0.0, g=(0.0, 0.0, 0.0), lam=3.0 / 16.0,
-                    s_e=1.0, s_eps=1.0, eq26_mode=0)
+                    s_e=1.0, s_eps=1.0, eq26_mode=0, ivsd_frozen=0)
     defaults.update(d)
     for k, v in defaults.items():
         if k == "tau":

@@ -371,6 +371,7 @@ struct ora_sim {
   double *psi;    /* [2][N] */
   double *F;      /* [2][3][N] */
   double *frozen; /* [2][q][ny*nz]: [0] comp-1 at outlet, [1] comp-2 at inlet */
+  double *psi0;   /* [2][N]: Eq. 17 on the initial densities (ivsd_frozen) */
   double flux_in[2], flux_out[2];
   int64_t step;
 };
@@ -421,6 +422,8 @@ static void set_err(char *err, const char *msg) {
   if (err) snprintf(err, 256, "%s", msg);
 }
 
+static void solid_psi(const ora_sim *s, int64_t n, const double *rho, double *psi1, double *psi2);
+
 ora_sim *ora_create(const ora_params *p, const uint8_t *solid, const double *rho0, char *err) {
   lattice L;
   if (make_lattice(p->q, &L)) { set_err(err, "q must be 9 or 19"); return NULL; }
@@ -437,6 +440,7 @@ ora_sim *ora_create(const ora_params *p, const uint8_t *solid, const double *rho
   }
   if (p->bc_set < 1 || p->bc_set > 3) { set_err(err, "bc_set must be 1, 2 or 3"); return NULL; }
   if (p->eq26_mode != 0 && p->eq26_mode != 1) { set_err(err, "eq26_mode must be 0 or 1"); return NULL; }
+  if (p->ivsd_frozen != 0 && p->ivsd_frozen != 1) { set_err(err, "ivsd_frozen must be 0 or 1"); return NULL; }
 
   ora_sim *s = (ora_sim *)calloc(1, sizeof(ora_sim));
   s->p = *p;
@@ -479,6 +483,7 @@ ora_sim *ora_create(const ora_params *p, const uint8_t *solid, const double *rho
   s->psi = (double *)calloc((size_t)(2 * N), sizeof(double));
   s->F = (double *)calloc((size_t)(6 * N), sizeof(double));
   s->frozen = (double *)calloc((size_t)(2 * q * s->ny * s->nz), sizeof(double));
+  s->psi0 = (double *)calloc((size_t)(2 * N), sizeof(double));
 
   /* READING (initial state): the given densities are placed as rest
    * equilibria w_i rho0 in the post-collision field, so the first step
@@ -499,6 +504,11 @@ ora_sim *ora_create(const ora_params *p, const uint8_t *solid, const double *rho
         FRZ(s, 1, i, t) = L.w[i] * rho0[N + ni];
       }
     }
+  /* Eq. 17, READING "frozen" (ivsd_frozen = 1): evaluated once, on the
+   * initial densities, and used at every step. */
+  if (p->ivsd_frozen)
+    for (int64_t n = 0; n < N; ++n)
+      if (solid[n]) solid_psi(s, n, rho0, &s->psi0[n], &s->psi0[N + n]);
   s->step = 0;
   return s;
 }
@@ -506,7 +516,7 @@ ora_sim *ora_create(const ora_params *p, const uint8_t *solid, const double *rho
 void ora_destroy(ora_sim *s) {
   if (!s) return;
   free(s->solid); free(s->fs); free(s->f); free(s->rho); free(s->psi);
-  free(s->F); free(s->frozen); free(s);
+  free(s->F); free(s->frozen); free(s->psi0); free(s);
 }
 
 void ora_set_bc(ora_sim *s, double rho_in1, double rho_out2) {
@@ -599,31 +609,41 @@ static void moments(ora_sim *s) {
     }
 }
 
-/* Eqs. 16-17 (IVSD): at a solid node the pseudopotential is the virtual
- * density chi^s * (w-weighted mean of rho^s over in-domain fluid neighbours).
- * READING: recomputed every step from the current densities; a solid node
- * with no fluid neighbour gets 0 (it never enters a fluid node's force).
- * At fluid nodes psi = rho (Sec. 2.1). */
-static void pseudopotential(ora_sim *s) {
+/* Eqs. 16-17 (IVSD): at a solid node n the pseudopotential is the virtual
+ * density chi^s * (w-weighted mean of rho^s over in-domain fluid neighbours),
+ * here of the density field rho ([2][N]).  A solid node with no fluid
+ * neighbour gets 0 (it never enters a fluid node's force). */
+static void solid_psi(const ora_sim *s, int64_t n, const double *rho, double *psi1, double *psi2) {
   const lattice *L = &s->L;
   const double chi[2] = {1.0 + s->p.xi, 1.0 - s->p.xi};
+  int x, y, z;
+  coords(s, n, &x, &y, &z);
+  double num[2] = {0.0, 0.0}, den = 0.0;
+  for (int i = 1; i < L->q; ++i) {
+    int64_t nb;
+    if (neighbor(s, x, y, z, L->e[i][0], L->e[i][1], L->e[i][2], &nb) != 0) continue;
+    if (s->solid[nb]) continue;
+    den += L->w[i];
+    for (int c = 0; c < 2; ++c) num[c] += L->w[i] * rho[(int64_t)c * s->N + nb];
+  }
+  *psi1 = den > 0.0 ? chi[0] * num[0] / den : 0.0;
+  *psi2 = den > 0.0 ? chi[1] * num[1] / den : 0.0;
+}
+
+/* The pseudopotential field: psi = rho at fluid nodes (Sec. 2.1); at solid
+ * nodes Eq. 17, READING: recomputed every step from the current densities
+ * (default), or the values Eq. 17 gave on the initial densities
+ * (ivsd_frozen). */
+static void pseudopotential(ora_sim *s) {
 #pragma omp parallel for schedule(static)
   for (int64_t n = 0; n < s->N; ++n) {
     if (!s->solid[n]) {
       for (int c = 0; c < 2; ++c) PSI(s, c, n) = RHO(s, c, n);
-      continue;
+    } else if (s->p.ivsd_frozen) {
+      for (int c = 0; c < 2; ++c) PSI(s, c, n) = s->psi0[(int64_t)c * s->N + n];
+    } else {
+      solid_psi(s, n, s->rho, &PSI(s, 0, n), &PSI(s, 1, n));
     }
-    int x, y, z;
-    coords(s, n, &x, &y, &z);
-    double num[2] = {0.0, 0.0}, den = 0.0;
-    for (int i = 1; i < L->q; ++i) {
-      int64_t nb;
-      if (neighbor(s, x, y, z, L->e[i][0], L->e[i][1], L->e[i][2], &nb) != 0) continue;
-      if (s->solid[nb]) continue;
-      den += L->w[i];
-      for (int c = 0; c < 2; ++c) num[c] += L->w[i] * RHO(s, c, nb);
-    }
-    for (int c = 0; c < 2; ++c) PSI(s, c, n) = den > 0.0 ? chi[c] * num[c] / den : 0.0;
   }
 }
 

@@ -40,7 +40,9 @@ typedef struct {
   int32_t eq26_mode;        /* reading of Eqs. 26-27: 0 the links hold their initial
                                values; 1 they take the node's own post-collision
                                values (the rule Eq. 28 states for Set-3's inlet) */
-  int32_t pad_;
+  int32_t ivsd_frozen;      /* reading of Eq. 17: 0 the virtual solid density follows
+                               the current fluid densities every step; 1 it is
+                               evaluated once, on the initial densities, and kept */
 } ora_params;
 
 typedef struct {

@@ -236,6 +236,7 @@ class Problem:
     s_e: float = 1.0
     s_eps: float = 1.0
     eq26_mode: int = 0          # Eqs. 26-27: 0 held initial values, 1 own post-collision values
+    ivsd_frozen: int = 0        # Eq. 17: 0 every step, 1 once on the initial densities
     name: str = ""
 
     @property

@@ -106,6 +106,36 @@ def test_ivsd_flat_wall_is_chi_times_density(xi):
     assert np.abs(psi[1, -1] - (1 - xi) * 0.9).max() < 1e-15
 
 
+@pytest.mark.parametrize("frozen", [0, 1])
+def test_ivsd_frozen_reading_keeps_the_initial_values(frozen):
+    """Eq. 17 read as evaluated once on the initial densities (ivsd_frozen)
+    against every step: a channel between flat walls starts uniform at
+    (0.3, 0.9) and is then reset to uniform rest equilibria at (0.7, 0.2).
+    The wall's virtual density must then be chi^s times the new densities
+    when recomputed, and chi^s times the initial ones when frozen; the fluid
+    nodes carry the new densities either way (Sec. 2.1-2.2)."""
+    nx, ny, xi = 6, 8, 0.3
+    mask = np.zeros((ny, nx), np.uint8)
+    mask[0] = mask[-1] = 1
+    rho0 = np.zeros((2, ny, nx))
+    rho0[0], rho0[1] = 0.3, 0.9
+    rho0[:, mask.astype(bool)] = 0
+    P = O.make_params(q=9, nx=nx, ny=ny, periodic=1, G=3.5, xi=xi, ivsd_frozen=frozen)
+    s = O.OracleSim(params=P, mask=mask, rho0=rho0)
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    fs = np.zeros((2, 9, ny, nx))
+    for c, r in enumerate((0.7, 0.2)):
+        fs[c] = w[:, None, None] * r
+    fs[:, :, mask.astype(bool)] = 0
+    s.set_fstar(fs)
+    psi = s.psi()
+    want = (0.3, 0.9) if frozen else (0.7, 0.2)
+    for c, chi in enumerate((1 + xi, 1 - xi)):
+        assert np.abs(psi[c, 0] - chi * want[c]).max() < 1e-15
+        assert np.abs(psi[c, -1] - chi * want[c]).max() < 1e-15
+        assert np.abs(psi[c, 1:-1] - (0.7, 0.2)[c]).max() < 1e-15
+
+
 def test_ivsd_weighted_mean_on_a_corner():
     """A solid node with fluid only at one axis and one diagonal neighbour:
     the weighted mean (w_axis rho_a + w_diag rho_d) / (w_axis + w_diag)."""
