@@ -123,6 +123,12 @@ typedef struct {
                              through collision and streaming: 0 (default) they
                              keep their initial values; 1 they take the node's
                              own post-collision values, the rule of Eq. 28 */
+  int32_t ivsd_frozen;    /* reading of Eq. 17, which the paper also evaluates at
+                             t = 0: 0 (default) the virtual solid density follows
+                             the current fluid densities every step; 1 it is
+                             evaluated once, on the initial densities (those of
+                             lbm_create or lbm_init_from_saturation), and held
+                             (checkpoints carry the held values) */
 } lbm_params;
 
 /* Observables at the current time (Eq. 14 pressure, Sec. 4.2 saturation).

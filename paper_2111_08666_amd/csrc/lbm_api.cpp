@@ -41,6 +41,7 @@ struct Layout {
   int32_t pitch;
   int64_t ystride, zstride, n_nodes;
   size_t buf_bytes, info_bytes, frozen_bytes, psi_bytes;
+  size_t ivsd0_off;  // within the frozen block: the held Eq. 17 values (ivsd_frozen), else 0
   // compacted layout
   bool compact;
   int64_t nf, nsolid;
@@ -138,7 +139,13 @@ Layout make_layout(const lbm_geometry &g, const lbm_params &p) {
   L.zstride = L.ystride * g.ny;
   L.buf_bytes = align_up((size_t)L.zstride * g.nz * sizeof(float));
   L.info_bytes = align_up((size_t)L.pitch * g.ny * g.nz * sizeof(uint32_t));
+  // held values: Eqs. 26-27 links, then (ivsd_frozen) Eq. 17 pairs per node
   L.frozen_bytes = align_up((size_t)2 * g.q * g.ny * g.nz * sizeof(float));
+  L.ivsd0_off = 0;
+  if (p.ivsd_frozen) {
+    L.ivsd0_off = L.frozen_bytes;
+    L.frozen_bytes += align_up((size_t)L.pitch * g.ny * g.nz * 2 * sizeof(float));
+  }
   L.psi_bytes = align_up((size_t)L.pitch * g.ny * g.nz * 2 * 2 * sizeof(float));  // two pair arrays
   L.compact = compact_strategy(resolve_strategy(g, p));
   if (L.compact) {  // validate() keeps q * cpitch * 4 bytes below 2^32
@@ -250,6 +257,7 @@ bool validate(const lbm_geometry *g, const lbm_params *p, const double *rho0, st
   if (p->collision < 0 || p->collision > 2) return bad(err, "collision must be SRT, MRT or TRT");
   if (p->bc_set < 1 || p->bc_set > 3) return bad(err, "bc_set must be 1, 2 or 3");
   if (p->eq26_mode != 0 && p->eq26_mode != 1) return bad(err, "eq26_mode must be 0 or 1");
+  if (p->ivsd_frozen != 0 && p->ivsd_frozen != 1) return bad(err, "ivsd_frozen must be 0 or 1");
   if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_BF16DEV) return bad(err, "unknown storage");
   if (p->math != LBM_MATH_F64 && p->math != LBM_MATH_F32) return bad(err, "unknown math precision");
   if (p->strategy < LBM_AUTO || p->strategy > LBM_COMPACT_FUSED) return bad(err, "unknown strategy");
@@ -559,6 +567,8 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
     InstDev h{};
     h.info = reinterpret_cast<const uint32_t *>(take(L.info_bytes));
     h.frozen = reinterpret_cast<const float *>(take(L.frozen_bytes));
+    h.ivsd0 = L.ivsd0_off ? reinterpret_cast<const float *>(reinterpret_cast<const char *>(h.frozen) + L.ivsd0_off)
+                          : nullptr;
     h.psi = reinterpret_cast<float *>(take(L.psi_bytes));
     h.f[0] = reinterpret_cast<float *>(take(L.buf_bytes));
     h.f[1] = reinterpret_cast<float *>(take(L.buf_bytes));
@@ -634,6 +644,7 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
     HIPCHK(b, hipMemcpyAsync(h.psi, r0.data(), sizeof(float) * r0.size(), hipMemcpyHostToDevice, b->stream));
     HIPCHK(b, hipMemcpyAsync(b->d_insts + i, &b->h.back(), sizeof(InstDev), hipMemcpyHostToDevice, b->stream));
     HIPCHK(b, launch_init(b->d_insts + i, h, h.psi, 0, b->stream));
+    if (h.ivsd0) HIPCHK(b, launch_ivsd_freeze(b->d_insts + i, h, 0, b->stream));
     HIPCHK(b, hipStreamSynchronize(b->stream));  // host staging vectors die here
   }
   // default plan: the split step for D3Q19 (its per-block working set does
@@ -965,6 +976,7 @@ lbm_status lbm_init_from_saturation(lbm_ctx *ctx, const float *sat, int32_t sat_
   }
   HIPCHK(b, launch_init_sat(b->d_insts, h, src, (float)threshold, (float)rho_major, (float)rho_minor, b->parity,
                             b->stream));
+  if (h.ivsd0) HIPCHK(b, launch_ivsd_freeze(b->d_insts, h, b->parity, b->stream));
   if (!sat_is_device) HIPCHK(b, hipStreamSynchronize(b->stream));
   b->psi_valid = false;
   b->unstable = false;

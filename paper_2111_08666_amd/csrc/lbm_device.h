@@ -41,6 +41,8 @@ struct InstDev {
   const uint32_t *info;   // node info words, index x + pitch * (y + ny * z)
   const float *frozen;    // [2][Q][ny*nz]: component-1 outlet / component-2 inlet links
   float *psi;             // two arrays of [nz][ny][pitch] (psi1, psi2) float pairs
+  const float *ivsd0;     // null, or [nz][ny][pitch] (psi1, psi2) pairs: Eq. 17 held from
+                          // the initial densities (frozen reading, ivsd_frozen)
   int64_t ystride, zstride;  // f buffers: row blocks of (y, z) at y * ystride + z * zstride
   int32_t nx, ny, nz, pitch;  // pitch = padded row length (a multiple of 64)
   int32_t periodic, open_x, bc_set, collision;
@@ -69,6 +71,7 @@ constexpr int kObsFields = 12;  // mass0 mass1 nfluid nwin swcount sumrw sumr pi
 // Launchers (defined in the .hip sources).
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, const float *rho0_dev,
                        int parity, hipStream_t s);
+hipError_t launch_ivsd_freeze(const InstDev *d_inst, const InstDev &h, int parity, hipStream_t s);
 hipError_t launch_poke(const InstDev *d_inst, const InstDev &h, int parity, int x, int y, int z, int s, int i,
                        float v, int32_t *status, hipStream_t st);
 // Rest equilibria of densities set from a saturation field (device, one

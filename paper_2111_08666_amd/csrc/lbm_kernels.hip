@@ -213,6 +213,57 @@ hipError_t launch_init_sat(const InstDev *d_inst, const InstDev &h, const float 
   return hipGetLastError();
 }
 
+// Frozen reading of Eq. 17 (ivsd_frozen): the virtual solid density at every
+// solid node next to fluid, from the state just set up (the rest equilibria
+// w_i rho0, whose node sums are the initial densities), held for every step.
+template <int Q, int ST>
+__global__ void ivsd_freeze_kernel(const InstDev *__restrict__ insts, int parity) {
+  const InstDev &d = insts[0];
+  const int64_t n_nodes = (int64_t)d.nx * d.ny * d.nz;
+  gcf *fin = G(d.f[parity]);
+  for (int64_t n = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; n < n_nodes;
+       n += (int64_t)gridDim.x * blockDim.x) {
+    const int x = n % d.nx;
+    const int64_t yz = n / d.nx;
+    const int y = yz % d.ny, z = yz / d.ny;
+    const int64_t pi = x + (int64_t)d.pitch * yz;
+    const uint32_t nb = d.info[pi];
+    if (!(nb & kSolid) || !(nb & kLinkMask)) continue;
+    const v2f v = ivsd_value<Q>(d, x, y, z, nb, [&](int xn, int yn, int zn) {
+      double r1 = 0, r2 = 0;  // the fluid neighbour's own populations
+      if (d.compact) {
+        const int64_t c = crank(d, xn, yn + (int64_t)d.ny * zn);
+        for (int i = 0; i < Q; ++i) {
+          r1 += cpop_get<Q, ST>(fin, d.cpitch, 0, i, c);
+          r2 += cpop_get<Q, ST>(fin, d.cpitch, 1, i, c);
+        }
+      } else {
+        const int64_t row = yn * d.ystride + zn * d.zstride;
+        for (int i = 0; i < Q; ++i) {
+          r1 += pop_get<Q, ST>(fin, d.pitch, 0, i, row, xn);
+          r2 += pop_get<Q, ST>(fin, d.pitch, 1, i, row, xn);
+        }
+      }
+      return v2f{(float)r1, (float)r2};
+    });
+    float *out = const_cast<float *>(d.ivsd0);
+    out[2 * pi] = v.x;
+    out[2 * pi + 1] = v.y;
+  }
+}
+
+hipError_t launch_ivsd_freeze(const InstDev *d_inst, const InstDev &h, int parity, hipStream_t s) {
+  const int g = grid_for((int64_t)h.nx * h.ny * h.nz);
+  if (h.q == 9) {
+    if (h.storage == 0) ivsd_freeze_kernel<9, 0><<<g, 256, 0, s>>>(d_inst, parity);
+    else ivsd_freeze_kernel<9, 1><<<g, 256, 0, s>>>(d_inst, parity);
+  } else {
+    if (h.storage == 0) ivsd_freeze_kernel<19, 0><<<g, 256, 0, s>>>(d_inst, parity);
+    else ivsd_freeze_kernel<19, 1><<<g, 256, 0, s>>>(d_inst, parity);
+  }
+  return hipGetLastError();
+}
+
 // One thread: overwrite one stored value of fluid node (x, y, z) in buffer
 // `parity` (population s, i with FP32 storage; the density word of component
 // s with BF16-deviation storage).  status: 0 written, 1 a solid node.

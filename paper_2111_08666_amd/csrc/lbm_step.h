@@ -60,6 +60,13 @@ typedef float v2f __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) const v2f gcv2f;
 typedef __attribute__((address_space(1))) v2f gv2f;
 
+// The virtual solid density kept for every step under the frozen reading
+// of Eq. 17 (ivsd_frozen: evaluated once, on the initial densities), at
+// dense index pi.
+__device__ __forceinline__ v2f ivsd_held(const InstDev &d, int64_t pi) {
+  return ((gcv2f *)d.ivsd0)[pi];
+}
+
 template <int Q>
 __device__ __forceinline__ float bf16_pop(gcf *__restrict__ b, int pitch, int s, int i, int64_t row, int x,
                                           float r) {
@@ -535,6 +542,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FusedShape<
       continue;
     const uint32_t nb = info[k];
     if (!(nb & kLinkMask)) continue;
+    if (d.ivsd0) {  // frozen reading of Eq. 17: the held value
+      const v2f h = ivsd_held(d, gx + (int64_t)d.pitch * gy[k]);
+      psi[r][lane] = V{(R)h.x, (R)h.y};
+      continue;
+    }
     R s1 = 0, s2 = 0, den = 0;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
@@ -722,6 +734,11 @@ __global__ __launch_bounds__(256) void step_d2q9_list(const InstDev *__restrict_
     }
     if (!row_in[k] || !col_in || !(nb & kSolid) || r < 1 || r > kRH - 2 || lane < 1 || lane > 62) continue;
     if (!(nb & kLinkMask)) continue;
+    if (d.ivsd0) {  // frozen reading of Eq. 17: the held value
+      const v2f h = ivsd_held(d, gx + (int64_t)d.pitch * gy[k]);
+      psi[r][lane] = V{(R)h.x, (R)h.y};
+      continue;
+    }
     R s1 = 0, s2 = 0, den = 0;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
@@ -920,6 +937,11 @@ __global__ __launch_bounds__(256) void step_d3q19(const InstDev *__restrict__ in
       if (!row_in[k] || !col_in || r < 1 || r > kRH3 - 2 || lane < 1 || lane > 62) continue;
       const uint32_t nb = infop[gx + (int64_t)d.pitch * gy[k] + islab * zz];
       if (!(nb & kSolid) || !(nb & kLinkMask)) continue;
+      if (d.ivsd0) {  // frozen reading of Eq. 17: the held value
+        const v2f h = ivsd_held(d, gx + (int64_t)d.pitch * gy[k] + islab * zz);
+        psi[slot][r][lane] = V{(R)h.x, (R)h.y};
+        continue;
+      }
       R s1 = 0, s2 = 0, den = 0;
 #pragma unroll
       for (int i = 1; i < 19; ++i) {
@@ -1103,12 +1125,11 @@ __global__ __launch_bounds__(256) void rho_kernel(const InstDev *__restrict__ in
   psi32(d, 0)[pi] = v2f{(float)sum_q<Q, double>(a), (float)sum_q<Q, double>(b)};
 }
 
-// Virtual solid density (Eq. 17) of solid node (x, y, z), dense index pi,
-// whose fluid neighbours are flagged in nb; fluid density of neighbour
-// x + e_i from dens(i, dense index), summed in FP64.
+// Virtual solid density (Eq. 17) of solid node (x, y, z), whose fluid
+// neighbours are flagged in nb; fluid density of neighbour (xn, yn, zn) from
+// dens(xn, yn, zn), summed in FP64.
 template <int Q, class DensF>
-__device__ __forceinline__ void ivsd_node(const InstDev &d, int x, int y, int z, int64_t pi, uint32_t nb,
-                                          DensF dens) {
+__device__ __forceinline__ v2f ivsd_value(const InstDev &d, int x, int y, int z, uint32_t nb, DensF dens) {
   using L = Lat<Q>;
   int xs[3];
   source_x(d, x, xs);  // xs[1 - e_x]: x + e_x with wrap
@@ -1126,7 +1147,15 @@ __device__ __forceinline__ void ivsd_node(const InstDev &d, int x, int y, int z,
     }
   }
   const double inv = rcp<double>(den);
-  psi32(d, 0)[pi] = v2f{(float)(d.chi1 * s1 * inv), (float)(d.chi2 * s2 * inv)};
+  return v2f{(float)(d.chi1 * s1 * inv), (float)(d.chi2 * s2 * inv)};
+}
+
+// Eq. 17 at solid node (x, y, z), dense index pi, into dense psi array 0
+// (the held value under the frozen reading).
+template <int Q, class DensF>
+__device__ __forceinline__ void ivsd_node(const InstDev &d, int x, int y, int z, int64_t pi, uint32_t nb,
+                                          DensF dens) {
+  psi32(d, 0)[pi] = d.ivsd0 ? ivsd_held(d, pi) : ivsd_value<Q>(d, x, y, z, nb, dens);
 }
 
 template <int Q>
@@ -1674,6 +1703,10 @@ __global__ __launch_bounds__(256) void fwd_ivsd_kernel(const InstDev *__restrict
   ckey_xyz(d, key, x, y, z);
   const uint32_t nb = ((gcu32 *)d.info)[key];
   gv2f *__restrict__ psi = psi32(d, parity);
+  if (d.ivsd0) {
+    psi[key] = ivsd_held(d, key);
+    return;
+  }
   int xs[3];
   source_x(d, x, xs);  // xs[1 - e_x]: x + e_x with wrap
   const int ym = y == 0 ? d.ny - 1 : y - 1, yp = y == d.ny - 1 ? 0 : y + 1;

@@ -45,7 +45,8 @@ class Params(C.Structure):
                 ("half_force_shift", C.c_int32), ("mrt_sj_mode", C.c_int32),
                 ("lam", C.c_double), ("s_e", C.c_double), ("s_eps", C.c_double),
                 ("storage", C.c_int32), ("math", C.c_int32),
-                ("strategy", C.c_int32), ("tile_rows", C.c_int32), ("eq26_mode", C.c_int32)]
+                ("strategy", C.c_int32), ("tile_rows", C.c_int32), ("eq26_mode", C.c_int32),
+                ("ivsd_frozen", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -153,6 +154,7 @@ def make_params(problem, storage=STORE_F32, math=MATH_F32, strategy=AUTO, tile_r
     p.strategy = strategy
     p.tile_rows = tile_rows
     p.eq26_mode = getattr(problem, "eq26_mode", 0)
+    p.ivsd_frozen = getattr(problem, "ivsd_frozen", 0)
     return p
 
 

@@ -22,6 +22,10 @@ hipError_t launch_observables(const InstDev *, const InstDev &, int, double *, i
 }
 hipError_t launch_density(const InstDev *, const InstDev &, int, float *, hipStream_t) { return hipErrorUnknown; }
 hipError_t launch_fwd_rebuild(const InstDev *, const InstDev &, int, hipStream_t) { return hipErrorUnknown; }
+hipError_t launch_ivsd_freeze(const InstDev *, const InstDev &, int, hipStream_t) { return hipErrorUnknown; }
+hipError_t launch_poke(const InstDev *, const InstDev &, int, int, int, int, int, int, float, int32_t *, hipStream_t) {
+  return hipErrorUnknown;
+}
 const char *step_kernel_name(int, int, int, int, int, int) { return "stub"; }
 int obs_blocks(const InstDev &) { return 1; }
 }  // namespace lbm
@@ -84,6 +88,11 @@ int main() {
       }
     c.p.bc_set = 3;
     c.p.eq26_mode = 0;
+    // the frozen reading of Eq. 17 adds its held values to the workspace
+    const size_t dyn = lbm_workspace_bytes(&c.g, &c.p);
+    c.p.ivsd_frozen = 1;
+    EXPECT(lbm_workspace_bytes(&c.g, &c.p) > dyn);
+    c.p.ivsd_frozen = 0;
     // a batch of three copies
     lbm_geometry gs[3] = {c.g, c.g, c.g};
     lbm_params ps[3] = {c.p, c.p, c.p};
@@ -97,6 +106,9 @@ int main() {
     EXPECT(lbm_workspace_bytes(&bad.g, &bad.p) == 0);
     bad = c;
     bad.p.eq26_mode = 2;
+    EXPECT(lbm_workspace_bytes(&bad.g, &bad.p) == 0);
+    bad = c;
+    bad.p.ivsd_frozen = -1;
     EXPECT(lbm_workspace_bytes(&bad.g, &bad.p) == 0);
     bad = c;
     bad.p.strategy = 9;
@@ -124,6 +136,7 @@ int main() {
   // null handles
   EXPECT(lbm_step(nullptr, 1) == LBM_EINVAL);
   EXPECT(lbm_init_from_saturation(nullptr, nullptr, 1, 0.5, 1.0, 0.027) == LBM_EINVAL);
+  EXPECT(lbm_debug_poke(nullptr, 0, 0, 0, 0, 0, 1.0f) == LBM_EINVAL);
   EXPECT(lbm_get_step(nullptr) == -1);
   EXPECT(lbm_destroy(nullptr) == LBM_OK);
   std::printf("api sanitizer driver: %d failed checks\n", fails);

@@ -1,6 +1,7 @@
 /* Sanitizer driver for the FP64 oracle (test infrastructure): runs small
  * D2Q9 and D3Q19 cases through every boundary set, both readings of
- * Eqs. 26-27 and every collision operator, and every read-out, so that an
+ * Eqs. 26-27 and of Eq. 17 and every collision operator, and every read-out,
+ * so that an
  * AddressSanitizer / UndefinedBehaviorSanitizer build sees each code path.
  * Exits 0 when every run stays finite. */
 #include <math.h>
@@ -11,7 +12,8 @@
 
 static unsigned rnd(unsigned *s) { *s = *s * 1103515245u + 12345u; return (*s >> 16) & 0x7fffu; }
 
-static int run_case(int q, int nx, int ny, int nz, int open_x, int bc_set, int eq26, int coll, unsigned seed) {
+static int run_case(int q, int nx, int ny, int nz, int open_x, int bc_set, int eq26, int coll, unsigned seed,
+                    int ivsd_frozen) {
   const int N = nx * ny * nz;
   uint8_t *solid = calloc((size_t)N, 1);
   double *rho0 = calloc((size_t)2 * N, sizeof(double));
@@ -35,7 +37,7 @@ static int run_case(int q, int nx, int ny, int nz, int open_x, int bc_set, int e
   p.bc_set = bc_set; p.collision = coll; p.half_force_shift = 1; p.mrt_sj_mode = 0;
   p.tau[0] = 1.7; p.tau[1] = 0.62; p.G = 3.5; p.xi = -0.3;
   p.rho_in1 = 1.02; p.rho_out2 = 1.0; p.rho_in2 = 0.027; p.rho_out1 = 0.027;
-  p.lambda = 3.0 / 16.0; p.s_e = 1.0; p.s_eps = 1.0; p.eq26_mode = eq26;
+  p.lambda = 3.0 / 16.0; p.s_e = 1.0; p.s_eps = 1.0; p.eq26_mode = eq26; p.ivsd_frozen = ivsd_frozen;
   char err[256];
   ora_sim *sim = ora_create(&p, solid, rho0, err);
   if (!sim) {
@@ -68,10 +70,10 @@ int main(void) {
   int fails = 0;
   for (int coll = 0; coll < 3; ++coll)
     for (int set = 1; set <= 3; ++set)
-      for (int eq26 = 0; eq26 < 2; ++eq26) fails += run_case(9, 40, 18, 1, 1, set, eq26, coll, 7u + set);
-  fails += run_case(9, 24, 20, 1, 0, 3, 0, 2, 3u);
-  for (int coll = 0; coll < 3; ++coll) fails += run_case(19, 20, 12, 10, 1, 3, coll == 1, coll, 11u);
-  fails += run_case(19, 12, 10, 8, 0, 3, 0, 2, 5u);
+      for (int eq26 = 0; eq26 < 2; ++eq26) fails += run_case(9, 40, 18, 1, 1, set, eq26, coll, 7u + set, eq26);
+  fails += run_case(9, 24, 20, 1, 0, 3, 0, 2, 3u, 0);
+  for (int coll = 0; coll < 3; ++coll) fails += run_case(19, 20, 12, 10, 1, 3, coll == 1, coll, 11u, coll == 2);
+  fails += run_case(19, 12, 10, 8, 0, 3, 0, 2, 5u, 1);
   /* building blocks */
   int32_t e[57], opp[19];
   double w[19], feq[19], S[19], u[3] = {0.02, -0.01, 0.005}, Fv[3] = {1e-4, 0, -2e-4};
