@@ -258,6 +258,8 @@ bool validate(const lbm_geometry *g, const lbm_params *p, const double *rho0, st
   if (p->bc_set < 1 || p->bc_set > 3) return bad(err, "bc_set must be 1, 2 or 3");
   if (p->eq26_mode != 0 && p->eq26_mode != 1) return bad(err, "eq26_mode must be 0 or 1");
   if (p->ivsd_frozen != 0 && p->ivsd_frozen != 1) return bad(err, "ivsd_frozen must be 0 or 1");
+  if (p->ivsd_frozen && round_up(g->nx, 64) * (int64_t)g->ny * g->nz >= ((int64_t)1 << 32))
+    return bad(err, "grid too large for the held values of Eq. 17 (32-bit dense index)");
   if (p->storage != LBM_STORE_F32 && p->storage != LBM_STORE_BF16DEV) return bad(err, "unknown storage");
   if (p->math != LBM_MATH_F64 && p->math != LBM_MATH_F32) return bad(err, "unknown math precision");
   if (p->strategy < LBM_AUTO || p->strategy > LBM_COMPACT_FUSED) return bad(err, "unknown strategy");

@@ -521,6 +521,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FusedShape<
       }
       rho1 = sum_q<9, R>(a);
       rho2 = sum_q<9, R>(b);
+    } else if (d.ivsd0 && row_in[k] && col_in && (info[k] & kLinkMask)) {
+      // frozen reading of Eq. 17: the held value (phase 2 then skips)
+      const v2f h = ivsd_held(d, (uint32_t)gx + (uint32_t)d.pitch * (uint32_t)gy[k]);
+      rho1 = (R)h.x;
+      rho2 = (R)h.y;
     }
     psi[rows[k]][lane] = V{rho1, rho2};
     if (k >= KR - KP && k < KR) {
@@ -535,18 +540,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FusedShape<
   __syncthreads();
 
   // Phase 2: psi at solid nodes = chi^s * weighted mean of fluid-neighbour rho^s
+  // (under the frozen reading of Eq. 17 phase 1 has put the held values)
+  const bool held = d.ivsd0 != nullptr;
 #pragma unroll
   for (int k = 0; k <= KR; ++k) {
     const int r = rows[k];
-    if (!row_in[k] || !col_in || !(info[k] & kSolid) || r < 1 || r > kRH - 2 || lane < 1 || lane > 62)
+    if (held || !row_in[k] || !col_in || !(info[k] & kSolid) || r < 1 || r > kRH - 2 || lane < 1 || lane > 62)
       continue;
     const uint32_t nb = info[k];
     if (!(nb & kLinkMask)) continue;
-    if (d.ivsd0) {  // frozen reading of Eq. 17: the held value
-      const v2f h = ivsd_held(d, gx + (int64_t)d.pitch * gy[k]);
-      psi[r][lane] = V{(R)h.x, (R)h.y};
-      continue;
-    }
     R s1 = 0, s2 = 0, den = 0;
 #pragma unroll
     for (int i = 1; i < 9; ++i) {
