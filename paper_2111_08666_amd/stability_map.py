@@ -16,7 +16,7 @@ operator and one JSON line.
 
 --tune-mrt adds a sweep of the MRT operator's free rates at high viscosity
 ratio (G = 3.5): the energy rates s_e = s_eps and the magic parameter
-Lambda (which sets s_q), with the wetting viscosity 0.04 or 0.01.
+Lambda (which sets s_q), with the wetting viscosity 0.04, 0.01 or 0.005.
 """
 import argparse
 import json
@@ -49,7 +49,7 @@ def cell(collision, M, G, nu_wet=NU_WET):
 
 def tune_mrt(steps=20000, log=print):
     """Stable MRT rate choices at M = 100 and 1000, G = 3.5."""
-    cells = [(M, nu, se, lam) for M in (100, 1000) for nu in (0.04, 0.01)
+    cells = [(M, nu, se, lam) for M in (100, 1000) for nu in (0.04, 0.01, 0.005)
              for se in (0.6, 0.8, 1.0, 1.2, 1.5) for lam in (1 / 12, 3 / 16, 1 / 4)]
     probs = []
     for M, nu, se, lam in cells:

@@ -9,7 +9,9 @@ finite and non-negative (M = 100 at G = 4.0 diverges under either momentum
 rate); with s_j = s_nu (mrt_sj_mode = 2)
 the M = 1 cells diverge at the inlet corner, where component 2's entering
 links take the node's own post-collision values (Eq. 28) while its momentum
-is over-relaxed (s_nu = 1.6 against s_q = 0.49)."""
+is over-relaxed (s_nu = 1.6 against s_q = 0.49).  At M = 1000 the default
+MRT rates run with a less viscous wetting phase (nu = 0.005), where SRT
+diverges."""
 import pytest
 
 from paper_2111_08666_amd import stability_map as SM
@@ -56,3 +58,36 @@ def test_momentum_rate_s_nu_diverges_at_m1(lbm):
     cells = [(1, G) for G in GS]
     obs = _run(lbm, 2, cells)
     assert all(o["flags"] & 1 for o in obs)
+
+
+def test_mrt_reaches_viscosity_ratio_1000(lbm):
+    """The viscosity ratio the paper names for MRT (M = 1000): with the
+    wetting component at nu = 0.005 (tau = 0.515) and the invading one at
+    nu = 5 (tau = 15.5), the default MRT rates run the drainage for 100 000
+    steps with every density finite and non-negative, and the invading
+    phase enters the medium under the larger pressure steps; SRT with the
+    same viscosities diverges."""
+    cells = [(1.02, 0.005), (1.05, 0.005), (1.1, 0.005), (1.05, 0.0033)]
+    probs = []
+    for rin, nu in cells:
+        p = SM.cell(1, 1000, 3.5, nu)
+        p.rho_in1 = rin
+        probs.append(p)
+    b = lbm.BatchSolver(probs)
+    try:
+        b.step_graph(1000, 100)
+        obs = b.observables(allow_unstable=True)
+    finally:
+        b.close()
+    for c, o in zip(cells, obs):
+        print(f"[stability] MRT M=1000 rho_in={c[0]} nu_w={c[1]} flags={o['flags']} S_w={o['s_w']:.3f}", flush=True)
+    assert all(o["flags"] == 0 for o in obs)
+    assert obs[1]["s_w"] < 0.95 and obs[2]["s_w"] < 0.95
+    srt = SM.cell(0, 1000, 3.5, 0.005)
+    srt.rho_in1 = 1.05
+    s = lbm.BatchSolver([srt])
+    try:
+        s.step_graph(1000, 20)
+        assert s.observables(allow_unstable=True)[0]["flags"] & 1
+    finally:
+        s.close()
