@@ -85,9 +85,14 @@ def main():
     ap.add_argument("--every", type=int, default=5000)
     ap.add_argument("--collision", type=int, default=0)
     ap.add_argument("--geom", default="", help="JSON overrides of the U's dimensions")
+    ap.add_argument("--variants", default="", help="comma-separated subset, e.g. set1,set2,set3")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
-    res = run(a.steps, a.every, a.collision, geom=json.loads(a.geom) if a.geom else None,
+    variants = VARIANTS
+    if a.variants:
+        want = a.variants.split(",")
+        variants = tuple(v for v in VARIANTS if variant_name(*v) in want)
+    res = run(a.steps, a.every, a.collision, variants=variants, geom=json.loads(a.geom) if a.geom else None,
               log=lambda m: print(m, flush=True))
     summary = {n: {"cup_water_final_over_initial": r["cup_mass2"][-1] / r["cup_mass2"][0],
                    "cup_water_min_over_initial": min(r["cup_mass2"]) / r["cup_mass2"][0],
