@@ -1018,13 +1018,13 @@ lbm_status lbm_batch_kernel_info(const lbm_batch *b, char *name, size_t name_len
       *grid_blocks = g;
     } else if (b->strategy == LBM_COMPACT) {
       int64_t g = 0;
-      for (const InstDev &h : b->h) g = std::max(g, (h.nf + 255) / 256);
+      for (const InstDev &h : b->h) g = std::max(g, (h.nf + kCompactThreads - 1) / kCompactThreads);
       *grid_blocks = g;
     } else {
       *grid_blocks = b->n_blocks;
     }
   }
-  if (block_threads) *block_threads = 256;
+  if (block_threads) *block_threads = b->strategy == LBM_COMPACT ? kCompactThreads : 256;
   return LBM_OK;
 }
 

@@ -25,6 +25,9 @@ constexpr int kTileY3 = 8;
 // Compacted 3D fused step: a tile is one row word (64 columns) by kFwdRows
 // rows, marching a chunk of z.
 constexpr int kFwdRows = 8;
+// Threads per block of the compacted split step's density and collision
+// kernels (thread per fluid node): 128 measured 2 % faster than 256 at 384^3.
+constexpr int kCompactThreads = 128;
 
 // Compacted layout: the fluid nodes of each (y, z) row, in x order, get
 // consecutive compact indices c.  A 64-node word of a row is described by its

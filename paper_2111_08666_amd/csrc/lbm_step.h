@@ -1792,14 +1792,15 @@ static void launch_split_q(int q, const InstDev *d, const InstDev &h, int parity
 template <int COLL, int ST, typename R>
 static void launch_compact_q(int q, const InstDev *d, const InstDev &h, int parity, hipStream_t s) {
   if (h.nf == 0) return;  // no fluid: nothing moves
-  const dim3 g((unsigned)((h.nf + 255) / 256)), gb((unsigned)((h.nbnd + 255) / 256)), b(256);
+  const dim3 g((unsigned)((h.nf + kCompactThreads - 1) / kCompactThreads)), b(kCompactThreads);
+  const dim3 gb((unsigned)((h.nbnd + 255) / 256)), bb(256);
   if (q == 9) {
     crho_kernel<9, ST><<<g, b, 0, s>>>(d, parity);
-    if (h.nbnd) cpsi_kernel<9><<<gb, b, 0, s>>>(d);
+    if (h.nbnd) cpsi_kernel<9><<<gb, bb, 0, s>>>(d);
     ccollide_kernel<9, COLL, ST, R><<<g, b, 0, s>>>(d, parity);
   } else {
     crho_kernel<19, ST><<<g, b, 0, s>>>(d, parity);
-    if (h.nbnd) cpsi_kernel<19><<<gb, b, 0, s>>>(d);
+    if (h.nbnd) cpsi_kernel<19><<<gb, bb, 0, s>>>(d);
     ccollide_kernel<19, COLL, ST, R><<<g, b, 0, s>>>(d, parity);
   }
 }
