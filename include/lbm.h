@@ -250,9 +250,11 @@ lbm_status lbm_kernel_info(const lbm_ctx *ctx, char *name, size_t name_len,
 /* Time every step variant the context's layout allows (dense: fused and
  * listed at each tile height, split; compacted: the compacted step, and in
  * 2D the compacted fused step at each tile height) for `steps` steps each
- * (even, >= 2) with HIP events and keep the fastest.  The timed steps are ordinary steps: the state advances by
- * (number of variants) x steps.  report (optional) receives one line per
- * variant with its milliseconds per step.  Synchronises the stream. */
+ * (even, >= 2) with HIP events, in two passes over the variants (the better
+ * time of each counts), and keep the fastest.  Every trial is 2 untimed and
+ * `steps` timed ordinary steps: the state advances by
+ * 2 x (number of variants) x (steps + 2).  report (optional) receives one
+ * line per variant with its milliseconds per step.  Synchronises the stream. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int64_t steps, char *report, size_t report_len);
 
 /* ---- batches: many instances of uneven size advanced together ----------
@@ -270,6 +272,20 @@ lbm_status lbm_batch_step(lbm_batch *b, int64_t n);
 /* n steps captured once into a HIP graph, replayed reps times (n even). */
 lbm_status lbm_batch_step_graph(lbm_batch *b, int64_t n, int64_t reps);
 lbm_status lbm_batch_observables(lbm_batch *b, lbm_obs *out /* k entries */);
+/* Retire (active[i] == 0) or re-admit (non-zero) instances: host array of k
+ * flags, all set at creation.  A retired instance is not advanced by
+ * lbm_batch_step / lbm_batch_step_graph (the flat block table and the
+ * per-instance launches leave it out, so it costs nothing); its state, step
+ * count (lbm_obs.step) and density read-outs stay as they were, and a
+ * re-admitted instance resumes from there bitwise as if it had never been
+ * retired.  Active instances advance bitwise as in a batch without the
+ * retired ones.  (LBM_COMPACT_FUSED in 3D rebuilds the psi it carries
+ * between steps after a change, as after any change of state outside a
+ * step; that rounds differently in the last FP32 place.)  A non-finite density in a retired instance does not stop
+ * the batch (lbm_batch_observables still reports it in its flags).  A change
+ * rebuilds the block table (synchronises the stream) and drops the captured
+ * graph; no change is a no-op. */
+lbm_status lbm_batch_set_active(lbm_batch *b, const int32_t *active);
 lbm_status lbm_batch_get_density(lbm_batch *b, int32_t k, float *dst, int32_t dst_is_device);
 lbm_status lbm_batch_destroy(lbm_batch *b);
 const char *lbm_batch_last_error(const lbm_batch *b);

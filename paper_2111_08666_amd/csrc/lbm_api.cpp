@@ -385,6 +385,13 @@ struct lbm_batch {
   // copy, for the edge lists) and whether the carried psi matches the state
   std::vector<std::vector<uint32_t>> ckey_host;
   bool psi_valid = false;
+  // retirement: per instance whether it advances, its two own population
+  // buffers (a retired instance points both f slots at its current one),
+  // the steps it has taken and whether its last observables were non-finite
+  std::vector<uint8_t> active;
+  std::vector<std::pair<float *, float *>> fown;
+  std::vector<int64_t> inst_step;
+  std::vector<uint8_t> bad;
 };
 
 struct lbm_ctx {
@@ -464,6 +471,7 @@ lbm_status apply_plan(lbm_batch *b, int strategy, int ty) {
     const Tiling t = make_tiling(b->q, h.nx, h.ny, h.nz, ty, strategy);
     h.tiles_x = t.tiles_x; h.tiles_y = t.tiles_y; h.tiles_z = t.tiles_z;
     h.block_base = (int32_t)base;
+    if (!b->active[(size_t)i]) continue;  // retired: no blocks in the table
     for (int64_t j = 0; j < t.blocks; ++j) table.push_back(i);
     base += t.blocks;
   }
@@ -496,8 +504,9 @@ lbm_status apply_plan(lbm_batch *b, int strategy, int ty) {
   b->strategy = strategy;
   b->ty = ty;
   b->n_blocks = base;
-  HIPCHK(b, hipMemcpyAsync(b->d_block_inst, table.data(), sizeof(int32_t) * table.size(),
-                           hipMemcpyHostToDevice, b->stream));
+  if (!table.empty())
+    HIPCHK(b, hipMemcpyAsync(b->d_block_inst, table.data(), sizeof(int32_t) * table.size(),
+                             hipMemcpyHostToDevice, b->stream));
   HIPCHK(b, hipMemcpyAsync(b->d_insts, b->h.data(), sizeof(InstDev) * b->h.size(), hipMemcpyHostToDevice,
                            b->stream));
   HIPCHK(b, hipStreamSynchronize(b->stream));
@@ -511,6 +520,7 @@ StepLaunch step_launch(const lbm_batch *b, int parity) {
   L.d_insts = b->d_insts;
   L.h = b->h.data();
   L.block_inst = b->k > 1 ? b->d_block_inst : nullptr;
+  L.active = b->active.data();
   L.n_blocks = b->n_blocks;
   L.k = b->k; L.q = b->q; L.collision = b->collision; L.storage = b->storage; L.math = b->math;
   L.strategy = b->strategy; L.ty = b->ty; L.parity = parity;
@@ -623,6 +633,10 @@ lbm_status create_batch(int32_t k, const lbm_geometry *g, const lbm_params *p,
     }
     b->h.push_back(h);
     b->lay.push_back(L);
+    b->active.push_back(1);
+    b->fown.emplace_back(h.f[0], h.f[1]);
+    b->inst_step.push_back(0);
+    b->bad.push_back(0);
     b->ckey_host.push_back(g[i].q == 19 ? ck : std::vector<uint32_t>());
     b->geom_hash.push_back(geometry_hash(g[i]));
     // held (frozen) links: rest equilibria of the initial densities
@@ -666,7 +680,8 @@ bool carries_psi(const lbm_batch *b) { return b->q == 19 && b->strategy == LBM_C
 
 lbm_status ensure_psi(lbm_batch *b) {
   if (!carries_psi(b) || b->psi_valid) return LBM_OK;
-  for (int i = 0; i < b->k; ++i) HIPCHK(b, launch_fwd_rebuild(b->d_insts + i, b->h[i], b->parity, b->stream));
+  for (int i = 0; i < b->k; ++i)
+    if (b->active[(size_t)i]) HIPCHK(b, launch_fwd_rebuild(b->d_insts + i, b->h[i], b->parity, b->stream));
   b->psi_valid = true;
   return LBM_OK;
 }
@@ -684,6 +699,8 @@ lbm_status batch_step(lbm_batch *b, int64_t n) {
     b->parity ^= 1;
     b->step++;
   }
+  for (int i = 0; i < b->k; ++i)
+    if (b->active[(size_t)i]) b->inst_step[(size_t)i] += n;
   return LBM_OK;
 }
 
@@ -719,13 +736,15 @@ lbm_status batch_step_graph(lbm_batch *b, int64_t n, int64_t reps) {
   for (int64_t r = 0; r < reps; ++r) {
     HIPCHK(b, hipGraphLaunch(b->gexec, b->stream));
     b->step += n;
+    for (int i = 0; i < b->k; ++i)
+      if (b->active[(size_t)i]) b->inst_step[(size_t)i] += n;
   }
   return LBM_OK;
 }
 
 void fill_obs(const lbm_batch *b, int i, const double *r, lbm_obs *o) {
   std::memset(o, 0, sizeof(*o));
-  o->step = b->step;
+  o->step = b->inst_step[(size_t)i];
   o->mass[0] = r[0];
   o->mass[1] = r[1];
   o->n_fluid = r[2];
@@ -741,7 +760,6 @@ void fill_obs(const lbm_batch *b, int i, const double *r, lbm_obs *o) {
   o->p_out = r[10] > 0 ? r[9] / r[10] : 0.0;
   o->pc = o->p_in - o->p_out;
   o->flags = (int32_t)r[11];
-  (void)i;
 }
 
 lbm_status batch_observables(lbm_batch *b, lbm_obs *out) {
@@ -755,7 +773,10 @@ lbm_status batch_observables(lbm_batch *b, lbm_obs *out) {
   bool bad_state = false;
   for (int i = 0; i < b->k; ++i) {
     fill_obs(b, i, r.data() + (size_t)kObsFields * i, out + i);
-    if (out[i].flags & 1) bad_state = true;  // a negative density (bit 1) is only reported
+    // a non-finite density stops the batch unless its instance is retired;
+    // a negative density (bit 1) is only reported
+    b->bad[(size_t)i] = (out[i].flags & 1) ? 1 : 0;
+    if (b->bad[(size_t)i] && b->active[(size_t)i]) bad_state = true;
   }
   if (bad_state) {
     b->unstable = true;
@@ -924,6 +945,8 @@ lbm_status lbm_load(lbm_ctx *ctx, const void *host_blob, size_t bytes) {
   const char *p = reinterpret_cast<const char *>(host_blob);
   b->parity = hd.parity;
   b->step = hd.step;
+  b->inst_step[0] = hd.step;
+  b->bad[0] = 0;
   b->h[0].rho_in1 = hd.rho_in1;
   b->h[0].rho_out2 = hd.rho_out2;
   HIPCHK(b, hipMemcpyAsync((void *)b->h[0].frozen, p + sizeof(hd), L.frozen_bytes, hipMemcpyHostToDevice,
@@ -983,6 +1006,8 @@ lbm_status lbm_init_from_saturation(lbm_ctx *ctx, const float *sat, int32_t sat_
   b->psi_valid = false;
   b->unstable = false;
   b->step = 0;
+  b->inst_step[0] = 0;
+  b->bad[0] = 0;
   return LBM_OK;
 }
 
@@ -1059,27 +1084,35 @@ lbm_status lbm_batch_autotune(lbm_batch *b, int64_t steps, char *report, size_t 
   hipEvent_t e0, e1;
   HIPCHK(b, hipEventCreate(&e0));
   HIPCHK(b, hipEventCreate(&e1));
+  // two passes over the variants, the better time of each counting: a single
+  // short trial right after a switch of variant can land several percent off
+  std::vector<float> ms_best(cands.size(), 1e30f);
+  for (int pass = 0; pass < 2; ++pass)
+    for (size_t ci = 0; ci < cands.size(); ++ci) {
+      const Cand &c = cands[ci];
+      lbm_status st = apply_plan(b, c.strategy, c.ty);
+      if (st != LBM_OK) return st;
+      st = batch_step(b, 2);  // warm-up
+      if (st != LBM_OK) return st;
+      HIPCHK(b, hipEventRecord(e0, b->stream));
+      st = batch_step(b, steps);
+      if (st != LBM_OK) return st;
+      HIPCHK(b, hipEventRecord(e1, b->stream));
+      HIPCHK(b, hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIPCHK(b, hipEventElapsedTime(&ms, e0, e1));
+      ms_best[ci] = std::min(ms_best[ci], ms / (float)steps);
+    }
   std::string rep;
   float best = 1e30f;
   Cand bestc = cands[0];
-  for (const Cand &c : cands) {
-    lbm_status st = apply_plan(b, c.strategy, c.ty);
-    if (st != LBM_OK) return st;
-    st = batch_step(b, 2);  // warm-up
-    if (st != LBM_OK) return st;
-    HIPCHK(b, hipEventRecord(e0, b->stream));
-    st = batch_step(b, steps);
-    if (st != LBM_OK) return st;
-    HIPCHK(b, hipEventRecord(e1, b->stream));
-    HIPCHK(b, hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIPCHK(b, hipEventElapsedTime(&ms, e0, e1));
-    ms /= (float)steps;
+  for (size_t ci = 0; ci < cands.size(); ++ci) {
+    const Cand &c = cands[ci];
     char line[128];
     std::snprintf(line, sizeof line, "%s %.5f ms/step\n",
-                  step_kernel_name(b->q, b->collision, b->storage, b->math, c.strategy, c.ty), ms);
+                  step_kernel_name(b->q, b->collision, b->storage, b->math, c.strategy, c.ty), ms_best[ci]);
     rep += line;
-    if (ms < best) { best = ms; bestc = c; }
+    if (ms_best[ci] < best) { best = ms_best[ci]; bestc = c; }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1106,6 +1139,37 @@ lbm_status lbm_batch_create(int32_t k, const lbm_geometry *geoms, const lbm_para
 lbm_status lbm_batch_step(lbm_batch *b, int64_t n) { return batch_step(b, n); }
 lbm_status lbm_batch_step_graph(lbm_batch *b, int64_t n, int64_t reps) { return batch_step_graph(b, n, reps); }
 lbm_status lbm_batch_observables(lbm_batch *b, lbm_obs *out) { return batch_observables(b, out); }
+
+// Retire or re-admit instances.  A retired instance keeps its state in the
+// buffer it was left in: both f slots point there, so every read (density,
+// observables) finds it whatever the batch parity; re-admission gives it its
+// other buffer back as the next step's destination.
+lbm_status lbm_batch_set_active(lbm_batch *b, const int32_t *active) {
+  if (!b) return fail(nullptr, LBM_EINVAL, "NULL handle");
+  if (!active) return fail(b, LBM_EINVAL, "active is NULL");
+  bool changed = false;
+  for (int i = 0; i < b->k; ++i) {
+    const uint8_t want = active[i] ? 1 : 0;
+    if (want == b->active[(size_t)i]) continue;
+    changed = true;
+    InstDev &h = b->h[(size_t)i];
+    const std::pair<float *, float *> &own = b->fown[(size_t)i];
+    float *cur = h.f[b->parity];
+    if (!want) {
+      h.f[0] = h.f[1] = cur;
+    } else {
+      h.f[b->parity] = cur;
+      h.f[b->parity ^ 1] = cur == own.first ? own.second : own.first;
+    }
+    b->active[(size_t)i] = want;
+  }
+  if (!changed) return LBM_OK;
+  b->unstable = false;
+  for (int i = 0; i < b->k; ++i)
+    if (b->active[(size_t)i] && b->bad[(size_t)i]) b->unstable = true;
+  // new block table and descriptors; drops the captured graph and the carried psi
+  return apply_plan(b, b->strategy, b->ty);
+}
 lbm_status lbm_batch_get_density(lbm_batch *b, int32_t k, float *dst, int32_t dst_is_device) {
   return batch_density(b, k, dst, dst_is_device);
 }

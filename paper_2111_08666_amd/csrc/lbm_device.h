@@ -88,8 +88,10 @@ struct StepLaunch {
   const InstDev *d_insts;
   const InstDev *h;            // host copies (grid sizes of the split kernels)
   const int32_t *block_inst;   // fused: block -> instance table (NULL for one instance)
-  int64_t n_blocks;
+  const uint8_t *active;       // host flags per instance: 0 = retired, not advanced (NULL: all)
+  int64_t n_blocks;            // fused: blocks of the advancing instances (may be 0)
   int k, q, collision, storage, math, strategy, ty, parity;
+  bool live(int i) const { return !active || active[i]; }
 };
 hipError_t launch_step(const StepLaunch &L, hipStream_t s);
 hipError_t launch_observables(const InstDev *d_inst, const InstDev &h_inst, int parity,

@@ -1752,9 +1752,11 @@ static void launch_fused_q(int q, int ty, const InstDev *d, const int32_t *bi, i
 // virtual solid densities, into the carried psi of the next step.
 template <int COLL, typename R>
 static void launch_fwd_q(const StepLaunch &L, hipStream_t s) {
+  if (L.n_blocks == 0) return;  // every instance retired
   fwd_step_d3q19<COLL, R><<<dim3((unsigned)L.n_blocks), dim3(kFwdThreads), 0, s>>>(L.d_insts, L.block_inst,
                                                                                   L.parity);
   for (int i = 0; i < L.k; ++i) {
+    if (!L.live(i)) continue;
     const InstDev &h = L.h[i];
     if (h.nedge)
       fwd_rho_kernel<19><<<dim3((unsigned)((h.nedge + 255) / 256)), dim3(256), 0, s>>>(L.d_insts + i, h.cedge,
@@ -1810,9 +1812,13 @@ static void launch_compact_q(int q, const InstDev *d, const InstDev &h, int pari
 template <int COLL, int ST, typename R>
 static void launch_st(const StepLaunch &L, hipStream_t s) {
   if (L.strategy == 2) {
-    for (int i = 0; i < L.k; ++i) launch_split_q<COLL, ST, R>(L.q, L.d_insts + i, L.h[i], L.parity, s);
+    for (int i = 0; i < L.k; ++i)
+      if (L.live(i)) launch_split_q<COLL, ST, R>(L.q, L.d_insts + i, L.h[i], L.parity, s);
   } else if (L.strategy == 3) {
-    for (int i = 0; i < L.k; ++i) launch_compact_q<COLL, ST, R>(L.q, L.d_insts + i, L.h[i], L.parity, s);
+    for (int i = 0; i < L.k; ++i)
+      if (L.live(i)) launch_compact_q<COLL, ST, R>(L.q, L.d_insts + i, L.h[i], L.parity, s);
+  } else if (L.n_blocks == 0) {
+    return;  // block-table strategies with every instance retired: nothing to launch
   } else if (L.strategy == 4) {
     launch_fused_list_q<COLL, ST, R>(L.q, L.ty, L.d_insts, L.block_inst, L.n_blocks, L.parity, s);
   } else if (L.strategy == 5 && L.q == 19) {

@@ -27,7 +27,7 @@ EXPORTS = [
     "lbm_destroy", "lbm_last_error", "lbm_kernel_info", "lbm_autotune", "lbm_batch_workspace_bytes",
     "lbm_batch_create", "lbm_batch_step", "lbm_batch_step_graph", "lbm_batch_observables",
     "lbm_batch_get_density", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_batch_kernel_info",
-    "lbm_batch_autotune",
+    "lbm_batch_autotune", "lbm_batch_set_active",
 ]
 
 
@@ -116,12 +116,13 @@ def lib():
         L.lbm_batch_last_error.argtypes = [vp]
         L.lbm_batch_kernel_info.argtypes = [vp, C.c_char_p, sz, C.POINTER(i64), C.POINTER(i32)]
         L.lbm_batch_autotune.argtypes = [vp, i64, C.c_char_p, sz]
+        L.lbm_batch_set_active.argtypes = [vp, C.POINTER(i32)]
         for name in ("lbm_create", "lbm_set_bc", "lbm_step", "lbm_step_graph", "lbm_observables",
                      "lbm_get_density", "lbm_save", "lbm_load", "lbm_destroy", "lbm_kernel_info",
                      "lbm_autotune",
                      "lbm_batch_create", "lbm_batch_step", "lbm_batch_step_graph",
                      "lbm_batch_observables", "lbm_batch_get_density", "lbm_batch_destroy",
-                     "lbm_batch_kernel_info", "lbm_batch_autotune"):
+                     "lbm_batch_kernel_info", "lbm_batch_autotune", "lbm_batch_set_active"):
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -375,6 +376,13 @@ class BatchSolver:
         out = np.empty((2,) + p.mask.shape, dtype=np.float32)
         self._chk(lib().lbm_batch_get_density(self._h, int(i), out.ctypes.data, 0))
         return out
+
+    def set_active(self, active):
+        """Retire (False) or re-admit (True) instances: one flag per instance."""
+        flags = [1 if a else 0 for a in active]
+        if len(flags) != len(self.problems):
+            raise ValueError("need one flag per instance")
+        self._chk(lib().lbm_batch_set_active(self._h, (C.c_int32 * len(flags))(*flags)))
 
     def autotune(self, steps=20) -> str:
         rep = C.create_string_buffer(1024)

@@ -138,6 +138,7 @@ int main() {
   EXPECT(lbm_init_from_saturation(nullptr, nullptr, 1, 0.5, 1.0, 0.027) == LBM_EINVAL);
   EXPECT(lbm_debug_poke(nullptr, 0, 0, 0, 0, 0, 1.0f) == LBM_EINVAL);
   EXPECT(lbm_get_step(nullptr) == -1);
+  EXPECT(lbm_batch_set_active(nullptr, nullptr) == LBM_EINVAL);
   EXPECT(lbm_destroy(nullptr) == LBM_OK);
   std::printf("api sanitizer driver: %d failed checks\n", fails);
   return fails != 0;

@@ -47,7 +47,7 @@ def ref():
 def _advance_like_bench(b, steps=200):
     """Autotune (ordinary steps), then graph replays up to `steps`."""
     rep = b.autotune(10)
-    done = 12 * len(rep.strip().splitlines())
+    done = 2 * 12 * len(rep.strip().splitlines())  # two passes of 2 + 10 steps per variant
     rest = steps - done
     assert rest > 0 and rest % 2 == 0
     b.step_graph(2, rest // 2)

@@ -86,7 +86,7 @@ def test_autotune_keeps_the_physics(lbm):
     n_var = len(rep.strip().splitlines())
     assert n_var == 7  # three tile heights, fused and listed, and the split step
     total = s.t
-    assert total == n_var * (4 + 2)
+    assert total == 2 * n_var * (4 + 2)  # two passes, 2 warm-up + 4 timed steps per trial
     s.step(200 - total)
     ref = _oracle_series(p, (200,))
     assert _rel_err(s.density(), ref[200], p.mask) <= REL_TOL
