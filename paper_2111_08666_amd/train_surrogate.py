@@ -57,70 +57,60 @@ def make_instances(idx, masks, n=256):
 
 def run_to_steady(problems, cap, check=1000, tol=1e-6, min_steps=2000, storage=lbm.STORE_F32, tag="",
                   run_all=False):
-    """As _run_to_steady; an instance whose density becomes non-finite stops
-    the batch, which then restarts without it (its result is None)."""
-    live = list(range(len(problems)))
-    while True:
-        try:
-            res = _run_to_steady([problems[i] for i in live], cap, check, tol, min_steps, storage, tag,
-                                 run_all)
-            break
-        except lbm.LbmError as e:
-            if e.status != lbm.LBM_EUNSTABLE:
-                raise
-            bad = [live[j] for j in e.bad]
-            log(f"[steady{tag}] non-finite density in instances {bad}: restarting without them")
-            live = [i for i in live if i not in bad]
-    out = [[None] * len(problems) for _ in range(4)]
-    for j, i in enumerate(live):
-        for r in range(4):
-            out[r][i] = res[r][j]
-    traj = np.full((len(problems), res[4].shape[1]), np.nan)
-    traj[live] = res[4]
-    return out[0], out[1], out[2], out[3], traj
-
-
-def _run_to_steady(problems, cap, check=1000, tol=1e-6, min_steps=2000, storage=lbm.STORE_F32, tag="",
-                   run_all=False):
     """Advance all problems in one batch until each one's window saturation
     (weighted, non-wetting) changes by less than tol over `check` steps.
-    Returns per-instance (steps, converged, S_nw, density) and the S_nw
-    trajectory (k x checks)."""
+    A settled instance is retired from the batch (it costs nothing more and
+    its state stays as it settled) unless run_all asks for trajectories to the
+    cap; an instance whose density becomes non-finite is retired at once and
+    reported as None, and the rest go on.  Returns per-instance (steps,
+    converged, S_nw, density) and the S_nw trajectory (k x checks, constant
+    after an instance settles, NaN for a failed one)."""
     k = len(problems)
     b = lbm.BatchSolver(problems, storage=storage)
     prev = [1.0 - o["s_w_weighted"] for o in b.observables()]
     traj = [list(prev)]
     steps = [cap] * k
     conv = [False] * k
+    failed = [False] * k
     snw = list(prev)
     dens = [None] * k
     t = 0
     t0 = time.time()
-    while t < cap and (run_all or not all(conv)):
+    while t < cap and (run_all or not all(c or f for c, f in zip(conv, failed))):
         b.step_graph(check, 1)
         t += check
         obs = b.observables(allow_unstable=True)
-        bad = [i for i, o in enumerate(obs) if o["flags"] & 1]
+        bad = [i for i, o in enumerate(obs) if o["flags"] & 1 and not failed[i]]
         if bad:
-            b.close()
-            err = lbm.LbmError(lbm.LBM_EUNSTABLE, "non-finite density")
-            err.bad = bad
-            raise err
+            log(f"[steady{tag}] non-finite density in instances {bad} at t={t}: retired")
+            for i in bad:
+                failed[i] = True
+        changed = bool(bad)
         for i, o in enumerate(obs):
+            if failed[i]:
+                continue
             s = 1.0 - o["s_w_weighted"]
             if not conv[i] and t >= min_steps and abs(s - prev[i]) < tol:
                 conv[i], steps[i], snw[i] = True, t, s
                 dens[i] = b.density(i)
+                changed = changed or not run_all
             prev[i] = s
+        if changed:
+            b.set_active([not f and (run_all or not c) for c, f in zip(conv, failed)])
         traj.append(list(prev))
         if t % (10 * check) == 0:
             log(f"[steady{tag}] t={t} converged {sum(conv)}/{k} ({time.time() - t0:.0f}s)")
     for i in range(k):
-        if not conv[i]:
+        if not conv[i] and not failed[i]:
             snw[i] = prev[i]
             dens[i] = b.density(i)
     b.close()
-    return steps, conv, snw, dens, np.array(traj).T
+    traj = np.array(traj).T
+    for i in range(k):
+        if failed[i]:
+            steps[i] = conv[i] = snw[i] = dens[i] = None
+            traj[i] = np.nan
+    return steps, conv, snw, dens, traj
 
 
 def cmd_gen(a):

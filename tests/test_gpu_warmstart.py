@@ -10,7 +10,9 @@ has not settled within its step budget falls back to the cold start and is
 charged the budget plus the whole cold run.  Counting inference and
 fallbacks, the warm starts must reach steady state in less wall time than the
 cold starts, and every warm result must lie within 0.01 in saturation of the
-cold steady state.  Above 90 degrees the non-wetting phase imbibes
+cold steady state.  The same comparison batched (cold starts in one batch,
+warm starts in another, settled instances retired from their batch, the
+fallbacks in a third batch) must reach the same steady states.  Above 90 degrees the non-wetting phase imbibes
 spontaneously and neither start settles within 3e5 steps (see
 weights/unet_drainage256.eval.json), so those instances are left out.
 
@@ -80,3 +82,9 @@ def test_warm_start_with_fallback_reaches_steady_state_sooner(mods):
     assert w["agree_within_s_tol"] == w["cold_settled"]
     assert w["wall_s"]["warm_with_fallback"] < w["wall_s"]["cold"]
     assert w["steps_total"]["warm_with_fallback"] < w["steps_total"]["cold"]
+    # batched, with settled instances retired: the same steady states
+    bt = w["batched"]
+    print(f"[warm] batched {bt}", flush=True)
+    assert bt["cold_settled"] == w["cold_settled"]
+    assert bt["agree_within_s_tol"] == bt["cold_settled"]
+    assert bt["fallbacks"] == w["fallbacks"]
