@@ -151,6 +151,12 @@ typedef struct {
                              a slightly negative minor-phase density near strongly
                              wetting walls is an artefact of the model, not a blow-up) */
   int32_t reserved;
+  double stag[3];         /* staggered momentum per axis: the sum over fluid nodes of
+                             (-1)^x j_x (resp. (-1)^y j_y, (-1)^z j_z), j the momentum of
+                             both components' streamed populations, over the total
+                             mass.  A checkerboard velocity mode that the densities do
+                             not show; in long runs it can grow until a node diverges
+                             (0 in 2D for z) */
 } lbm_obs;
 
 typedef struct lbm_ctx lbm_ctx;

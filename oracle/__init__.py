@@ -40,7 +40,7 @@ class OraObs(C.Structure):
         ("p_in", C.c_double), ("p_out", C.c_double), ("pc", C.c_double),
         ("n_in", C.c_double), ("n_out", C.c_double),
         ("flux_in", C.c_double * 2), ("flux_out", C.c_double * 2),
-        ("flags", C.c_int32), ("pad", C.c_int32),
+        ("flags", C.c_int32), ("pad", C.c_int32), ("stag", C.c_double * 3),
     ]
 
     def to_dict(self):

@@ -779,12 +779,23 @@ void ora_observables(ora_sim *s, ora_obs *o) {
       if (x == 0) { pin += P; o->n_in += 1.0; }
       else { pout += P; o->n_out += 1.0; }
     }
+    /* momentum of the streamed populations, both components, signed by
+       the parity of each coordinate */
+    const int xyz[3] = {x, y, z};
+    for (int d = 0; d < 3; ++d) {
+      double j = 0.0;
+      for (int c = 0; c < 2; ++c)
+        for (int i = 0; i < s->L.q; ++i) j += s->L.e[i][d] * FF(s, c, i, n);
+      o->stag[d] += (xyz[d] & 1) ? -j : j;
+    }
   }
   o->s_w = o->n_window > 0 ? o->sw_count / o->n_window : 0.0;
   o->s_w_weighted = o->sum_rho > 0 ? o->sum_rho_w / o->sum_rho : 0.0;
   o->p_in = o->n_in > 0 ? pin / o->n_in : 0.0;
   o->p_out = o->n_out > 0 ? pout / o->n_out : 0.0;
   o->pc = o->p_in - o->p_out;
+  const double m = o->mass[0] + o->mass[1];
+  for (int d = 0; d < 3; ++d) o->stag[d] = m > 0.0 ? o->stag[d] / m : 0.0;
   for (int c = 0; c < 2; ++c) {
     o->flux_in[c] = s->flux_in[c];
     o->flux_out[c] = s->flux_out[c];

@@ -59,6 +59,9 @@ typedef struct {
   double flux_out[2];       /* sum of post-collision populations that left the domain */
   int32_t flags;            /* bit0 non-finite density, bit1 negative density */
   int32_t pad;
+  double stag[3];           /* staggered momentum: sum over fluid nodes of (-1)^x j_x
+                               (resp. y, z) over the total mass, j the momentum of both
+                               components' streamed populations */
 } ora_obs;
 
 typedef struct ora_sim ora_sim;

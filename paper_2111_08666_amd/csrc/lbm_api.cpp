@@ -759,7 +759,9 @@ void fill_obs(const lbm_batch *b, int i, const double *r, lbm_obs *o) {
   o->p_in = r[8] > 0 ? r[7] / r[8] : 0.0;
   o->p_out = r[10] > 0 ? r[9] / r[10] : 0.0;
   o->pc = o->p_in - o->p_out;
-  o->flags = (int32_t)r[11];
+  o->flags = (int32_t)r[14];
+  const double m = r[0] + r[1];
+  for (int d = 0; d < 3; ++d) o->stag[d] = m > 0 ? r[11 + d] / m : 0.0;
 }
 
 lbm_status batch_observables(lbm_batch *b, lbm_obs *out) {

@@ -69,7 +69,8 @@ struct InstDev {
 };
 
 // Reduction record written per block by the observables kernel.
-constexpr int kObsFields = 12;  // mass0 mass1 nfluid nwin swcount sumrw sumr pin nin pout nout flags
+constexpr int kObsFields = 15;  // mass0 mass1 nfluid nwin swcount sumrw sumr pin nin pout nout
+                                // stag_x stag_y stag_z flags
 
 // Launchers (defined in the .hip sources).
 hipError_t launch_init(const InstDev *d_inst, const InstDev &h_inst, const float *rho0_dev,

@@ -93,6 +93,19 @@ __global__ __launch_bounds__(256) void obs_kernel(const InstDev *__restrict__ in
       if (x == 0) { acc[7] += P; acc[8] += 1.0; }
       else { acc[9] += P; acc[10] += 1.0; }
     }
+    // staggered momentum: both components' momentum with the sign of (-1)^x
+    // (resp. y, z), a checkerboard mode the densities do not show
+    double jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const double t = (double)a[i] + (double)b[i];
+      jx += Lat<Q>::ex[i] * t;
+      jy += Lat<Q>::ey[i] * t;
+      jz += Lat<Q>::ez[i] * t;
+    }
+    acc[11] += (x & 1) ? -jx : jx;
+    acc[12] += (y & 1) ? -jy : jy;
+    acc[13] += (z & 1) ? -jz : jz;
   }
   __shared__ double red[4][kObsFields];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

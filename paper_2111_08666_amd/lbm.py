@@ -56,7 +56,7 @@ class Obs(C.Structure):
                 ("s_w", C.c_double), ("s_w_weighted", C.c_double),
                 ("p_in", C.c_double), ("p_out", C.c_double), ("pc", C.c_double),
                 ("n_in", C.c_double), ("n_out", C.c_double),
-                ("flags", C.c_int32), ("reserved", C.c_int32)]
+                ("flags", C.c_int32), ("reserved", C.c_int32), ("stag", C.c_double * 3)]
 
     def to_dict(self):
         out = {}

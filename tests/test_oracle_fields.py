@@ -401,3 +401,43 @@ def test_pressure_form_holds_a_mixture_at_rest_under_a_body_force():
         return abs((p[xb] - p[xa]) - rise) / rise
     assert rel_miss(G) < 1e-6
     assert rel_miss(G / 2) > 0.05 and rel_miss(0.0) > 0.05
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_staggered_momentum_flips_sign_under_streaming(q):
+    """The staggered momentum observable on a closed form.  Post-collision
+    populations carrying a checkerboard velocity u_d = a_d (-1)^(coordinate d),
+    f*_i = w_i rho_s (1 + 3 e_i . u), in a fully periodic box of even size:
+    after streaming, every link with e_id != 0 arrives from a node of the
+    other parity, so the streamed momentum along d is -a_d (-1)^(coordinate)
+    times the node's total density (sum_i w_i e_id^2 = 1/3, and the mixed
+    terms cancel in pairs).  The observable, the signed sum over the total
+    mass, is therefore exactly -a_d: the mode flips sign at every step."""
+    shape = (4, 6) if q == 9 else (4, 4, 6)  # (ny, nx) or (nz, ny, nx)
+    dims = len(shape)
+    rho = (0.7, 0.3)
+    amp = (0.011, -0.004, 0.007)[:dims]  # along x, y, z
+    e, w, _ = O.lattice(q)
+    grids = np.meshgrid(*[np.arange(n) for n in shape], indexing="ij")
+    coord = {0: grids[-1], 1: grids[-2]}  # x, y
+    if dims == 3:
+        coord[2] = grids[0]  # z
+    u = [amp[d] * (-1.0) ** coord[d] for d in range(dims)]
+    fs = np.zeros((2, q) + shape)
+    for c in range(2):
+        for i in range(q):
+            eu = sum(e[i][d] * u[d] for d in range(dims))
+            fs[c, i] = w[i] * rho[c] * (1.0 + 3.0 * eu)
+    mask = np.zeros(shape, np.uint8)
+    r0 = np.zeros((2,) + shape)
+    r0[0], r0[1] = rho
+    kw = dict(q=q, nx=shape[-1], ny=shape[-2], periodic=3 if dims == 2 else 7, open_x=0, G=0.0)
+    if dims == 3:
+        kw["nz"] = shape[0]
+    s = O.OracleSim(params=O.make_params(**kw), mask=mask, rho0=r0)
+    s.set_fstar(fs)
+    st = s.observables()["stag"]
+    for d in range(dims):
+        assert st[d] == pytest.approx(-amp[d], abs=1e-15), (d, st)
+    if dims == 2:
+        assert st[2] == 0.0
