@@ -175,10 +175,11 @@ def run(steps=200000, audit=1000, problem=None, log=print, stop_at_breakthrough=
                  "mass_audit": {"n": len(m1), "mass1_min": min(m1), "mass1_max": max(m1),
                                 "mass2_min": min(m2), "mass2_max": max(m2),
                                 "finite": bool(np.all(np.isfinite(m1 + m2))), "flags": flags},
-                 "column_means": inlet, "non_finite": where, "breakthrough": through, "blowup": blowup}
+                 "column_means": inlet, "non_finite": where, "breakthrough": through, "blowup": blowup,
+                 "stag": o["stag"]}
             rec.append(r)
             log(f"[pc_sw] {k:2d} {phase:10s} rho_in1 {rin:.4f} rho_out2 {rout:.4f}: P_c {r['pc']:+.5f} "
-                f"S_w {r['s_w']:.4f} (weighted {r['s_w_weighted']:.4f}) flags {flags}"
+                f"S_w {r['s_w']:.4f} (weighted {r['s_w_weighted']:.4f}) stag_x {o['stag'][0]:+.1e} flags {flags}"
                 f"{' breakthrough' if through else ''} ({time.time() - t0:.0f}s)")
             if flags & 1:
                 break
