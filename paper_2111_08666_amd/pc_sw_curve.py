@@ -3,7 +3,7 @@
 stepwise pressure increments (Sec. 4.2, Figs. 10 and 12), on one GPU.
 
     python -m paper_2111_08666_amd.pc_sw_curve [--size 1024x512] [--steps 200000] [--audit 1000] [--out curve.json]
-        [--all-increments] [--raw-medium] [--locate-blowup]
+        [--all-increments] [--raw-medium] [--locate-blowup] [--collision 2] [--lam 0.1875]
 
 Drainage raises the inlet density of component 1 (the invading oil) over
 ten levels, rho_in1 = 1 + 3 dP with dP from 1e-3 to 2e-2 (geometric), each
@@ -186,7 +186,7 @@ def run(steps=200000, audit=1000, problem=None, log=print, stop_at_breakthrough=
     finally:
         s.close()
     return {"workload": p.name, "nx": p.nx, "ny": p.ny, "steps_per_increment": steps, "audit_every": audit,
-            "kernel": kernel, "G": p.G, "xi": p.xi, "tau": list(p.tau), "collision": p.collision,
+            "kernel": kernel, "G": p.G, "xi": p.xi, "tau": list(p.tau), "collision": p.collision, "lam": p.lam,
             "stop_at_breakthrough": stop_at_breakthrough, "wall_s": round(time.time() - t0, 1), "increments": rec}
 
 
@@ -203,11 +203,18 @@ def main():
     ap.add_argument("--raw-medium", action="store_true", help="keep the medium's narrow throats open")
     ap.add_argument("--locate-blowup", action="store_true",
                     help="checkpoint every audit and replay a blow-up step by step")
+    ap.add_argument("--collision", type=int, default=None, help="0 SRT, 1 MRT (the default), 2 TRT")
+    ap.add_argument("--lam", type=float, default=None, help="TRT/MRT magic parameter (default 3/16)")
     a = ap.parse_args()
     log = lambda m: print(m, file=sys.stderr, flush=True)  # noqa: E731
     nx, ny = (int(v) for v in a.size.split("x"))
-    res = run(a.steps, a.audit, problem=study_problem(nx, ny, a.xi, close=not a.raw_medium), log=log,
-              stop_at_breakthrough=not a.all_increments, locate=a.locate_blowup)
+    prob = study_problem(nx, ny, a.xi, close=not a.raw_medium)
+    if a.collision is not None:
+        prob.collision = a.collision
+    if a.lam is not None:
+        prob.lam = a.lam
+    res = run(a.steps, a.audit, problem=prob, log=log, stop_at_breakthrough=not a.all_increments,
+              locate=a.locate_blowup)
     print(json.dumps(res), flush=True)
     if a.out:
         with open(a.out, "w") as f:
