@@ -45,6 +45,14 @@ typedef __attribute__((address_space(1))) const char gcc;
 typedef __attribute__((address_space(1))) char gc;
 __device__ __forceinline__ float ldg(gcf *base, uint32_t boff) { return *(gcf *)((gcc *)base + boff); }
 __device__ __forceinline__ void stg(gf *base, uint32_t boff, float v) { *(gf *)((gc *)base + boff) = v; }
+// Non-temporal store: for the 3D split steps' post-collision stream, which is
+// not read again before the caches have turned over (the next step's density
+// kernel starts after the whole GB-sized buffer is written), so keeping it
+// in L2 only evicts the pull and psi working sets.  (The 2D steps re-read
+// their cache-resident buffers and are slower with it.)
+__device__ __forceinline__ void stg_nt(gf *base, uint32_t boff, float v) {
+  __builtin_nontemporal_store(v, (gf *)((gc *)base + boff));
+}
 
 // ---------------------------------------------------------------------------
 // population access by storage kind; a node is addressed by its row block
@@ -126,8 +134,9 @@ __device__ __forceinline__ void pop_get2(gcf *__restrict__ b, int pitch, int i, 
   }
 }
 
-// Store both components' post-collision populations of one node.
-template <int Q, int ST>
+// Store both components' post-collision populations of one node (NT:
+// non-temporal FP32 stores).
+template <int Q, int ST, bool NT = false>
 __device__ __forceinline__ void pop_store(gf *__restrict__ b, int pitch, int64_t row, int x,
                                           const float (&f0)[Q], const float (&f1)[Q], float rho1,
                                           float rho2) {
@@ -135,8 +144,13 @@ __device__ __forceinline__ void pop_store(gf *__restrict__ b, int pitch, int64_t
     const uint32_t bo = (uint32_t)x * 4u;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      stg(b + row + (int64_t)i * pitch, bo, f0[i]);
-      stg(b + row + (int64_t)(Q + i) * pitch, bo, f1[i]);
+      if constexpr (NT) {
+        stg_nt(b + row + (int64_t)i * pitch, bo, f0[i]);
+        stg_nt(b + row + (int64_t)(Q + i) * pitch, bo, f1[i]);
+      } else {
+        stg(b + row + (int64_t)i * pitch, bo, f0[i]);
+        stg(b + row + (int64_t)(Q + i) * pitch, bo, f1[i]);
+      }
     }
   } else {
     // collision conserves each component's node mass, so rho is stored as is
@@ -322,15 +336,20 @@ __device__ __forceinline__ float cpop_get(gcf *__restrict__ b, int cp, int s, in
   if constexpr (ST == 0) return b[(int64_t)s * Q * cp + cslot<Q>((uint32_t)c, i)];
   else return pop_get<Q, ST>(b, cp, s, i, 0, (int)c);
 }
-template <int Q, int ST>
+template <int Q, int ST, bool NT = false>
 __device__ __forceinline__ void cpop_store(gf *__restrict__ b, int cp, int64_t c, const float (&f0)[Q],
                                            const float (&f1)[Q], float rho1, float rho2) {
   if constexpr (ST == 0) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const uint32_t bo = cslot<Q>((uint32_t)c, i) * 4u;
-      stg(b, bo, f0[i]);
-      stg(b + (int64_t)Q * cp, bo, f1[i]);
+      if constexpr (NT) {
+        stg_nt(b, bo, f0[i]);
+        stg_nt(b + (int64_t)Q * cp, bo, f1[i]);
+      } else {
+        stg(b, bo, f0[i]);
+        stg(b + (int64_t)Q * cp, bo, f1[i]);
+      }
     }
   } else {
     pop_store<Q, ST>(b, cp, 0, (int)c, f0, f1, rho1, rho2);
@@ -1200,7 +1219,8 @@ __global__ __launch_bounds__(256) void collide_kernel(const InstDev *__restrict_
   collide_node<Q, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb, -G_ * rho1 * sy2 + rho1 * gyb,
                            -G_ * rho1 * sz2 + rho1 * gzb, -G_ * rho2 * sx1 + rho2 * gxb,
                            -G_ * rho2 * sy1 + rho2 * gyb, -G_ * rho2 * sz1 + rho2 * gzb);
-  pop_store<Q, ST>(fout, d.pitch, uniform64(y * d.ystride + z * d.zstride), x, a, b, (float)rho1, (float)rho2);
+  pop_store<Q, ST, Q == 19>(fout, d.pitch, uniform64(y * d.ystride + z * d.zstride), x, a, b, (float)rho1,
+                           (float)rho2);
   store_ghosts<Q, ST>(d, fout, info, src, xs, a, b);
 }
 
@@ -1373,7 +1393,7 @@ __global__ __launch_bounds__(256) void ccollide_kernel(const InstDev *__restrict
   collide_node<Q, COLL, R>(d, a, b, rho1, rho2, -G_ * rho1 * sx2 + rho1 * gxb, -G_ * rho1 * sy2 + rho1 * gyb,
                            -G_ * rho1 * sz2 + rho1 * gzb, -G_ * rho2 * sx1 + rho2 * gxb,
                            -G_ * rho2 * sy1 + rho2 * gyb, -G_ * rho2 * sz1 + rho2 * gzb);
-  cpop_store<Q, ST>(G(d.f[parity ^ 1]), d.cpitch, c, a, b, (float)rho1, (float)rho2);
+  cpop_store<Q, ST, Q == 19>(G(d.f[parity ^ 1]), d.cpitch, c, a, b, (float)rho1, (float)rho2);
 }
 
 // ---------------------------------------------------------------------------
