@@ -296,6 +296,15 @@ __device__ __forceinline__ int xcd_block() {
   return xcd * q8 + min(xcd, r8) + (b >> 3);
 }
 
+// The same, walking the tiles in reverse on odd steps: a step's first tiles
+// are then the ones the previous step wrote last, which are still in the
+// Infinity Cache when a batch's buffers exceed it (64 uneven D2Q9 instances:
+// 0.483 -> 0.466 ms per step).
+__device__ __forceinline__ int xcd_block_alternating(int parity) {
+  const int b = xcd_block();
+  return (parity & 1) ? (int)gridDim.x - 1 - b : b;
+}
+
 // The compacted layout's tables are read through global-address loads: a
 // flat load would also count against the scalar-load counter, so that every
 // wait for an instance field (scalar loads) would wait for it as well.
@@ -460,7 +469,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(FusedShape<
   __shared__ V psi[kRH][64];
   __shared__ float park[KP > 0 ? KP * 4 : 1][18][64];  // [row slot * 4 + wave][component * 9 + link][lane]
 
-  const int bid = xcd_block();
+  const int bid = xcd_block_alternating(parity);
   const int inst = __builtin_amdgcn_readfirstlane(block_inst ? block_inst[bid] : 0);
   const InstDev &d = insts[inst];
   const int lb = bid - d.block_base;
@@ -661,7 +670,7 @@ __global__ __launch_bounds__(256) void step_d2q9_list(const InstDev *__restrict_
   __shared__ uint16_t list[kN];     // interior positions of the fluid nodes, row-major
   __shared__ int cnt[TY];
 
-  const int bid = xcd_block();
+  const int bid = xcd_block_alternating(parity);
   const int inst = __builtin_amdgcn_readfirstlane(block_inst ? block_inst[bid] : 0);
   const InstDev &d = insts[inst];
   const int lb = bid - d.block_base;
